@@ -1,0 +1,24 @@
+"""CPU oracle for the hierarchical-hybrid-grid full-multigrid solve, its error estimator and
+the adjoint gradient.
+
+TEST INFRASTRUCTURE ONLY.  This package is imported by ``tests/``, by ``__graft_entry__.smoke``
+and by the ``cpu_baseline`` leg of ``bench.py`` -- nothing in the product package imports,
+links or executes it.  It shares no code with the HIP library: it builds every fine level by
+recursive refinement of each macro element (2D: 4-split at edge midpoints; 3D: Bey's eight
+children), assembles global sparse matrices element by element, and runs a textbook FMG on
+them in float64.
+
+Parity status per function (what pins it is listed in the tests):
+  refine.*      pinned: DoF-count formula, volume sum, lattice equality, congruence classes
+  assemble.*    pinned: symmetry, zero row sums, affine kernel, closed-form stencils,
+                Galerkin identities, 1^T M 1 = |Omega|
+  fmg.*         pinned: direct sparse solve, MMS O(h^2) rates, linearity of MG
+  estimate.*    pinned: brute-force quadrature, affine special case, effectivity bounds
+                (Theorem on eta_j bounds, closed forms reproduced from Tables 1-2)
+  adjoint.*     pinned: duality J = g^T u = lambda^T b, finite differences
+  fmg.simulate_mixed   parity unpinned beyond convergence to the float64 fixed point
+"""
+from .refine import Hierarchy, build_hierarchy
+from . import assemble, colour, fmg, estimate, adjoint
+
+__all__ = ["Hierarchy", "build_hierarchy", "assemble", "colour", "fmg", "estimate", "adjoint"]

@@ -1,0 +1,92 @@
+"""Colour classes for the Gauss-Seidel smoother.
+
+The paper smooths with Gauss-Seidel (Section 5; and the scaling study's V(2,2) cycles) but
+does not fix an ordering.  The reading taken here: a forward multicolour sweep, colour
+0, 1, ..., C-1, where every colour class is an independent set of the fine-mesh graph, so
+updating a class simultaneously equals updating it point by point.
+
+Two rules:
+* red-black: colour = parity of the sum of the node's integer grid coordinates (coordinates
+  times 2^(p+l), with 2^p the smallest power of two making every macro vertex integral).
+  It is exact Gauss-Seidel only on meshes whose off-axis couplings vanish (right-isosceles
+  triangles, Kuhn tetrahedra); ``is_proper_for`` checks that against a matrix.
+* multicolour: a node interior to a macro element with integer barycentrics (c_0..c_d) in
+  the macro's vertex order gets (c_1 + 2 c_2) mod 3 in 2D and (c_1 + 2 c_2 + 3 c_3) mod 4 in
+  3D; the remaining (interface) nodes are coloured greedily, first-fit, in canonical DoF
+  order, avoiding every already coloured neighbour in the mesh graph.
+Nodes on the Dirichlet boundary are never updated and get colour -1.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def _dyadic_power(coords: np.ndarray) -> int:
+    for p in range(0, 40):
+        s = coords * (2.0 ** p)
+        if np.all(s == np.round(s)):
+            return p
+    raise ValueError("coarse coordinates are not dyadic")
+
+
+def red_black(h, l: int) -> np.ndarray:
+    lv = h.levels[l]
+    p = _dyadic_power(h.coarse_coords)
+    ic = np.round(lv.X * (2.0 ** (p + l))).astype(np.int64)
+    col = (ic.sum(axis=1) % 2).astype(np.int64)
+    col[lv.boundary] = -1
+    return col
+
+
+def mesh_graph(lv) -> sp.csr_matrix:
+    E = lv.E
+    d1 = E.shape[1]
+    r, c = [], []
+    for i in range(d1):
+        for j in range(d1):
+            if i != j:
+                r.append(E[:, i]); c.append(E[:, j])
+    r = np.concatenate(r); c = np.concatenate(c)
+    G = sp.coo_matrix((np.ones(r.size, dtype=np.int8), (r, c)), shape=(lv.n, lv.n)).tocsr()
+    G.data[:] = 1
+    return G
+
+
+def multicolour(h, l: int) -> np.ndarray:
+    lv = h.levels[l]
+    d = h.d
+    bary = lv.node_bary
+    inner = (bary > 0).sum(axis=1) == d + 1
+    col = np.full(lv.n, -1, dtype=np.int64)
+    if d == 2:
+        ci = (bary[:, 1] + 2 * bary[:, 2]) % 3
+    else:
+        ci = (bary[:, 1] + 2 * bary[:, 2] + 3 * bary[:, 3]) % 4
+    col[inner] = ci[inner]
+    G = mesh_graph(lv)
+    order = h.canonical_order(l)
+    for i in order:
+        if inner[i] or lv.boundary[i]:
+            continue
+        nb = G.indices[G.indptr[i]:G.indptr[i + 1]]
+        used = set(int(c) for c in col[nb] if c >= 0)
+        c = 0
+        while c in used:
+            c += 1
+        col[i] = c
+    return col
+
+
+def classes(col: np.ndarray) -> list[np.ndarray]:
+    C = int(col.max()) + 1 if col.size and col.max() >= 0 else 0
+    return [np.nonzero(col == c)[0] for c in range(C)]
+
+
+def is_proper_for(col: np.ndarray, A: sp.csr_matrix, tol: float = 0.0) -> bool:
+    """True if no two distinct nodes of the same colour are coupled by A (|A_ij| > tol)."""
+    Acoo = A.tocoo()
+    m = (Acoo.row != Acoo.col) & (np.abs(Acoo.data) > tol)
+    r, c = Acoo.row[m], Acoo.col[m]
+    same = (col[r] == col[c]) & (col[r] >= 0)
+    return not bool(np.any(same))
