@@ -1,0 +1,173 @@
+/*
+ * hhg.h -- C ABI of the MI355X (gfx950) hierarchical-hybrid-grid full-multigrid library.
+ *
+ * The library solves the P1 finite-element diffusion problem  -div(kappa grad u) = f  with
+ * Dirichlet data g on a hierarchical hybrid grid: a coarse simplicial macro mesh T_0
+ * (triangles in 2D, tetrahedra in 3D) refined uniformly L times (Section 2 of the kl-refinement
+ * paper).  It runs the full multigrid of Algorithm 4 (procedure FMG) matrix-free on the GPU
+ * and computes the FMG-difference error estimate of Section 4 (procedure ErrorEstimate of
+ * Algorithm 4), plus an adjoint gradient of a goal functional.
+ *
+ * Conventions shared by every entry point
+ *   - Status codes: every call returns HHG_OK (0) or a negative hhg_status; nothing aborts,
+ *     throws across the ABI or prints.  hhg_last_error() gives a message for the last failure
+ *     on that context (thread-local for calls that had no context).
+ *   - Ownership: the caller owns every buffer it passes; the library copies host mesh arrays
+ *     during hhg_setup and never frees caller memory.  The device workspace is allocated by
+ *     the caller (for example by PyTorch) and must outlive the context.
+ *   - Memory spaces: arguments documented "device" are HIP device pointers on the device that
+ *     was current at hhg_bind_workspace; "host" are ordinary host pointers.
+ *   - Vectors: float64, one entry per degree of freedom (DoF) of a level, in the library's
+ *     canonical DoF order: coarse-vertex DoFs by vertex id, then DoFs interior to coarse
+ *     edges, then (3D) interior to coarse faces, then interior to macro elements.  Edges and
+ *     faces are numbered by their sorted global vertex tuples; within a primitive DoFs are
+ *     ordered lexicographically by their integer coordinates along the primitive's vertices
+ *     (sorted by global id), last coordinate most significant; inside a macro element, by the
+ *     coordinates along the element's own vertex order.  hhg_dof_coords exports this order.
+ *   - Streams: all device work is enqueued on the stream given to hhg_bind_workspace.  Calls
+ *     that return host values synchronise that stream first.
+ *   - Calls on one context must not overlap (they share the workspace).
+ */
+#ifndef HHG_H
+#define HHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hhg_ctx_s* hhg_ctx;
+
+typedef enum {
+  HHG_OK = 0,
+  HHG_EINVAL = -1,    /* bad argument or option                                           */
+  HHG_EMESH = -2,     /* invalid macro mesh (degenerate or inverted cell, non-manifold face)  */
+  HHG_ENOMEM = -3,    /* workspace too small                                                */
+  HHG_EHIP = -4,      /* a HIP runtime call failed                                         */
+  HHG_ENOTCONV = -5,  /* iteration stagnated or produced NaN                                */
+  HHG_ESTATE = -6     /* call made in the wrong state (no workspace, no preceding solve)    */
+} hhg_status;
+
+enum { HHG_KAPPA_MACRO = 0, HHG_KAPPA_P1 = 1 };
+enum { HHG_GS_REDBLACK = 0, HHG_GS_MULTICOLOR = 1, HHG_JACOBI = 2 };
+enum { HHG_FP64 = 0, HHG_FP32_REFINED = 1 };
+enum { HHG_OP_STIFFNESS = 0, HHG_OP_MASS = 1 };
+
+/* Coarse macro mesh T_0.  All arrays are host memory and are copied by hhg_setup. */
+typedef struct {
+  int dim;                    /* 2 (triangles) or 3 (tetrahedra)                               */
+  int64_t n_vertices;
+  const double* coords;       /* n_vertices * dim, row-major                                   */
+  int64_t n_cells;
+  const int32_t* cells;       /* n_cells * (dim+1) vertex ids; vertex 0 is the local origin    */
+  const uint8_t* dirichlet;   /* per vertex: 1 = Dirichlet.  A boundary vertex, edge or face is
+                                 Dirichlet when all its vertices are flagged.  NULL = the whole
+                                 boundary is Dirichlet.                                       */
+  const double* kappa_cell;   /* per macro coefficient; NULL = 1                               */
+} hhg_mesh;
+
+typedef struct {
+  int coefficient;            /* HHG_KAPPA_MACRO: kappa constant per macro element;
+                                 HHG_KAPPA_P1: nodal coefficient set by hhg_set_kappa_nodal,
+                                 averaged over the vertices of every micro element            */
+  int smoother;               /* HHG_GS_REDBLACK | HHG_GS_MULTICOLOR | HHG_JACOBI              */
+  double jacobi_omega;        /* damping of the Jacobi smoother (0 selects 2/3)                */
+} hhg_options;
+
+typedef struct {
+  int nu;                     /* V-cycles per FMG level (Algorithm 4's nu)                     */
+  int pre, post;              /* V(pre, post) smoothing sweeps                                 */
+  int precision;              /* HHG_FP64, or HHG_FP32_REFINED: float32 V-cycles on the
+                                 correction inside float64 residual/update steps              */
+  double rtol;                /* extra cycles on level L until ||r|| <= rtol * ||r_0||, where
+                                 r_0 is the residual of u = g on the boundary and 0 inside     */
+  int max_iter;               /* cap on those extra cycles (0 = FMG only)                      */
+} hhg_solve_params;
+
+typedef struct {
+  int vcycles;                /* V-cycles on all FMG levels plus extra cycles                  */
+  int ir_steps;               /* extra cycles on level L                                       */
+  double final_rel_residual;  /* ||r|| / ||r_0|| after the solve (computed only if max_iter>0) */
+  double ms_total;            /* device time of the solve (HIP events), milliseconds          */
+} hhg_solve_stats;
+
+/* Validate the macro mesh, build primitives, per-macro stencils and colourings for levels
+ * 0..L (Section 2 hierarchy), and plan the workspace.  L >= 1.  On failure *out is NULL. */
+hhg_status hhg_setup(const hhg_mesh* coarse, int L, const hhg_options* opt, hhg_ctx* out);
+
+/* Bytes of device workspace the context needs. */
+hhg_status hhg_workspace_bytes(hhg_ctx ctx, size_t* bytes);
+
+/* Bind caller-allocated device memory (>= hhg_workspace_bytes, 256-byte aligned) and a HIP
+ * stream (NULL = default stream); uploads tables.  Must precede every device call. */
+hhg_status hhg_bind_workspace(hhg_ctx ctx, void* device_ptr, size_t bytes, void* hip_stream);
+
+/* Number of DoFs (including Dirichlet ones) on a level, 0 <= level <= L. */
+hhg_status hhg_num_dofs(hhg_ctx ctx, int level, int64_t* n);
+
+/* Coordinates of the DoFs of a level in canonical order: device, num_dofs * dim doubles. */
+hhg_status hhg_dof_coords(hhg_ctx ctx, int level, double* device_xyz);
+
+/* Replace the per-macro coefficients (host, n_cells values > 0); refactors level 0. */
+hhg_status hhg_set_kappa_cell(hhg_ctx ctx, const double* host_kappa);
+
+/* Nodal coefficient on level L (device, canonical order, values > 0); HHG_KAPPA_P1 only.
+ * Coarser levels use its values at their nodes. */
+hhg_status hhg_set_kappa_nodal(hhg_ctx ctx, const double* device_kappa);
+
+/* Full multigrid solve of A_L u = b_L (equation of the per-level linear system, Section 4.5)
+ * with b_l = M_l f_l on every level l (f_l = nodal values of f) and u = g on Dirichlet DoFs,
+ * following procedure FMG of Algorithm 4, then optional extra cycles.  f_nodal, g_nodal and
+ * u_out are device vectors on level L.  The prolongated level solutions w_l are kept for
+ * hhg_estimate.  stats may be NULL. */
+hhg_status hhg_fmg_solve(hhg_ctx ctx, const double* f_nodal, const double* g_nodal, double* u_out,
+                         const hhg_solve_params* params, hhg_solve_stats* stats);
+
+/* Error estimate of procedure ErrorEstimate (Algorithm 4) from the last hhg_fmg_solve, for
+ * 0 < j < L: eta_cell_host[T] = ||u_L - w_{L-1}||_{L2(T)} for every macro T (host, n_cells),
+ * *eta_j = theta^j ||e~_{L-j}||, *theta_est = ||e~_{L-j}|| / ||e~_{L-j-1}||,
+ * *norm_e = ||e~_{L-j}||.  Any output pointer may be NULL.  Synchronises the stream. */
+hhg_status hhg_estimate(hhg_ctx ctx, int j, double* eta_cell_host, double* eta_j, double* theta_est,
+                        double* norm_e);
+
+/* y = A x or y = M x on a level with the full (unconstrained) assembled matrix; x, y device
+ * vectors in canonical order (op = HHG_OP_STIFFNESS | HHG_OP_MASS). */
+hhg_status hhg_apply(hhg_ctx ctx, int level, int op, const double* x, double* y);
+
+/* y = M_L x (mass matrix on level L), device vectors; used for L2 goal functionals. */
+hhg_status hhg_mass_apply(hhg_ctx ctx, const double* x, double* y);
+
+/* Smoother sweeps on one level: u (device, in/out) <- `sweeps` sweeps for A u = b with the
+ * context's smoother; b (device) is the assembled right-hand side; Dirichlet DoFs are kept. */
+hhg_status hhg_smooth(hhg_ctx ctx, int level, double* u, const double* b, int sweeps);
+
+/* r_c = P^T r_f restricted from level (level) to level-1, zero on coarse Dirichlet DoFs;
+ * e_f = P e_c prolongated from level-1 to level.  Device vectors in canonical order. */
+hhg_status hhg_restrict(hhg_ctx ctx, int level, const double* r_fine, double* r_coarse);
+hhg_status hhg_prolongate(hhg_ctx ctx, int level, const double* e_coarse, double* e_fine);
+
+/* Gradient of J(u(f, kappa)) for the converged discrete solution: solves the adjoint system
+ * A lambda = dJdu (lambda = 0 on Dirichlet DoFs) by FMG + extra cycles after recomputing u,
+ * then dJdf = M_L lambda (device, level L) and dJdkappa_host[e] = -lambda^T A_e u (host,
+ * n_cells; A_e = unit-coefficient stiffness of macro e).  Either output may be NULL. */
+hhg_status hhg_adjoint(hhg_ctx ctx, const double* f_nodal, const double* g_nodal, const double* dJdu,
+                       double* dJdf, double* dJdkappa_host, const hhg_solve_params* params);
+
+/* Time `sweeps` smoother sweeps on level L on internal vectors (precision HHG_FP64 or
+ * HHG_FP32_REFINED = float32); returns device milliseconds and algorithmic bytes moved. */
+hhg_status hhg_bench_smoother(hhg_ctx ctx, int precision, int sweeps, double* ms, double* bytes);
+
+/* Relative residuals ||r|| / ||r_0|| after each extra cycle of the last solve on this context
+ * (host array of `capacity` doubles); *count receives the number recorded. */
+hhg_status hhg_residual_history(hhg_ctx ctx, double* out, int capacity, int* count);
+
+const char* hhg_status_string(hhg_status s);
+const char* hhg_last_error(hhg_ctx ctx);
+void hhg_destroy(hhg_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HHG_H */

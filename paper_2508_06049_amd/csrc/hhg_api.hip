@@ -1,0 +1,713 @@
+// C ABI of the HHG library and the host-side multigrid driver.
+//
+// The driver sequences kernel launches on the bound stream:
+//   FMG (Algorithm 4, procedure FMG): level-0 exact solve, then for l = 1..L the prolongation
+//   of the level-(l-1) solution (stored as w_{l-1}, Dirichlet data written on the boundary)
+//   followed by nu V(pre,post) cycles; optional extra cycles on level L.
+//   FP32_REFINED: every cycle is  r = b - A u (float64, stored float32), a float32 V-cycle on
+//   the correction from zero, u += e (float64).  Level 0 is solved in float64 in both modes.
+//   ErrorEstimate (Algorithm 4): one fused kernel over level L forms u_L - w_{L-1} and
+//   u_L - P w_{L-2} and their per-macro mass norms.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hhg_internal.h"
+#include "hhg_kernels.h"
+#include "hhg_lattice.h"
+
+using namespace hhg;
+
+namespace {
+
+thread_local std::string g_err;
+
+#define HIPCHK(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      c->err = std::string(#call) + ": " + hipGetErrorString(e_);                 \
+      return HHG_EHIP;                                                            \
+    }                                                                             \
+  } while (0)
+
+#define LAUNCHCHK()                                                               \
+  do {                                                                            \
+    hipError_t e_ = hipGetLastError();                                            \
+    if (e_ != hipSuccess) {                                                       \
+      c->err = std::string("kernel launch: ") + hipGetErrorString(e_);            \
+      return HHG_EHIP;                                                            \
+    }                                                                             \
+  } while (0)
+
+#define TRY(x)                       \
+  do {                               \
+    hhg_status s_ = (x);             \
+    if (s_ != HHG_OK) return s_;     \
+  } while (0)
+
+inline hipStream_t ST(hhg_ctx c) { return (hipStream_t)c->stream; }
+
+LK lk_of(hhg_ctx c, int l) {
+  const Level& lv = c->lev[l];
+  LK k;
+  k.n = lv.n;
+  k.l = lv.l;
+  k.S = lv.S;
+  k.Sraw = (int)lv.Sraw;
+  k.NI = (int)lv.NI;
+  k.nEd = (int)lv.nEd;
+  k.nFd = (int)lv.nFd;
+  k.nIface = lv.nIface;
+  k.ndof = lv.ndof;
+  k.nmacro = (int)c->nC;
+  return k;
+}
+
+// stiffness scales like n^(2-d), mass like n^(-d) relative to the n = 1 tables
+double sA(hhg_ctx c, int l) { return c->dim == 2 ? 1.0 : std::ldexp(1.0, -l); }
+double sM(hhg_ctx c, int l) { return std::ldexp(1.0, -c->dim * l); }
+bool p1(hhg_ctx c) { return c->opt.coefficient == HHG_KAPPA_P1; }
+double omega(hhg_ctx c) { return c->opt.jacobi_omega > 0 ? c->opt.jacobi_omega : 2.0 / 3.0; }
+
+hhg_status check_ready(hhg_ctx c) {
+  if (!c) return HHG_EINVAL;
+  if (!c->bound) { c->err = "no workspace bound"; return HHG_ESTATE; }
+  if (p1(c) && !c->kappa_nodal_set) { c->err = "HHG_KAPPA_P1 needs hhg_set_kappa_nodal first"; return HHG_ESTATE; }
+  return HHG_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// precision-specific level arrays
+template <typename T> struct Arr;
+template <> struct Arr<double> {
+  static double*& x(Level& l) { return l.x; }
+  static double*& t(Level& l) { return l.t; }
+  static double*& rc(Level& l) { return l.rc; }
+};
+template <> struct Arr<float> {
+  static float*& x(Level& l) { return l.x32; }
+  static float*& t(Level& l) { return l.t32; }
+  static float*& rc(Level& l) { return l.b32; }
+};
+
+template <typename T>
+hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
+  Level& lv = c->lev[l];
+  const LK k = lk_of(c, l);
+  const bool jac = c->opt.smoother == HHG_JACOBI;
+  const int rb = c->opt.smoother == HHG_GS_REDBLACK ? 1 : 0;
+  for (int s = 0; s < sweeps; ++s) {
+    T* x = Arr<T>::x(lv);
+    if (jac) {
+      T* y = Arr<T>::t(lv);
+      launch_smooth_interior<T>(c->dim, p1(c), k, c->tab, x, y, b, 0, 0, 1, omega(c), sA(c, l), lv.kn, ST(c));
+      launch_smooth_iface<T>(c->dim, p1(c), k, c->tab, nullptr, (int)lv.nIface, x, y, b, 1, omega(c), sA(c, l), lv.kn,
+                             ST(c));
+      std::swap(Arr<T>::x(lv), Arr<T>::t(lv));
+    } else {
+      for (int col = 0; col < lv.ncolours; ++col) {
+        if (col < lv.interior_colours)
+          launch_smooth_interior<T>(c->dim, p1(c), k, c->tab, x, x, b, col, rb, 0, 0.0, sA(c, l), lv.kn, ST(c));
+        const int cnt = lv.colour_off[col + 1] - lv.colour_off[col];
+        launch_smooth_iface<T>(c->dim, p1(c), k, c->tab, lv.d_colour_list + lv.colour_off[col], cnt, x, x, b, 0, 0.0,
+                               sA(c, l), lv.kn, ST(c));
+      }
+    }
+  }
+  LAUNCHCHK();
+  return HHG_OK;
+}
+
+// level-0 step: x (+)= A_II^{-1} r on the inner coarse vertices
+template <typename T>
+hhg_status coarse_step(hhg_ctx c, const T* b, bool x_is_zero) {
+  Level& l0 = c->lev[0];
+  T* x = Arr<T>::x(l0);
+  if (x_is_zero) {
+    launch_coarse<T>(c->n0, c->d_ccopy_off, c->d_ccopy, c->d_ainv, b, x, 0, ST(c));
+  } else {
+    T* r = Arr<T>::t(l0);
+    launch_apply<T, T>(c->dim, p1(c), lk_of(c, 0), c->tab, x, b, r, 0, sA(c, 0), 1.0, -1.0, 1, l0.kn, ST(c));
+    launch_coarse<T>(c->n0, c->d_ccopy_off, c->d_ccopy, c->d_ainv, r, x, 1, ST(c));
+  }
+  LAUNCHCHK();
+  return HHG_OK;
+}
+
+// V(pre,post) cycle on level l for A x_l = b; x_is_zero lets the coarsest step skip a residual
+template <typename T>
+hhg_status vcycle(hhg_ctx c, int l, const T* b, int pre, int post, bool x_is_zero) {
+  if (l == 0) return coarse_step<T>(c, b, x_is_zero);
+  Level& lv = c->lev[l];
+  Level& lc = c->lev[l - 1];
+  TRY(smooth<T>(c, l, b, pre));
+  launch_apply<T, T>(c->dim, p1(c), lk_of(c, l), c->tab, Arr<T>::x(lv), b, Arr<T>::t(lv), 0, sA(c, l), 1.0, -1.0, 1,
+                     lv.kn, ST(c));
+  launch_restrict<T>(c->dim, lk_of(c, l), lk_of(c, l - 1), c->tab, Arr<T>::t(lv), Arr<T>::rc(lc), ST(c));
+  launch_fill<T>(Arr<T>::x(lc), lc.nfull, (T)0, ST(c));   // homogeneous correction, Dirichlet copies included
+  TRY(vcycle<T>(c, l - 1, Arr<T>::rc(lc), pre, post, true));
+  launch_prolong<T>(c->dim, lk_of(c, l), lk_of(c, l - 1), c->tab, Arr<T>::x(lc), Arr<T>::x(lv), (T*)nullptr,
+                    (const T*)nullptr, 0, ST(c));
+  TRY(smooth<T>(c, l, b, post));
+  LAUNCHCHK();
+  return HHG_OK;
+}
+
+// one cycle on level l of the selected precision for x_l (float64) and rhs bf_l
+hhg_status cycle(hhg_ctx c, int l, const double* b, const hhg_solve_params& p) {
+  Level& lv = c->lev[l];
+  if (p.precision == HHG_FP64) return vcycle<double>(c, l, b, p.pre, p.post, false);
+  // residual in float64, stored as float32 right-hand side of the correction equation
+  launch_apply<double, float>(c->dim, p1(c), lk_of(c, l), c->tab, lv.x, b, lv.b32, 0, sA(c, l), 1.0, -1.0, 1, lv.kn,
+                              ST(c));
+  // interface rows: sum the per-macro partials in float64 before rounding (owner copy only)
+  launch_iface_residual<double, float>(c->dim, p1(c), lk_of(c, l), c->tab, lv.x, b, lv.b32, sA(c, l), lv.kn, ST(c));
+  launch_fill<float>(lv.x32, lv.nfull, 0.0f, ST(c));
+  TRY(vcycle<float>(c, l, lv.b32, p.pre, p.post, l == 0));
+  launch_add_f32(lv.x, lv.x32, lv.nfull, ST(c));
+  LAUNCHCHK();
+  return HHG_OK;
+}
+
+// ||b - A x|| over the non-Dirichlet DoFs of level l (uses t_l), returned on the host
+hhg_status residual_norm(hhg_ctx c, int l, const double* x, const double* b, double* out) {
+  Level& lv = c->lev[l];
+  launch_apply<double, double>(c->dim, p1(c), lk_of(c, l), c->tab, x, b, lv.t, 0, sA(c, l), 1.0, -1.0, 1, lv.kn, ST(c));
+  launch_sqnorm(c->dim, lk_of(c, l), c->tab, lv.t, c->d_red, c->d_scal, ST(c));
+  LAUNCHCHK();
+  double h = 0;
+  HIPCHK(hipMemcpyAsync(&h, c->d_scal, sizeof(double), hipMemcpyDeviceToHost, ST(c)));
+  HIPCHK(hipStreamSynchronize(ST(c)));
+  *out = std::sqrt(h);
+  return HHG_OK;
+}
+
+// FMG given bf_l and g_l on all levels; result in lev[L].x, w_l in lev[l+1].w
+hhg_status fmg_core(hhg_ctx c, const hhg_solve_params& p, hhg_solve_stats* stats) {
+  const int L = c->L;
+  int vcycles = 0;
+  Level& l0 = c->lev[0];
+  launch_init_dirichlet(c->dim, lk_of(c, 0), c->tab, l0.g, l0.x, 0.0, ST(c));
+  TRY(coarse_step<double>(c, l0.bf, false));
+  for (int l = 1; l <= L; ++l) {
+    Level& lv = c->lev[l];
+    launch_prolong<double>(c->dim, lk_of(c, l), lk_of(c, l - 1), c->tab, c->lev[l - 1].x, lv.x, lv.w, lv.g, 2, ST(c));
+    for (int it = 0; it < p.nu; ++it) { TRY(cycle(c, l, lv.bf, p)); ++vcycles; }
+  }
+  LAUNCHCHK();
+  int extra = 0;
+  double rel = 0.0;
+  if (p.max_iter > 0) {
+    Level& lL = c->lev[L];
+    // reference residual: u = g on the boundary, 0 inside (assembled into rc_L as scratch)
+    launch_init_dirichlet(c->dim, lk_of(c, L), c->tab, lL.g, c->d_aux1, 0.0, ST(c));
+    double r0 = 0, r = 0;
+    TRY(residual_norm(c, L, c->d_aux1, lL.bf, &r0));
+    TRY(residual_norm(c, L, lL.x, lL.bf, &r));
+    rel = r0 > 0 ? r / r0 : 0.0;
+    c->res_hist.clear();
+    while (extra < p.max_iter && rel > p.rtol) {
+      TRY(cycle(c, L, lL.bf, p));
+      ++extra;
+      ++vcycles;
+      TRY(residual_norm(c, L, lL.x, lL.bf, &r));
+      rel = r0 > 0 ? r / r0 : 0.0;
+      c->res_hist.push_back(rel);
+      if (!std::isfinite(rel)) { c->err = "residual is not finite"; return HHG_ENOTCONV; }
+      // stagnation: less than 10% reduction over the last four cycles
+      const size_t nh = c->res_hist.size();
+      if (nh >= 8 && rel > 0.9 * c->res_hist[nh - 5] && rel > p.rtol) {
+        if (rel <= 1e-9) break;   // round-off floor of the float64 residual
+        c->err = "extra cycles stagnate at relative residual " + std::to_string(rel) + " after " + std::to_string(extra) +
+                 " cycles";
+        if (stats) { stats->vcycles = vcycles; stats->ir_steps = extra; stats->final_rel_residual = rel; }
+        return HHG_ENOTCONV;
+      }
+    }
+  }
+  if (stats) {
+    stats->vcycles = vcycles;
+    stats->ir_steps = extra;
+    stats->final_rel_residual = rel;
+  }
+  return HHG_OK;
+}
+
+// right-hand sides of the primal problem on every level from nodal f and g on level L
+hhg_status setup_rhs(hhg_ctx c, const double* f_nodal, const double* g_nodal) {
+  const int L = c->L;
+  Level& lL = c->lev[L];
+  launch_canon_to_full(c->dim, lk_of(c, L), c->tab, f_nodal, lL.t, 0, ST(c));
+  launch_canon_to_full(c->dim, lk_of(c, L), c->tab, g_nodal, lL.g, 0, ST(c));
+  for (int l = 0; l < L; ++l) {
+    launch_inject(c->dim, lk_of(c, L), lk_of(c, l), lL.t, c->lev[l].t, ST(c));
+    launch_inject(c->dim, lk_of(c, L), lk_of(c, l), lL.g, c->lev[l].g, ST(c));
+  }
+  for (int l = 0; l <= L; ++l) {
+    Level& lv = c->lev[l];
+    launch_apply<double, double>(c->dim, false, lk_of(c, l), c->tab, lv.t, nullptr, lv.bf, 1, sM(c, l), 0.0, 1.0, 1,
+                                 nullptr, ST(c));
+  }
+  LAUNCHCHK();
+  return HHG_OK;
+}
+
+hhg_status validate_params(hhg_ctx c, const hhg_solve_params* p) {
+  if (!p) { c->err = "params is NULL"; return HHG_EINVAL; }
+  if (p->nu < 1 || p->pre < 0 || p->post < 0 || p->max_iter < 0 ||
+      (p->precision != HHG_FP64 && p->precision != HHG_FP32_REFINED)) {
+    c->err = "invalid solve parameters";
+    return HHG_EINVAL;
+  }
+  return HHG_OK;
+}
+
+hhg_status upload_coarse(hhg_ctx c) {
+  if (c->n0 > 0)
+    HIPCHK(hipMemcpyAsync(c->d_ainv, c->Ainv.data(), c->Ainv.size() * 8, hipMemcpyHostToDevice, ST(c)));
+  HIPCHK(hipStreamSynchronize(ST(c)));
+  return HHG_OK;
+}
+
+// prolongate a level-`from` vector up to level `to` through the given per-level scratch
+const double* prolong_chain(hhg_ctx c, const double* v, int from, int to, bool use_rc) {
+  for (int l = from + 1; l <= to; ++l) {
+    double* dst = use_rc ? c->lev[l].rc : c->lev[l].t;
+    launch_prolong<double>(c->dim, lk_of(c, l), lk_of(c, l - 1), c->tab, v, dst, (double*)nullptr,
+                           (const double*)nullptr, 1, ST(c));
+    v = dst;
+  }
+  return v;
+}
+
+// per-macro [||u - a||_T^2, ||u - P b||_T^2] into host vectors
+hhg_status estimate_pair(hhg_ctx c, const double* a, const double* bc, std::vector<double>& s1, std::vector<double>& s2) {
+  const int L = c->L;
+  double* out = c->d_red + (c->red_capacity - 2 * c->nC - 8);
+  launch_estimate(c->dim, lk_of(c, L), lk_of(c, L - 1), c->tab, c->lev[L].x, a, bc, c->d_red, out, sM(c, L), ST(c));
+  LAUNCHCHK();
+  std::vector<double> h(2 * c->nC);
+  HIPCHK(hipMemcpyAsync(h.data(), out, h.size() * 8, hipMemcpyDeviceToHost, ST(c)));
+  HIPCHK(hipStreamSynchronize(ST(c)));
+  s1.resize(c->nC);
+  s2.resize(c->nC);
+  for (int64_t m = 0; m < c->nC; ++m) { s1[m] = h[2 * m]; s2[m] = h[2 * m + 1]; }
+  return HHG_OK;
+}
+
+}  // namespace
+
+// =========================================================================================
+extern "C" {
+
+const char* hhg_status_string(hhg_status s) {
+  switch (s) {
+    case HHG_OK: return "HHG_OK";
+    case HHG_EINVAL: return "HHG_EINVAL: invalid argument";
+    case HHG_EMESH: return "HHG_EMESH: invalid mesh";
+    case HHG_ENOMEM: return "HHG_ENOMEM: workspace too small";
+    case HHG_EHIP: return "HHG_EHIP: HIP runtime error";
+    case HHG_ENOTCONV: return "HHG_ENOTCONV: no convergence";
+    case HHG_ESTATE: return "HHG_ESTATE: wrong state";
+  }
+  return "unknown status";
+}
+
+const char* hhg_last_error(hhg_ctx c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+hhg_status hhg_setup(const hhg_mesh* mesh, int L, const hhg_options* opt, hhg_ctx* out) {
+  if (!out) { g_err = "out is NULL"; return HHG_EINVAL; }
+  *out = nullptr;
+  if (!mesh || !opt) { g_err = "mesh or options is NULL"; return HHG_EINVAL; }
+  if (mesh->dim != 2 && mesh->dim != 3) { g_err = "dim must be 2 or 3"; return HHG_EINVAL; }
+  if (L < 1 || L > (mesh->dim == 3 ? 9 : 12)) { g_err = "level L out of range"; return HHG_EINVAL; }
+  if (mesh->n_vertices <= 0 || mesh->n_cells <= 0 || !mesh->coords || !mesh->cells) { g_err = "empty mesh"; return HHG_EMESH; }
+  if (opt->smoother < HHG_GS_REDBLACK || opt->smoother > HHG_JACOBI ||
+      (opt->coefficient != HHG_KAPPA_MACRO && opt->coefficient != HHG_KAPPA_P1)) {
+    g_err = "invalid options";
+    return HHG_EINVAL;
+  }
+  hhg_ctx c = new (std::nothrow) hhg_ctx_s();
+  if (!c) { g_err = "out of host memory"; return HHG_ENOMEM; }
+  c->dim = mesh->dim;
+  c->L = L;
+  c->opt = *opt;
+  c->nV = mesh->n_vertices;
+  c->nC = mesh->n_cells;
+  const int nv = c->dim + 1;
+  c->coords.assign(mesh->coords, mesh->coords + c->nV * c->dim);
+  c->cells.assign(mesh->cells, mesh->cells + c->nC * nv);
+  c->kappa_cell.assign(c->nC, 1.0);
+  if (mesh->kappa_cell) c->kappa_cell.assign(mesh->kappa_cell, mesh->kappa_cell + c->nC);
+  for (double k : c->kappa_cell)
+    if (!(k > 0) || !std::isfinite(k)) { g_err = "kappa_cell must be positive"; delete c; return HHG_EINVAL; }
+  if (mesh->dirichlet) c->vdir_user.assign(mesh->dirichlet, mesh->dirichlet + c->nV);
+  hhg_status s = build_topology(c);
+  if (s == HHG_OK) s = build_stencils(c);
+  if (s != HHG_OK) { g_err = c->err; delete c; return s; }
+  // levels
+  c->lev.resize(L + 1);
+  for (int l = 0; l <= L; ++l) {
+    Level& lv = c->lev[l];
+    lv.l = l;
+    lv.n = 1 << l;
+    const int n = lv.n;
+    lv.Sraw = c->dim == 3 ? tet_count(n) : tri_count(n);
+    lv.S = (lv.Sraw + 63) / 64 * 64;
+    lv.NI = c->dim == 3 ? tet_count(n - 4) : tri_count(n - 3);
+    lv.nEd = n - 1;
+    lv.nFd = tri_count(n - 3);
+    lv.nIface = c->nV + (int64_t)c->nE * lv.nEd + (c->dim == 3 ? (int64_t)c->nF * lv.nFd : 0);
+    lv.ndof = lv.nIface + c->nC * lv.NI;
+    lv.nfull = c->nC * lv.S;
+  }
+  s = build_colouring(c);
+  if (s == HHG_OK) s = build_coarse(c, nullptr);
+  if (s != HHG_OK) { g_err = c->err; delete c; return s; }
+  plan_workspace(c);
+  *out = c;
+  return HHG_OK;
+}
+
+hhg_status hhg_workspace_bytes(hhg_ctx c, size_t* bytes) {
+  if (!c || !bytes) return HHG_EINVAL;
+  *bytes = c->ws_bytes;
+  return HHG_OK;
+}
+
+hhg_status hhg_bind_workspace(hhg_ctx c, void* ptr, size_t bytes, void* stream) {
+  if (!c) return HHG_EINVAL;
+  if (!ptr || bytes < c->ws_bytes) { c->err = "workspace too small"; return HHG_ENOMEM; }
+  if (((uintptr_t)ptr & 255) != 0) { c->err = "workspace must be 256-byte aligned"; return HHG_EINVAL; }
+  c->ws = (char*)ptr;
+  c->stream = stream;
+  hipStream_t st = ST(c);
+  const int d = c->dim, nv = d + 1;
+  char* w = c->ws;
+  HIPCHK(hipMemsetAsync(w, 0, c->ws_bytes, st));
+  auto up = [&](int64_t off, const void* src, size_t n) -> hipError_t {
+    if (n == 0) return hipSuccess;
+    return hipMemcpyAsync(w + off, src, n, hipMemcpyHostToDevice, st);
+  };
+  HIPCHK(up(c->o_stiff, c->stiff.data(), c->stiff.size() * 8));
+  HIPCHK(up(c->o_mass, c->mass.data(), c->mass.size() * 8));
+  HIPCHK(up(c->o_elemK, c->elemK.data(), c->elemK.size() * 8));
+  HIPCHK(up(c->o_kappa, c->kappa_cell.data(), c->kappa_cell.size() * 8));
+  HIPCHK(up(c->o_subprim, c->subprim.data(), c->subprim.size() * 4));
+  HIPCHK(up(c->o_suborder, c->suborder.data(), c->suborder.size()));
+  HIPCHK(up(c->o_dirbits, c->dirbits.data(), c->dirbits.size() * 2));
+  HIPCHK(up(c->o_ownbits, c->ownbits.data(), c->ownbits.size() * 2));
+  HIPCHK(up(c->o_rbpar, c->rbpar.data(), c->rbpar.size() * 4));
+  HIPCHK(up(c->o_incoff, c->inc_off.data(), c->inc_off.size() * 4));
+  HIPCHK(up(c->o_inc, c->inc.data(), c->inc.size() * sizeof(Inc)));
+  HIPCHK(up(c->o_primdir, c->primdir.data(), c->primdir.size()));
+  HIPCHK(up(c->o_ccopyoff, c->coarse_copy_off.data(), c->coarse_copy_off.size() * 4));
+  HIPCHK(up(c->o_ccopy, c->coarse_copy.data(), c->coarse_copy.size() * 8));
+  std::vector<double> mx(c->nC * nv * d);
+  for (int64_t m = 0; m < c->nC; ++m)
+    for (int a = 0; a < nv; ++a)
+      for (int q = 0; q < d; ++q) mx[(m * nv + a) * d + q] = c->coords[c->cells[m * nv + a] * d + q];
+  HIPCHK(up(c->o_mxyz, mx.data(), mx.size() * 8));
+  Tables& t = c->tab;
+  t.dim = d;
+  t.nmacro = (int)c->nC;
+  t.nV = (int)c->nV;
+  t.nE = c->nE;
+  t.nF = c->nF;
+  t.stiff = (const double*)(w + c->o_stiff);
+  t.mass = (const double*)(w + c->o_mass);
+  t.elemK = (const double*)(w + c->o_elemK);
+  t.kappa = (const double*)(w + c->o_kappa);
+  t.subprim = (const int32_t*)(w + c->o_subprim);
+  t.suborder = (const uint8_t*)(w + c->o_suborder);
+  t.dirbits = (const uint16_t*)(w + c->o_dirbits);
+  t.ownbits = (const uint16_t*)(w + c->o_ownbits);
+  t.rbpar = (const int32_t*)(w + c->o_rbpar);
+  t.inc_off = (const int32_t*)(w + c->o_incoff);
+  t.inc = (const Inc*)(w + c->o_inc);
+  t.primdir = (const uint8_t*)(w + c->o_primdir);
+  for (int q = 0; q < kMaxMask; ++q) { t.validdirs[q] = c->validdirs[q]; t.incvalid[q] = c->incvalid[q]; }
+  c->d_red = (double*)(w + c->o_red);
+  c->d_scal = (double*)(w + c->o_scal);
+  c->d_ccopy_off = (int32_t*)(w + c->o_ccopyoff);
+  c->d_ccopy = (int64_t*)(w + c->o_ccopy);
+  c->d_ainv = (double*)(w + c->o_ainv);
+  c->d_aux0 = (double*)(w + c->o_aux0);
+  c->d_aux1 = (double*)(w + c->o_aux1);
+  for (auto& lv : c->lev) {
+    lv.x = (double*)(w + lv.off_x);
+    lv.t = (double*)(w + lv.off_t);
+    lv.bf = (double*)(w + lv.off_bf);
+    lv.rc = (double*)(w + lv.off_rc);
+    lv.g = (double*)(w + lv.off_g);
+    lv.w = (double*)(w + lv.off_w);
+    lv.kn = lv.off_kn >= 0 ? (double*)(w + lv.off_kn) : nullptr;
+    lv.x32 = (float*)(w + lv.off_x32);
+    lv.t32 = (float*)(w + lv.off_t32);
+    lv.b32 = (float*)(w + lv.off_b32);
+    lv.d_colour_list = (int32_t*)(w + lv.off_cl);
+    HIPCHK(up(lv.off_cl, lv.colour_list.data(), lv.colour_list.size() * 4));
+  }
+  if (!c->ev0) {
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    c->ev0 = a;
+    c->ev1 = b;
+  }
+  c->bound = true;
+  c->solved = false;
+  return upload_coarse(c);
+}
+
+hhg_status hhg_num_dofs(hhg_ctx c, int level, int64_t* n) {
+  if (!c || !n) return HHG_EINVAL;
+  if (level < 0 || level > c->L) { c->err = "level out of range"; return HHG_EINVAL; }
+  *n = c->lev[level].ndof;
+  return HHG_OK;
+}
+
+hhg_status hhg_dof_coords(hhg_ctx c, int level, double* xyz) {
+  if (!c || !xyz) return HHG_EINVAL;
+  if (!c->bound) { c->err = "no workspace bound"; return HHG_ESTATE; }
+  if (level < 0 || level > c->L) { c->err = "level out of range"; return HHG_EINVAL; }
+  launch_dof_coords(c->dim, lk_of(c, level), c->tab, (const double*)(c->ws + c->o_mxyz), nullptr, xyz, ST(c));
+  LAUNCHCHK();
+  return HHG_OK;
+}
+
+hhg_status hhg_set_kappa_cell(hhg_ctx c, const double* kappa) {
+  if (!c || !kappa) return HHG_EINVAL;
+  for (int64_t m = 0; m < c->nC; ++m)
+    if (!(kappa[m] > 0) || !std::isfinite(kappa[m])) { c->err = "kappa_cell must be positive"; return HHG_EINVAL; }
+  c->kappa_cell.assign(kappa, kappa + c->nC);
+  TRY(build_coarse(c, nullptr));
+  if (c->bound) {
+    HIPCHK(hipMemcpyAsync(c->ws + c->o_kappa, c->kappa_cell.data(), c->nC * 8, hipMemcpyHostToDevice, ST(c)));
+    TRY(upload_coarse(c));
+  }
+  c->solved = false;
+  return HHG_OK;
+}
+
+hhg_status hhg_set_kappa_nodal(hhg_ctx c, const double* kappa) {
+  if (!c || !kappa) return HHG_EINVAL;
+  if (!p1(c)) { c->err = "hhg_set_kappa_nodal needs HHG_KAPPA_P1"; return HHG_ESTATE; }
+  if (!c->bound) { c->err = "no workspace bound"; return HHG_ESTATE; }
+  const int L = c->L;
+  launch_canon_to_full(c->dim, lk_of(c, L), c->tab, kappa, c->lev[L].kn, 0, ST(c));
+  for (int l = 0; l < L; ++l) launch_inject(c->dim, lk_of(c, L), lk_of(c, l), c->lev[L].kn, c->lev[l].kn, ST(c));
+  LAUNCHCHK();
+  std::vector<double> kv(c->nV);
+  HIPCHK(hipMemcpyAsync(kv.data(), kappa, c->nV * 8, hipMemcpyDeviceToHost, ST(c)));   // vertices lead the order
+  HIPCHK(hipStreamSynchronize(ST(c)));
+  for (double k : kv)
+    if (!(k > 0) || !std::isfinite(k)) { c->err = "nodal kappa must be positive"; return HHG_EINVAL; }
+  TRY(build_coarse(c, kv.data()));
+  TRY(upload_coarse(c));
+  c->kappa_nodal_set = true;
+  c->solved = false;
+  return HHG_OK;
+}
+
+hhg_status hhg_fmg_solve(hhg_ctx c, const double* f, const double* g, double* u_out, const hhg_solve_params* p,
+                         hhg_solve_stats* stats) {
+  TRY(check_ready(c));
+  TRY(validate_params(c, p));
+  if (!f || !g || !u_out) { c->err = "NULL vector"; return HHG_EINVAL; }
+  HIPCHK(hipEventRecord((hipEvent_t)c->ev0, ST(c)));
+  TRY(setup_rhs(c, f, g));
+  hhg_solve_stats st{};
+  hhg_status s = fmg_core(c, *p, &st);
+  if (s != HHG_OK && s != HHG_ENOTCONV) return s;
+  launch_full_to_canon(c->dim, lk_of(c, c->L), c->tab, c->lev[c->L].x, u_out, 0, ST(c));
+  LAUNCHCHK();
+  HIPCHK(hipEventRecord((hipEvent_t)c->ev1, ST(c)));
+  if (stats) {
+    HIPCHK(hipEventSynchronize((hipEvent_t)c->ev1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, (hipEvent_t)c->ev0, (hipEvent_t)c->ev1));
+    st.ms_total = ms;
+    *stats = st;
+  }
+  c->solved = (s == HHG_OK);
+  c->last_nu = p->nu;
+  return s;
+}
+
+hhg_status hhg_estimate(hhg_ctx c, int j, double* eta_cell, double* eta_j, double* theta_est, double* norm_e) {
+  TRY(check_ready(c));
+  if (!c->solved) { c->err = "hhg_estimate needs a preceding successful hhg_fmg_solve"; return HHG_ESTATE; }
+  const int L = c->L;
+  if (j < 1 || j >= L) { c->err = "need 0 < j < L"; return HHG_EINVAL; }
+  const int l = L - j;
+  // w_k is stored on level k+1 (lev[k+1].w)
+  std::vector<double> a1, a2;
+  // j = 1 pair: (w_{L-1} on L, w_{L-2} on L-1) -> eta_T and, for j = 1, the global estimate
+  const double* wL1 = c->lev[L].w;
+  const double* wL2 = c->lev[L - 1].w;
+  if (L - 1 == 0) { c->err = "L >= 2 required for the estimate"; return HHG_EINVAL; }
+  TRY(estimate_pair(c, wL1, wL2, a1, a2));
+  std::vector<double> s_l = a1, s_lm1 = a2;
+  if (j > 1) {
+    // e~_l = u_L - I_{l+1}^L w_l,  e~_{l-1} = u_L - I_l^L w_{l-1} (last prolongation fused)
+    const double* A = prolong_chain(c, c->lev[l + 1].w, l + 1, L, true);
+    const double* B = prolong_chain(c, c->lev[l].w, l, L - 1, false);
+    TRY(estimate_pair(c, A, B, s_l, s_lm1));
+  }
+  double n1 = 0, n2 = 0;
+  for (int64_t m = 0; m < c->nC; ++m) { n1 += s_l[m]; n2 += s_lm1[m]; }
+  n1 = std::sqrt(std::max(n1, 0.0));
+  n2 = std::sqrt(std::max(n2, 0.0));
+  const double theta = n2 > 0 ? n1 / n2 : 0.0;
+  if (eta_cell)
+    for (int64_t m = 0; m < c->nC; ++m) eta_cell[m] = std::sqrt(std::max(a1[m], 0.0));
+  if (eta_j) *eta_j = std::pow(theta, j) * n1;
+  if (theta_est) *theta_est = theta;
+  if (norm_e) *norm_e = n1;
+  return HHG_OK;
+}
+
+hhg_status hhg_apply(hhg_ctx c, int level, int op, const double* x, double* y) {
+  TRY(check_ready(c));
+  if (level < 0 || level > c->L || (op != HHG_OP_STIFFNESS && op != HHG_OP_MASS) || !x || !y) {
+    c->err = "invalid argument";
+    return HHG_EINVAL;
+  }
+  Level& lv = c->lev[level];
+  launch_canon_to_full(c->dim, lk_of(c, level), c->tab, x, lv.rc, 0, ST(c));
+  launch_apply<double, double>(c->dim, op == HHG_OP_STIFFNESS && p1(c), lk_of(c, level), c->tab, lv.rc, nullptr, lv.t,
+                               op == HHG_OP_STIFFNESS ? 0 : 1, op == HHG_OP_STIFFNESS ? sA(c, level) : sM(c, level), 0.0,
+                               1.0, 0, lv.kn, ST(c));
+  launch_full_to_canon(c->dim, lk_of(c, level), c->tab, lv.t, y, 1, ST(c));
+  LAUNCHCHK();
+  c->solved = false;
+  return HHG_OK;
+}
+
+hhg_status hhg_mass_apply(hhg_ctx c, const double* x, double* y) {
+  if (!c) return HHG_EINVAL;
+  return hhg_apply(c, c->L, HHG_OP_MASS, x, y);
+}
+
+hhg_status hhg_smooth(hhg_ctx c, int level, double* u, const double* b, int sweeps) {
+  TRY(check_ready(c));
+  if (level < 1 || level > c->L || !u || !b || sweeps < 0) { c->err = "invalid argument"; return HHG_EINVAL; }
+  Level& lv = c->lev[level];
+  launch_canon_to_full(c->dim, lk_of(c, level), c->tab, u, lv.x, 0, ST(c));
+  launch_canon_to_full(c->dim, lk_of(c, level), c->tab, b, lv.rc, 1, ST(c));
+  LAUNCHCHK();
+  TRY(smooth<double>(c, level, lv.rc, sweeps));
+  launch_full_to_canon(c->dim, lk_of(c, level), c->tab, lv.x, u, 0, ST(c));
+  LAUNCHCHK();
+  c->solved = false;
+  return HHG_OK;
+}
+
+hhg_status hhg_restrict(hhg_ctx c, int level, const double* rf, double* rcn) {
+  TRY(check_ready(c));
+  if (level < 1 || level > c->L || !rf || !rcn) { c->err = "invalid argument"; return HHG_EINVAL; }
+  Level& lf = c->lev[level];
+  Level& lc = c->lev[level - 1];
+  launch_canon_to_full(c->dim, lk_of(c, level), c->tab, rf, lf.t, 2, ST(c));
+  launch_restrict<double>(c->dim, lk_of(c, level), lk_of(c, level - 1), c->tab, lf.t, lc.rc, ST(c));
+  launch_full_to_canon(c->dim, lk_of(c, level - 1), c->tab, lc.rc, rcn, 1, ST(c));
+  LAUNCHCHK();
+  c->solved = false;
+  return HHG_OK;
+}
+
+hhg_status hhg_prolongate(hhg_ctx c, int level, const double* ec, double* ef) {
+  TRY(check_ready(c));
+  if (level < 1 || level > c->L || !ec || !ef) { c->err = "invalid argument"; return HHG_EINVAL; }
+  Level& lf = c->lev[level];
+  Level& lc = c->lev[level - 1];
+  launch_canon_to_full(c->dim, lk_of(c, level - 1), c->tab, ec, lc.rc, 0, ST(c));
+  launch_prolong<double>(c->dim, lk_of(c, level), lk_of(c, level - 1), c->tab, lc.rc, lf.t, (double*)nullptr,
+                         (const double*)nullptr, 1, ST(c));
+  launch_full_to_canon(c->dim, lk_of(c, level), c->tab, lf.t, ef, 0, ST(c));
+  LAUNCHCHK();
+  c->solved = false;
+  return HHG_OK;
+}
+
+hhg_status hhg_adjoint(hhg_ctx c, const double* f, const double* g, const double* dJdu, double* dJdf, double* dJdk,
+                       const hhg_solve_params* p) {
+  TRY(check_ready(c));
+  TRY(validate_params(c, p));
+  if (!f || !g || !dJdu) { c->err = "NULL vector"; return HHG_EINVAL; }
+  const int L = c->L;
+  Level& lL = c->lev[L];
+  // 1. recompute u (nothing from the forward pass is stored)
+  TRY(setup_rhs(c, f, g));
+  TRY(fmg_core(c, *p, nullptr));
+  launch_copy(c->d_aux0, lL.x, lL.nfull, ST(c));   // keep u
+  // 2. adjoint right-hand side on level L (dual, Dirichlet rows zero), restricted downwards
+  launch_canon_to_full(c->dim, lk_of(c, L), c->tab, dJdu, lL.bf, 2, ST(c));
+  for (int l = L; l >= 1; --l)
+    launch_restrict<double>(c->dim, lk_of(c, l), lk_of(c, l - 1), c->tab, c->lev[l].bf, c->lev[l - 1].bf, ST(c));
+  for (int l = 0; l <= L; ++l) launch_fill<double>(c->lev[l].g, c->lev[l].nfull, 0.0, ST(c));
+  LAUNCHCHK();
+  // 3. lambda by FMG + extra cycles (homogeneous Dirichlet data)
+  TRY(fmg_core(c, *p, nullptr));
+  // 4. dJ/df = M lambda
+  if (dJdf) {
+    launch_apply<double, double>(c->dim, false, lk_of(c, L), c->tab, lL.x, nullptr, lL.t, 1, sM(c, L), 0.0, 1.0, 0,
+                                 nullptr, ST(c));
+    launch_full_to_canon(c->dim, lk_of(c, L), c->tab, lL.t, dJdf, 1, ST(c));
+  }
+  // 5. dJ/dkappa_e = -lambda^T A_e u
+  if (dJdk) {
+    double* out = c->d_red + (c->red_capacity - c->nC - 8);
+    launch_bilinear(c->dim, lk_of(c, L), c->tab, lL.x, c->d_aux0, c->d_red, out, sA(c, L), ST(c));
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(dJdk, out, c->nC * 8, hipMemcpyDeviceToHost, ST(c)));
+    HIPCHK(hipStreamSynchronize(ST(c)));
+    for (int64_t m = 0; m < c->nC; ++m) dJdk[m] = -dJdk[m];
+  }
+  LAUNCHCHK();
+  c->solved = false;
+  return HHG_OK;
+}
+
+hhg_status hhg_bench_smoother(hhg_ctx c, int precision, int sweeps, double* ms, double* bytes) {
+  TRY(check_ready(c));
+  if (sweeps < 1 || (precision != HHG_FP64 && precision != HHG_FP32_REFINED)) { c->err = "invalid argument"; return HHG_EINVAL; }
+  const int L = c->L;
+  Level& lL = c->lev[L];
+  HIPCHK(hipEventRecord((hipEvent_t)c->ev0, ST(c)));
+  if (precision == HHG_FP64) TRY(smooth<double>(c, L, lL.bf, sweeps));
+  else TRY(smooth<float>(c, L, lL.b32, sweeps));
+  HIPCHK(hipEventRecord((hipEvent_t)c->ev1, ST(c)));
+  HIPCHK(hipEventSynchronize((hipEvent_t)c->ev1));
+  float t = 0;
+  HIPCHK(hipEventElapsedTime(&t, (hipEvent_t)c->ev0, (hipEvent_t)c->ev1));
+  if (ms) *ms = t;
+  const double per = precision == HHG_FP64 ? 24.0 + (p1(c) ? 8.0 : 0.0) : 12.0 + (p1(c) ? 8.0 : 0.0);
+  if (bytes) *bytes = per * (double)lL.ndof * sweeps;
+  c->solved = false;
+  return HHG_OK;
+}
+
+hhg_status hhg_residual_history(hhg_ctx c, double* out, int capacity, int* count) {
+  if (!c || !count || capacity < 0 || (capacity > 0 && !out)) return HHG_EINVAL;
+  const int n = (int)c->res_hist.size();
+  *count = n;
+  for (int q = 0; q < std::min(n, capacity); ++q) out[q] = c->res_hist[q];
+  return HHG_OK;
+}
+
+void hhg_destroy(hhg_ctx c) {
+  if (!c) return;
+  if (c->ev0) (void)hipEventDestroy((hipEvent_t)c->ev0);
+  if (c->ev1) (void)hipEventDestroy((hipEvent_t)c->ev1);
+  delete c;
+}
+
+}  // extern "C"

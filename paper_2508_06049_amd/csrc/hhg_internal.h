@@ -1,0 +1,166 @@
+// Internal declarations of the HHG library: lattice geometry of a refined macro element,
+// the per-context plan, and the kernel launch interface.
+//
+// Lattice of one macro element refined to level l (n = 2^l micro intervals per edge): the
+// micro nodes are the points x0 + (i/n)(x1-x0) + (j/n)(x2-x0) [+ (k/n)(x3-x0)] with integer
+// barycentric coordinates c = (n-i-j-k, i, j, k) >= 0.  Uniform refinement (the 4-split in
+// 2D, Bey's rule in 3D) produces the lattice triangulation whose edges run along
+//   2D: +-{e1, e2, e2-e1}
+//   3D: +-{e1, e2, e3, e2-e1, e3-e1, e3-e2, e1-e2+e3}
+// (in 3D, with p = (i, i+j, i+j+k) it is the Kuhn triangulation of the unit-cube lattice).
+// Every vector of a level is stored per macro over its whole closure, in the order
+//   3D: slab k (outer), row j, index i (inner);   2D: row j (outer), index i (inner),
+// padded to a multiple of 64 entries per macro.  DoFs on macro vertices, edges and faces are
+// therefore stored once per adjacent macro (ghost copies).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hhg.h"
+
+namespace hhg {
+
+constexpr int kMaxMask = 16;   // zero-set masks of the barycentric coordinates (bit q: c_q == 0)
+constexpr int kNDir3 = 15, kNDir2 = 7;
+constexpr int kNType3 = 6, kNType2 = 2;
+
+// direction tables: index 0 is the centre, 1..H positive, H+1..2H negative
+constexpr int kDir3[7][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {-1, 1, 0}, {-1, 0, 1}, {0, -1, 1}, {1, -1, 1}};
+constexpr int kDir2[3][2] = {{1, 0}, {0, 1}, {-1, 1}};
+
+// A macro-primitive incidence: macro `macro` contains the primitive; slot[r] is the local
+// vertex slot (0..dim) of the primitive's r-th vertex (sorted by global id); mask has bit q
+// set for every local slot q that is not a vertex of the primitive.
+struct Inc {
+  int32_t macro;
+  uint8_t slot[3];
+  uint8_t mask;
+};
+
+// Device-side tables, all living inside the bound workspace.
+struct Tables {
+  int dim = 0;
+  int nmacro = 0;
+  int nV = 0, nE = 0, nF = 0;          // primitive counts
+  const double* stiff = nullptr;       // [nmacro][16][ndir] unit-coefficient stiffness, n = 1 scale
+  const double* mass = nullptr;        // [nmacro][16][ndir] mass, n = 1 scale
+  const double* elemK = nullptr;       // [nmacro][ntype][(d+1)^2] unit element stiffness, n = 1 scale
+  const double* kappa = nullptr;       // [nmacro]
+  const int32_t* subprim = nullptr;    // [nmacro][16] global primitive id of the sub-primitive with that zero-set
+  const uint8_t* suborder = nullptr;   // [nmacro][16] slots of that primitive sorted by global id, 2 bits each
+  const uint16_t* dirbits = nullptr;   // [nmacro] bit `mask` set: that sub-primitive is Dirichlet
+  const uint16_t* ownbits = nullptr;   // [nmacro] bit `mask` set: this macro is the lowest-id owner
+  const int32_t* rbpar = nullptr;      // [nmacro][4] red-black parity: x0 parity at level scale factor, s1, s2, s3
+  const int32_t* inc_off = nullptr;    // [nprim+1] CSR offsets into inc
+  const Inc* inc = nullptr;            // incidences, macro id ascending per primitive
+  const uint8_t* primdir = nullptr;    // [nprim] primitive is Dirichlet
+  uint16_t validdirs[kMaxMask] = {};   // per zero-set mask: directions whose neighbour is in the closure
+  uint32_t incvalid[kMaxMask] = {};    // per zero-set mask: incident (type, vertex) pairs inside the macro
+};
+
+// Per-level layout and buffers.
+struct Level {
+  int l = 0, n = 1;
+  int64_t Sraw = 0, S = 0;      // closure entries per macro (raw / padded)
+  int64_t NI = 0;               // macro-interior DoFs per macro
+  int64_t nEd = 0, nFd = 0;     // DoFs interior to one edge / one face
+  int64_t nIface = 0;           // DoFs on vertices, edges, faces (canonical prefix)
+  int64_t ndof = 0;             // canonical DoF count
+  int64_t nfull = 0;            // nmacro * S
+  int ncolours = 0;             // colours used by the Gauss-Seidel sweep
+  int interior_colours = 0;     // colours present among macro-interior DoFs
+  std::vector<int32_t> colour_off;     // host: CSR offsets of the interface colour lists
+  std::vector<int32_t> colour_list;    // host: interface DoF ids per colour (non-Dirichlet)
+  // device buffers (inside workspace)
+  double *x = nullptr, *t = nullptr, *bf = nullptr, *rc = nullptr, *g = nullptr, *w = nullptr, *kn = nullptr;
+  float *x32 = nullptr, *t32 = nullptr, *b32 = nullptr;
+  int32_t* d_colour_list = nullptr;
+  int64_t off_x = 0, off_t = 0, off_bf = 0, off_rc = 0, off_g = 0, off_w = 0, off_kn = -1, off_x32 = 0, off_t32 = 0,
+          off_b32 = 0, off_cl = 0;
+};
+
+}  // namespace hhg
+
+// The opaque context.
+struct hhg_ctx_s {
+  int dim = 0, L = 0;
+  hhg_options opt{};
+  int64_t nV = 0, nC = 0;
+  std::vector<double> coords;       // nV * dim
+  std::vector<int32_t> cells;       // nC * (dim+1)
+  std::vector<double> kappa_cell;   // nC
+  std::vector<uint8_t> vdir_user;   // per vertex (empty = whole boundary)
+  int dyadic_p = 0;                 // smallest p with coords * 2^p integral (-1: not dyadic)
+
+  // primitives (host)
+  std::vector<int32_t> edges;       // nE * 2 sorted
+  std::vector<int32_t> faces;       // nF * 3 sorted
+  int nE = 0, nF = 0;
+  std::vector<uint8_t> primdir;     // nprim
+  std::vector<int32_t> inc_off;     // nprim + 1
+  std::vector<hhg::Inc> inc;
+  std::vector<int32_t> subprim;     // nC * 16
+  std::vector<uint8_t> suborder;    // nC * 16
+  std::vector<uint16_t> dirbits, ownbits;
+  std::vector<int32_t> rbpar;       // nC * 4
+  std::vector<double> stiff, mass, elemK;
+  std::vector<uint16_t> validdirs;  // [16] bitmask of valid directions per zero-set mask
+  std::vector<uint32_t> incvalid;   // [16] bitmask of valid incident (type, vertex) pairs
+
+  // coarse (level 0) solve
+  int n0 = 0;                       // inner coarse vertices
+  std::vector<int32_t> coarse_vertex;      // inner vertex ids
+  std::vector<int32_t> coarse_copy_off;    // CSR into coarse_copy
+  std::vector<int64_t> coarse_copy;        // full-layout indices at level 0
+  std::vector<double> Ainv;                // n0 * n0
+
+  std::vector<hhg::Level> lev;
+  hhg::Tables tab;
+
+  // workspace
+  size_t ws_bytes = 0;
+  char* ws = nullptr;
+  void* stream = nullptr;
+  bool bound = false;
+  bool solved = false;
+  bool kappa_nodal_set = false;
+  // workspace offsets of tables
+  int64_t o_stiff = 0, o_mass = 0, o_elemK = 0, o_kappa = 0, o_subprim = 0, o_suborder = 0, o_dirbits = 0,
+          o_ownbits = 0, o_rbpar = 0, o_incoff = 0, o_inc = 0, o_primdir = 0, o_ccopyoff = 0, o_ccopy = 0,
+          o_ainv = 0, o_red = 0, o_scal = 0, o_mxyz = 0, o_aux0 = 0, o_aux1 = 0;
+  int64_t red_capacity = 0;         // doubles in the reduction scratch
+  double* d_red = nullptr;          // reduction scratch
+  double* d_scal = nullptr;         // small scalar scratch
+  int32_t* d_ccopy_off = nullptr;
+  int64_t* d_ccopy = nullptr;
+  double* d_ainv = nullptr;
+  double* d_aux0 = nullptr;         // level-L scratch: the recomputed solution inside hhg_adjoint
+  double* d_aux1 = nullptr;         // level-L scratch: reference iterate of the residual norm
+
+  void* ev0 = nullptr;              // hipEvent_t pair for timing
+  void* ev1 = nullptr;
+  int last_nu = 0;                  // FMG parameters of the last solve (estimator needs L >= 2)
+  std::vector<double> res_hist;     // relative residual after each extra cycle of the last solve
+
+  std::string err;
+};
+
+namespace hhg {
+
+// host setup (hhg_setup.cpp)
+hhg_status build_topology(hhg_ctx c);
+hhg_status build_stencils(hhg_ctx c);
+hhg_status build_colouring(hhg_ctx c);
+hhg_status build_coarse(hhg_ctx c, const double* kappa_vertex /* nullable, per vertex */);
+void plan_workspace(hhg_ctx c);
+
+// index helpers shared by host code
+int64_t tet_count(int64_t m);
+int64_t tri_count(int64_t m);
+int64_t lin_closure(int dim, int n, int i, int j, int k);
+int zero_mask(int dim, int n, int i, int j, int k);
+// canonical DoF index of closure point (i,j,k) of macro m on level with n = 2^l
+int64_t canonical_index(hhg_ctx c, const Level& lv, int m, int i, int j, int k);
+
+}  // namespace hhg

@@ -1,0 +1,59 @@
+// Launch interface of the HHG kernels (hhg_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hhg_internal.h"
+
+namespace hhg {
+
+// level descriptor passed to kernels by value
+struct LK {
+  int n = 1, l = 0;
+  int64_t S = 0;
+  int Sraw = 0, NI = 0, nEd = 0, nFd = 0;
+  int64_t nIface = 0, ndof = 0;
+  int nmacro = 0;
+};
+
+template <typename T>
+void launch_smooth_interior(int dim, bool p1, const LK& lk, const Tables& tb, const T* uin, T* uout, const T* b, int colour,
+                            int rb, int jacobi, double omega, double sA, const double* kn, hipStream_t st);
+template <typename T>
+void launch_smooth_iface(int dim, bool p1, const LK& lk, const Tables& tb, const int32_t* list, int count, const T* uin,
+                         T* uout, const T* b, int jacobi, double omega, double sA, const double* kn, hipStream_t st);
+template <typename Tin, typename Tout>
+void launch_apply(int dim, bool p1, const LK& lk, const Tables& tb, const Tin* x, const Tin* b, Tout* y, int op,
+                  double scale, double alpha, double beta, int zero_dir, const double* kn, hipStream_t st);
+template <typename Tin, typename Tout>
+void launch_iface_residual(int dim, bool p1, const LK& lk, const Tables& tb, const Tin* x, const Tin* b, Tout* y,
+                           double sA, const double* kn, hipStream_t st);
+template <typename T>
+void launch_restrict(int dim, const LK& f, const LK& c, const Tables& tb, const T* rf, T* bc, hipStream_t st);
+template <typename T>
+void launch_prolong(int dim, const LK& f, const LK& c, const Tables& tb, const T* ec, T* uf, T* w, const T* g, int mode,
+                    hipStream_t st);
+void launch_inject(int dim, const LK& fine, const LK& coarse, const double* src, double* dst, hipStream_t st);
+void launch_init_dirichlet(int dim, const LK& lk, const Tables& tb, const double* g, double* x, double inner,
+                           hipStream_t st);
+template <typename T>
+void launch_coarse(int n0, const int32_t* coff, const int64_t* copy, const double* Ainv, const T* rhs, T* x, int accumulate,
+                   hipStream_t st);
+void launch_sqnorm(int dim, const LK& lk, const Tables& tb, const double* r, double* partial, double* out, hipStream_t st);
+void launch_estimate(int dim, const LK& f, const LK& c, const Tables& tb, const double* u, const double* a,
+                     const double* bc, double* partial, double* out, double sM, hipStream_t st);
+void launch_bilinear(int dim, const LK& lk, const Tables& tb, const double* x, const double* y, double* partial,
+                     double* out, double sA, hipStream_t st);
+void launch_canon_to_full(int dim, const LK& lk, const Tables& tb, const double* canon, double* full, int mode,
+                          hipStream_t st);
+void launch_full_to_canon(int dim, const LK& lk, const Tables& tb, const double* full, double* canon, int mode,
+                          hipStream_t st);
+void launch_dof_coords(int dim, const LK& lk, const Tables& tb, const double* mxyz, const int32_t* cells, double* xyz,
+                       hipStream_t st);
+template <typename T>
+void launch_fill(T* x, int64_t n, T v, hipStream_t st);
+void launch_add_f32(double* u, const float* e, int64_t n, hipStream_t st);
+void launch_copy(double* dst, const double* src, int64_t n, hipStream_t st);
+
+}  // namespace hhg

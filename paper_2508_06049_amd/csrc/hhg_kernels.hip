@@ -1,0 +1,885 @@
+// HIP kernels of the HHG library for gfx950 (wave64).
+//
+// Data layout (see hhg_internal.h): every level vector is stored per macro element over its
+// whole closure, so a micro node on a macro vertex, edge or face has one copy per adjacent
+// macro.  Two kinds of vectors live in this layout:
+//   primal (solutions, corrections, nodal data): all copies hold the same value;
+//   dual (right-hand sides, residuals): copies hold per-macro partial sums whose total is the
+//        assembled value (each macro contributes the rows of its own micro elements).
+// With this split the residual, the restriction P^T, the prolongation P and the mass/stiffness
+// products are purely macro-local; only the smoother's interface update and the norms sum
+// over the copies of a DoF (additive collection from the adjacent volume macros, Section 4.5).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hhg_internal.h"
+#include "hhg_kernels.h"
+#include "hhg_lattice.h"
+
+namespace hhg {
+
+// ------------------------------------------------------------------------------------------
+// index helpers
+__device__ __forceinline__ int d_tet(int m) { return m < 0 ? 0 : ((m + 1) * (m + 2) * (m + 3)) / 6; }
+__device__ __forceinline__ int d_lin2(int n, int i, int j) { return j * (n + 1) - (j * (j - 1)) / 2 + i; }
+
+template <int D>
+__device__ __forceinline__ int d_lin(int n, int i, int j, int k) {
+  if constexpr (D == 2) {
+    return d_lin2(n, i, j);
+  } else {
+    const int m = n - k;
+    return d_tet(n) - d_tet(m) + d_lin2(m, i, j);
+  }
+}
+
+__device__ __forceinline__ void d_dec2(int n, int s, int& i, int& j) {
+  const double a = 2.0 * n + 3.0;
+  int jj = (int)floor(0.5 * (a - sqrt(fmax(a * a - 8.0 * s, 0.0))));
+  jj = max(0, min(jj, n));
+  while (jj < n && d_lin2(n, 0, jj + 1) <= s) ++jj;
+  while (jj > 0 && d_lin2(n, 0, jj) > s) --jj;
+  j = jj;
+  i = s - d_lin2(n, 0, jj);
+}
+
+template <int D>
+__device__ __forceinline__ void d_dec(int n, int s, int& i, int& j, int& k) {
+  if constexpr (D == 2) {
+    k = 0;
+    d_dec2(n, s, i, j);
+  } else {
+    const int r = d_tet(n) - s;   // >= 1
+    int m = (int)cbrt(6.0 * r) - 2;
+    m = max(0, min(m, n));
+    while (d_tet(m) < r) ++m;
+    while (m > 0 && d_tet(m - 1) >= r) --m;
+    k = n - m;
+    d_dec2(m, s - (d_tet(n) - d_tet(m)), i, j);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ int d_mask(int n, int i, int j, int k) {
+  const int c0 = n - i - j - (D == 3 ? k : 0);
+  int mk = (c0 == 0 ? 1 : 0) | (i == 0 ? 2 : 0) | (j == 0 ? 4 : 0);
+  if constexpr (D == 3) mk |= (k == 0 ? 8 : 0);
+  return mk;
+}
+
+template <int D>
+__device__ __forceinline__ void d_off(int q, int& a, int& b, int& c) {
+  if constexpr (D == 3) {
+    a = kOff3[q][0]; b = kOff3[q][1]; c = kOff3[q][2];
+  } else {
+    a = kOff2[q][0]; b = kOff2[q][1]; c = 0;
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void d_typeoff(int t, int v, int& a, int& b, int& c) {
+  if constexpr (D == 3) {
+    a = kType3[t][v][0]; b = kType3[t][v][1]; c = kType3[t][v][2];
+  } else {
+    a = kType2[t][v][0]; b = kType2[t][v][1]; c = 0;
+  }
+}
+
+template <int D> constexpr int ndir() { return D == 3 ? kNDir3 : kNDir2; }
+template <int D> constexpr int ntype() { return D == 3 ? kNType3 : kNType2; }
+
+// block-wide sum of one double (blockDim.x == 256, wave64)
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return r;
+}
+
+// interface DoF t -> primitive p and coordinates along its sorted vertices
+__device__ __forceinline__ void d_iface_decode(const LK& lk, const Tables& tb, int64_t t, int& p, int co[3], int& np) {
+  const int n = lk.n;
+  co[0] = co[1] = co[2] = 0;
+  if (t < tb.nV) { p = (int)t; co[0] = n; np = 1; return; }
+  t -= tb.nV;
+  if (t < (int64_t)tb.nE * lk.nEd) {
+    p = tb.nV + (int)(t / lk.nEd);
+    const int a = (int)(t % lk.nEd) + 1;
+    co[0] = n - a; co[1] = a; np = 2;
+    return;
+  }
+  t -= (int64_t)tb.nE * lk.nEd;
+  p = tb.nV + tb.nE + (int)(t / lk.nFd);
+  int a, b;
+  d_dec2(n - 3, (int)(t % lk.nFd), a, b);
+  co[1] = a + 1; co[2] = b + 1; co[0] = n - co[1] - co[2]; np = 3;
+}
+
+// canonical DoF index of closure point (i,j,k) of macro m
+template <int D>
+__device__ __forceinline__ int64_t d_canon(const LK& lk, const Tables& tb, int m, int i, int j, int k) {
+  const int n = lk.n;
+  const int mask = d_mask<D>(n, i, j, k);
+  if (mask == 0) return lk.nIface + (int64_t)m * lk.NI + d_lin<D>(n - D - 1, i - 1, j - 1, k - 1);
+  const int p = tb.subprim[m * kMaxMask + mask];
+  const int ord = tb.suborder[m * kMaxMask + mask];
+  const int cc[4] = {n - i - j - (D == 3 ? k : 0), i, j, k};
+  if (p < tb.nV) return p;
+  if (p < tb.nV + tb.nE) return tb.nV + (int64_t)(p - tb.nV) * lk.nEd + (cc[(ord >> 2) & 3] - 1);
+  const int a = cc[(ord >> 2) & 3], b = cc[(ord >> 4) & 3];
+  return tb.nV + (int64_t)tb.nE * lk.nEd + (int64_t)(p - tb.nV - tb.nE) * lk.nFd + d_lin2(n - 3, a - 1, b - 1);
+}
+
+// value of P e_c at fine closure point (i,j,k) (fine n), coarse vector with macro base cbase
+template <int D, typename T>
+__device__ __forceinline__ T d_prolong_val(int nc, const T* __restrict__ ec, int64_t cbase, int i, int j, int k) {
+  const int p = (i & 1) | ((j & 1) << 1) | ((D == 3 ? (k & 1) : 0) << 2);
+  if (p == 0) return ec[cbase + d_lin<D>(nc, i >> 1, j >> 1, k >> 1)];
+  int a, b, c;
+  if constexpr (D == 3) { a = kParDir3[p][0]; b = kParDir3[p][1]; c = kParDir3[p][2]; }
+  else { a = kParDir2[p][0]; b = kParDir2[p][1]; c = 0; }
+  const T lo = ec[cbase + d_lin<D>(nc, (i - a) >> 1, (j - b) >> 1, (k - c) >> 1)];
+  const T hi = ec[cbase + d_lin<D>(nc, (i + a) >> 1, (j + b) >> 1, (k + c) >> 1)];
+  return (T)0.5 * (lo + hi);
+}
+
+// row of the partial operator of macro m at closure point (i,j,k) with zero-set `mask`:
+// off = sum_{neighbours} a_q x_q, diag = a_centre.  Constant-coefficient stencil table.
+template <int D, typename T>
+__device__ __forceinline__ void d_row_const(const LK& lk, const double* __restrict__ W, uint32_t valid, double scale,
+                                            const T* __restrict__ x, int64_t base, int i, int j, int k, T& off, T& diag) {
+  constexpr int ND = ndir<D>();
+  T acc = (T)0;
+#pragma unroll
+  for (int q = 1; q < ND; ++q) {
+    if (!((valid >> q) & 1)) continue;
+    int a, b, c;
+    d_off<D>(q, a, b, c);
+    acc += (T)(scale * W[q]) * x[base + d_lin<D>(lk.n, i + a, j + b, k + c)];
+  }
+  off = acc;
+  diag = (T)(scale * W[0]);
+}
+
+// same with a nodal coefficient: every incident micro element contributes with the mean of
+// the nodal coefficient over its vertices
+template <int D, typename T>
+__device__ __forceinline__ void d_row_p1(const LK& lk, const double* __restrict__ EK, uint32_t incvalid, double scale,
+                                         const double* __restrict__ kn, const T* __restrict__ x, int64_t base, int i,
+                                         int j, int k, T& off, T& diag) {
+  constexpr int NV = D + 1, NT = ntype<D>();
+  T acc = (T)0, dg = (T)0;
+  for (int t = 0; t < NT; ++t) {
+#pragma unroll
+    for (int a = 0; a < NV; ++a) {
+      if (!((incvalid >> (t * NV + a)) & 1)) continue;
+      int oa0, oa1, oa2;
+      d_typeoff<D>(t, a, oa0, oa1, oa2);
+      int idx[NV];
+      double ks = 0.0;
+#pragma unroll
+      for (int b = 0; b < NV; ++b) {
+        int o0, o1, o2;
+        d_typeoff<D>(t, b, o0, o1, o2);
+        idx[b] = d_lin<D>(lk.n, i + o0 - oa0, j + o1 - oa1, k + o2 - oa2);
+        ks += kn[base + idx[b]];
+      }
+      ks *= scale / NV;
+      const double* Kr = EK + (t * NV + a) * NV;
+#pragma unroll
+      for (int b = 0; b < NV; ++b) {
+        if (b == a) dg += (T)(ks * Kr[b]);
+        else acc += (T)(ks * Kr[b]) * x[base + idx[b]];
+      }
+    }
+  }
+  off = acc;
+  diag = dg;
+}
+
+// ------------------------------------------------------------------------------------------
+// smoothers
+template <int D, typename T, bool P1>
+__global__ void __launch_bounds__(256) k_smooth_interior(LK lk, Tables tb, const T* __restrict__ uin, T* __restrict__ uout,
+                                                          const T* __restrict__ b, int colour, int rb, int jacobi,
+                                                          double omega, double sA, const double* __restrict__ kn) {
+  const int nchunk = (lk.NI + 255) >> 8;
+  const int m = blockIdx.x / nchunk;
+  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
+  if (s >= lk.NI) return;
+  int i, j, k;
+  d_dec<D>(lk.n - D - 1, s, i, j, k);
+  ++i; ++j;
+  if constexpr (D == 3) ++k;
+  if (!jacobi) {
+    int c;
+    if (rb) {
+      const int* rp = tb.rbpar + m * 4;
+      c = (i * rp[1] + j * rp[2] + (D == 3 ? k * rp[3] : 0)) & 1;
+    } else {
+      c = D == 2 ? (i + 2 * j) % 3 : (i + 2 * j + 3 * k) % 4;
+    }
+    if (c != colour) return;
+  }
+  const int64_t base = (int64_t)m * lk.S;
+  const int ctr = d_lin<D>(lk.n, i, j, k);
+  T off, diag;
+  if constexpr (P1) {
+    d_row_p1<D, T>(lk, tb.elemK + (size_t)m * ntype<D>() * (D + 1) * (D + 1), tb.incvalid[0], sA, kn, uin, base, i, j, k,
+                   off, diag);
+  } else {
+    d_row_const<D, T>(lk, tb.stiff + (size_t)m * kMaxMask * ndir<D>(), tb.validdirs[0], sA * tb.kappa[m], uin, base, i,
+                      j, k, off, diag);
+  }
+  if (jacobi) {
+    const T u0 = uin[base + ctr];
+    uout[base + ctr] = u0 + (T)omega * (b[base + ctr] - off - diag * u0) / diag;
+  } else {
+    uout[base + ctr] = (b[base + ctr] - off) / diag;
+  }
+}
+
+template <int D, typename T, bool P1>
+__global__ void __launch_bounds__(256) k_smooth_iface(LK lk, Tables tb, const int32_t* __restrict__ list, int count,
+                                                       const T* __restrict__ uin, T* __restrict__ uout,
+                                                       const T* __restrict__ b, int jacobi, double omega, double sA,
+                                                       const double* __restrict__ kn) {
+  const int tid = blockIdx.x * 256 + threadIdx.x;
+  if (tid >= count) return;
+  const int64_t t = list ? (int64_t)list[tid] : (int64_t)tid;
+  int p, co[3], np;
+  d_iface_decode(lk, tb, t, p, co, np);
+  const int q0 = tb.inc_off[p], q1 = tb.inc_off[p + 1];
+  const bool dir = tb.primdir[p] != 0;
+  T rhs = (T)0, off = (T)0, diag = (T)0, uold = (T)0;
+  for (int q = q0; q < q1; ++q) {
+    const Inc in = tb.inc[q];
+    int lc[4] = {0, 0, 0, 0};
+    for (int r = 0; r < np; ++r) lc[in.slot[r]] = co[r];
+    const int64_t base = (int64_t)in.macro * lk.S;
+    const int ctr = d_lin<D>(lk.n, lc[1], lc[2], lc[3]);
+    if (q == q0) uold = uin[base + ctr];
+    if (dir) continue;
+    rhs += b[base + ctr];
+    T o, dg;
+    if constexpr (P1) {
+      d_row_p1<D, T>(lk, tb.elemK + (size_t)in.macro * ntype<D>() * (D + 1) * (D + 1), tb.incvalid[in.mask], sA, kn,
+                     uin, base, lc[1], lc[2], lc[3], o, dg);
+    } else {
+      d_row_const<D, T>(lk, tb.stiff + ((size_t)in.macro * kMaxMask + in.mask) * ndir<D>(), tb.validdirs[in.mask],
+                        sA * tb.kappa[in.macro], uin, base, lc[1], lc[2], lc[3], o, dg);
+    }
+    off += o;
+    diag += dg;
+  }
+  T unew;
+  if (dir) unew = uold;
+  else if (jacobi) unew = uold + (T)omega * (rhs - off - diag * uold) / diag;
+  else unew = (rhs - off) / diag;
+  for (int q = q0; q < q1; ++q) {
+    const Inc in = tb.inc[q];
+    int lc[4] = {0, 0, 0, 0};
+    for (int r = 0; r < np; ++r) lc[in.slot[r]] = co[r];
+    uout[(int64_t)in.macro * lk.S + d_lin<D>(lk.n, lc[1], lc[2], lc[3])] = unew;
+  }
+}
+
+// Assembled residual rows at interface DoFs: r = sum_m (b_m - A_m x) in Tin precision, stored
+// in the lowest-id copy (other copies 0, Dirichlet DoFs 0).  Used when a float64 residual is
+// handed to float32 cycles: the per-macro partial rows are one-sided differences that cancel
+// only after summation, so they are summed before rounding.
+template <int D, typename Tin, typename Tout, bool P1>
+__global__ void __launch_bounds__(256) k_iface_residual(LK lk, Tables tb, const Tin* __restrict__ x,
+                                                         const Tin* __restrict__ b, Tout* __restrict__ y, double sA,
+                                                         const double* __restrict__ kn) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= lk.nIface) return;
+  int p, co[3], np;
+  d_iface_decode(lk, tb, t, p, co, np);
+  const int q0 = tb.inc_off[p], q1 = tb.inc_off[p + 1];
+  const bool dir = tb.primdir[p] != 0;
+  Tin r = (Tin)0;
+  if (!dir) {
+    for (int q = q0; q < q1; ++q) {
+      const Inc in = tb.inc[q];
+      int lc[4] = {0, 0, 0, 0};
+      for (int rr = 0; rr < np; ++rr) lc[in.slot[rr]] = co[rr];
+      const int64_t base = (int64_t)in.macro * lk.S;
+      const int ctr = d_lin<D>(lk.n, lc[1], lc[2], lc[3]);
+      Tin o, dg;
+      if constexpr (P1) {
+        d_row_p1<D, Tin>(lk, tb.elemK + (size_t)in.macro * ntype<D>() * (D + 1) * (D + 1), tb.incvalid[in.mask], sA,
+                         kn, x, base, lc[1], lc[2], lc[3], o, dg);
+      } else {
+        d_row_const<D, Tin>(lk, tb.stiff + ((size_t)in.macro * kMaxMask + in.mask) * ndir<D>(),
+                            tb.validdirs[in.mask], sA * tb.kappa[in.macro], x, base, lc[1], lc[2], lc[3], o, dg);
+      }
+      r += b[base + ctr] - o - dg * x[base + ctr];
+    }
+  }
+  for (int q = q0; q < q1; ++q) {
+    const Inc in = tb.inc[q];
+    int lc[4] = {0, 0, 0, 0};
+    for (int rr = 0; rr < np; ++rr) lc[in.slot[rr]] = co[rr];
+    y[(int64_t)in.macro * lk.S + d_lin<D>(lk.n, lc[1], lc[2], lc[3])] = (Tout)(q == q0 ? r : (Tin)0);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// y = alpha * b + beta * (A_m x) per macro over the closure (dual output); zero on Dirichlet
+// nodes when zero_dir.  op 0: stiffness (scaled by kappa), 1: mass.
+template <int D, typename Tin, typename Tout, bool P1>
+__global__ void __launch_bounds__(256) k_apply(LK lk, Tables tb, const Tin* __restrict__ x, const Tin* __restrict__ b,
+                                                Tout* __restrict__ y, int op, double scale, double alpha, double beta,
+                                                int zero_dir, const double* __restrict__ kn) {
+  const int nchunk = (lk.Sraw + 255) >> 8;
+  const int m = blockIdx.x / nchunk;
+  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
+  if (s >= lk.Sraw) return;
+  int i, j, k;
+  d_dec<D>(lk.n, s, i, j, k);
+  const int mask = d_mask<D>(lk.n, i, j, k);
+  const int64_t base = (int64_t)m * lk.S;
+  if (zero_dir && ((tb.dirbits[m] >> mask) & 1)) { y[base + s] = (Tout)0; return; }
+  Tin off, diag;
+  if (op == 0) {
+    if constexpr (P1) {
+      d_row_p1<D, Tin>(lk, tb.elemK + (size_t)m * ntype<D>() * (D + 1) * (D + 1), tb.incvalid[mask], scale, kn, x, base,
+                       i, j, k, off, diag);
+    } else {
+      d_row_const<D, Tin>(lk, tb.stiff + ((size_t)m * kMaxMask + mask) * ndir<D>(), tb.validdirs[mask],
+                          scale * tb.kappa[m], x, base, i, j, k, off, diag);
+    }
+  } else {
+    d_row_const<D, Tin>(lk, tb.mass + ((size_t)m * kMaxMask + mask) * ndir<D>(), tb.validdirs[mask], scale, x, base, i,
+                        j, k, off, diag);
+  }
+  const Tin ax = off + diag * x[base + s];
+  Tin v = (Tin)beta * ax;
+  if (b) v += (Tin)alpha * b[base + s];
+  y[base + s] = (Tout)v;
+}
+
+// r_c = P^T r_f per macro (dual in, dual out); zero on coarse Dirichlet nodes
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_restrict(LK f, LK c, Tables tb, const T* __restrict__ rf, T* __restrict__ bc) {
+  const int nchunk = (c.Sraw + 255) >> 8;
+  const int m = blockIdx.x / nchunk;
+  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
+  if (s >= c.Sraw) return;
+  int i, j, k;
+  d_dec<D>(c.n, s, i, j, k);
+  const int mask = d_mask<D>(c.n, i, j, k);
+  const int64_t cb = (int64_t)m * c.S, fb = (int64_t)m * f.S;
+  if ((tb.dirbits[m] >> mask) & 1) { bc[cb + s] = (T)0; return; }
+  const uint32_t valid = tb.validdirs[mask];
+  const int fi = 2 * i, fj = 2 * j, fk = 2 * k;
+  T acc = (T)0;
+#pragma unroll
+  for (int q = 1; q < ndir<D>(); ++q) {
+    if (!((valid >> q) & 1)) continue;
+    int a, b2, cc;
+    d_off<D>(q, a, b2, cc);
+    acc += rf[fb + d_lin<D>(f.n, fi + a, fj + b2, fk + cc)];
+  }
+  bc[cb + s] = rf[fb + d_lin<D>(f.n, fi, fj, fk)] + (T)0.5 * acc;
+}
+
+// prolongation over the fine closure.  mode 0: uf += P ec on non-Dirichlet nodes;
+// mode 1: uf = P ec everywhere; mode 2 (FMG): w = P ec, uf = P ec (g on Dirichlet nodes).
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_prolong(LK f, LK c, Tables tb, const T* __restrict__ ec, T* __restrict__ uf,
+                                                  T* __restrict__ w, const T* __restrict__ g, int mode) {
+  const int nchunk = (f.Sraw + 255) >> 8;
+  const int m = blockIdx.x / nchunk;
+  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
+  if (s >= f.Sraw) return;
+  int i, j, k;
+  d_dec<D>(f.n, s, i, j, k);
+  const int64_t fb = (int64_t)m * f.S;
+  const bool dir = (tb.dirbits[m] >> d_mask<D>(f.n, i, j, k)) & 1;
+  if (mode == 0 && dir) return;
+  const T v = d_prolong_val<D, T>(c.n, ec, (int64_t)m * c.S, i, j, k);
+  if (mode == 0) uf[fb + s] += v;
+  else if (mode == 1) uf[fb + s] = v;
+  else {
+    w[fb + s] = v;
+    uf[fb + s] = dir ? g[fb + s] : v;
+  }
+}
+
+// dst (level l) = src (level L) at the same points: nodal injection
+template <int D>
+__global__ void __launch_bounds__(256) k_inject(LK fine, LK coarse, const double* __restrict__ src, double* __restrict__ dst,
+                                                 int shift) {
+  const int nchunk = (coarse.Sraw + 255) >> 8;
+  const int m = blockIdx.x / nchunk;
+  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
+  if (s >= coarse.Sraw) return;
+  int i, j, k;
+  d_dec<D>(coarse.n, s, i, j, k);
+  dst[(int64_t)m * coarse.S + s] = src[(int64_t)m * fine.S + d_lin<D>(fine.n, i << shift, j << shift, k << shift)];
+}
+
+// x = g on Dirichlet nodes, `inner` elsewhere
+template <int D>
+__global__ void __launch_bounds__(256) k_init_dirichlet(LK lk, Tables tb, const double* __restrict__ g,
+                                                         double* __restrict__ x, double inner) {
+  const int nchunk = (lk.Sraw + 255) >> 8;
+  const int m = blockIdx.x / nchunk;
+  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
+  if (s >= lk.Sraw) return;
+  int i, j, k;
+  d_dec<D>(lk.n, s, i, j, k);
+  const int64_t base = (int64_t)m * lk.S;
+  x[base + s] = ((tb.dirbits[m] >> d_mask<D>(lk.n, i, j, k)) & 1) ? g[base + s] : inner;
+}
+
+// level 0: x (+)= A_II^{-1} (assembled rhs) on the inner coarse vertices; one thread per row
+template <typename T>
+__global__ void __launch_bounds__(256) k_coarse(int n0, const int32_t* __restrict__ coff, const int64_t* __restrict__ copy,
+                                                 const double* __restrict__ Ainv, const T* __restrict__ rhs,
+                                                 T* __restrict__ x, int accumulate) {
+  extern __shared__ double sr[];
+  for (int r = threadIdx.x; r < n0; r += blockDim.x) {
+    double s = 0.0;
+    for (int q = coff[r]; q < coff[r + 1]; ++q) s += (double)rhs[copy[q]];
+    sr[r] = s;
+  }
+  __syncthreads();
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n0) return;
+  double e = 0.0;
+  for (int col = 0; col < n0; ++col) e += Ainv[(size_t)col * n0 + row] * sr[col];   // symmetric, coalesced
+  for (int q = coff[row]; q < coff[row + 1]; ++q) {
+    const int64_t ix = copy[q];
+    x[ix] = accumulate ? (T)((double)x[ix] + e) : (T)e;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// reductions
+// sum over macro-interior nodes of r^2 (per block partials)
+template <int D>
+__global__ void __launch_bounds__(256) k_sq_interior(LK lk, const double* __restrict__ r, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const int nchunk = (lk.NI + 255) >> 8;
+  const int m = blockIdx.x / nchunk;
+  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
+  double v = 0.0;
+  if (s < lk.NI) {
+    int i, j, k;
+    d_dec<D>(lk.n - D - 1, s, i, j, k);
+    const double x = r[(int64_t)m * lk.S + d_lin<D>(lk.n, i + 1, j + 1, k + (D == 3 ? 1 : 0))];
+    v = x * x;
+  }
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = v;
+}
+
+// sum over non-Dirichlet interface DoFs of (sum of copies)^2 (dual vector)
+template <int D>
+__global__ void __launch_bounds__(256) k_sq_iface(LK lk, Tables tb, const double* __restrict__ r, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double v = 0.0;
+  if (t < lk.nIface) {
+    int p, co[3], np;
+    d_iface_decode(lk, tb, t, p, co, np);
+    if (!tb.primdir[p]) {
+      double s = 0.0;
+      for (int q = tb.inc_off[p]; q < tb.inc_off[p + 1]; ++q) {
+        const Inc in = tb.inc[q];
+        int lc[4] = {0, 0, 0, 0};
+        for (int rr = 0; rr < np; ++rr) lc[in.slot[rr]] = co[rr];
+        s += r[(int64_t)in.macro * lk.S + d_lin<D>(lk.n, lc[1], lc[2], lc[3])];
+      }
+      v = s * s;
+    }
+  }
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = v;
+}
+
+__global__ void __launch_bounds__(256) k_sum(const double* __restrict__ partial, int n, double* __restrict__ out) {
+  __shared__ double sh[4];
+  double v = 0.0;
+  for (int q = threadIdx.x; q < n; q += 256) v += partial[q];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) *out = v;
+}
+
+// Estimator: per macro T, sum over the closure nodes q of T of e(q) (M_T e)(q) for
+// e1 = u - a (a on level L) and e2 = u - P bc (bc on level L-1), M_T the mass matrix of T's
+// own micro elements.  Per-block partials [macro][chunk][2].
+template <int D>
+__global__ void __launch_bounds__(256) k_estimate(LK f, LK c, Tables tb, const double* __restrict__ u,
+                                                   const double* __restrict__ a, const double* __restrict__ bc,
+                                                   double* __restrict__ partial, double sM) {
+  __shared__ double sh[4];
+  const int nchunk = (f.Sraw + 255) >> 8;
+  const int m = blockIdx.x / nchunk;
+  const int chunk = blockIdx.x - m * nchunk;
+  const int s = chunk * 256 + threadIdx.x;
+  double v1 = 0.0, v2 = 0.0;
+  if (s < f.Sraw) {
+    int i, j, k;
+    d_dec<D>(f.n, s, i, j, k);
+    const int mask = d_mask<D>(f.n, i, j, k);
+    const int64_t fb = (int64_t)m * f.S, cb = (int64_t)m * c.S;
+    const double* W = tb.mass + ((size_t)m * kMaxMask + mask) * ndir<D>();
+    const uint32_t valid = tb.validdirs[mask];
+    double m1 = 0.0, m2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < ndir<D>(); ++q) {
+      if (q && !((valid >> q) & 1)) continue;
+      int o0, o1, o2;
+      d_off<D>(q, o0, o1, o2);
+      const int ii = i + o0, jj = j + o1, kk = k + o2;
+      const int lq = d_lin<D>(f.n, ii, jj, kk);
+      const double uq = u[fb + lq];
+      const double e1 = uq - a[fb + lq];
+      const double e2 = uq - d_prolong_val<D, double>(c.n, bc, cb, ii, jj, kk);
+      m1 += W[q] * e1;
+      m2 += W[q] * e2;
+    }
+    const double uc = u[fb + s];
+    v1 = (uc - a[fb + s]) * m1 * sM;
+    v2 = (uc - d_prolong_val<D, double>(c.n, bc, cb, i, j, k)) * m2 * sM;
+  }
+  v1 = block_sum(v1, sh);
+  v2 = block_sum(v2, sh);
+  if (threadIdx.x == 0) {
+    partial[((size_t)m * nchunk + chunk) * 2 + 0] = v1;
+    partial[((size_t)m * nchunk + chunk) * 2 + 1] = v2;
+  }
+}
+
+// per macro: sum over closure nodes of x(q) (A_m^unit y)(q) (unit-coefficient stiffness)
+template <int D>
+__global__ void __launch_bounds__(256) k_bilinear(LK lk, Tables tb, const double* __restrict__ x,
+                                                   const double* __restrict__ y, double* __restrict__ partial, double sA) {
+  __shared__ double sh[4];
+  const int nchunk = (lk.Sraw + 255) >> 8;
+  const int m = blockIdx.x / nchunk;
+  const int chunk = blockIdx.x - m * nchunk;
+  const int s = chunk * 256 + threadIdx.x;
+  double v = 0.0;
+  if (s < lk.Sraw) {
+    int i, j, k;
+    d_dec<D>(lk.n, s, i, j, k);
+    const int mask = d_mask<D>(lk.n, i, j, k);
+    const int64_t base = (int64_t)m * lk.S;
+    double off, diag;
+    d_row_const<D, double>(lk, tb.stiff + ((size_t)m * kMaxMask + mask) * ndir<D>(), tb.validdirs[mask], sA, y, base, i,
+                           j, k, off, diag);
+    v = x[base + s] * (off + diag * y[base + s]);
+  }
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) partial[(size_t)m * nchunk + chunk] = v;
+}
+
+// out[m * nval + v] = sum over chunks (fixed order)
+__global__ void __launch_bounds__(256) k_macro_sum(const double* __restrict__ partial, int nmacro, int nchunk, int nval,
+                                                   double* __restrict__ out) {
+  const int id = blockIdx.x * 256 + threadIdx.x;
+  if (id >= nmacro * nval) return;
+  const int m = id / nval, v = id - m * nval;
+  double s = 0.0;
+  for (int q = 0; q < nchunk; ++q) s += partial[((size_t)m * nchunk + q) * nval + v];
+  out[id] = s;
+}
+
+// ------------------------------------------------------------------------------------------
+// canonical <-> per-macro layout
+// mode 0: primal (every copy gets the value); 1: dual (owner copy gets it, others 0);
+// 2: dual with Dirichlet nodes zeroed
+template <int D>
+__global__ void __launch_bounds__(256) k_canon_to_full(LK lk, Tables tb, const double* __restrict__ canon,
+                                                        double* __restrict__ full, int mode) {
+  const int nchunk = (lk.Sraw + 255) >> 8;
+  const int m = blockIdx.x / nchunk;
+  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
+  if (s >= lk.Sraw) return;
+  int i, j, k;
+  d_dec<D>(lk.n, s, i, j, k);
+  const int mask = d_mask<D>(lk.n, i, j, k);
+  double v = canon[d_canon<D>(lk, tb, m, i, j, k)];
+  if (mode >= 1 && mask != 0 && !((tb.ownbits[m] >> mask) & 1)) v = 0.0;
+  if (mode == 2 && ((tb.dirbits[m] >> mask) & 1)) v = 0.0;
+  full[(int64_t)m * lk.S + s] = v;
+}
+
+// mode 0: primal (lowest-id copy); 1: dual (sum of copies)
+template <int D>
+__global__ void __launch_bounds__(256) k_full_to_canon(LK lk, Tables tb, const double* __restrict__ full,
+                                                        double* __restrict__ canon, int mode) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= lk.ndof) return;
+  if (t >= lk.nIface) {
+    const int64_t u = t - lk.nIface;
+    const int m = (int)(u / lk.NI);
+    int i, j, k;
+    d_dec<D>(lk.n - D - 1, (int)(u - (int64_t)m * lk.NI), i, j, k);
+    canon[t] = full[(int64_t)m * lk.S + d_lin<D>(lk.n, i + 1, j + 1, k + (D == 3 ? 1 : 0))];
+    return;
+  }
+  int p, co[3], np;
+  d_iface_decode(lk, tb, t, p, co, np);
+  double s = 0.0;
+  const int q1 = mode == 0 ? tb.inc_off[p] + 1 : tb.inc_off[p + 1];
+  for (int q = tb.inc_off[p]; q < q1; ++q) {
+    const Inc in = tb.inc[q];
+    int lc[4] = {0, 0, 0, 0};
+    for (int r = 0; r < np; ++r) lc[in.slot[r]] = co[r];
+    s += full[(int64_t)in.macro * lk.S + d_lin<D>(lk.n, lc[1], lc[2], lc[3])];
+  }
+  canon[t] = s;
+}
+
+// coordinates of canonical DoFs: x = x0 + sum_q (c_q / n)(x_q - x0) in the first adjacent macro
+template <int D>
+__global__ void __launch_bounds__(256) k_dof_coords(LK lk, Tables tb, const double* __restrict__ mxyz,
+                                                     const int32_t* __restrict__ cells, double* __restrict__ xyz) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= lk.ndof) return;
+  int m, lc[4] = {0, 0, 0, 0};
+  if (t >= lk.nIface) {
+    const int64_t u = t - lk.nIface;
+    m = (int)(u / lk.NI);
+    int i, j, k;
+    d_dec<D>(lk.n - D - 1, (int)(u - (int64_t)m * lk.NI), i, j, k);
+    lc[1] = i + 1; lc[2] = j + 1; lc[3] = D == 3 ? k + 1 : 0;
+  } else {
+    int p, co[3], np;
+    d_iface_decode(lk, tb, t, p, co, np);
+    const Inc in = tb.inc[tb.inc_off[p]];
+    m = in.macro;
+    for (int r = 0; r < np; ++r) lc[in.slot[r]] = co[r];
+  }
+  const double* X = mxyz + (size_t)m * (D + 1) * D;
+  const double inv = 1.0 / lk.n;
+  for (int q = 0; q < D; ++q) {
+    double v = X[q];
+    for (int a = 1; a <= D; ++a) v += (lc[a] * inv) * (X[a * D + q] - X[q]);
+    xyz[t * D + q] = v;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// elementwise
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill(T* __restrict__ x, int64_t n, T v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+__global__ void __launch_bounds__(256) k_add_f32(double* __restrict__ u, const float* __restrict__ e, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) u[i] += (double)e[i];
+}
+__global__ void __launch_bounds__(256) k_copy(double* __restrict__ dst, const double* __restrict__ src, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------------------------------
+// launchers
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+#define HHG_DISPATCH_D(dim, F, ...) \
+  do {                              \
+    if ((dim) == 3) F<3> __VA_ARGS__; \
+    else F<2> __VA_ARGS__;           \
+  } while (0)
+
+template <typename T>
+void launch_smooth_interior(int dim, bool p1, const LK& lk, const Tables& tb, const T* uin, T* uout, const T* b, int colour,
+                            int rb, int jacobi, double omega, double sA, const double* kn, hipStream_t st) {
+  if (lk.NI <= 0) return;
+  const unsigned g = (unsigned)(lk.nmacro * ((lk.NI + 255) / 256));
+  if (dim == 3) {
+    if (p1) k_smooth_interior<3, T, true><<<g, 256, 0, st>>>(lk, tb, uin, uout, b, colour, rb, jacobi, omega, sA, kn);
+    else k_smooth_interior<3, T, false><<<g, 256, 0, st>>>(lk, tb, uin, uout, b, colour, rb, jacobi, omega, sA, kn);
+  } else {
+    if (p1) k_smooth_interior<2, T, true><<<g, 256, 0, st>>>(lk, tb, uin, uout, b, colour, rb, jacobi, omega, sA, kn);
+    else k_smooth_interior<2, T, false><<<g, 256, 0, st>>>(lk, tb, uin, uout, b, colour, rb, jacobi, omega, sA, kn);
+  }
+}
+
+template <typename T>
+void launch_smooth_iface(int dim, bool p1, const LK& lk, const Tables& tb, const int32_t* list, int count, const T* uin,
+                         T* uout, const T* b, int jacobi, double omega, double sA, const double* kn, hipStream_t st) {
+  if (count <= 0) return;
+  const unsigned g = nblk(count);
+  if (dim == 3) {
+    if (p1) k_smooth_iface<3, T, true><<<g, 256, 0, st>>>(lk, tb, list, count, uin, uout, b, jacobi, omega, sA, kn);
+    else k_smooth_iface<3, T, false><<<g, 256, 0, st>>>(lk, tb, list, count, uin, uout, b, jacobi, omega, sA, kn);
+  } else {
+    if (p1) k_smooth_iface<2, T, true><<<g, 256, 0, st>>>(lk, tb, list, count, uin, uout, b, jacobi, omega, sA, kn);
+    else k_smooth_iface<2, T, false><<<g, 256, 0, st>>>(lk, tb, list, count, uin, uout, b, jacobi, omega, sA, kn);
+  }
+}
+
+template <typename Tin, typename Tout>
+void launch_apply(int dim, bool p1, const LK& lk, const Tables& tb, const Tin* x, const Tin* b, Tout* y, int op,
+                  double scale, double alpha, double beta, int zero_dir, const double* kn, hipStream_t st) {
+  const unsigned g = (unsigned)(lk.nmacro * ((lk.Sraw + 255) / 256));
+  if (dim == 3) {
+    if (p1) k_apply<3, Tin, Tout, true><<<g, 256, 0, st>>>(lk, tb, x, b, y, op, scale, alpha, beta, zero_dir, kn);
+    else k_apply<3, Tin, Tout, false><<<g, 256, 0, st>>>(lk, tb, x, b, y, op, scale, alpha, beta, zero_dir, kn);
+  } else {
+    if (p1) k_apply<2, Tin, Tout, true><<<g, 256, 0, st>>>(lk, tb, x, b, y, op, scale, alpha, beta, zero_dir, kn);
+    else k_apply<2, Tin, Tout, false><<<g, 256, 0, st>>>(lk, tb, x, b, y, op, scale, alpha, beta, zero_dir, kn);
+  }
+}
+
+template <typename Tin, typename Tout>
+void launch_iface_residual(int dim, bool p1, const LK& lk, const Tables& tb, const Tin* x, const Tin* b, Tout* y,
+                           double sA, const double* kn, hipStream_t st) {
+  if (lk.nIface <= 0) return;
+  const unsigned g = nblk(lk.nIface);
+  if (dim == 3) {
+    if (p1) k_iface_residual<3, Tin, Tout, true><<<g, 256, 0, st>>>(lk, tb, x, b, y, sA, kn);
+    else k_iface_residual<3, Tin, Tout, false><<<g, 256, 0, st>>>(lk, tb, x, b, y, sA, kn);
+  } else {
+    if (p1) k_iface_residual<2, Tin, Tout, true><<<g, 256, 0, st>>>(lk, tb, x, b, y, sA, kn);
+    else k_iface_residual<2, Tin, Tout, false><<<g, 256, 0, st>>>(lk, tb, x, b, y, sA, kn);
+  }
+}
+
+template <typename T>
+void launch_restrict(int dim, const LK& f, const LK& c, const Tables& tb, const T* rf, T* bc, hipStream_t st) {
+  const unsigned g = (unsigned)(c.nmacro * ((c.Sraw + 255) / 256));
+  if (dim == 3) k_restrict<3, T><<<g, 256, 0, st>>>(f, c, tb, rf, bc);
+  else k_restrict<2, T><<<g, 256, 0, st>>>(f, c, tb, rf, bc);
+}
+
+template <typename T>
+void launch_prolong(int dim, const LK& f, const LK& c, const Tables& tb, const T* ec, T* uf, T* w, const T* g, int mode,
+                    hipStream_t st) {
+  const unsigned gr = (unsigned)(f.nmacro * ((f.Sraw + 255) / 256));
+  if (dim == 3) k_prolong<3, T><<<gr, 256, 0, st>>>(f, c, tb, ec, uf, w, g, mode);
+  else k_prolong<2, T><<<gr, 256, 0, st>>>(f, c, tb, ec, uf, w, g, mode);
+}
+
+void launch_inject(int dim, const LK& fine, const LK& coarse, const double* src, double* dst, hipStream_t st) {
+  const unsigned g = (unsigned)(coarse.nmacro * ((coarse.Sraw + 255) / 256));
+  const int shift = fine.l - coarse.l;
+  if (dim == 3) k_inject<3><<<g, 256, 0, st>>>(fine, coarse, src, dst, shift);
+  else k_inject<2><<<g, 256, 0, st>>>(fine, coarse, src, dst, shift);
+}
+
+void launch_init_dirichlet(int dim, const LK& lk, const Tables& tb, const double* g, double* x, double inner,
+                           hipStream_t st) {
+  const unsigned gr = (unsigned)(lk.nmacro * ((lk.Sraw + 255) / 256));
+  if (dim == 3) k_init_dirichlet<3><<<gr, 256, 0, st>>>(lk, tb, g, x, inner);
+  else k_init_dirichlet<2><<<gr, 256, 0, st>>>(lk, tb, g, x, inner);
+}
+
+template <typename T>
+void launch_coarse(int n0, const int32_t* coff, const int64_t* copy, const double* Ainv, const T* rhs, T* x, int accumulate,
+                   hipStream_t st) {
+  if (n0 <= 0) return;
+  k_coarse<T><<<nblk(n0), 256, (size_t)n0 * sizeof(double), st>>>(n0, coff, copy, Ainv, rhs, x, accumulate);
+}
+
+void launch_sqnorm(int dim, const LK& lk, const Tables& tb, const double* r, double* partial, double* out, hipStream_t st) {
+  const unsigned g1 = (unsigned)(lk.NI > 0 ? lk.nmacro * ((lk.NI + 255) / 256) : 0);
+  const unsigned g2 = nblk(lk.nIface);
+  if (g1) {
+    if (dim == 3) k_sq_interior<3><<<g1, 256, 0, st>>>(lk, r, partial);
+    else k_sq_interior<2><<<g1, 256, 0, st>>>(lk, r, partial);
+  }
+  if (g2) {
+    if (dim == 3) k_sq_iface<3><<<g2, 256, 0, st>>>(lk, tb, r, partial + g1);
+    else k_sq_iface<2><<<g2, 256, 0, st>>>(lk, tb, r, partial + g1);
+  }
+  k_sum<<<1, 256, 0, st>>>(partial, (int)(g1 + g2), out);
+}
+
+void launch_estimate(int dim, const LK& f, const LK& c, const Tables& tb, const double* u, const double* a,
+                     const double* bc, double* partial, double* out, double sM, hipStream_t st) {
+  const int nchunk = (int)((f.Sraw + 255) / 256);
+  const unsigned g = (unsigned)(f.nmacro * nchunk);
+  if (dim == 3) k_estimate<3><<<g, 256, 0, st>>>(f, c, tb, u, a, bc, partial, sM);
+  else k_estimate<2><<<g, 256, 0, st>>>(f, c, tb, u, a, bc, partial, sM);
+  k_macro_sum<<<nblk((int64_t)f.nmacro * 2), 256, 0, st>>>(partial, f.nmacro, nchunk, 2, out);
+}
+
+void launch_bilinear(int dim, const LK& lk, const Tables& tb, const double* x, const double* y, double* partial,
+                     double* out, double sA, hipStream_t st) {
+  const int nchunk = (int)((lk.Sraw + 255) / 256);
+  const unsigned g = (unsigned)(lk.nmacro * nchunk);
+  if (dim == 3) k_bilinear<3><<<g, 256, 0, st>>>(lk, tb, x, y, partial, sA);
+  else k_bilinear<2><<<g, 256, 0, st>>>(lk, tb, x, y, partial, sA);
+  k_macro_sum<<<nblk(lk.nmacro), 256, 0, st>>>(partial, lk.nmacro, nchunk, 1, out);
+}
+
+void launch_canon_to_full(int dim, const LK& lk, const Tables& tb, const double* canon, double* full, int mode,
+                          hipStream_t st) {
+  const unsigned g = (unsigned)(lk.nmacro * ((lk.Sraw + 255) / 256));
+  if (dim == 3) k_canon_to_full<3><<<g, 256, 0, st>>>(lk, tb, canon, full, mode);
+  else k_canon_to_full<2><<<g, 256, 0, st>>>(lk, tb, canon, full, mode);
+}
+
+void launch_full_to_canon(int dim, const LK& lk, const Tables& tb, const double* full, double* canon, int mode,
+                          hipStream_t st) {
+  if (dim == 3) k_full_to_canon<3><<<nblk(lk.ndof), 256, 0, st>>>(lk, tb, full, canon, mode);
+  else k_full_to_canon<2><<<nblk(lk.ndof), 256, 0, st>>>(lk, tb, full, canon, mode);
+}
+
+void launch_dof_coords(int dim, const LK& lk, const Tables& tb, const double* mxyz, const int32_t* cells, double* xyz,
+                       hipStream_t st) {
+  if (dim == 3) k_dof_coords<3><<<nblk(lk.ndof), 256, 0, st>>>(lk, tb, mxyz, cells, xyz);
+  else k_dof_coords<2><<<nblk(lk.ndof), 256, 0, st>>>(lk, tb, mxyz, cells, xyz);
+}
+
+template <typename T>
+void launch_fill(T* x, int64_t n, T v, hipStream_t st) {
+  if (n > 0) k_fill<T><<<nblk(n), 256, 0, st>>>(x, n, v);
+}
+void launch_add_f32(double* u, const float* e, int64_t n, hipStream_t st) {
+  if (n > 0) k_add_f32<<<nblk(n), 256, 0, st>>>(u, e, n);
+}
+void launch_copy(double* dst, const double* src, int64_t n, hipStream_t st) {
+  if (n > 0) k_copy<<<nblk(n), 256, 0, st>>>(dst, src, n);
+}
+
+// explicit instantiations
+template void launch_smooth_interior<double>(int, bool, const LK&, const Tables&, const double*, double*, const double*,
+                                             int, int, int, double, double, const double*, hipStream_t);
+template void launch_smooth_interior<float>(int, bool, const LK&, const Tables&, const float*, float*, const float*, int,
+                                            int, int, double, double, const double*, hipStream_t);
+template void launch_smooth_iface<double>(int, bool, const LK&, const Tables&, const int32_t*, int, const double*,
+                                          double*, const double*, int, double, double, const double*, hipStream_t);
+template void launch_smooth_iface<float>(int, bool, const LK&, const Tables&, const int32_t*, int, const float*, float*,
+                                         const float*, int, double, double, const double*, hipStream_t);
+template void launch_apply<double, double>(int, bool, const LK&, const Tables&, const double*, const double*, double*,
+                                           int, double, double, double, int, const double*, hipStream_t);
+template void launch_apply<double, float>(int, bool, const LK&, const Tables&, const double*, const double*, float*, int,
+                                          double, double, double, int, const double*, hipStream_t);
+template void launch_apply<float, float>(int, bool, const LK&, const Tables&, const float*, const float*, float*, int,
+                                         double, double, double, int, const double*, hipStream_t);
+template void launch_iface_residual<double, float>(int, bool, const LK&, const Tables&, const double*, const double*,
+                                                  float*, double, const double*, hipStream_t);
+template void launch_iface_residual<double, double>(int, bool, const LK&, const Tables&, const double*, const double*,
+                                                   double*, double, const double*, hipStream_t);
+template void launch_restrict<double>(int, const LK&, const LK&, const Tables&, const double*, double*, hipStream_t);
+template void launch_restrict<float>(int, const LK&, const LK&, const Tables&, const float*, float*, hipStream_t);
+template void launch_prolong<double>(int, const LK&, const LK&, const Tables&, const double*, double*, double*,
+                                     const double*, int, hipStream_t);
+template void launch_prolong<float>(int, const LK&, const LK&, const Tables&, const float*, float*, float*, const float*,
+                                    int, hipStream_t);
+template void launch_coarse<double>(int, const int32_t*, const int64_t*, const double*, const double*, double*, int,
+                                    hipStream_t);
+template void launch_coarse<float>(int, const int32_t*, const int64_t*, const double*, const float*, float*, int,
+                                   hipStream_t);
+template void launch_fill<double>(double*, int64_t, double, hipStream_t);
+template void launch_fill<float>(float*, int64_t, float, hipStream_t);
+
+}  // namespace hhg

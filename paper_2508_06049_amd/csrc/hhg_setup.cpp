@@ -1,0 +1,586 @@
+// Host-side setup of the HHG library: macro-mesh validation and primitives, per-macro
+// stencils from the macro geometry, Gauss-Seidel colourings, the level-0 factorisation and
+// the workspace plan.  Nothing here touches the GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+
+#include "hhg_internal.h"
+#include "hhg_lattice.h"
+
+namespace hhg {
+
+int64_t tri_count(int64_t m) { return m < 0 ? 0 : (m + 1) * (m + 2) / 2; }
+int64_t tet_count(int64_t m) { return m < 0 ? 0 : (m + 1) * (m + 2) * (m + 3) / 6; }
+static int64_t lin2(int64_t n, int64_t i, int64_t j) { return j * (n + 1) - j * (j - 1) / 2 + i; }
+
+int64_t lin_closure(int dim, int n, int i, int j, int k) {
+  if (dim == 2) return lin2(n, i, j);
+  int m = n - k;
+  return tet_count(n) - tet_count(m) + lin2(m, i, j);
+}
+
+int zero_mask(int dim, int n, int i, int j, int k) {
+  int c0 = n - i - j - (dim == 3 ? k : 0);
+  int mk = (c0 == 0 ? 1 : 0) | (i == 0 ? 2 : 0) | (j == 0 ? 4 : 0);
+  if (dim == 3 && k == 0) mk |= 8;
+  return mk;
+}
+
+static int nprim(hhg_ctx c) { return (int)c->nV + c->nE + c->nF; }
+
+// ---------------------------------------------------------------------------------------
+// topology
+static double simplex_det(int d, const double* x0, const double* x1, const double* x2, const double* x3) {
+  if (d == 2) {
+    double a = x1[0] - x0[0], b = x2[0] - x0[0], cc = x1[1] - x0[1], dd = x2[1] - x0[1];
+    return a * dd - b * cc;
+  }
+  double a[3], b[3], e[3];
+  for (int q = 0; q < 3; ++q) { a[q] = x1[q] - x0[q]; b[q] = x2[q] - x0[q]; e[q] = x3[q] - x0[q]; }
+  return a[0] * (b[1] * e[2] - b[2] * e[1]) - a[1] * (b[0] * e[2] - b[2] * e[0]) + a[2] * (b[0] * e[1] - b[1] * e[0]);
+}
+
+hhg_status build_topology(hhg_ctx c) {
+  const int d = c->dim, nv = d + 1;
+  const int64_t nC = c->nC;
+  for (int64_t m = 0; m < nC; ++m)
+    for (int a = 0; a < nv; ++a) {
+      int v = c->cells[m * nv + a];
+      if (v < 0 || v >= c->nV) { c->err = "cell vertex id out of range"; return HHG_EMESH; }
+      for (int b = 0; b < a; ++b)
+        if (c->cells[m * nv + b] == v) { c->err = "cell with repeated vertex"; return HHG_EMESH; }
+    }
+  // degenerate cells
+  double scale = 0.0;
+  for (double x : c->coords) scale = std::max(scale, std::fabs(x));
+  if (scale == 0.0) scale = 1.0;
+  for (int64_t m = 0; m < nC; ++m) {
+    const int* cv = &c->cells[m * nv];
+    const double* X = c->coords.data();
+    double det = simplex_det(d, X + cv[0] * d, X + cv[1] * d, X + cv[2] * d, d == 3 ? X + cv[3] * d : nullptr);
+    if (!(std::fabs(det) > 1e-13 * std::pow(scale, d))) { c->err = "degenerate macro element " + std::to_string(m); return HHG_EMESH; }
+  }
+  // edges and faces
+  std::map<std::array<int, 2>, int> emap;
+  std::map<std::array<int, 3>, int> fmap;
+  std::vector<std::array<int, 2>> E;
+  std::vector<std::array<int, 3>> F;
+  for (int64_t m = 0; m < nC; ++m) {
+    const int* cv = &c->cells[m * nv];
+    for (int a = 0; a < nv; ++a)
+      for (int b = a + 1; b < nv; ++b) {
+        std::array<int, 2> e{std::min(cv[a], cv[b]), std::max(cv[a], cv[b])};
+        emap.emplace(e, 0);
+      }
+    if (d == 3)
+      for (int s = 0; s < 4; ++s) {
+        std::array<int, 3> f;
+        int q = 0;
+        for (int a = 0; a < 4; ++a) if (a != s) f[q++] = cv[a];
+        std::sort(f.begin(), f.end());
+        fmap.emplace(f, 0);
+      }
+  }
+  for (auto& kv : emap) { kv.second = (int)E.size(); E.push_back(kv.first); }
+  for (auto& kv : fmap) { kv.second = (int)F.size(); F.push_back(kv.first); }
+  c->nE = (int)E.size();
+  c->nF = (int)F.size();
+  c->edges.resize(2 * E.size());
+  for (size_t e = 0; e < E.size(); ++e) { c->edges[2 * e] = E[e][0]; c->edges[2 * e + 1] = E[e][1]; }
+  c->faces.resize(3 * F.size());
+  for (size_t f = 0; f < F.size(); ++f) for (int q = 0; q < 3; ++q) c->faces[3 * f + q] = F[f][q];
+
+  const int NP = nprim(c);
+  auto prim_of = [&](const std::vector<int>& sv) -> int {
+    if (sv.size() == 1) return sv[0];
+    if (sv.size() == 2) return (int)c->nV + emap.at({sv[0], sv[1]});
+    return (int)c->nV + c->nE + fmap.at({sv[0], sv[1], sv[2]});
+  };
+  // facet adjacency counts -> boundary primitives
+  std::vector<int> facet_count(d == 2 ? c->nE : c->nF, 0);
+  for (int64_t m = 0; m < nC; ++m) {
+    const int* cv = &c->cells[m * nv];
+    for (int s = 0; s < nv; ++s) {
+      std::vector<int> sv;
+      for (int a = 0; a < nv; ++a) if (a != s) sv.push_back(cv[a]);
+      std::sort(sv.begin(), sv.end());
+      int p = prim_of(sv) - (int)c->nV - (d == 3 ? c->nE : 0);
+      facet_count[p]++;
+    }
+  }
+  std::vector<uint8_t> onb(NP, 0);
+  for (size_t p = 0; p < facet_count.size(); ++p) {
+    if (facet_count[p] > 2) { c->err = "non-manifold facet"; return HHG_EMESH; }
+    if (facet_count[p] == 1) {
+      std::vector<int> sv;
+      if (d == 2) sv = {E[p][0], E[p][1]};
+      else sv = {F[p][0], F[p][1], F[p][2]};
+      // all sub-primitives of the facet lie on the boundary
+      int k = (int)sv.size();
+      for (int sub = 1; sub < (1 << k); ++sub) {
+        std::vector<int> t;
+        for (int q = 0; q < k; ++q) if (sub & (1 << q)) t.push_back(sv[q]);
+        onb[prim_of(t)] = 1;
+      }
+    }
+  }
+  c->primdir.assign(NP, 0);
+  for (int p = 0; p < NP; ++p) {
+    if (!onb[p]) continue;
+    if (c->vdir_user.empty()) { c->primdir[p] = 1; continue; }
+    std::vector<int> sv;
+    if (p < c->nV) sv = {p};
+    else if (p < c->nV + c->nE) sv = {E[p - c->nV][0], E[p - c->nV][1]};
+    else sv = {F[p - c->nV - c->nE][0], F[p - c->nV - c->nE][1], F[p - c->nV - c->nE][2]};
+    bool all = true;
+    for (int v : sv) all = all && c->vdir_user[v];
+    c->primdir[p] = all ? 1 : 0;
+  }
+  // incidences and per-macro sub-primitive tables
+  std::vector<std::vector<Inc>> plist(NP);
+  c->subprim.assign(nC * kMaxMask, -1);
+  c->suborder.assign(nC * kMaxMask, 0);
+  c->dirbits.assign(nC, 0);
+  c->ownbits.assign(nC, 0);
+  const int full = (1 << nv) - 1;
+  for (int64_t m = 0; m < nC; ++m) {
+    const int* cv = &c->cells[m * nv];
+    for (int keep = 1; keep < full; ++keep) {   // set of local slots that span the primitive
+      std::vector<std::pair<int, int>> vs;      // (global id, slot)
+      for (int a = 0; a < nv; ++a) if (keep & (1 << a)) vs.push_back({cv[a], a});
+      std::sort(vs.begin(), vs.end());
+      std::vector<int> sv;
+      for (auto& pr : vs) sv.push_back(pr.first);
+      int p = prim_of(sv);
+      int mask = full & ~keep;
+      Inc in{};
+      in.macro = (int32_t)m;
+      uint8_t packed = 0;
+      for (size_t r = 0; r < vs.size(); ++r) { in.slot[r] = (uint8_t)vs[r].second; packed |= (uint8_t)(vs[r].second << (2 * r)); }
+      in.mask = (uint8_t)mask;
+      plist[p].push_back(in);
+      c->subprim[m * kMaxMask + mask] = p;
+      c->suborder[m * kMaxMask + mask] = packed;
+      if (c->primdir[p]) c->dirbits[m] |= (uint16_t)(1u << mask);
+    }
+  }
+  c->inc_off.assign(NP + 1, 0);
+  c->inc.clear();
+  for (int p = 0; p < NP; ++p) {
+    // macro ids ascend because macros were visited in order
+    c->inc_off[p] = (int32_t)c->inc.size();
+    for (auto& in : plist[p]) c->inc.push_back(in);
+    if (!plist[p].empty()) {
+      const Inc& own = plist[p][0];
+      c->ownbits[own.macro] |= (uint16_t)(1u << own.mask);
+    }
+  }
+  c->inc_off[NP] = (int32_t)c->inc.size();
+  // dyadic scale for red-black parity
+  c->dyadic_p = -1;
+  for (int p = 0; p <= 40 && c->dyadic_p < 0; ++p) {
+    bool ok = true;
+    double s = std::ldexp(1.0, p);
+    for (double x : c->coords) { double y = x * s; if (y != std::floor(y) || std::fabs(y) > 9.0e15) { ok = false; break; } }
+    if (ok) c->dyadic_p = p;
+  }
+  c->rbpar.assign(nC * 4, 0);
+  if (c->dyadic_p >= 0) {
+    double s = std::ldexp(1.0, c->dyadic_p);
+    for (int64_t m = 0; m < nC; ++m) {
+      const int* cv = &c->cells[m * nv];
+      long long x0s = 0;
+      for (int q = 0; q < d; ++q) x0s += (long long)(c->coords[cv[0] * d + q] * s);
+      c->rbpar[m * 4 + 0] = (int)(((x0s % 2) + 2) % 2);
+      for (int a = 1; a < nv; ++a) {
+        long long sa = 0;
+        for (int q = 0; q < d; ++q) sa += (long long)((c->coords[cv[a] * d + q] - c->coords[cv[0] * d + q]) * s);
+        c->rbpar[m * 4 + a] = (int)(((sa % 2) + 2) % 2);
+      }
+    }
+  }
+  return HHG_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// stencils
+static void element_matrices(int d, const double y[4][3], double K[4][4], double Mm[4][4]) {
+  double J[3][3] = {{0}}, G[3][3] = {{0}};
+  for (int a = 0; a < d; ++a)
+    for (int q = 0; q < d; ++q) J[q][a] = y[a + 1][q] - y[0][q];   // columns y_a - y_0
+  double det;
+  if (d == 2) {
+    det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    G[0][0] = J[1][1] / det; G[0][1] = -J[0][1] / det;
+    G[1][0] = -J[1][0] / det; G[1][1] = J[0][0] / det;
+  } else {
+    det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+          J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    G[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+    G[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    G[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    G[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+    G[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    G[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    G[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+    G[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    G[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+  }
+  // rows of G = J^{-1} are the gradients of lambda_1..lambda_d
+  double g[4][3] = {{0}};
+  for (int a = 0; a < d; ++a)
+    for (int q = 0; q < d; ++q) { g[a + 1][q] = G[a][q]; g[0][q] -= G[a][q]; }
+  double vol = std::fabs(det) / (d == 2 ? 2.0 : 6.0);
+  for (int a = 0; a <= d; ++a)
+    for (int b = 0; b <= d; ++b) {
+      double s = 0;
+      for (int q = 0; q < d; ++q) s += g[a][q] * g[b][q];
+      K[a][b] = vol * s;
+      Mm[a][b] = vol * (a == b ? 2.0 : 1.0) / ((d + 1) * (d + 2));
+    }
+}
+
+static bool dir_valid(int dim, int mask, int di, int dj, int dk) {
+  int dc[4] = {-(di + dj + dk), di, dj, dk};
+  if (dim == 2) dc[0] = -(di + dj);
+  for (int q = 0; q <= dim; ++q)
+    if ((mask >> q) & 1)
+      if (dc[q] < 0) return false;
+  return true;
+}
+
+hhg_status build_stencils(hhg_ctx c) {
+  const int d = c->dim, nv = d + 1;
+  const int ND = d == 3 ? kNDir3 : kNDir2, NT = d == 3 ? kNType3 : kNType2;
+  const int64_t nC = c->nC;
+  c->validdirs.assign(kMaxMask, 0);
+  for (int mask = 0; mask < kMaxMask; ++mask)
+    for (int q = 0; q < ND; ++q) {
+      int di = d == 3 ? kOff3[q][0] : kOff2[q][0];
+      int dj = d == 3 ? kOff3[q][1] : kOff2[q][1];
+      int dk = d == 3 ? kOff3[q][2] : 0;
+      if (dir_valid(d, mask, di, dj, dk)) c->validdirs[mask] |= (uint16_t)(1u << q);
+    }
+  // valid incident (type, vertex) pairs per mask: every other element vertex offset valid
+  c->incvalid.assign(kMaxMask, 0);
+  for (int mask = 0; mask < kMaxMask; ++mask)
+    for (int t = 0; t < NT; ++t)
+      for (int a = 0; a < nv; ++a) {
+        bool ok = true;
+        for (int b = 0; b < nv; ++b) {
+          int o[3] = {0, 0, 0};
+          for (int q = 0; q < d; ++q) o[q] = (d == 3 ? kType3[t][b][q] - kType3[t][a][q] : kType2[t][b][q] - kType2[t][a][q]);
+          ok = ok && dir_valid(d, mask, o[0], o[1], o[2]);
+        }
+        if (ok) c->incvalid[mask] |= (1u << (t * nv + a));
+      }
+  c->stiff.assign(nC * kMaxMask * ND, 0.0);
+  c->mass.assign(nC * kMaxMask * ND, 0.0);
+  c->elemK.assign(nC * NT * nv * nv, 0.0);
+  for (int64_t m = 0; m < nC; ++m) {
+    const int* cv = &c->cells[m * nv];
+    double X[4][3] = {{0}};
+    for (int a = 0; a < nv; ++a) for (int q = 0; q < d; ++q) X[a][q] = c->coords[cv[a] * d + q];
+    for (int t = 0; t < NT; ++t) {
+      double y[4][3] = {{0}};
+      for (int a = 0; a < nv; ++a)
+        for (int q = 0; q < d; ++q) {
+          double v = X[0][q];
+          for (int s = 0; s < d; ++s) {
+            int o = d == 3 ? kType3[t][a][s] : kType2[t][a][s];
+            v += o * (X[s + 1][q] - X[0][q]);
+          }
+          y[a][q] = v;
+        }
+      double K[4][4], Mm[4][4];
+      element_matrices(d, y, K, Mm);
+      for (int a = 0; a < nv; ++a)
+        for (int b = 0; b < nv; ++b) c->elemK[((m * NT + t) * nv + a) * nv + b] = K[a][b];
+      for (int mask = 0; mask < kMaxMask; ++mask)
+        for (int a = 0; a < nv; ++a) {
+          if (!((c->incvalid[mask] >> (t * nv + a)) & 1)) continue;
+          for (int b = 0; b < nv; ++b) {
+            int o[3] = {0, 0, 0};
+            for (int q = 0; q < d; ++q) o[q] = (d == 3 ? kType3[t][b][q] - kType3[t][a][q] : kType2[t][b][q] - kType2[t][a][q]);
+            int di = d == 3 ? dir_index3(o[0], o[1], o[2]) : dir_index2(o[0], o[1]);
+            c->stiff[(m * kMaxMask + mask) * ND + di] += K[a][b];
+            c->mass[(m * kMaxMask + mask) * ND + di] += Mm[a][b];
+          }
+        }
+    }
+    // snap round-off couplings (right angles give exact zeros in exact arithmetic)
+    double mx = 0;
+    for (int q = 0; q < kMaxMask * ND; ++q) mx = std::max(mx, std::fabs(c->stiff[m * kMaxMask * ND + q]));
+    for (int q = 0; q < kMaxMask * ND; ++q)
+      if (std::fabs(c->stiff[m * kMaxMask * ND + q]) < 1e-14 * mx) c->stiff[m * kMaxMask * ND + q] = 0.0;
+    for (int q = 0; q < NT * nv * nv; ++q)
+      if (std::fabs(c->elemK[m * NT * nv * nv + q]) < 1e-14 * mx) c->elemK[m * NT * nv * nv + q] = 0.0;
+  }
+  // red-black exactness: every nonzero off-centre coupling must change the parity
+  if (c->opt.smoother == HHG_GS_REDBLACK) {
+    if (c->dyadic_p < 0) { c->err = "red-black colouring needs dyadic coordinates"; return HHG_EINVAL; }
+    for (int64_t m = 0; m < nC; ++m)
+      for (int t = 0; t < NT; ++t)
+        for (int a = 0; a < nv; ++a)
+          for (int b = 0; b < nv; ++b) {
+            if (a == b || c->elemK[((m * NT + t) * nv + a) * nv + b] == 0.0) continue;
+            int par = 0;
+            for (int q = 0; q < d; ++q) {
+              int o = d == 3 ? kType3[t][b][q] - kType3[t][a][q] : kType2[t][b][q] - kType2[t][a][q];
+              par += o * c->rbpar[m * 4 + 1 + q];
+            }
+            if (((par % 2) + 2) % 2 == 0) {
+              c->err = "red-black Gauss-Seidel is not exact on macro " + std::to_string(m) +
+                       " (same-colour coupling); use HHG_GS_MULTICOLOR";
+              return HHG_EINVAL;
+            }
+          }
+  }
+  return HHG_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// canonical numbering and colouring
+int64_t canonical_index(hhg_ctx c, const Level& lv, int m, int i, int j, int k) {
+  const int d = c->dim, n = lv.n;
+  int mask = zero_mask(d, n, i, j, k);
+  if (mask == 0) {
+    int64_t li = lin_closure(d, n - d - 1, i - 1, j - 1, k - 1);
+    return lv.nIface + (int64_t)m * lv.NI + li;
+  }
+  int p = c->subprim[m * kMaxMask + mask];
+  uint8_t ord = c->suborder[m * kMaxMask + mask];
+  int cc[4] = {n - i - j - (d == 3 ? k : 0), i, j, k};
+  if (p < c->nV) return p;
+  if (p < c->nV + c->nE) {
+    int a = cc[(ord >> 2) & 3];
+    return c->nV + (int64_t)(p - c->nV) * lv.nEd + (a - 1);
+  }
+  int a = cc[(ord >> 2) & 3], b = cc[(ord >> 4) & 3];
+  return c->nV + (int64_t)c->nE * lv.nEd + (int64_t)(p - c->nV - c->nE) * lv.nFd + lin2(n - 3, a - 1, b - 1);
+}
+
+// interface DoF t -> primitive and coordinates along the primitive's sorted vertices
+static void iface_decode(hhg_ctx c, const Level& lv, int64_t t, int& p, int co[3]) {
+  const int n = lv.n;
+  co[0] = co[1] = co[2] = 0;
+  if (t < c->nV) { p = (int)t; co[0] = n; return; }
+  t -= c->nV;
+  if (t < (int64_t)c->nE * lv.nEd) {
+    p = c->nV + (int)(t / lv.nEd);
+    int a = (int)(t % lv.nEd) + 1;
+    co[0] = n - a; co[1] = a;
+    return;
+  }
+  t -= (int64_t)c->nE * lv.nEd;
+  p = c->nV + c->nE + (int)(t / lv.nFd);
+  int64_t s = t % lv.nFd;
+  int side = n - 3, b = 0;
+  while (lin2(side, 0, b + 1) <= s && b + 1 <= side) ++b;
+  int a = (int)(s - lin2(side, 0, b));
+  co[1] = a + 1; co[2] = b + 1; co[0] = n - co[1] - co[2];
+}
+
+static int interior_colour(hhg_ctx c, int l, int m, int i, int j, int k) {
+  if (c->opt.smoother == HHG_JACOBI) return 0;
+  if (c->opt.smoother == HHG_GS_REDBLACK) {
+    const int* rp = &c->rbpar[m * 4];
+    int s = (l == 0 ? rp[0] : 0) + i * rp[1] + j * rp[2] + (c->dim == 3 ? k * rp[3] : 0);
+    return s & 1;
+  }
+  return c->dim == 2 ? (i + 2 * j) % 3 : (i + 2 * j + 3 * k) % 4;
+}
+
+hhg_status build_colouring(hhg_ctx c) {
+  const int d = c->dim;
+  const int ND = d == 3 ? kNDir3 : kNDir2;
+  for (auto& lv : c->lev) {
+    std::vector<int> col(lv.nIface, -1);
+    for (int64_t t = 0; t < lv.nIface; ++t) {
+      int p, co[3];
+      iface_decode(c, lv, t, p, co);
+      if (c->primdir[p]) continue;
+      const Inc& in0 = c->inc[c->inc_off[p]];
+      int cc[4] = {0, 0, 0, 0};
+      int np = p < c->nV ? 1 : (p < c->nV + c->nE ? 2 : 3);
+      for (int r = 0; r < np; ++r) cc[in0.slot[r]] = co[r];
+      if (c->opt.smoother != HHG_GS_MULTICOLOR) {
+        col[t] = interior_colour(c, lv.l, in0.macro, cc[1], cc[2], cc[3]);
+        continue;
+      }
+      // greedy first fit against every coloured neighbour
+      uint64_t used = 0;
+      for (int q = c->inc_off[p]; q < c->inc_off[p + 1]; ++q) {
+        const Inc& in = c->inc[q];
+        int lc[4] = {0, 0, 0, 0};
+        for (int r = 0; r < np; ++r) lc[in.slot[r]] = co[r];
+        for (int dd = 1; dd < ND; ++dd) {
+          if (!((c->validdirs[in.mask] >> dd) & 1)) continue;
+          int i2 = lc[1] + (d == 3 ? kOff3[dd][0] : kOff2[dd][0]);
+          int j2 = lc[2] + (d == 3 ? kOff3[dd][1] : kOff2[dd][1]);
+          int k2 = d == 3 ? lc[3] + kOff3[dd][2] : 0;
+          int mk = zero_mask(d, lv.n, i2, j2, k2);
+          int cn;
+          if (mk == 0) cn = interior_colour(c, lv.l, in.macro, i2, j2, k2);
+          else {
+            int64_t t2 = canonical_index(c, lv, in.macro, i2, j2, k2);
+            cn = col[t2];
+          }
+          if (cn >= 0 && cn < 64) used |= (1ull << cn);
+        }
+      }
+      int cnew = 0;
+      while ((used >> cnew) & 1) ++cnew;
+      col[t] = cnew;
+    }
+    int maxc = -1;
+    for (int v : col) maxc = std::max(maxc, v);
+    lv.interior_colours = 0;
+    if (lv.NI > 0) lv.interior_colours = c->opt.smoother == HHG_JACOBI ? 1 : (c->opt.smoother == HHG_GS_REDBLACK ? 2 : (d == 2 ? 3 : 4));
+    lv.ncolours = std::max(lv.interior_colours, maxc + 1);
+    lv.colour_off.assign(lv.ncolours + 1, 0);
+    for (int v : col) if (v >= 0) lv.colour_off[v + 1]++;
+    for (int q = 0; q < lv.ncolours; ++q) lv.colour_off[q + 1] += lv.colour_off[q];
+    lv.colour_list.assign(lv.colour_off[lv.ncolours], 0);
+    std::vector<int32_t> fill(lv.colour_off.begin(), lv.colour_off.end() - 1);
+    for (int64_t t = 0; t < lv.nIface; ++t)
+      if (col[t] >= 0) lv.colour_list[fill[col[t]]++] = (int32_t)t;
+  }
+  return HHG_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// level 0: dense inverse of the inner block of A_0
+hhg_status build_coarse(hhg_ctx c, const double* kappa_vertex) {
+  const int d = c->dim, nv = d + 1;
+  std::vector<int> idx(c->nV, -1);
+  c->coarse_vertex.clear();
+  for (int v = 0; v < c->nV; ++v)
+    if (!c->primdir[v]) { idx[v] = (int)c->coarse_vertex.size(); c->coarse_vertex.push_back(v); }
+  const int n0 = (int)c->coarse_vertex.size();
+  c->n0 = n0;
+  const Level& l0 = c->lev[0];
+  c->coarse_copy_off.assign(n0 + 1, 0);
+  c->coarse_copy.clear();
+  for (int r = 0; r < n0; ++r) {
+    int v = c->coarse_vertex[r];
+    c->coarse_copy_off[r] = (int32_t)c->coarse_copy.size();
+    for (int q = c->inc_off[v]; q < c->inc_off[v + 1]; ++q) {
+      const Inc& in = c->inc[q];
+      c->coarse_copy.push_back((int64_t)in.macro * l0.S + in.slot[0]);   // at n = 1, lin == slot
+    }
+  }
+  c->coarse_copy_off[n0] = (int32_t)c->coarse_copy.size();
+  c->Ainv.assign((size_t)n0 * n0, 0.0);
+  if (n0 == 0) return HHG_OK;
+  std::vector<double> A((size_t)n0 * n0, 0.0);
+  for (int64_t m = 0; m < c->nC; ++m) {
+    const int* cv = &c->cells[m * nv];
+    double y[4][3] = {{0}};
+    for (int a = 0; a < nv; ++a) for (int q = 0; q < d; ++q) y[a][q] = c->coords[cv[a] * d + q];
+    double K[4][4], Mm[4][4];
+    element_matrices(d, y, K, Mm);
+    double kap = c->kappa_cell[m];
+    if (c->opt.coefficient == HHG_KAPPA_P1) {
+      kap = 0;
+      for (int a = 0; a < nv; ++a) kap += kappa_vertex ? kappa_vertex[cv[a]] : 1.0;
+      kap /= nv;
+    }
+    for (int a = 0; a < nv; ++a)
+      for (int b = 0; b < nv; ++b) {
+        int ra = idx[cv[a]], rb = idx[cv[b]];
+        if (ra >= 0 && rb >= 0) A[(size_t)ra * n0 + rb] += kap * K[a][b];
+      }
+  }
+  // Cholesky A = R^T R (upper R stored in A), then inverse column by column
+  for (int k = 0; k < n0; ++k) {
+    const double akk = A[(size_t)k * n0 + k];
+    double s = akk;
+    for (int q = 0; q < k; ++q) s -= A[(size_t)q * n0 + k] * A[(size_t)q * n0 + k];
+    if (!(s > 1e-10 * akk)) { c->err = "level-0 matrix is not positive definite (no Dirichlet boundary?)"; return HHG_EINVAL; }
+    double rkk = std::sqrt(s);
+    A[(size_t)k * n0 + k] = rkk;
+    for (int j = k + 1; j < n0; ++j) {
+      double t = A[(size_t)k * n0 + j];
+      for (int q = 0; q < k; ++q) t -= A[(size_t)q * n0 + k] * A[(size_t)q * n0 + j];
+      A[(size_t)k * n0 + j] = t / rkk;
+    }
+  }
+  std::vector<double> y(n0), x(n0);
+  for (int col = 0; col < n0; ++col) {
+    // R^T y = e_col
+    for (int i = 0; i < n0; ++i) {
+      double t = (i == col) ? 1.0 : 0.0;
+      for (int q = 0; q < i; ++q) t -= A[(size_t)q * n0 + i] * y[q];
+      y[i] = t / A[(size_t)i * n0 + i];
+    }
+    // R x = y
+    for (int i = n0 - 1; i >= 0; --i) {
+      double t = y[i];
+      for (int q = i + 1; q < n0; ++q) t -= A[(size_t)i * n0 + q] * x[q];
+      x[i] = t / A[(size_t)i * n0 + i];
+    }
+    for (int i = 0; i < n0; ++i) c->Ainv[(size_t)i * n0 + col] = x[i];
+  }
+  return HHG_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// workspace plan
+static int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+void plan_workspace(hhg_ctx c) {
+  const int d = c->dim, nv = d + 1;
+  const int ND = d == 3 ? kNDir3 : kNDir2, NT = d == 3 ? kNType3 : kNType2;
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) { int64_t o = off; off = align256(off + std::max<int64_t>(bytes, 1)); return o; };
+  const int64_t nC = c->nC;
+  c->o_stiff = take(nC * kMaxMask * ND * 8);
+  c->o_mass = take(nC * kMaxMask * ND * 8);
+  c->o_elemK = take(nC * NT * nv * nv * 8);
+  c->o_kappa = take(nC * 8);
+  c->o_subprim = take(nC * kMaxMask * 4);
+  c->o_suborder = take(nC * kMaxMask);
+  c->o_dirbits = take(nC * 2);
+  c->o_ownbits = take(nC * 2);
+  c->o_rbpar = take(nC * 16);
+  c->o_incoff = take((int64_t)c->inc_off.size() * 4);
+  c->o_inc = take((int64_t)c->inc.size() * sizeof(Inc));
+  c->o_primdir = take((int64_t)c->primdir.size());
+  c->o_ccopyoff = take((int64_t)(c->n0 + 1) * 4);
+  c->o_ccopy = take((int64_t)c->coarse_copy.size() * 8 + 8);
+  c->o_ainv = take((int64_t)c->n0 * c->n0 * 8 + 8);
+  // reduction scratch: per macro per block (4 values) on the finest level, and per block norms
+  const Level& lt = c->lev[c->L];
+  int64_t bpm = (lt.Sraw + 255) / 256;
+  int64_t nblk_norm = nC * ((lt.NI + 255) / 256) + (lt.nIface + 255) / 256 + 16;
+  c->red_capacity = std::max<int64_t>(nC * bpm * 4, nblk_norm) + 1024;
+  c->o_red = take(c->red_capacity * 8);
+  c->o_scal = take(64 * 8);
+  c->o_mxyz = take(nC * nv * d * 8);
+  c->o_aux0 = take(lt.nfull * 8);
+  c->o_aux1 = take(lt.nfull * 8);
+  for (auto& lv : c->lev) {
+    const int64_t nf = lv.nfull;
+    lv.off_x = take(nf * 8);
+    lv.off_t = take(nf * 8);
+    lv.off_bf = take(nf * 8);
+    lv.off_rc = take(nf * 8);
+    lv.off_g = take(nf * 8);
+    lv.off_w = take(nf * 8);
+    lv.off_kn = c->opt.coefficient == HHG_KAPPA_P1 ? take(nf * 8) : -1;
+    lv.off_x32 = take(nf * 4);
+    lv.off_t32 = take(nf * 4);
+    lv.off_b32 = take(nf * 4);
+    lv.off_cl = take((int64_t)lv.colour_list.size() * 4);
+  }
+  c->ws_bytes = (size_t)off;
+}
+
+}  // namespace hhg

@@ -1,0 +1,105 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared entry point, and its
+host-side setup (validation, primitive counts, colour classes) behaves -- no GPU calls."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import refine
+from workloads import meshes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hhg.h")
+
+
+def _lib():
+    from paper_2508_06049_amd import _lib as L
+    return L
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hhg_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    lib = L.load()
+    decl = declared_functions()
+    assert len(decl) >= 19
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert sorted(L.exported_symbols()) == decl
+
+
+@pytest.mark.parametrize("mk,L", [(meshes.unit_square_2tri, 5), (meshes.lshape_6tri, 4),
+                                  (lambda: meshes.kuhn_cube(1), 4), (lambda: meshes.kuhn_cube(2), 3)])
+def test_setup_dof_counts_match_oracle(mk, L):
+    m = mk()
+    lib = _lib().load()
+    ctx, keep = _lib().setup_host(m.coords, m.cells, L, "multicolour")
+    h = refine.Hierarchy(m.coords, m.cells, L)
+    for l in range(L + 1):
+        n = C.c_int64()
+        assert lib.hhg_num_dofs(ctx, l, C.byref(n)) == 0
+        assert n.value == h.levels[l].n
+    nb = C.c_size_t()
+    assert lib.hhg_workspace_bytes(ctx, C.byref(nb)) == 0 and nb.value > 0
+    lib.hhg_destroy(ctx)
+
+
+def test_full_size_dof_counts():
+    lib = _lib().load()
+    for mk, L, want in [(lambda: meshes.kuhn_cube(1), 7, 129 ** 3), (lambda: meshes.kuhn_cube(4), 6, 257 ** 3),
+                        (meshes.unit_square_2tri, 5, 1089)]:
+        m = mk()
+        ctx, keep = _lib().setup_host(m.coords, m.cells, L, "redblack")
+        n = C.c_int64()
+        lib.hhg_num_dofs(ctx, L, C.byref(n))
+        assert n.value == want
+        lib.hhg_destroy(ctx)
+
+
+def test_setup_rejects_bad_meshes_and_options():
+    L = _lib()
+    # degenerate triangle
+    with pytest.raises(L.HHGError) as e:
+        L.setup_host(np.array([[0.0, 0.0], [1.0, 0.0], [2.0, 0.0]]), np.array([[0, 1, 2]]), 2)
+    assert e.value.status == L.HHG_EMESH
+    # vertex id out of range
+    with pytest.raises(L.HHGError) as e:
+        L.setup_host(np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]]), np.array([[0, 1, 5]]), 2)
+    assert e.value.status == L.HHG_EMESH
+    # non-manifold: three triangles on one edge
+    c = np.array([[0.0, 0.0], [1.0, 0.0], [0.5, 1.0], [0.5, -1.0], [0.25, 0.5]])
+    with pytest.raises(L.HHGError) as e:
+        L.setup_host(c, np.array([[0, 1, 2], [0, 1, 3], [0, 1, 4]]), 2)
+    assert e.value.status == L.HHG_EMESH
+    # red-black on a mesh where it is not exact Gauss-Seidel
+    with pytest.raises(L.HHGError) as e:
+        L.setup_host(np.array([[0.0, 0.0], [1.0, 0.0], [0.5, 1.0]]), np.array([[0, 1, 2]]), 3, "redblack")
+    assert e.value.status == L.HHG_EINVAL
+    # level out of range
+    m = meshes.unit_square_2tri()
+    with pytest.raises(L.HHGError):
+        L.setup_host(m.coords, m.cells, 0)
+    # no Dirichlet boundary at all -> singular level-0 system
+    m = meshes.unit_square_grid(2)
+    with pytest.raises(L.HHGError):
+        L.setup_host(m.coords, m.cells, 2, "multicolour", dirichlet=np.zeros(m.n_vertices, np.uint8))
+
+
+def test_calls_without_workspace_fail_cleanly():
+    L = _lib()
+    lib = L.load()
+    m = meshes.unit_square_2tri()
+    ctx, keep = L.setup_host(m.coords, m.cells, 3)
+    p = L.hhg_solve_params(1, 2, 2, 0, 0.0, 0)
+    assert lib.hhg_fmg_solve(ctx, None, None, None, C.byref(p), None) == L.HHG_ESTATE
+    assert lib.hhg_estimate(ctx, 1, None, None, None, None) == L.HHG_ESTATE
+    assert b"workspace" in lib.hhg_last_error(ctx)
+    assert lib.hhg_status_string(L.HHG_EMESH).startswith(b"HHG_EMESH")
+    lib.hhg_destroy(ctx)

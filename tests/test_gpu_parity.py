@@ -1,0 +1,258 @@
+"""Parity of the HIP library against the CPU oracle, element by element, on seeded inputs.
+
+Sizes are chosen so the oracle runs in seconds while every kernel sees several 256-wide
+blocks per macro and a ragged tail.  Tolerances (float64): 1e-12 relative to the solution
+for solver outputs, 1e-12 * ||u|| (absolute) for estimator quantities, 1e-10 relative for
+gradients; single operator applications are compared at 1e-13.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_common import hip_context, oracle_hierarchy, rel_err, to_dev, to_host
+from oracle import adjoint, assemble, colour, estimate, fmg
+from workloads import meshes, problems
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def generic_tet():
+    m = meshes.CoarseMesh(np.array([[0.0, 0.0, 0.0], [1.0, 0.25, 0.0], [0.5, 1.0, 0.125], [0.25, 0.5, 1.0]]),
+                          np.array([[0, 1, 2, 3]], dtype=np.int32), "generic_tet")
+    return m
+
+
+def two_generic_tets():
+    c = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.25, 1.0, 0.0], [0.5, 0.25, 1.0], [0.75, 0.5, -1.0]])
+    return meshes.CoarseMesh(c, np.array([[0, 1, 2, 3], [1, 0, 2, 4]], dtype=np.int32), "two_tets")
+
+
+MESHES = {
+    "square": (meshes.unit_square_2tri, 5, "redblack"),
+    "lshape": (meshes.lshape_6tri, 4, "multicolour"),
+    "grid4": (lambda: meshes.unit_square_grid(4), 4, "multicolour"),
+    "kuhn1": (lambda: meshes.kuhn_cube(1), 4, "redblack"),
+    "kuhn2": (lambda: meshes.kuhn_cube(2), 3, "multicolour"),
+    "tet": (generic_tet, 4, "multicolour"),
+    "twotets": (two_generic_tets, 4, "multicolour"),
+}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_dof_coordinates_bit_exact(name):
+    mk, L, sm = MESHES[name]
+    _note("coords", name, L)
+    m = mk()
+    h, perms = oracle_hierarchy(m, L)
+    hh = hip_context(m, L, sm)
+    for l in range(L + 1):
+        assert hh.num_dofs(l) == h.levels[l].n
+        x = to_host(hh.dof_coords(l))
+        assert np.array_equal(x, h.levels[l].X[perms[l]]), f"level {l}"
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_operators_match(name):
+    mk, L, sm = MESHES[name]
+    _note("apply", name, L)
+    m = mk()
+    h, perms = oracle_hierarchy(m, L)
+    kc = problems.kappa_cells_uniform(3, m.n_cells)
+    hh = hip_context(m, L, sm, kappa_cell=kc)
+    rng = np.random.default_rng(0)
+    for l in (L - 1, L):
+        lv = h.levels[l]
+        p = perms[l]
+        x = rng.standard_normal(lv.n)
+        A = assemble.stiffness(lv, kappa_cell=kc)
+        M = assemble.mass(lv)
+        ya = to_host(hh.apply(l, "stiffness", to_dev(x[p])))
+        ym = to_host(hh.apply(l, "mass", to_dev(x[p])))
+        assert rel_err(ya, (A @ x)[p]) < 1e-13
+        assert rel_err(ym, (M @ x)[p]) < 1e-13
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_transfers_match(name):
+    mk, L, sm = MESHES[name]
+    _note("transfer", name, L)
+    m = mk()
+    h, perms = oracle_hierarchy(m, L)
+    hh = hip_context(m, L, sm)
+    rng = np.random.default_rng(1)
+    for l in range(1, L + 1):
+        P = assemble.prolongation(h, l - 1)
+        ec = rng.standard_normal(h.levels[l - 1].n)
+        ef = to_host(hh.prolongate(l, to_dev(ec[perms[l - 1]])))
+        assert rel_err(ef, (P @ ec)[perms[l]]) < 1e-15
+        rf = rng.standard_normal(h.levels[l].n)
+        rz = rf.copy()
+        rz[h.levels[l].boundary] = 0.0
+        want = P.T @ rz
+        want[h.levels[l - 1].boundary] = 0.0
+        got = to_host(hh.restrict(l, to_dev(rf[perms[l]])))
+        assert rel_err(got, want[perms[l - 1]]) < 1e-14
+
+
+@pytest.mark.parametrize("name,smoother", [("square", "redblack"), ("lshape", "multicolour"),
+                                           ("lshape", "jacobi"), ("kuhn1", "redblack"),
+                                           ("kuhn2", "multicolour"), ("tet", "multicolour"),
+                                           ("twotets", "multicolour"), ("grid4", "multicolour")])
+def test_smoother_matches(name, smoother):
+    mk, L, _ = MESHES[name]
+    _note("smooth", name, smoother, L)
+    m = mk()
+    h, perms = oracle_hierarchy(m, L)
+    kc = problems.kappa_cells_uniform(4, m.n_cells)
+    hh = hip_context(m, L, smoother, kappa_cell=kc)
+    S = fmg.FMGSolver(h, kappa_cell=kc, smoother=smoother)
+    rng = np.random.default_rng(2)
+    p = perms[L]
+    u = rng.standard_normal(h.levels[L].n)
+    b = rng.standard_normal(h.levels[L].n)
+    uo = u.copy()
+    S.smooth(L, uo, b, 2)
+    ug = to_dev(u[p])
+    hh.smooth(L, ug, to_dev(b[p]), 2)
+    assert rel_err(to_host(ug), uo[p]) < 1e-12
+
+
+def _rhs(name, X, dim):
+    if name in ("square",):
+        return problems.sine2d_f(X), np.zeros(len(X))
+    if name in ("lshape",):
+        return np.zeros(len(X)), problems.lshape_u(X)
+    if dim == 2:
+        return problems.sine2d_f(X), 0.25 + X[:, 0] - 0.5 * X[:, 1]
+    return problems.fourier3d(X, problems.fourier_amplitudes(0)), np.zeros(len(X))
+
+
+@pytest.mark.parametrize("name,smoother,nu,extra", [
+    ("square", "redblack", 1, 0), ("square", "redblack", 2, 30), ("lshape", "multicolour", 1, 0),
+    ("lshape", "jacobi", 2, 0), ("grid4", "multicolour", 1, 0), ("kuhn1", "redblack", 1, 0),
+    ("kuhn2", "multicolour", 2, 0), ("twotets", "multicolour", 1, 0), ("kuhn1", "redblack", 1, 30)])
+def test_fmg_matches(name, smoother, nu, extra):
+    mk, L, _ = MESHES[name]
+    _note("fmg", name, smoother, nu, extra, L)
+    m = mk()
+    h, perms = oracle_hierarchy(m, L)
+    kc = problems.kappa_cells_uniform(5, m.n_cells) if m.dim == 3 else None
+    hh = hip_context(m, L, smoother, kappa_cell=kc)
+    X = h.levels[L].X
+    f, g = _rhs(name, X, m.dim)
+    S = fmg.FMGSolver(h, kappa_cell=kc, smoother=smoother)
+    b = S.rhs_levels(f)
+    uo, wo = S.fmg(b, g, nu=nu)
+    if extra:
+        S.extra_cycles(uo, b[L], g, rtol=1e-300, max_iter=extra)
+    p = perms[L]
+    ug, st = hh.fmg_solve(to_dev(f[p]), to_dev(g[p]), nu=nu, pre=2, post=2, rtol=1e-300 if extra else 0.0,
+                          max_iter=extra)
+    scale = np.abs(uo).max()
+    assert np.abs(to_host(ug) - uo[p]).max() <= 1e-12 * scale
+    if extra:
+        assert nu * L < st.vcycles <= nu * L + extra
+    else:
+        assert st.vcycles == nu * L
+
+
+@pytest.mark.parametrize("name,smoother,j", [("square", "redblack", 1), ("square", "redblack", 2),
+                                             ("lshape", "multicolour", 1), ("kuhn2", "multicolour", 1),
+                                             ("twotets", "multicolour", 2)])
+def test_estimator_matches(name, smoother, j):
+    mk, L, _ = MESHES[name]
+    _note("estimate", name, smoother, j, L)
+    m = mk()
+    h, perms = oracle_hierarchy(m, L)
+    hh = hip_context(m, L, smoother)
+    X = h.levels[L].X
+    f, g = _rhs(name, X, m.dim)
+    S = fmg.FMGSolver(h, smoother=smoother)
+    b = S.rhs_levels(f)
+    uo, wo = S.fmg(b, g, nu=2)
+    est = estimate.error_estimate(S, uo, wo, j)
+    p = perms[L]
+    hh.fmg_solve(to_dev(f[p]), to_dev(g[p]), nu=2)
+    eg = hh.estimate(j)
+    tol = 1e-12 * max(np.sqrt(uo @ (S.sys[L].M @ uo)), 1e-30)
+    assert np.abs(eg["eta_T"] - est["eta_T"]).max() <= tol
+    assert abs(eg["norm_e"] - est["norm_e_l"]) <= tol
+    assert abs(eg["eta_j"] - est["eta_j"]) <= tol
+    assert abs(eg["theta"] - est["theta"]) <= 1e-10
+
+
+def test_estimate_requires_solve():
+    from paper_2508_06049_amd import HHGError
+    m = meshes.unit_square_2tri()
+    hh = hip_context(m, 3, "redblack")
+    with pytest.raises(HHGError):
+        hh.estimate(1)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_adjoint_matches(precision):
+    m = meshes.kuhn_cube(2)
+    L = 3
+    _note("adjoint", precision)
+    h, perms = oracle_hierarchy(m, L)
+    kc = problems.kappa_cells_uniform(55, m.n_cells)
+    hh = hip_context(m, L, "redblack", kappa_cell=kc)
+    X = h.levels[L].X
+    f = problems.fourier3d(X, problems.fourier_amplitudes(5))
+    g = np.zeros(len(X))
+    wg = problems.gaussian3d(X)
+    S = fmg.FMGSolver(h, kappa_cell=kc, smoother="redblack")
+    M = S.sys[L].M
+    dJdu = M @ wg
+    ref = adjoint.gradient(S, f, g, dJdu)
+    p = perms[L]
+    dJdf, dJdk = hh.adjoint(to_dev(f[p]), to_dev(g[p]), to_dev(dJdu[p]), nu=1, precision=precision, rtol=1e-14,
+                            max_iter=60)
+    assert rel_err(to_host(dJdf), ref["dJdf"][p]) < 1e-10
+    assert rel_err(dJdk, ref["dJdkappa"]) < 1e-10
+
+
+def test_p1_coefficient_fmg_matches():
+    m = meshes.kuhn_cube(1)
+    L = 4
+    _note("p1 kappa fmg")
+    h, perms = oracle_hierarchy(m, L)
+    X = h.levels[L].X
+    kap = problems.kappa_smooth3d(X)
+    f = problems.fourier3d(X, problems.fourier_amplitudes(0))
+    g = np.zeros(len(X))
+    hh = hip_context(m, L, "redblack", coefficient="p1")
+    p = perms[L]
+    hh.set_kappa_nodal(to_dev(kap[p]))
+    S = fmg.FMGSolver(h, kappa_nodal=kap, smoother="redblack")
+    A = S.sys[L].A
+    x = np.random.default_rng(9).standard_normal(len(X))
+    assert rel_err(to_host(hh.apply(L, "stiffness", to_dev(x[p]))), (A @ x)[p]) < 1e-13
+    b = S.rhs_levels(f)
+    uo, _ = S.fmg(b, g, nu=1)
+    ug, _ = hh.fmg_solve(to_dev(f[p]), to_dev(g[p]), nu=1)
+    assert np.abs(to_host(ug) - uo[p]).max() <= 1e-12 * np.abs(uo).max()
+
+
+@pytest.mark.parametrize("name", ["square", "lshape", "kuhn1"])
+def test_mixed_precision_reaches_fp64_solution(name):
+    mk, L, sm = MESHES[name]
+    _note("mixed", name)
+    m = mk()
+    h, perms = oracle_hierarchy(m, L)
+    hh = hip_context(m, L, sm)
+    X = h.levels[L].X
+    f, g = _rhs(name, X, m.dim)
+    S = fmg.FMGSolver(h, smoother=sm)
+    b = S.rhs_levels(f)
+    ud = S.direct(L, b[L], g)
+    p = perms[L]
+    ug, st = hh.fmg_solve(to_dev(f[p]), to_dev(g[p]), nu=1, precision="fp32_refined", rtol=1e-12, max_iter=60)
+    assert st.final_rel_residual <= 1e-12
+    assert np.abs(to_host(ug) - ud[p]).max() <= 1e-9 * np.abs(ud).max()
