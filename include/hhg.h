@@ -155,9 +155,14 @@ hhg_status hhg_prolongate(hhg_ctx ctx, int level, const double* e_coarse, double
 hhg_status hhg_adjoint(hhg_ctx ctx, const double* f_nodal, const double* g_nodal, const double* dJdu,
                        double* dJdf, double* dJdkappa_host, const hhg_solve_params* params);
 
-/* Time `sweeps` smoother sweeps on level L on internal vectors (precision HHG_FP64 or
- * HHG_FP32_REFINED = float32); returns device milliseconds and algorithmic bytes moved. */
-hhg_status hhg_bench_smoother(hhg_ctx ctx, int precision, int sweeps, double* ms, double* bytes);
+/* Time `sweeps` smoother sweeps on level L on internal vectors (precision HHG_FP64, or
+ * HHG_FP32_REFINED = float32 sweeps).  *ms: device time of all sweeps (HIP events);
+ * *bytes: algorithmic bytes they move (24 B per DoF-update in float64, 12 B in float32, plus
+ * 8 B for a nodal coefficient).  If launch_ms / launch_bytes are not NULL, every launch of the
+ * macro-interior smoother kernel is bracketed by events: *launch_ms is its average duration
+ * and *launch_bytes the algorithmic bytes of one such launch.  Outputs may be NULL. */
+hhg_status hhg_bench_smoother(hhg_ctx ctx, int precision, int sweeps, double* ms, double* bytes, double* launch_ms,
+                              double* launch_bytes);
 
 /* Relative residuals ||r|| / ||r_0|| after each extra cycle of the last solve on this context
  * (host array of `capacity` doubles); *count receives the number recorded. */

@@ -1,19 +1,22 @@
 """Colour classes for the Gauss-Seidel smoother.
 
 The paper smooths with Gauss-Seidel (Section 5; and the scaling study's V(2,2) cycles) but
-does not fix an ordering.  The reading taken here: a forward multicolour sweep, colour
-0, 1, ..., C-1, where every colour class is an independent set of the fine-mesh graph, so
-updating a class simultaneously equals updating it point by point.
+does not fix an ordering.  The reading taken here: a forward sweep that first updates every
+node interior to a macro element, colour class by colour class, and then every node on the
+macro vertices/edges/faces (the interface), again class by class.  Every colour class is an
+independent set of the fine-mesh graph, so updating a class simultaneously equals updating
+its nodes one after the other.
 
-Two rules:
-* red-black: colour = parity of the sum of the node's integer grid coordinates (coordinates
-  times 2^(p+l), with 2^p the smallest power of two making every macro vertex integral).
-  It is exact Gauss-Seidel only on meshes whose off-axis couplings vanish (right-isosceles
-  triangles, Kuhn tetrahedra); ``is_proper_for`` checks that against a matrix.
-* multicolour: a node interior to a macro element with integer barycentrics (c_0..c_d) in
-  the macro's vertex order gets (c_1 + 2 c_2) mod 3 in 2D and (c_1 + 2 c_2 + 3 c_3) mod 4 in
-  3D; the remaining (interface) nodes are coloured greedily, first-fit, in canonical DoF
-  order, avoiding every already coloured neighbour in the mesh graph.
+Colours:
+* interior nodes, red-black rule: parity of the sum of the node's integer grid coordinates
+  (coordinates times 2^(p+l), 2^p the smallest power of two making every macro vertex
+  integral); classes 0 and 1.  Exact Gauss-Seidel only on meshes whose off-axis couplings
+  vanish (right-isosceles triangles, Kuhn tetrahedra); ``is_proper_for`` checks that.
+* interior nodes, multicolour rule: with integer barycentrics (c_0..c_d) in the macro's vertex
+  order, (c_1 + 2 c_2) mod 3 in 2D and (c_1 + 2 c_2 + 3 c_3) mod 4 in 3D; classes 0..C-1.
+* interface nodes come after all interior classes: red-black gives C + parity; multicolour
+  colours them greedily, first fit, in canonical DoF order, avoiding already coloured
+  interface neighbours, and numbers those classes from C on.
 Nodes on the Dirichlet boundary are never updated and get colour -1.
 """
 from __future__ import annotations
@@ -30,11 +33,16 @@ def _dyadic_power(coords: np.ndarray) -> int:
     raise ValueError("coarse coordinates are not dyadic")
 
 
+def _interior_mask(h, l):
+    return (h.levels[l].node_bary > 0).sum(axis=1) == h.d + 1
+
+
 def red_black(h, l: int) -> np.ndarray:
     lv = h.levels[l]
     p = _dyadic_power(h.coarse_coords)
     ic = np.round(lv.X * (2.0 ** (p + l))).astype(np.int64)
     col = (ic.sum(axis=1) % 2).astype(np.int64)
+    col[~_interior_mask(h, l)] += 2
     col[lv.boundary] = -1
     return col
 
@@ -57,7 +65,8 @@ def multicolour(h, l: int) -> np.ndarray:
     lv = h.levels[l]
     d = h.d
     bary = lv.node_bary
-    inner = (bary > 0).sum(axis=1) == d + 1
+    inner = _interior_mask(h, l)
+    C = 3 if d == 2 else 4
     col = np.full(lv.n, -1, dtype=np.int64)
     if d == 2:
         ci = (bary[:, 1] + 2 * bary[:, 2]) % 3
@@ -70,8 +79,8 @@ def multicolour(h, l: int) -> np.ndarray:
         if inner[i] or lv.boundary[i]:
             continue
         nb = G.indices[G.indptr[i]:G.indptr[i + 1]]
-        used = set(int(c) for c in col[nb] if c >= 0)
-        c = 0
+        used = set(int(c) for c, q in zip(col[nb], nb) if c >= 0 and not inner[q])
+        c = C
         while c in used:
             c += 1
         col[i] = c
@@ -79,8 +88,10 @@ def multicolour(h, l: int) -> np.ndarray:
 
 
 def classes(col: np.ndarray) -> list[np.ndarray]:
+    """Non-empty colour classes in sweep order."""
     C = int(col.max()) + 1 if col.size and col.max() >= 0 else 0
-    return [np.nonzero(col == c)[0] for c in range(C)]
+    out = [np.nonzero(col == c)[0] for c in range(C)]
+    return [c for c in out if c.size]
 
 
 def is_proper_for(col: np.ndarray, A: sp.csr_matrix, tol: float = 0.0) -> bool:

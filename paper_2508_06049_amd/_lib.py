@@ -65,7 +65,8 @@ _SIGS = {
     "hhg_restrict": (C.c_int, [_ctx, C.c_int, _dp, _dp]),
     "hhg_prolongate": (C.c_int, [_ctx, C.c_int, _dp, _dp]),
     "hhg_adjoint": (C.c_int, [_ctx, _dp, _dp, _dp, _dp, C.POINTER(C.c_double), C.POINTER(hhg_solve_params)]),
-    "hhg_bench_smoother": (C.c_int, [_ctx, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "hhg_bench_smoother": (C.c_int, [_ctx, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "hhg_residual_history": (C.c_int, [_ctx, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_int)]),
     "hhg_status_string": (C.c_char_p, [C.c_int]),
     "hhg_last_error": (C.c_char_p, [_ctx]),
@@ -268,11 +269,12 @@ class HHG:
                self.ctx)
         return dJdf, dJdk
 
-    def bench_smoother(self, precision="fp64", sweeps: int = 10):
-        ms, nbytes = C.c_double(), C.c_double()
-        _check(self.lib.hhg_bench_smoother(self.ctx, PRECISIONS[precision], sweeps, C.byref(ms), C.byref(nbytes)),
-               self.ctx)
-        return ms.value, nbytes.value
+    def bench_smoother(self, precision="fp64", sweeps: int = 10, per_launch: bool = True) -> dict:
+        ms, nbytes, lms, lbytes = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+        _check(self.lib.hhg_bench_smoother(self.ctx, PRECISIONS[precision], sweeps, C.byref(ms), C.byref(nbytes),
+                                           C.byref(lms) if per_launch else None,
+                                           C.byref(lbytes) if per_launch else None), self.ctx)
+        return dict(ms=ms.value, bytes=nbytes.value, launch_ms=lms.value, launch_bytes=lbytes.value)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -96,28 +96,62 @@ template <> struct Arr<float> {
   static float*& rc(Level& l) { return l.b32; }
 };
 
+// interior smoother launch(es); while profiling, finest-level launches are bracketed by events
+template <typename T>
+void interior_launch(hhg_ctx c, int l, const LK& k, const T* x, T* y, const T* b, int col, int rb, int jac) {
+  Level& lv = c->lev[l];
+  const bool fine = l == c->L;
+  const bool rec = fine && c->prof_on && c->prof_used + 2 <= (int)c->prof_ev.size();
+  if (rec) (void)hipEventRecord((hipEvent_t)c->prof_ev[c->prof_used], ST(c));
+  int64_t npts;
+  if (col < 0) {   // all interior colours fused in one launch
+    launch_gs_fused<T>(c->dim, p1(c), k, c->tab, const_cast<T*>(x), b, lv.d_tiles, (int)lv.tiles.size(), lv.d_itab, rb,
+                       sA(c, l), fine, ST(c));
+    npts = lv.NI * c->nC;
+  } else {
+    launch_smooth_interior<T>(c->dim, p1(c), k, c->tab, x, y, b, col, rb, jac, omega(c), sA(c, l), lv.kn, fine, ST(c));
+    npts = jac ? lv.NI * c->nC : lv.interior_per_colour[col];
+  }
+  if (rec) {
+    (void)hipEventRecord((hipEvent_t)c->prof_ev[c->prof_used + 1], ST(c));
+    c->prof_used += 2;
+    const double per = (double)sizeof(T) * 3.0 + (p1(c) ? 8.0 : 0.0);
+    c->prof_bytes += per * (double)npts;
+  }
+}
+
+bool fused_available(hhg_ctx c, int l, size_t tsize) {
+  const Level& lv = c->lev[l];
+  if (p1(c) || lv.NI <= 0 || c->opt.smoother == HHG_JACOBI || c->no_fused) return false;
+  if (c->dim == 2) return !lv.tiles.empty();
+  return !lv.itab.empty() && (size_t)lv.Sraw * tsize <= 64 * 1024;
+}
+
 template <typename T>
 hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
   Level& lv = c->lev[l];
   const LK k = lk_of(c, l);
   const bool jac = c->opt.smoother == HHG_JACOBI;
   const int rb = c->opt.smoother == HHG_GS_REDBLACK ? 1 : 0;
+  const bool fused = fused_available(c, l, sizeof(T));
   for (int s = 0; s < sweeps; ++s) {
     T* x = Arr<T>::x(lv);
     if (jac) {
       T* y = Arr<T>::t(lv);
-      launch_smooth_interior<T>(c->dim, p1(c), k, c->tab, x, y, b, 0, 0, 1, omega(c), sA(c, l), lv.kn, ST(c));
+      interior_launch<T>(c, l, k, x, y, b, 0, 0, 1);
       launch_smooth_iface<T>(c->dim, p1(c), k, c->tab, nullptr, (int)lv.nIface, x, y, b, 1, omega(c), sA(c, l), lv.kn,
                              ST(c));
       std::swap(Arr<T>::x(lv), Arr<T>::t(lv));
-    } else {
-      for (int col = 0; col < lv.ncolours; ++col) {
-        if (col < lv.interior_colours)
-          launch_smooth_interior<T>(c->dim, p1(c), k, c->tab, x, x, b, col, rb, 0, 0.0, sA(c, l), lv.kn, ST(c));
-        const int cnt = lv.colour_off[col + 1] - lv.colour_off[col];
-        launch_smooth_iface<T>(c->dim, p1(c), k, c->tab, lv.d_colour_list + lv.colour_off[col], cnt, x, x, b, 0, 0.0,
-                               sA(c, l), lv.kn, ST(c));
-      }
+      continue;
+    }
+    // macro interiors first (all colours), then the interface colour classes
+    if (fused) interior_launch<T>(c, l, k, x, x, b, -1, rb, 0);
+    else
+      for (int col = 0; col < lv.interior_colours; ++col) interior_launch<T>(c, l, k, x, x, b, col, rb, 0);
+    for (int col = lv.interior_colours; col < lv.ncolours; ++col) {
+      const int cnt = lv.colour_off[col + 1] - lv.colour_off[col];
+      launch_smooth_iface<T>(c->dim, p1(c), k, c->tab, lv.d_colour_list + lv.colour_off[col], cnt, x, x, b, 0, 0.0,
+                             sA(c, l), lv.kn, ST(c));
     }
   }
   LAUNCHCHK();
@@ -453,6 +487,10 @@ hhg_status hhg_bind_workspace(hhg_ctx c, void* ptr, size_t bytes, void* stream) 
     lv.b32 = (float*)(w + lv.off_b32);
     lv.d_colour_list = (int32_t*)(w + lv.off_cl);
     HIPCHK(up(lv.off_cl, lv.colour_list.data(), lv.colour_list.size() * 4));
+    lv.d_tiles = (int32_t*)(w + lv.off_tiles);
+    HIPCHK(up(lv.off_tiles, lv.tiles.data(), lv.tiles.size() * 4));
+    lv.d_itab = (uint32_t*)(w + lv.off_itab);
+    HIPCHK(up(lv.off_itab, lv.itab.data(), lv.itab.size() * 4));
   }
   if (!c->ev0) {
     hipEvent_t a, b;
@@ -676,14 +714,26 @@ hhg_status hhg_adjoint(hhg_ctx c, const double* f, const double* g, const double
   return HHG_OK;
 }
 
-hhg_status hhg_bench_smoother(hhg_ctx c, int precision, int sweeps, double* ms, double* bytes) {
+hhg_status hhg_bench_smoother(hhg_ctx c, int precision, int sweeps, double* ms, double* bytes, double* launch_ms,
+                              double* launch_bytes) {
   TRY(check_ready(c));
   if (sweeps < 1 || (precision != HHG_FP64 && precision != HHG_FP32_REFINED)) { c->err = "invalid argument"; return HHG_EINVAL; }
   const int L = c->L;
   Level& lL = c->lev[L];
+  // events around every finest-level interior launch of the timed sweeps
+  const int need = 2 * sweeps * std::max(lL.ncolours, 1);
+  while ((int)c->prof_ev.size() < need) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    c->prof_ev.push_back(e);
+  }
+  c->prof_used = 0;
+  c->prof_bytes = 0.0;
+  c->prof_on = launch_ms != nullptr || launch_bytes != nullptr;
   HIPCHK(hipEventRecord((hipEvent_t)c->ev0, ST(c)));
-  if (precision == HHG_FP64) TRY(smooth<double>(c, L, lL.bf, sweeps));
-  else TRY(smooth<float>(c, L, lL.b32, sweeps));
+  hhg_status s = precision == HHG_FP64 ? smooth<double>(c, L, lL.bf, sweeps) : smooth<float>(c, L, lL.b32, sweeps);
+  c->prof_on = false;
+  TRY(s);
   HIPCHK(hipEventRecord((hipEvent_t)c->ev1, ST(c)));
   HIPCHK(hipEventSynchronize((hipEvent_t)c->ev1));
   float t = 0;
@@ -691,6 +741,15 @@ hhg_status hhg_bench_smoother(hhg_ctx c, int precision, int sweeps, double* ms, 
   if (ms) *ms = t;
   const double per = precision == HHG_FP64 ? 24.0 + (p1(c) ? 8.0 : 0.0) : 12.0 + (p1(c) ? 8.0 : 0.0);
   if (bytes) *bytes = per * (double)lL.ndof * sweeps;
+  const int pairs = c->prof_used / 2;
+  double tot = 0.0;
+  for (int q = 0; q < pairs; ++q) {
+    float e = 0;
+    HIPCHK(hipEventElapsedTime(&e, (hipEvent_t)c->prof_ev[2 * q], (hipEvent_t)c->prof_ev[2 * q + 1]));
+    tot += e;
+  }
+  if (launch_ms) *launch_ms = pairs ? tot / pairs : 0.0;
+  if (launch_bytes) *launch_bytes = pairs ? c->prof_bytes / pairs : 0.0;
   c->solved = false;
   return HHG_OK;
 }
@@ -705,6 +764,7 @@ hhg_status hhg_residual_history(hhg_ctx c, double* out, int capacity, int* count
 
 void hhg_destroy(hhg_ctx c) {
   if (!c) return;
+  for (void* e : c->prof_ev) (void)hipEventDestroy((hipEvent_t)e);
   if (c->ev0) (void)hipEventDestroy((hipEvent_t)c->ev0);
   if (c->ev1) (void)hipEventDestroy((hipEvent_t)c->ev1);
   delete c;

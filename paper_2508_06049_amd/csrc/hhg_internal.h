@@ -24,6 +24,9 @@ namespace hhg {
 constexpr int kMaxMask = 16;   // zero-set masks of the barycentric coordinates (bit q: c_q == 0)
 constexpr int kNDir3 = 15, kNDir2 = 7;
 constexpr int kNType3 = 6, kNType2 = 2;
+// fused interior sweeps: 2D core tile (i x j) and the largest 3D macro level kept whole in LDS
+constexpr int kTileI = 128, kTileJ = 16;
+constexpr int kMacroLdsN = 32;
 
 // direction tables: index 0 is the centre, 1..H positive, H+1..2H negative
 constexpr int kDir3[7][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {-1, 1, 0}, {-1, 0, 1}, {0, -1, 1}, {1, -1, 1}};
@@ -70,14 +73,19 @@ struct Level {
   int64_t nfull = 0;            // nmacro * S
   int ncolours = 0;             // colours used by the Gauss-Seidel sweep
   int interior_colours = 0;     // colours present among macro-interior DoFs
+  std::vector<int64_t> interior_per_colour;   // macro-interior DoFs of each colour (all macros)
   std::vector<int32_t> colour_off;     // host: CSR offsets of the interface colour lists
   std::vector<int32_t> colour_list;    // host: interface DoF ids per colour (non-Dirichlet)
   // device buffers (inside workspace)
   double *x = nullptr, *t = nullptr, *bf = nullptr, *rc = nullptr, *g = nullptr, *w = nullptr, *kn = nullptr;
   float *x32 = nullptr, *t32 = nullptr, *b32 = nullptr;
   int32_t* d_colour_list = nullptr;
+  std::vector<int32_t> tiles;          // 2D: interior tiles (ti | tj << 16) of the fused sweep
+  std::vector<uint32_t> itab;          // 3D, n <= kMacroLdsN: interior points (i | j << 10 | k << 20)
+  int32_t* d_tiles = nullptr;
+  uint32_t* d_itab = nullptr;
   int64_t off_x = 0, off_t = 0, off_bf = 0, off_rc = 0, off_g = 0, off_w = 0, off_kn = -1, off_x32 = 0, off_t32 = 0,
-          off_b32 = 0, off_cl = 0;
+          off_b32 = 0, off_cl = 0, off_tiles = 0, off_itab = 0;
 };
 
 }  // namespace hhg
@@ -142,6 +150,12 @@ struct hhg_ctx_s {
   void* ev1 = nullptr;
   int last_nu = 0;                  // FMG parameters of the last solve (estimator needs L >= 2)
   std::vector<double> res_hist;     // relative residual after each extra cycle of the last solve
+  // per-launch timing of the finest-level interior smoother (hhg_bench_smoother)
+  std::vector<void*> prof_ev;       // hipEvent_t pairs
+  int prof_used = 0;
+  bool prof_on = false;
+  bool no_fused = false;            // force class-by-class interior launches (testing)
+  double prof_bytes = 0.0;
 
   std::string err;
 };

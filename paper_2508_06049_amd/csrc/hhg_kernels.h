@@ -19,7 +19,11 @@ struct LK {
 
 template <typename T>
 void launch_smooth_interior(int dim, bool p1, const LK& lk, const Tables& tb, const T* uin, T* uout, const T* b, int colour,
-                            int rb, int jacobi, double omega, double sA, const double* kn, hipStream_t st);
+                            int rb, int jacobi, double omega, double sA, const double* kn, bool fine, hipStream_t st);
+// fused interior Gauss-Seidel sweep (all interior colours); false if not available for the level
+template <typename T>
+bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, const T* b, const int32_t* tiles, int ntiles,
+                     const uint32_t* itab, int rb, double sA, bool fine, hipStream_t st);
 template <typename T>
 void launch_smooth_iface(int dim, bool p1, const LK& lk, const Tables& tb, const int32_t* list, int count, const T* uin,
                          T* uout, const T* b, int jacobi, double omega, double sA, const double* kn, hipStream_t st);

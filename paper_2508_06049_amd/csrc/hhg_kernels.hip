@@ -204,7 +204,8 @@ __device__ __forceinline__ void d_row_p1(const LK& lk, const double* __restrict_
 
 // ------------------------------------------------------------------------------------------
 // smoothers
-template <int D, typename T, bool P1>
+// FINE only labels the launches on the finest level (separate profiler statistics)
+template <int D, typename T, bool P1, bool FINE>
 __global__ void __launch_bounds__(256) k_smooth_interior(LK lk, Tables tb, const T* __restrict__ uin, T* __restrict__ uout,
                                                           const T* __restrict__ b, int colour, int rb, int jacobi,
                                                           double omega, double sA, const double* __restrict__ kn) {
@@ -327,6 +328,102 @@ __global__ void __launch_bounds__(256) k_iface_residual(LK lk, Tables tb, const 
     int lc[4] = {0, 0, 0, 0};
     for (int rr = 0; rr < np; ++rr) lc[in.slot[rr]] = co[rr];
     y[(int64_t)in.macro * lk.S + d_lin<D>(lk.n, lc[1], lc[2], lc[3])] = (Tout)(q == q0 ? r : (Tin)0);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Fused Gauss-Seidel sweep over the macro-interior nodes of a 2D level: every interior colour
+// class in one launch (the interface nodes stay fixed during this part of the sweep).  A
+// block owns a TI x TJ core tile and loads it with a halo of C layers into LDS.  Colour pass
+// c updates the nodes of colour c at distance >= c+1 from the edge of the loaded region;
+// those values equal what C class-by-class passes over the whole macro produce, because
+// each pass only needs correct values one layer further out.  After C passes the core is
+// exact and is written back; the halo work is redundant.  u is read once (plus halo), b once
+// per update, u written once.
+template <typename T, int C, int TI, int TJ, bool FINE>
+__global__ void __launch_bounds__(256) k_gs2d_fused(LK lk, Tables tb, T* __restrict__ u, const T* __restrict__ b,
+                                                     const int32_t* __restrict__ tiles, int ntiles, int rb, double sA) {
+  constexpr int H = C, RW = TI + 2 * H, RH = TJ + 2 * H, NR = RW * RH;
+  __shared__ T su[NR];
+  const int m = blockIdx.x / ntiles;
+  const int tile = tiles[blockIdx.x - m * ntiles];
+  const int i0 = 1 + (tile & 0xffff) * TI - H, j0 = 1 + (tile >> 16) * TJ - H;
+  const int n = lk.n;
+  const int64_t base = (int64_t)m * lk.S;
+  for (int idx = threadIdx.x; idx < NR; idx += 256) {
+    const int r = idx / RW, q = idx - r * RW;
+    const int i = i0 + q, j = j0 + r;
+    if (i >= 0 && j >= 0 && i + j <= n) su[idx] = u[base + d_lin2(n, i, j)];
+  }
+  __syncthreads();
+  const double* W = tb.stiff + (size_t)m * kMaxMask * 7;
+  const double ks = sA * tb.kappa[m];
+  const T w1 = (T)(ks * W[1]), w2 = (T)(ks * W[2]), w3 = (T)(ks * W[3]);
+  const T w4 = (T)(ks * W[4]), w5 = (T)(ks * W[5]), w6 = (T)(ks * W[6]);
+  const T dg = (T)(ks * W[0]);
+  const int s1 = rb ? tb.rbpar[m * 4 + 1] : 0, s2 = rb ? tb.rbpar[m * 4 + 2] : 0;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    for (int idx = threadIdx.x; idx < NR; idx += 256) {
+      const int r = idx / RW, q = idx - r * RW;
+      if (r < c + 1 || r >= RH - 1 - c || q < c + 1 || q >= RW - 1 - c) continue;
+      const int i = i0 + q, j = j0 + r;
+      if (i < 1 || j < 1 || i + j > n - 1) continue;
+      const int col = rb ? ((i * s1 + j * s2) & 1) : (i + 2 * j) % 3;
+      if (col != c) continue;
+      const T acc = w1 * su[idx + 1] + w2 * su[idx + RW] + w3 * su[idx + RW - 1] + w4 * su[idx - 1] +
+                    w5 * su[idx - RW] + w6 * su[idx - RW + 1];
+      su[idx] = (b[base + d_lin2(n, i, j)] - acc) / dg;
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < NR; idx += 256) {
+    const int r = idx / RW, q = idx - r * RW;
+    if (r < H || r >= H + TJ || q < H || q >= H + TI) continue;
+    const int i = i0 + q, j = j0 + r;
+    if (i < 1 || j < 1 || i + j > n - 1) continue;
+    u[base + d_lin2(n, i, j)] = su[idx];
+  }
+}
+
+// Fused Gauss-Seidel sweep over the interior of small 3D macros: one block per macro holds the
+// whole closure of u in LDS and runs every interior colour pass there; b is read once per
+// update from global memory.
+template <typename T, int C, bool FINE>
+__global__ void __launch_bounds__(1024) k_gs3d_macro(LK lk, Tables tb, T* __restrict__ u, const T* __restrict__ b,
+                                                      const uint32_t* __restrict__ itab, int rb, double sA) {
+  extern __shared__ unsigned char smem_raw[];
+  T* su = reinterpret_cast<T*>(smem_raw);
+  const int m = blockIdx.x;
+  const int n = lk.n;
+  const int64_t base = (int64_t)m * lk.S;
+  for (int s = threadIdx.x; s < lk.Sraw; s += blockDim.x) su[s] = u[base + s];
+  __syncthreads();
+  const double* W = tb.stiff + (size_t)m * kMaxMask * 15;
+  const double ks = sA * tb.kappa[m];
+  T w[15];
+#pragma unroll
+  for (int q = 0; q < 15; ++q) w[q] = (T)(ks * W[q]);
+  const int* rp = tb.rbpar + m * 4;
+  const int s1 = rb ? rp[1] : 0, s2 = rb ? rp[2] : 0, s3 = rb ? rp[3] : 0;
+  for (int c = 0; c < C; ++c) {
+    for (int t = threadIdx.x; t < lk.NI; t += blockDim.x) {
+      const uint32_t pk = itab[t];
+      const int i = pk & 1023, j = (pk >> 10) & 1023, k = pk >> 20;
+      const int col = rb ? ((i * s1 + j * s2 + k * s3) & 1) : (i + 2 * j + 3 * k) % 4;
+      if (col != c) continue;
+      T acc = (T)0;
+#pragma unroll
+      for (int q = 1; q < 15; ++q) acc += w[q] * su[d_lin<3>(n, i + kOff3[q][0], j + kOff3[q][1], k + kOff3[q][2])];
+      const int ctr = d_lin<3>(n, i, j, k);
+      su[ctr] = (b[base + ctr] - acc) / w[0];
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < lk.NI; t += blockDim.x) {
+    const uint32_t pk = itab[t];
+    const int ctr = d_lin<3>(n, pk & 1023, (pk >> 10) & 1023, pk >> 20);
+    u[base + ctr] = su[ctr];
   }
 }
 
@@ -699,16 +796,42 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 template <typename T>
 void launch_smooth_interior(int dim, bool p1, const LK& lk, const Tables& tb, const T* uin, T* uout, const T* b, int colour,
-                            int rb, int jacobi, double omega, double sA, const double* kn, hipStream_t st) {
+                            int rb, int jacobi, double omega, double sA, const double* kn, bool fine, hipStream_t st) {
   if (lk.NI <= 0) return;
   const unsigned g = (unsigned)(lk.nmacro * ((lk.NI + 255) / 256));
+#define HHG_SI(D, P, F) k_smooth_interior<D, T, P, F><<<g, 256, 0, st>>>(lk, tb, uin, uout, b, colour, rb, jacobi, omega, sA, kn)
   if (dim == 3) {
-    if (p1) k_smooth_interior<3, T, true><<<g, 256, 0, st>>>(lk, tb, uin, uout, b, colour, rb, jacobi, omega, sA, kn);
-    else k_smooth_interior<3, T, false><<<g, 256, 0, st>>>(lk, tb, uin, uout, b, colour, rb, jacobi, omega, sA, kn);
+    if (p1) { if (fine) HHG_SI(3, true, true); else HHG_SI(3, true, false); }
+    else { if (fine) HHG_SI(3, false, true); else HHG_SI(3, false, false); }
   } else {
-    if (p1) k_smooth_interior<2, T, true><<<g, 256, 0, st>>>(lk, tb, uin, uout, b, colour, rb, jacobi, omega, sA, kn);
-    else k_smooth_interior<2, T, false><<<g, 256, 0, st>>>(lk, tb, uin, uout, b, colour, rb, jacobi, omega, sA, kn);
+    if (p1) { if (fine) HHG_SI(2, true, true); else HHG_SI(2, true, false); }
+    else { if (fine) HHG_SI(2, false, true); else HHG_SI(2, false, false); }
   }
+#undef HHG_SI
+}
+
+template <typename T>
+bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, const T* b, const int32_t* tiles, int ntiles,
+                     const uint32_t* itab, int rb, double sA, bool fine, hipStream_t st) {
+  if (p1 || lk.NI <= 0) return false;
+  if (dim == 2) {
+    if (ntiles <= 0) return false;
+    const unsigned g = (unsigned)(lk.nmacro * ntiles);
+#define HHG_F2(C, F) k_gs2d_fused<T, C, kTileI, kTileJ, F><<<g, 256, 0, st>>>(lk, tb, u, b, tiles, ntiles, rb, sA)
+    if (rb) { if (fine) HHG_F2(2, true); else HHG_F2(2, false); }
+    else { if (fine) HHG_F2(3, true); else HHG_F2(3, false); }
+#undef HHG_F2
+    return true;
+  }
+  if (!itab || lk.n > kMacroLdsN) return false;
+  const size_t shm = (size_t)lk.Sraw * sizeof(T);
+  if (shm > 64 * 1024) return false;
+  const unsigned blk = lk.NI >= 512 ? 1024 : 256;
+#define HHG_F3(C, F) k_gs3d_macro<T, C, F><<<(unsigned)lk.nmacro, blk, shm, st>>>(lk, tb, u, b, itab, rb, sA)
+  if (rb) { if (fine) HHG_F3(2, true); else HHG_F3(2, false); }
+  else { if (fine) HHG_F3(4, true); else HHG_F3(4, false); }
+#undef HHG_F3
+  return true;
 }
 
 template <typename T>
@@ -852,9 +975,13 @@ void launch_copy(double* dst, const double* src, int64_t n, hipStream_t st) {
 
 // explicit instantiations
 template void launch_smooth_interior<double>(int, bool, const LK&, const Tables&, const double*, double*, const double*,
-                                             int, int, int, double, double, const double*, hipStream_t);
+                                             int, int, int, double, double, const double*, bool, hipStream_t);
 template void launch_smooth_interior<float>(int, bool, const LK&, const Tables&, const float*, float*, const float*, int,
-                                            int, int, double, double, const double*, hipStream_t);
+                                            int, int, double, double, const double*, bool, hipStream_t);
+template bool launch_gs_fused<double>(int, bool, const LK&, const Tables&, double*, const double*, const int32_t*, int,
+                                      const uint32_t*, int, double, bool, hipStream_t);
+template bool launch_gs_fused<float>(int, bool, const LK&, const Tables&, float*, const float*, const int32_t*, int,
+                                     const uint32_t*, int, double, bool, hipStream_t);
 template void launch_smooth_iface<double>(int, bool, const LK&, const Tables&, const int32_t*, int, const double*,
                                           double*, const double*, int, double, double, const double*, hipStream_t);
 template void launch_smooth_iface<float>(int, bool, const LK&, const Tables&, const int32_t*, int, const float*, float*,

@@ -398,8 +398,10 @@ static int interior_colour(hhg_ctx c, int l, int m, int i, int j, int k) {
 }
 
 hhg_status build_colouring(hhg_ctx c) {
+  // Sweep order: macro-interior colour classes 0..Cint-1, then interface classes Cint, ...
   const int d = c->dim;
   const int ND = d == 3 ? kNDir3 : kNDir2;
+  const int Cint = c->opt.smoother == HHG_JACOBI ? 1 : (c->opt.smoother == HHG_GS_REDBLACK ? 2 : (d == 2 ? 3 : 4));
   for (auto& lv : c->lev) {
     std::vector<int> col(lv.nIface, -1);
     for (int64_t t = 0; t < lv.nIface; ++t) {
@@ -410,11 +412,12 @@ hhg_status build_colouring(hhg_ctx c) {
       int cc[4] = {0, 0, 0, 0};
       int np = p < c->nV ? 1 : (p < c->nV + c->nE ? 2 : 3);
       for (int r = 0; r < np; ++r) cc[in0.slot[r]] = co[r];
-      if (c->opt.smoother != HHG_GS_MULTICOLOR) {
-        col[t] = interior_colour(c, lv.l, in0.macro, cc[1], cc[2], cc[3]);
+      if (c->opt.smoother == HHG_JACOBI) { col[t] = Cint; continue; }
+      if (c->opt.smoother == HHG_GS_REDBLACK) {
+        col[t] = Cint + interior_colour(c, lv.l, in0.macro, cc[1], cc[2], cc[3]);
         continue;
       }
-      // greedy first fit against every coloured neighbour
+      // greedy first fit against the interface neighbours coloured so far
       uint64_t used = 0;
       for (int q = c->inc_off[p]; q < c->inc_off[p + 1]; ++q) {
         const Inc& in = c->inc[q];
@@ -425,25 +428,28 @@ hhg_status build_colouring(hhg_ctx c) {
           int i2 = lc[1] + (d == 3 ? kOff3[dd][0] : kOff2[dd][0]);
           int j2 = lc[2] + (d == 3 ? kOff3[dd][1] : kOff2[dd][1]);
           int k2 = d == 3 ? lc[3] + kOff3[dd][2] : 0;
-          int mk = zero_mask(d, lv.n, i2, j2, k2);
-          int cn;
-          if (mk == 0) cn = interior_colour(c, lv.l, in.macro, i2, j2, k2);
-          else {
-            int64_t t2 = canonical_index(c, lv, in.macro, i2, j2, k2);
-            cn = col[t2];
-          }
+          if (zero_mask(d, lv.n, i2, j2, k2) == 0) continue;
+          const int cn = col[canonical_index(c, lv, in.macro, i2, j2, k2)];
           if (cn >= 0 && cn < 64) used |= (1ull << cn);
         }
       }
-      int cnew = 0;
+      int cnew = Cint;
       while ((used >> cnew) & 1) ++cnew;
       col[t] = cnew;
     }
     int maxc = -1;
     for (int v : col) maxc = std::max(maxc, v);
-    lv.interior_colours = 0;
-    if (lv.NI > 0) lv.interior_colours = c->opt.smoother == HHG_JACOBI ? 1 : (c->opt.smoother == HHG_GS_REDBLACK ? 2 : (d == 2 ? 3 : 4));
-    lv.ncolours = std::max(lv.interior_colours, maxc + 1);
+    lv.interior_colours = Cint;
+    lv.ncolours = std::max(Cint, maxc + 1);
+    lv.interior_per_colour.assign(Cint, 0);
+    if (lv.NI > 0) {
+      const int n = lv.n;
+      for (int64_t m = 0; m < c->nC; ++m)
+        for (int k = (d == 3 ? 1 : 0); k <= (d == 3 ? n - 3 : 0); ++k)
+          for (int j = 1; j <= n - 2 - (d == 3 ? k : 0); ++j)
+            for (int i = 1; i <= n - 1 - j - (d == 3 ? k : 0); ++i)
+              lv.interior_per_colour[interior_colour(c, lv.l, (int)m, i, j, k)]++;
+    }
     lv.colour_off.assign(lv.ncolours + 1, 0);
     for (int v : col) if (v >= 0) lv.colour_off[v + 1]++;
     for (int q = 0; q < lv.ncolours; ++q) lv.colour_off[q + 1] += lv.colour_off[q];
@@ -451,6 +457,19 @@ hhg_status build_colouring(hhg_ctx c) {
     std::vector<int32_t> fill(lv.colour_off.begin(), lv.colour_off.end() - 1);
     for (int64_t t = 0; t < lv.nIface; ++t)
       if (col[t] >= 0) lv.colour_list[fill[col[t]]++] = (int32_t)t;
+    // tables of the fused interior sweeps
+    lv.tiles.clear();
+    lv.itab.clear();
+    if (d == 2 && lv.NI > 0) {
+      for (int tj = 0; 1 + tj * kTileJ <= lv.n - 2; ++tj)
+        for (int ti = 0; 1 + ti * kTileI + 1 + tj * kTileJ <= lv.n - 1; ++ti) lv.tiles.push_back(ti | (tj << 16));
+    }
+    if (d == 3 && lv.NI > 0 && lv.n <= kMacroLdsN) {
+      const int n = lv.n;
+      for (int k = 1; k <= n - 3; ++k)
+        for (int j = 1; j <= n - 2 - k; ++j)
+          for (int i = 1; i <= n - 1 - j - k; ++i) lv.itab.push_back((uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20));
+    }
   }
   return HHG_OK;
 }
@@ -579,6 +598,8 @@ void plan_workspace(hhg_ctx c) {
     lv.off_t32 = take(nf * 4);
     lv.off_b32 = take(nf * 4);
     lv.off_cl = take((int64_t)lv.colour_list.size() * 4);
+    lv.off_tiles = take((int64_t)lv.tiles.size() * 4);
+    lv.off_itab = take((int64_t)lv.itab.size() * 4);
   }
   c->ws_bytes = (size_t)off;
 }

@@ -41,10 +41,17 @@ MESHES = {
     "kuhn2": (lambda: meshes.kuhn_cube(2), 3, "multicolour"),
     "tet": (generic_tet, 4, "multicolour"),
     "twotets": (two_generic_tets, 4, "multicolour"),
+    # larger levels: several fused-sweep tiles per macro in 2D; the largest 3D level swept in
+    # LDS (n = 32) and one above it (class-by-class launches)
+    "square8": (meshes.unit_square_2tri, 8, "redblack"),
+    "lshape7": (meshes.lshape_6tri, 7, "multicolour"),
+    "kuhn1_5": (lambda: meshes.kuhn_cube(1), 5, "redblack"),
+    "kuhn1_6": (lambda: meshes.kuhn_cube(1), 6, "multicolour"),
 }
+SMALL = ["square", "lshape", "grid4", "kuhn1", "kuhn2", "tet", "twotets"]
 
 
-@pytest.mark.parametrize("name", list(MESHES))
+@pytest.mark.parametrize("name", SMALL)
 def test_dof_coordinates_bit_exact(name):
     mk, L, sm = MESHES[name]
     _note("coords", name, L)
@@ -57,7 +64,7 @@ def test_dof_coordinates_bit_exact(name):
         assert np.array_equal(x, h.levels[l].X[perms[l]]), f"level {l}"
 
 
-@pytest.mark.parametrize("name", list(MESHES))
+@pytest.mark.parametrize("name", SMALL)
 def test_operators_match(name):
     mk, L, sm = MESHES[name]
     _note("apply", name, L)
@@ -78,7 +85,7 @@ def test_operators_match(name):
         assert rel_err(ym, (M @ x)[p]) < 1e-13
 
 
-@pytest.mark.parametrize("name", list(MESHES))
+@pytest.mark.parametrize("name", SMALL)
 def test_transfers_match(name):
     mk, L, sm = MESHES[name]
     _note("transfer", name, L)
@@ -103,7 +110,10 @@ def test_transfers_match(name):
 @pytest.mark.parametrize("name,smoother", [("square", "redblack"), ("lshape", "multicolour"),
                                            ("lshape", "jacobi"), ("kuhn1", "redblack"),
                                            ("kuhn2", "multicolour"), ("tet", "multicolour"),
-                                           ("twotets", "multicolour"), ("grid4", "multicolour")])
+                                           ("twotets", "multicolour"), ("grid4", "multicolour"),
+                                           ("square8", "redblack"), ("lshape7", "multicolour"),
+                                           ("kuhn1_5", "redblack"), ("kuhn1_5", "multicolour"),
+                                           ("kuhn1_6", "multicolour"), ("kuhn1_6", "redblack")])
 def test_smoother_matches(name, smoother):
     mk, L, _ = MESHES[name]
     _note("smooth", name, smoother, L)
@@ -124,9 +134,9 @@ def test_smoother_matches(name, smoother):
 
 
 def _rhs(name, X, dim):
-    if name in ("square",):
+    if name.startswith("square"):
         return problems.sine2d_f(X), np.zeros(len(X))
-    if name in ("lshape",):
+    if name.startswith("lshape"):
         return np.zeros(len(X)), problems.lshape_u(X)
     if dim == 2:
         return problems.sine2d_f(X), 0.25 + X[:, 0] - 0.5 * X[:, 1]
@@ -136,7 +146,9 @@ def _rhs(name, X, dim):
 @pytest.mark.parametrize("name,smoother,nu,extra", [
     ("square", "redblack", 1, 0), ("square", "redblack", 2, 30), ("lshape", "multicolour", 1, 0),
     ("lshape", "jacobi", 2, 0), ("grid4", "multicolour", 1, 0), ("kuhn1", "redblack", 1, 0),
-    ("kuhn2", "multicolour", 2, 0), ("twotets", "multicolour", 1, 0), ("kuhn1", "redblack", 1, 30)])
+    ("kuhn2", "multicolour", 2, 0), ("twotets", "multicolour", 1, 0), ("kuhn1", "redblack", 1, 30),
+    ("square8", "redblack", 1, 0), ("lshape7", "multicolour", 1, 0), ("kuhn1_5", "redblack", 1, 0),
+    ("kuhn1_6", "multicolour", 1, 0)])
 def test_fmg_matches(name, smoother, nu, extra):
     mk, L, _ = MESHES[name]
     _note("fmg", name, smoother, nu, extra, L)

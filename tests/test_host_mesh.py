@@ -1,0 +1,106 @@
+"""CPU tests of the host-side k-refinement: marking and red-green refinement (Section 3,
+Algorithm 3)."""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2508_06049_amd import mesh as M
+from oracle.assemble import element_geometry
+from workloads import meshes
+
+
+def _facets(cells, d):
+    out = {}
+    for ci, c in enumerate(cells):
+        for f in itertools.combinations(sorted(int(v) for v in c), d):
+            out.setdefault(f, []).append(ci)
+    return out
+
+
+def _check_conforming(mesh, volume):
+    d = mesh.dim
+    _, vol = element_geometry(mesh.coords, mesh.cells)
+    assert vol.min() > 0
+    assert abs(vol.sum() - volume) < 1e-12
+    fac = _facets(mesh.cells, d)
+    assert max(len(v) for v in fac.values()) <= 2
+    # no hanging node: no vertex lies in the interior of another cell's edge
+    X = mesh.coords
+    edges = {tuple(sorted(e)) for c in mesh.cells for e in itertools.combinations(c, 2)}
+    mids = {tuple(0.5 * (X[a] + X[b])) for a, b in edges}
+    for p in map(tuple, X):
+        if p in mids:
+            # a vertex at an edge midpoint must be a vertex of every cell containing that edge
+            for a, b in edges:
+                if tuple(0.5 * (X[a] + X[b])) == p:
+                    raise AssertionError("hanging node")
+    # boundary facets lie on the domain boundary: total boundary measure
+    return fac
+
+
+def test_mark_fraction_ceil_and_ties():
+    eta = np.array([1.0, 3.0, 3.0, 2.0, 0.5, 3.0, 0.1, 0.2, 0.3, 0.4, 0.45])
+    assert list(M.mark_fraction(eta, 0.1)) == [1, 2]          # ceil(1.1) = 2, ties -> lower ids
+    assert list(M.mark_fraction(eta, 0.125)) == [1, 2]
+    assert len(M.mark_fraction(eta, 1.0)) == eta.size
+
+
+def test_lshape_corner_refinement_is_conforming():
+    m = M.lshape_corner_refined(6)
+    assert m.n_cells == 144
+    fac = _check_conforming(m, 3.0)
+    # the smallest macros touch the corner and have edge length 2^-6
+    o = int(np.nonzero((m.coords == 0).all(1))[0][0])
+    touching = [c for c in m.cells if o in c]
+    lens = [np.linalg.norm(m.coords[a] - m.coords[b]) for c in touching for a, b in itertools.combinations(c, 2)]
+    assert min(lens) == 2.0 ** -6
+
+
+def test_green_triangles_are_reverted():
+    rg = M.RedGreen2D(meshes.unit_square_grid(2))
+    cells, _ = rg.conforming()
+    rg.refine([0])
+    c1, p1 = rg.conforming()
+    n_red_leaves = len(rg.tris)
+    # an empty refinement step keeps the mesh, and greens are never stored
+    rg.refine([])
+    c2, _ = rg.conforming()
+    assert sorted(map(tuple, c1)) == sorted(map(tuple, c2))
+    assert len(rg.tris) == n_red_leaves
+    assert len(c1) > len(rg.tris)   # greens present in the output only
+    # marking a green cell refines its red parent
+    green = [i for i in range(len(c1)) if sum(1 for q in p1 if q == p1[i]) == 2][0]
+    rg.refine([green])
+    m = rg.mesh()
+    _check_conforming(m, 1.0)
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3])
+def test_red_green_3d_conforming(steps):
+    rg = M.RedGreen3D(meshes.kuhn_cube(2))
+    cells, _ = rg.conforming()
+    rng = np.random.default_rng(steps)
+    for _ in range(steps):
+        marked = rng.choice(len(cells), max(1, len(cells) // 8), replace=False)
+        rg.refine(marked)
+        cells, _ = rg.conforming()
+    m = rg.mesh()
+    fac = _check_conforming(m, 1.0)
+    # boundary faces cover the cube surface (area 6)
+    area = 0.0
+    for f, cs in fac.items():
+        if len(cs) == 1:
+            P = m.coords[list(f)]
+            area += 0.5 * np.linalg.norm(np.cross(P[1] - P[0], P[2] - P[0]))
+    assert abs(area - 6.0) < 1e-12
+
+
+def test_green_types_3d_only_three():
+    # after closure every irregular cell has hanging nodes on one edge, two opposite edges or one face
+    rg = M.RedGreen3D(meshes.kuhn_cube(2))
+    cells, _ = rg.conforming()
+    rg.refine([0, 5, 17])
+    for t in rg.tets:
+        he = rg._hanging_edges(t)
+        assert len(he) in (0, 1, 2, 3)
