@@ -34,8 +34,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # the finest-level interior smoother kernel per workload type (float32 sweeps)
 KERNEL_NAME = {
-    (2, "multicolour", "macro"): "k_gs2d_fused<float, 3, 128, 16, true>",
-    (2, "redblack", "macro"): "k_gs2d_fused<float, 2, 128, 16, true>",
+    (2, "multicolour", "macro"): "k_gs2d_fused<float, 3, 32, 1, true>",
+    (2, "redblack", "macro"): "k_gs2d_fused<float, 2, 32, 1, true>",
     (3, "multicolour", "macro"): "k_gs3d_macro<float, 4, true>",
     (3, "redblack", "macro"): "k_gs3d_macro<float, 2, true>",
 }

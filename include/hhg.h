@@ -74,7 +74,12 @@ typedef struct {
                                  averaged over the vertices of every micro element            */
   int smoother;               /* HHG_GS_REDBLACK | HHG_GS_MULTICOLOR | HHG_JACOBI              */
   double jacobi_omega;        /* damping of the Jacobi smoother (0 selects 2/3)                */
+  int flags;                  /* HHG_FLAG_NO_FUSED: sweep macro interiors one colour class per
+                                 launch instead of all classes in one launch (same result up to
+                                 rounding; for checking the fused kernels)                    */
 } hhg_options;
+
+enum { HHG_FLAG_NO_FUSED = 1 };
 
 typedef struct {
   int nu;                     /* V-cycles per FMG level (Algorithm 4's nu)                     */

@@ -21,6 +21,7 @@ HHG_KAPPA_MACRO, HHG_KAPPA_P1 = 0, 1
 HHG_GS_REDBLACK, HHG_GS_MULTICOLOR, HHG_JACOBI = 0, 1, 2
 HHG_FP64, HHG_FP32_REFINED = 0, 1
 HHG_OP_STIFFNESS, HHG_OP_MASS = 0, 1
+HHG_FLAG_NO_FUSED = 1
 
 SMOOTHERS = {"redblack": HHG_GS_REDBLACK, "multicolour": HHG_GS_MULTICOLOR, "jacobi": HHG_JACOBI}
 PRECISIONS = {"fp64": HHG_FP64, "fp32_refined": HHG_FP32_REFINED}
@@ -33,7 +34,7 @@ class hhg_mesh(C.Structure):
 
 
 class hhg_options(C.Structure):
-    _fields_ = [("coefficient", C.c_int), ("smoother", C.c_int), ("jacobi_omega", C.c_double)]
+    _fields_ = [("coefficient", C.c_int), ("smoother", C.c_int), ("jacobi_omega", C.c_double), ("flags", C.c_int)]
 
 
 class hhg_solve_params(C.Structure):
@@ -130,7 +131,7 @@ class SolveStats:
 
 
 def setup_host(coords, cells, L: int, smoother: str = "redblack", coefficient: str = "macro",
-               kappa_cell=None, dirichlet=None, omega: float = 0.0):
+               kappa_cell=None, dirichlet=None, omega: float = 0.0, flags: int = 0):
     """Call hhg_setup (host only).  Returns (ctx handle, keep-alive arrays)."""
     lib = load()
     coords = np.ascontiguousarray(coords, dtype=np.float64)
@@ -154,6 +155,7 @@ def setup_host(coords, cells, L: int, smoother: str = "redblack", coefficient: s
     o.coefficient = HHG_KAPPA_P1 if coefficient == "p1" else HHG_KAPPA_MACRO
     o.smoother = SMOOTHERS[smoother]
     o.jacobi_omega = omega
+    o.flags = flags
     ctx = _ctx()
     _check(lib.hhg_setup(C.byref(m), L, C.byref(o), C.byref(ctx)), None)
     return ctx, keep
@@ -163,14 +165,14 @@ class HHG:
     """One HHG context bound to a torch-allocated workspace on a CUDA (HIP) device."""
 
     def __init__(self, coords, cells, L: int, smoother: str = "redblack", coefficient: str = "macro",
-                 kappa_cell=None, dirichlet=None, omega: float = 0.0, device="cuda:0"):
+                 kappa_cell=None, dirichlet=None, omega: float = 0.0, device="cuda:0", flags: int = 0):
         import torch
         self.lib = load()
         self.dim = int(np.asarray(coords).shape[1])
         self.n_cells = int(np.asarray(cells).shape[0])
         self.L = L
         self.coefficient = coefficient
-        self.ctx, _ = setup_host(coords, cells, L, smoother, coefficient, kappa_cell, dirichlet, omega)
+        self.ctx, _ = setup_host(coords, cells, L, smoother, coefficient, kappa_cell, dirichlet, omega, flags)
         nb = C.c_size_t()
         _check(self.lib.hhg_workspace_bytes(self.ctx, C.byref(nb)), self.ctx)
         self.device = torch.device(device)

@@ -87,11 +87,13 @@ hhg_status check_ready(hhg_ctx c) {
 template <typename T> struct Arr;
 template <> struct Arr<double> {
   static double*& x(Level& l) { return l.x; }
+  static double*& x2(Level& l) { return l.x2; }
   static double*& t(Level& l) { return l.t; }
   static double*& rc(Level& l) { return l.rc; }
 };
 template <> struct Arr<float> {
   static float*& x(Level& l) { return l.x32; }
+  static float*& x2(Level& l) { return l.x2_32; }
   static float*& t(Level& l) { return l.t32; }
   static float*& rc(Level& l) { return l.b32; }
 };
@@ -105,7 +107,7 @@ void interior_launch(hhg_ctx c, int l, const LK& k, const T* x, T* y, const T* b
   if (rec) (void)hipEventRecord((hipEvent_t)c->prof_ev[c->prof_used], ST(c));
   int64_t npts;
   if (col < 0) {   // all interior colours fused in one launch
-    launch_gs_fused<T>(c->dim, p1(c), k, c->tab, const_cast<T*>(x), b, lv.d_tiles, (int)lv.tiles.size(), lv.d_itab, rb,
+    launch_gs_fused<T>(c->dim, p1(c), k, c->tab, const_cast<T*>(x), y, b, lv.d_tiles, (int)lv.tiles.size(), lv.d_itab, rb,
                        sA(c, l), fine, ST(c));
     npts = lv.NI * c->nC;
   } else {
@@ -134,25 +136,36 @@ hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
   const bool jac = c->opt.smoother == HHG_JACOBI;
   const int rb = c->opt.smoother == HHG_GS_REDBLACK ? 1 : 0;
   const bool fused = fused_available(c, l, sizeof(T));
+  const bool twobuf = fused && c->dim == 2;   // out-of-place interior sweep, see k_gs2d_fused
   for (int s = 0; s < sweeps; ++s) {
     T* x = Arr<T>::x(lv);
     if (jac) {
       T* y = Arr<T>::t(lv);
       interior_launch<T>(c, l, k, x, y, b, 0, 0, 1);
-      launch_smooth_iface<T>(c->dim, p1(c), k, c->tab, nullptr, (int)lv.nIface, x, y, b, 1, omega(c), sA(c, l), lv.kn,
-                             ST(c));
+      launch_smooth_iface<T>(c->dim, p1(c), k, c->tab, nullptr, (int)lv.nIface, x, x, y, (T*)nullptr, b, 1, omega(c),
+                             sA(c, l), lv.kn, ST(c));
       std::swap(Arr<T>::x(lv), Arr<T>::t(lv));
       continue;
     }
-    // macro interiors first (all colours), then the interface colour classes
-    if (fused) interior_launch<T>(c, l, k, x, x, b, -1, rb, 0);
+    // macro interiors first (all colours), then the interface colour classes; with two buffers
+    // the interface reads interior neighbours from the new buffer y and interface values from x
+    // (current), and writes both
+    T* y = twobuf ? Arr<T>::x2(lv) : x;
+    if (fused) interior_launch<T>(c, l, k, x, y, b, -1, rb, 0);
     else
       for (int col = 0; col < lv.interior_colours; ++col) interior_launch<T>(c, l, k, x, x, b, col, rb, 0);
-    for (int col = lv.interior_colours; col < lv.ncolours; ++col) {
-      const int cnt = lv.colour_off[col + 1] - lv.colour_off[col];
-      launch_smooth_iface<T>(c->dim, p1(c), k, c->tab, lv.d_colour_list + lv.colour_off[col], cnt, x, x, b, 0, 0.0,
-                             sA(c, l), lv.kn, ST(c));
+    T* mir = twobuf ? x : (T*)nullptr;
+    if (lv.max_iface_class <= kIfaceOneGroup) {
+      launch_iface_sweep_1wg<T>(c->dim, p1(c), k, c->tab, lv.d_colour_list, lv.d_colour_off, lv.interior_colours,
+                                lv.ncolours, y, x, y, mir, b, sA(c, l), lv.kn, ST(c));
+    } else {
+      for (int col = lv.interior_colours; col < lv.ncolours; ++col) {
+        const int cnt = lv.colour_off[col + 1] - lv.colour_off[col];
+        launch_smooth_iface<T>(c->dim, p1(c), k, c->tab, lv.d_colour_list + lv.colour_off[col], cnt, y, x, y, mir, b, 0,
+                               0.0, sA(c, l), lv.kn, ST(c));
+      }
     }
+    if (twobuf) std::swap(Arr<T>::x(lv), Arr<T>::x2(lv));
   }
   LAUNCHCHK();
   return HHG_OK;
@@ -372,6 +385,7 @@ hhg_status hhg_setup(const hhg_mesh* mesh, int L, const hhg_options* opt, hhg_ct
   c->dim = mesh->dim;
   c->L = L;
   c->opt = *opt;
+  c->no_fused = (opt->flags & HHG_FLAG_NO_FUSED) != 0;
   c->nV = mesh->n_vertices;
   c->nC = mesh->n_cells;
   const int nv = c->dim + 1;
@@ -483,10 +497,14 @@ hhg_status hhg_bind_workspace(hhg_ctx c, void* ptr, size_t bytes, void* stream) 
     lv.w = (double*)(w + lv.off_w);
     lv.kn = lv.off_kn >= 0 ? (double*)(w + lv.off_kn) : nullptr;
     lv.x32 = (float*)(w + lv.off_x32);
+    lv.x2 = (double*)(w + lv.off_x2);
+    lv.x2_32 = (float*)(w + lv.off_x2_32);
     lv.t32 = (float*)(w + lv.off_t32);
     lv.b32 = (float*)(w + lv.off_b32);
     lv.d_colour_list = (int32_t*)(w + lv.off_cl);
     HIPCHK(up(lv.off_cl, lv.colour_list.data(), lv.colour_list.size() * 4));
+    lv.d_colour_off = (int32_t*)(w + lv.off_coff);
+    HIPCHK(up(lv.off_coff, lv.colour_off.data(), lv.colour_off.size() * 4));
     lv.d_tiles = (int32_t*)(w + lv.off_tiles);
     HIPCHK(up(lv.off_tiles, lv.tiles.data(), lv.tiles.size() * 4));
     lv.d_itab = (uint32_t*)(w + lv.off_itab);

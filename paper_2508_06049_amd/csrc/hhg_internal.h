@@ -24,9 +24,13 @@ namespace hhg {
 constexpr int kMaxMask = 16;   // zero-set masks of the barycentric coordinates (bit q: c_q == 0)
 constexpr int kNDir3 = 15, kNDir2 = 7;
 constexpr int kNType3 = 6, kNType2 = 2;
-// fused interior sweeps: 2D core tile (i x j) and the largest 3D macro level kept whole in LDS
-constexpr int kTileI = 128, kTileJ = 16;
+// fused interior sweeps: 2D core tile of (256 - 2 C) columns x kTileJ rows (C = interior
+// colours), and the largest 3D macro level kept whole in LDS
+constexpr int kTileJ = 32;
 constexpr int kMacroLdsN = 32;
+// levels whose largest interface colour class has at most this many DoFs sweep all interface
+// classes in one single-workgroup launch
+constexpr int kIfaceOneGroup = 4096;
 
 // direction tables: index 0 is the centre, 1..H positive, H+1..2H negative
 constexpr int kDir3[7][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {-1, 1, 0}, {-1, 0, 1}, {0, -1, 1}, {1, -1, 1}};
@@ -79,13 +83,17 @@ struct Level {
   // device buffers (inside workspace)
   double *x = nullptr, *t = nullptr, *bf = nullptr, *rc = nullptr, *g = nullptr, *w = nullptr, *kn = nullptr;
   float *x32 = nullptr, *t32 = nullptr, *b32 = nullptr;
+  double* x2 = nullptr;                // second iterate buffer of the out-of-place 2D fused sweep
+  float* x2_32 = nullptr;
   int32_t* d_colour_list = nullptr;
+  int32_t* d_colour_off = nullptr;
+  int max_iface_class = 0;
   std::vector<int32_t> tiles;          // 2D: interior tiles (ti | tj << 16) of the fused sweep
   std::vector<uint32_t> itab;          // 3D, n <= kMacroLdsN: interior points (i | j << 10 | k << 20)
   int32_t* d_tiles = nullptr;
   uint32_t* d_itab = nullptr;
   int64_t off_x = 0, off_t = 0, off_bf = 0, off_rc = 0, off_g = 0, off_w = 0, off_kn = -1, off_x32 = 0, off_t32 = 0,
-          off_b32 = 0, off_cl = 0, off_tiles = 0, off_itab = 0;
+          off_b32 = 0, off_cl = 0, off_tiles = 0, off_itab = 0, off_x2 = 0, off_x2_32 = 0, off_coff = 0;
 };
 
 }  // namespace hhg

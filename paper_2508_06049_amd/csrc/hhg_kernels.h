@@ -21,12 +21,21 @@ template <typename T>
 void launch_smooth_interior(int dim, bool p1, const LK& lk, const Tables& tb, const T* uin, T* uout, const T* b, int colour,
                             int rb, int jacobi, double omega, double sA, const double* kn, bool fine, hipStream_t st);
 // fused interior Gauss-Seidel sweep (all interior colours); false if not available for the level
+// (2D reads u and writes the interior of uo; 3D updates u in place and ignores uo)
 template <typename T>
-bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, const T* b, const int32_t* tiles, int ntiles,
-                     const uint32_t* itab, int rb, double sA, bool fine, hipStream_t st);
+bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* uo, const T* b, const int32_t* tiles,
+                     int ntiles, const uint32_t* itab, int rb, double sA, bool fine, hipStream_t st);
+// interface update of one colour class (xi: source of interior neighbours, xf: of interface
+// neighbours; umirror, if not NULL, receives the new values too)
 template <typename T>
-void launch_smooth_iface(int dim, bool p1, const LK& lk, const Tables& tb, const int32_t* list, int count, const T* uin,
-                         T* uout, const T* b, int jacobi, double omega, double sA, const double* kn, hipStream_t st);
+void launch_smooth_iface(int dim, bool p1, const LK& lk, const Tables& tb, const int32_t* list, int count, const T* xi,
+                         const T* xf, T* uout, T* umirror, const T* b, int jacobi, double omega, double sA,
+                         const double* kn, hipStream_t st);
+// interface classes c0..c1-1 in one single-workgroup launch
+template <typename T>
+void launch_iface_sweep_1wg(int dim, bool p1, const LK& lk, const Tables& tb, const int32_t* list, const int32_t* coff,
+                            int c0, int c1, const T* xi, const T* xf, T* uout, T* umirror, const T* b, double sA,
+                            const double* kn, hipStream_t st);
 template <typename Tin, typename Tout>
 void launch_apply(int dim, bool p1, const LK& lk, const Tables& tb, const Tin* x, const Tin* b, Tout* y, int op,
                   double scale, double alpha, double beta, int zero_dir, const double* kn, hipStream_t st);

@@ -245,14 +245,15 @@ __global__ void __launch_bounds__(256) k_smooth_interior(LK lk, Tables tb, const
   }
 }
 
+// Gauss-Seidel (or Jacobi) update of one interface DoF t: the assembled row is the sum of the
+// partial rows of all macros containing it.  Interior neighbours are read from xi, interface
+// neighbours (and the DoF's own old value) from xf; the new value goes to every copy in uout
+// and, if given, in umirror.  (xi and xf differ during the out-of-place 2D sweep.)
 template <int D, typename T, bool P1>
-__global__ void __launch_bounds__(256) k_smooth_iface(LK lk, Tables tb, const int32_t* __restrict__ list, int count,
-                                                       const T* __restrict__ uin, T* __restrict__ uout,
-                                                       const T* __restrict__ b, int jacobi, double omega, double sA,
-                                                       const double* __restrict__ kn) {
-  const int tid = blockIdx.x * 256 + threadIdx.x;
-  if (tid >= count) return;
-  const int64_t t = list ? (int64_t)list[tid] : (int64_t)tid;
+__device__ __forceinline__ void iface_update(const LK& lk, const Tables& tb, int64_t t, const T* xi, const T* xf, T* uout,
+                                             T* umirror, const T* __restrict__ b, int jacobi, double omega, double sA,
+                                             const double* __restrict__ kn) {
+  constexpr int NV = D + 1;
   int p, co[3], np;
   d_iface_decode(lk, tb, t, p, co, np);
   const int q0 = tb.inc_off[p], q1 = tb.inc_off[p + 1];
@@ -262,21 +263,52 @@ __global__ void __launch_bounds__(256) k_smooth_iface(LK lk, Tables tb, const in
     const Inc in = tb.inc[q];
     int lc[4] = {0, 0, 0, 0};
     for (int r = 0; r < np; ++r) lc[in.slot[r]] = co[r];
+    const int i = lc[1], j = lc[2], k = lc[3];
     const int64_t base = (int64_t)in.macro * lk.S;
-    const int ctr = d_lin<D>(lk.n, lc[1], lc[2], lc[3]);
-    if (q == q0) uold = uin[base + ctr];
+    const int ctr = d_lin<D>(lk.n, i, j, k);
+    if (q == q0) uold = xf[base + ctr];
     if (dir) continue;
     rhs += b[base + ctr];
-    T o, dg;
     if constexpr (P1) {
-      d_row_p1<D, T>(lk, tb.elemK + (size_t)in.macro * ntype<D>() * (D + 1) * (D + 1), tb.incvalid[in.mask], sA, kn,
-                     uin, base, lc[1], lc[2], lc[3], o, dg);
+      const double* EK = tb.elemK + (size_t)in.macro * ntype<D>() * NV * NV;
+      const uint32_t iv = tb.incvalid[in.mask];
+      for (int ty = 0; ty < ntype<D>(); ++ty) {
+        for (int a = 0; a < NV; ++a) {
+          if (!((iv >> (ty * NV + a)) & 1)) continue;
+          int oa0, oa1, oa2;
+          d_typeoff<D>(ty, a, oa0, oa1, oa2);
+          T val[NV];
+          double ks = 0.0;
+          for (int bb = 0; bb < NV; ++bb) {
+            int o0, o1, o2;
+            d_typeoff<D>(ty, bb, o0, o1, o2);
+            const int i2 = i + o0 - oa0, j2 = j + o1 - oa1, k2 = k + o2 - oa2;
+            const int l2 = d_lin<D>(lk.n, i2, j2, k2);
+            val[bb] = (d_mask<D>(lk.n, i2, j2, k2) ? xf : xi)[base + l2];
+            ks += kn[base + l2];
+          }
+          ks *= sA / NV;
+          const double* Kr = EK + (ty * NV + a) * NV;
+          for (int bb = 0; bb < NV; ++bb) {
+            if (bb == a) diag += (T)(ks * Kr[bb]);
+            else off += (T)(ks * Kr[bb]) * val[bb];
+          }
+        }
+      }
     } else {
-      d_row_const<D, T>(lk, tb.stiff + ((size_t)in.macro * kMaxMask + in.mask) * ndir<D>(), tb.validdirs[in.mask],
-                        sA * tb.kappa[in.macro], uin, base, lc[1], lc[2], lc[3], o, dg);
+      const double* W = tb.stiff + ((size_t)in.macro * kMaxMask + in.mask) * ndir<D>();
+      const uint32_t valid = tb.validdirs[in.mask];
+      const double scale = sA * tb.kappa[in.macro];
+#pragma unroll
+      for (int dd = 1; dd < ndir<D>(); ++dd) {
+        if (!((valid >> dd) & 1)) continue;
+        int a, b2, c;
+        d_off<D>(dd, a, b2, c);
+        const int i2 = i + a, j2 = j + b2, k2 = k + c;
+        off += (T)(scale * W[dd]) * (d_mask<D>(lk.n, i2, j2, k2) ? xf : xi)[base + d_lin<D>(lk.n, i2, j2, k2)];
+      }
+      diag += (T)(scale * W[0]);
     }
-    off += o;
-    diag += dg;
   }
   T unew;
   if (dir) unew = uold;
@@ -286,7 +318,36 @@ __global__ void __launch_bounds__(256) k_smooth_iface(LK lk, Tables tb, const in
     const Inc in = tb.inc[q];
     int lc[4] = {0, 0, 0, 0};
     for (int r = 0; r < np; ++r) lc[in.slot[r]] = co[r];
-    uout[(int64_t)in.macro * lk.S + d_lin<D>(lk.n, lc[1], lc[2], lc[3])] = unew;
+    const int64_t ix = (int64_t)in.macro * lk.S + d_lin<D>(lk.n, lc[1], lc[2], lc[3]);
+    uout[ix] = unew;
+    if (umirror) umirror[ix] = unew;
+  }
+}
+
+template <int D, typename T, bool P1>
+__global__ void __launch_bounds__(256) k_smooth_iface(LK lk, Tables tb, const int32_t* __restrict__ list, int count,
+                                                       const T* xi, const T* xf, T* uout, T* umirror,
+                                                       const T* __restrict__ b, int jacobi, double omega, double sA,
+                                                       const double* __restrict__ kn) {
+  const int tid = blockIdx.x * 256 + threadIdx.x;
+  if (tid >= count) return;
+  iface_update<D, T, P1>(lk, tb, list ? (int64_t)list[tid] : (int64_t)tid, xi, xf, uout, umirror, b, jacobi, omega, sA,
+                         kn);
+}
+
+// every interface colour class c0..c1-1 of one sweep in a single workgroup (small levels):
+// one launch instead of one per class, classes separated by barriers
+template <int D, typename T, bool P1>
+__global__ void __launch_bounds__(1024) k_iface_sweep_1wg(LK lk, Tables tb, const int32_t* __restrict__ list,
+                                                           const int32_t* __restrict__ coff, int c0, int c1,
+                                                           const T* xi, const T* xf, T* uout, T* umirror,
+                                                           const T* __restrict__ b, double sA,
+                                                           const double* __restrict__ kn) {
+  for (int c = c0; c < c1; ++c) {
+    const int e = coff[c + 1];
+    for (int k = coff[c] + (int)threadIdx.x; k < e; k += (int)blockDim.x)
+      iface_update<D, T, P1>(lk, tb, (int64_t)list[k], xi, xf, uout, umirror, b, 0, 0.0, sA, kn);
+    __syncthreads();
   }
 }
 
@@ -334,55 +395,95 @@ __global__ void __launch_bounds__(256) k_iface_residual(LK lk, Tables tb, const 
 // ------------------------------------------------------------------------------------------
 // Fused Gauss-Seidel sweep over the macro-interior nodes of a 2D level: every interior colour
 // class in one launch (the interface nodes stay fixed during this part of the sweep).  A
-// block owns a TI x TJ core tile and loads it with a halo of C layers into LDS.  Colour pass
+// block owns a core tile of (256 - 2C) columns x TJ rows and loads it with a halo of C layers;
+// one thread per column of the loaded region, so every row load is contiguous.  Colour pass
 // c updates the nodes of colour c at distance >= c+1 from the edge of the loaded region;
-// those values equal what C class-by-class passes over the whole macro produce, because
-// each pass only needs correct values one layer further out.  After C passes the core is
-// exact and is written back; the halo work is redundant.  u is read once (plus halo), b once
-// per update, u written once.
-template <typename T, int C, int TI, int TJ, bool FINE>
-__global__ void __launch_bounds__(256) k_gs2d_fused(LK lk, Tables tb, T* __restrict__ u, const T* __restrict__ b,
-                                                     const int32_t* __restrict__ tiles, int ntiles, int rb, double sA) {
-  constexpr int H = C, RW = TI + 2 * H, RH = TJ + 2 * H, NR = RW * RH;
-  __shared__ T su[NR];
-  const int m = blockIdx.x / ntiles;
-  const int tile = tiles[blockIdx.x - m * ntiles];
-  const int i0 = 1 + (tile & 0xffff) * TI - H, j0 = 1 + (tile >> 16) * TJ - H;
+// those values equal what C class-by-class passes over the whole macro produce, because each
+// pass only needs correct values one layer further out.  After C passes the core is exact
+// and is written back; the halo work is redundant.  u is read once (plus halo), b is held in
+// registers for the column, u is written once.
+template <typename T, int C, int TJ, bool FINE>
+__device__ __forceinline__ void gs2d_subtile(const LK& lk, const T* __restrict__ u, T* __restrict__ uo,
+                                             const T* __restrict__ b, T* su, int m,
+                                             int i0, int j0, int rb, int s1, int s2, T w1, T w2, T w3, T w4, T w5, T w6,
+                                             T inv) {
+  constexpr int H = C, RW = 256, TI = RW - 2 * H, RH = TJ + 2 * H;
   const int n = lk.n;
   const int64_t base = (int64_t)m * lk.S;
-  for (int idx = threadIdx.x; idx < NR; idx += 256) {
-    const int r = idx / RW, q = idx - r * RW;
-    const int i = i0 + q, j = j0 + r;
-    if (i >= 0 && j >= 0 && i + j <= n) su[idx] = u[base + d_lin2(n, i, j)];
+  const int q = threadIdx.x;
+  const int i = i0 + q;
+  T ureg[RH], breg[RH];
+  // branch-free loads (out-of-closure rows read the macro's first entry and are discarded), so
+  // every row load of the column is in flight at once
+  int roff = j0 * (n + 1) - (j0 * (j0 - 1)) / 2;
+#pragma unroll
+  for (int r = 0; r < RH; ++r) {
+    const int j = j0 + r;
+    const bool in = i >= 0 && j >= 0 && i + j <= n;
+    const int64_t g = base + (in ? roff + i : 0);
+    ureg[r] = u[g];
+    breg[r] = b[g];
+    roff += n + 1 - j;
+  }
+#pragma unroll
+  for (int r = 0; r < RH; ++r) {
+    const int j = j0 + r;
+    if (i >= 0 && j >= 0 && i + j <= n) su[r * RW + q] = ureg[r];
   }
   __syncthreads();
+  // colour of (i, j0): red-black parity or (i + 2 j) mod 3; advancing j adds s2 (mod 2) or 2 (mod 3)
+  const int col0 = rb ? ((i * s1 + j0 * s2) & 1) : (((i + 2 * j0) % 3) + 3) % 3;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const bool qok = q >= c + 1 && q <= RW - 2 - c;
+#pragma unroll
+    for (int r = c + 1; r <= RH - 2 - c; ++r) {
+      const int j = j0 + r;
+      const int col = rb ? ((col0 + r * s2) & 1) : (col0 + 2 * r) % 3;
+      if (qok && col == c && i >= 1 && j >= 1 && i + j <= n - 1) {
+        const int x = r * RW + q;
+        const T acc = w1 * su[x + 1] + w2 * su[x + RW] + w3 * su[x + RW - 1] + w4 * su[x - 1] + w5 * su[x - RW] +
+                      w6 * su[x - RW + 1];
+        su[x] = (breg[r] - acc) * inv;
+      }
+    }
+    __syncthreads();
+  }
+  if (q >= H && q < H + TI && i >= 1) {
+    int ro = (j0 + H) * (n + 1) - ((j0 + H) * (j0 + H - 1)) / 2;
+#pragma unroll
+    for (int r = H; r < H + TJ; ++r) {
+      const int j = j0 + r;
+      if (j >= 1 && i + j <= n - 1) uo[base + ro + i] = su[r * RW + q];
+      ro += n + 1 - j;
+    }
+  }
+  __syncthreads();
+}
+
+// tile of (256 - 2C) columns x TJ rows, processed as SUB consecutive sub-tiles of TJ/SUB rows.
+// Reads u, writes the interior of uo: tiles overlap in their halos, so an in-place update
+// would let one tile read rows another tile has already written.
+template <typename T, int C, int TJ, int SUB, bool FINE>
+__global__ void __launch_bounds__(256) k_gs2d_fused(LK lk, Tables tb, const T* __restrict__ u, T* __restrict__ uo,
+                                                     const T* __restrict__ b,
+                                                     const int32_t* __restrict__ tiles, int ntiles, int rb, double sA) {
+  constexpr int H = C, RW = 256, TI = RW - 2 * H, TS = TJ / SUB, RH = TS + 2 * H;
+  __shared__ T su[RH * RW];
+  const int m = blockIdx.x / ntiles;
+  const int tile = tiles[blockIdx.x - m * ntiles];
+  const int i0 = 1 + (tile & 0xffff) * TI - H;
   const double* W = tb.stiff + (size_t)m * kMaxMask * 7;
   const double ks = sA * tb.kappa[m];
   const T w1 = (T)(ks * W[1]), w2 = (T)(ks * W[2]), w3 = (T)(ks * W[3]);
   const T w4 = (T)(ks * W[4]), w5 = (T)(ks * W[5]), w6 = (T)(ks * W[6]);
-  const T dg = (T)(ks * W[0]);
+  const T inv = (T)(1.0 / (ks * W[0]));
   const int s1 = rb ? tb.rbpar[m * 4 + 1] : 0, s2 = rb ? tb.rbpar[m * 4 + 2] : 0;
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
-    for (int idx = threadIdx.x; idx < NR; idx += 256) {
-      const int r = idx / RW, q = idx - r * RW;
-      if (r < c + 1 || r >= RH - 1 - c || q < c + 1 || q >= RW - 1 - c) continue;
-      const int i = i0 + q, j = j0 + r;
-      if (i < 1 || j < 1 || i + j > n - 1) continue;
-      const int col = rb ? ((i * s1 + j * s2) & 1) : (i + 2 * j) % 3;
-      if (col != c) continue;
-      const T acc = w1 * su[idx + 1] + w2 * su[idx + RW] + w3 * su[idx + RW - 1] + w4 * su[idx - 1] +
-                    w5 * su[idx - RW] + w6 * su[idx - RW + 1];
-      su[idx] = (b[base + d_lin2(n, i, j)] - acc) / dg;
-    }
-    __syncthreads();
-  }
-  for (int idx = threadIdx.x; idx < NR; idx += 256) {
-    const int r = idx / RW, q = idx - r * RW;
-    if (r < H || r >= H + TJ || q < H || q >= H + TI) continue;
-    const int i = i0 + q, j = j0 + r;
-    if (i < 1 || j < 1 || i + j > n - 1) continue;
-    u[base + d_lin2(n, i, j)] = su[idx];
+  for (int sub = 0; sub < SUB; ++sub) {
+    const int j0 = 1 + (tile >> 16) * TJ + sub * TS - H;
+    if (j0 + H > lk.n - 2) break;
+    gs2d_subtile<T, C, TS, FINE>(lk, u, uo, b, su, m, i0, j0, rb, s1, s2, w1, w2, w3, w4, w5, w6, inv);
   }
 }
 
@@ -811,13 +912,14 @@ void launch_smooth_interior(int dim, bool p1, const LK& lk, const Tables& tb, co
 }
 
 template <typename T>
-bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, const T* b, const int32_t* tiles, int ntiles,
-                     const uint32_t* itab, int rb, double sA, bool fine, hipStream_t st) {
+bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* uo, const T* b, const int32_t* tiles,
+                     int ntiles, const uint32_t* itab, int rb, double sA, bool fine, hipStream_t st) {
   if (p1 || lk.NI <= 0) return false;
   if (dim == 2) {
     if (ntiles <= 0) return false;
     const unsigned g = (unsigned)(lk.nmacro * ntiles);
-#define HHG_F2(C, F) k_gs2d_fused<T, C, kTileI, kTileJ, F><<<g, 256, 0, st>>>(lk, tb, u, b, tiles, ntiles, rb, sA)
+#define HHG_F2(C, F) \
+  k_gs2d_fused<T, C, kTileJ, sizeof(T) == 8 ? 2 : 1, F><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA)
     if (rb) { if (fine) HHG_F2(2, true); else HHG_F2(2, false); }
     else { if (fine) HHG_F2(3, true); else HHG_F2(3, false); }
 #undef HHG_F2
@@ -835,17 +937,34 @@ bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, con
 }
 
 template <typename T>
-void launch_smooth_iface(int dim, bool p1, const LK& lk, const Tables& tb, const int32_t* list, int count, const T* uin,
-                         T* uout, const T* b, int jacobi, double omega, double sA, const double* kn, hipStream_t st) {
+void launch_smooth_iface(int dim, bool p1, const LK& lk, const Tables& tb, const int32_t* list, int count, const T* xi,
+                         const T* xf, T* uout, T* umirror, const T* b, int jacobi, double omega, double sA,
+                         const double* kn, hipStream_t st) {
   if (count <= 0) return;
   const unsigned g = nblk(count);
+#define HHG_IF(D, P) \
+  k_smooth_iface<D, T, P><<<g, 256, 0, st>>>(lk, tb, list, count, xi, xf, uout, umirror, b, jacobi, omega, sA, kn)
   if (dim == 3) {
-    if (p1) k_smooth_iface<3, T, true><<<g, 256, 0, st>>>(lk, tb, list, count, uin, uout, b, jacobi, omega, sA, kn);
-    else k_smooth_iface<3, T, false><<<g, 256, 0, st>>>(lk, tb, list, count, uin, uout, b, jacobi, omega, sA, kn);
+    if (p1) HHG_IF(3, true); else HHG_IF(3, false);
   } else {
-    if (p1) k_smooth_iface<2, T, true><<<g, 256, 0, st>>>(lk, tb, list, count, uin, uout, b, jacobi, omega, sA, kn);
-    else k_smooth_iface<2, T, false><<<g, 256, 0, st>>>(lk, tb, list, count, uin, uout, b, jacobi, omega, sA, kn);
+    if (p1) HHG_IF(2, true); else HHG_IF(2, false);
   }
+#undef HHG_IF
+}
+
+template <typename T>
+void launch_iface_sweep_1wg(int dim, bool p1, const LK& lk, const Tables& tb, const int32_t* list, const int32_t* coff,
+                            int c0, int c1, const T* xi, const T* xf, T* uout, T* umirror, const T* b, double sA,
+                            const double* kn, hipStream_t st) {
+  if (c1 <= c0) return;
+#define HHG_IW(D, P) \
+  k_iface_sweep_1wg<D, T, P><<<1, 1024, 0, st>>>(lk, tb, list, coff, c0, c1, xi, xf, uout, umirror, b, sA, kn)
+  if (dim == 3) {
+    if (p1) HHG_IW(3, true); else HHG_IW(3, false);
+  } else {
+    if (p1) HHG_IW(2, true); else HHG_IW(2, false);
+  }
+#undef HHG_IW
 }
 
 template <typename Tin, typename Tout>
@@ -978,14 +1097,22 @@ template void launch_smooth_interior<double>(int, bool, const LK&, const Tables&
                                              int, int, int, double, double, const double*, bool, hipStream_t);
 template void launch_smooth_interior<float>(int, bool, const LK&, const Tables&, const float*, float*, const float*, int,
                                             int, int, double, double, const double*, bool, hipStream_t);
-template bool launch_gs_fused<double>(int, bool, const LK&, const Tables&, double*, const double*, const int32_t*, int,
-                                      const uint32_t*, int, double, bool, hipStream_t);
-template bool launch_gs_fused<float>(int, bool, const LK&, const Tables&, float*, const float*, const int32_t*, int,
-                                     const uint32_t*, int, double, bool, hipStream_t);
+template bool launch_gs_fused<double>(int, bool, const LK&, const Tables&, double*, double*, const double*,
+                                      const int32_t*, int, const uint32_t*, int, double, bool, hipStream_t);
+template bool launch_gs_fused<float>(int, bool, const LK&, const Tables&, float*, float*, const float*, const int32_t*,
+                                     int, const uint32_t*, int, double, bool, hipStream_t);
 template void launch_smooth_iface<double>(int, bool, const LK&, const Tables&, const int32_t*, int, const double*,
-                                          double*, const double*, int, double, double, const double*, hipStream_t);
-template void launch_smooth_iface<float>(int, bool, const LK&, const Tables&, const int32_t*, int, const float*, float*,
-                                         const float*, int, double, double, const double*, hipStream_t);
+                                          const double*, double*, double*, const double*, int, double, double,
+                                          const double*, hipStream_t);
+template void launch_smooth_iface<float>(int, bool, const LK&, const Tables&, const int32_t*, int, const float*,
+                                         const float*, float*, float*, const float*, int, double, double, const double*,
+                                         hipStream_t);
+template void launch_iface_sweep_1wg<double>(int, bool, const LK&, const Tables&, const int32_t*, const int32_t*, int,
+                                             int, const double*, const double*, double*, double*, const double*, double,
+                                             const double*, hipStream_t);
+template void launch_iface_sweep_1wg<float>(int, bool, const LK&, const Tables&, const int32_t*, const int32_t*, int, int,
+                                            const float*, const float*, float*, float*, const float*, double,
+                                            const double*, hipStream_t);
 template void launch_apply<double, double>(int, bool, const LK&, const Tables&, const double*, const double*, double*,
                                            int, double, double, double, int, const double*, hipStream_t);
 template void launch_apply<double, float>(int, bool, const LK&, const Tables&, const double*, const double*, float*, int,

@@ -439,6 +439,14 @@ hhg_status build_colouring(hhg_ctx c) {
     }
     int maxc = -1;
     for (int v : col) maxc = std::max(maxc, v);
+    // Dirichlet interface DoFs join the first interface class: their update only rewrites
+    // their own (fixed) value, into both iterate buffers of the out-of-place 2D sweep
+    for (int64_t t = 0; t < lv.nIface; ++t) {
+      int p, co[3];
+      iface_decode(c, lv, t, p, co);
+      if (c->primdir[p]) col[t] = Cint;
+    }
+    maxc = std::max(maxc, lv.nIface > 0 ? Cint : -1);
     lv.interior_colours = Cint;
     lv.ncolours = std::max(Cint, maxc + 1);
     lv.interior_per_colour.assign(Cint, 0);
@@ -453,6 +461,9 @@ hhg_status build_colouring(hhg_ctx c) {
     lv.colour_off.assign(lv.ncolours + 1, 0);
     for (int v : col) if (v >= 0) lv.colour_off[v + 1]++;
     for (int q = 0; q < lv.ncolours; ++q) lv.colour_off[q + 1] += lv.colour_off[q];
+    lv.max_iface_class = 0;
+    for (int q = Cint; q < lv.ncolours; ++q)
+      lv.max_iface_class = std::max(lv.max_iface_class, lv.colour_off[q + 1] - lv.colour_off[q]);
     lv.colour_list.assign(lv.colour_off[lv.ncolours], 0);
     std::vector<int32_t> fill(lv.colour_off.begin(), lv.colour_off.end() - 1);
     for (int64_t t = 0; t < lv.nIface; ++t)
@@ -461,8 +472,9 @@ hhg_status build_colouring(hhg_ctx c) {
     lv.tiles.clear();
     lv.itab.clear();
     if (d == 2 && lv.NI > 0) {
+      const int TI = 256 - 2 * Cint;
       for (int tj = 0; 1 + tj * kTileJ <= lv.n - 2; ++tj)
-        for (int ti = 0; 1 + ti * kTileI + 1 + tj * kTileJ <= lv.n - 1; ++ti) lv.tiles.push_back(ti | (tj << 16));
+        for (int ti = 0; 1 + ti * TI + 1 + tj * kTileJ <= lv.n - 1; ++ti) lv.tiles.push_back(ti | (tj << 16));
     }
     if (d == 3 && lv.NI > 0 && lv.n <= kMacroLdsN) {
       const int n = lv.n;
@@ -599,6 +611,9 @@ void plan_workspace(hhg_ctx c) {
     lv.off_b32 = take(nf * 4);
     lv.off_cl = take((int64_t)lv.colour_list.size() * 4);
     lv.off_tiles = take((int64_t)lv.tiles.size() * 4);
+    lv.off_coff = take((int64_t)lv.colour_off.size() * 4);
+    lv.off_x2 = take(d == 2 ? nf * 8 : 0);
+    lv.off_x2_32 = take(d == 2 ? nf * 4 : 0);
     lv.off_itab = take((int64_t)lv.itab.size() * 4);
   }
   c->ws_bytes = (size_t)off;
