@@ -16,7 +16,9 @@ Parity status per function (what pins it is listed in the tests):
   estimate.*    pinned: brute-force quadrature, affine special case, effectivity bounds
                 (Theorem on eta_j bounds, closed forms reproduced from Tables 1-2)
   adjoint.*     pinned: duality J = g^T u = lambda^T b, finite differences
-  fmg.simulate_mixed   parity unpinned beyond convergence to the float64 fixed point
+  The float32-refined form of the solve has no oracle function: the library's result is
+  compared with the float64 direct solution it converges to (its fixed point); the float32
+  V-cycle inside it is parity unpinned.
 """
 from .refine import Hierarchy, build_hierarchy
 from . import assemble, colour, fmg, estimate, adjoint
