@@ -24,8 +24,8 @@ namespace hhg {
 constexpr int kMaxMask = 16;   // zero-set masks of the barycentric coordinates (bit q: c_q == 0)
 constexpr int kNDir3 = 15, kNDir2 = 7;
 constexpr int kNType3 = 6, kNType2 = 2;
-// fused interior sweeps: 2D core tile of (256 - 2 C) columns x kTileJ rows (C = interior
-// colours), and the largest 3D macro level kept whole in LDS
+// fused interior sweeps: 2D core tile of (64 - 2 C) columns (one wavefront) x kTileJ rows
+// (C = interior colours), and the largest 3D macro level kept whole in LDS
 constexpr int kTileJ = 32;
 constexpr int kMacroLdsN = 32;
 // levels whose largest interface colour class has at most this many DoFs sweep all interface

@@ -393,85 +393,142 @@ __global__ void __launch_bounds__(256) k_iface_residual(LK lk, Tables tb, const 
 }
 
 // ------------------------------------------------------------------------------------------
+// raw buffer access to one macro's block: a wave-uniform descriptor (scalar registers) plus a
+// 32-bit per-lane byte offset, so address arithmetic costs one VGPR per access.  The
+// descriptor's size bounds the access: loads past it return 0 and stores are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t d_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ void d_bload(__amdgpu_buffer_rsrc_t r, uint32_t off, float& v) {
+  v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void d_bload(__amdgpu_buffer_rsrc_t r, uint32_t off, double& v) {
+  v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void d_bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void d_bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v),
+                                        r, off, 0, 0);
+}
+
+// value held by lane q+1 (from_next) or lane q-1 (from_prev) of the wavefront: full-wave DPP
+// shifts (wave_shl:1 / wave_shr:1).  The end lanes get their own value back; callers discard
+// them.
+__device__ __forceinline__ float from_next(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_prev(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_next(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_prev(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
+}
+
 // Fused Gauss-Seidel sweep over the macro-interior nodes of a 2D level: every interior colour
-// class in one launch (the interface nodes stay fixed during this part of the sweep).  A
-// block owns a core tile of (256 - 2C) columns x TJ rows and loads it with a halo of C layers;
-// one thread per column of the loaded region, so every row load is contiguous.  Colour pass
-// c updates the nodes of colour c at distance >= c+1 from the edge of the loaded region;
-// those values equal what C class-by-class passes over the whole macro produce, because each
-// pass only needs correct values one layer further out.  After C passes the core is exact
-// and is written back; the halo work is redundant.  u is read once (plus halo), b is held in
-// registers for the column, u is written once.
-template <typename T, int C, int TJ, bool FINE>
-__device__ __forceinline__ void gs2d_subtile(const LK& lk, const T* __restrict__ u, T* __restrict__ uo,
-                                             const T* __restrict__ b, T* su, int m,
-                                             int i0, int j0, int rb, int s1, int s2, T w1, T w2, T w3, T w4, T w5, T w6,
-                                             T inv) {
-  constexpr int H = C, RW = 256, TI = RW - 2 * H, RH = TJ + 2 * H;
-  const int n = lk.n;
-  const int64_t base = (int64_t)m * lk.S;
-  const int q = threadIdx.x;
+// class in one launch (the interface nodes stay fixed during this part of the sweep).  Each
+// wavefront owns a core tile of (64 - 2C) columns x TS rows and loads it with a halo of C
+// layers, one lane per column, every row of u and b into registers (all loads in flight at
+// once, each row load contiguous).  Colour pass c updates the nodes of colour c at distance
+// >= c+1 from the edge of the loaded region, reading row neighbours from the adjacent lanes
+// through DPP shifts; those values equal what C class-by-class passes over the whole macro
+// produce, because each pass only needs correct values one layer further out.  After C passes
+// the core is exact and is written to uo; the halo work is redundant.  No LDS and no barriers.
+template <typename T, int C, int TS, bool FINE>
+__device__ __forceinline__ void gs2d_wave_tile(int n, __amdgpu_buffer_rsrc_t um, __amdgpu_buffer_rsrc_t uom,
+                                               __amdgpu_buffer_rsrc_t bm, int i0, int j0, int rb, int s1, int s2,
+                                               T w1, T w2, T w3, T w4, T w5, T w6, T inv) {
+  constexpr int H = C, RH = TS + 2 * H;
+  const int q = threadIdx.x & 63;
   const int i = i0 + q;
-  T ureg[RH], breg[RH];
-  // branch-free loads (out-of-closure rows read the macro's first entry and are discarded), so
-  // every row load of the column is in flight at once
+  T ur[RH], br[RH];
+  // branch-free loads: nodes outside the closure read the macro's first entry; no interior
+  // update ever reads them.  um, bm, uom describe this macro's block (wave-uniform), the
+  // per-lane offsets are 32-bit byte offsets.
   int roff = j0 * (n + 1) - (j0 * (j0 - 1)) / 2;
 #pragma unroll
   for (int r = 0; r < RH; ++r) {
     const int j = j0 + r;
     const bool in = i >= 0 && j >= 0 && i + j <= n;
-    const int64_t g = base + (in ? roff + i : 0);
-    ureg[r] = u[g];
-    breg[r] = b[g];
+    // unsigned 32-bit byte offset from the wave-uniform base: scalar-base + vector-offset loads
+    const uint32_t g = in ? (uint32_t)(roff + i) * (uint32_t)sizeof(T) : 0u;
+    d_bload(um, g, ur[r]);
+    d_bload(bm, g, br[r]);
     roff += n + 1 - j;
   }
-#pragma unroll
-  for (int r = 0; r < RH; ++r) {
-    const int j = j0 + r;
-    if (i >= 0 && j >= 0 && i + j <= n) su[r * RW + q] = ureg[r];
-  }
-  __syncthreads();
-  // colour of (i, j0): red-black parity or (i + 2 j) mod 3; advancing j adds s2 (mod 2) or 2 (mod 3)
+  // colour of (i, j0): red-black parity or (i + 2 j) mod 3.  Row r has colour col0 + r s2
+  // (mod 2) or col0 + 2 r (mod 3); with r and c compile-time constants the colour test is one
+  // compare.  The update is a select, so every lane stays active for the DPP shifts.
   const int col0 = rb ? ((i * s1 + j0 * s2) & 1) : (((i + 2 * j0) % 3) + 3) % 3;
+  // node (i, j0 + r) is interior iff rlo <= r <= rhi
+  const int rhi = n - 1 - j0 - i, rlo = 1 - j0;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    const bool qok = q >= c + 1 && q <= RW - 2 - c;
+    const bool lok = q >= c + 1 && q <= 62 - c && i >= 1;
+    // re-materialise the per-lane bounds in each pass so the per-row compares are made where
+    // they are used instead of being hoisted (and held) for every row at once
+    int cl = col0, hi = rhi, lo = rlo;
+    asm volatile("" : "+v"(cl), "+v"(hi), "+v"(lo));
+    // neighbours from the adjacent lanes: from_next(row r) is the (i+1, j) value for row r and
+    // the (i+1, j-1) value for row r+1; from_prev(row r+1) is the (i-1, j+1) value for row r and
+    // the (i-1, j) value for row r+1.  Nodes of colour c never neighbour each other, so the
+    // shifts taken before a row's update stay valid for the next row.
+    T nx_dn = from_next(ur[c]);
+    T pv_r = from_prev(ur[c + 1]);
 #pragma unroll
     for (int r = c + 1; r <= RH - 2 - c; ++r) {
-      const int j = j0 + r;
-      const int col = rb ? ((col0 + r * s2) & 1) : (col0 + 2 * r) % 3;
-      if (qok && col == c && i >= 1 && j >= 1 && i + j <= n - 1) {
-        const int x = r * RW + q;
-        const T acc = w1 * su[x + 1] + w2 * su[x + RW] + w3 * su[x + RW - 1] + w4 * su[x - 1] + w5 * su[x - RW] +
-                      w6 * su[x - RW + 1];
-        su[x] = (breg[r] - acc) * inv;
-      }
+      const T nx_r = from_next(ur[r]);
+      const T pv_up = from_prev(ur[r + 1]);
+      const T acc = w1 * nx_r + w2 * ur[r + 1] + w3 * pv_up + w4 * pv_r + w5 * ur[r - 1] + w6 * nx_dn;
+      const T v = (br[r] - acc) * inv;
+      bool act;
+      if (rb) act = ((cl ^ ((r & 1) & s2)) == c);
+      else act = (cl == ((c - 2 * r) % 3 + 3) % 3);
+      act = act && lok && (r >= lo) && (r <= hi);
+      ur[r] = act ? v : ur[r];
+      nx_dn = nx_r;
+      pv_r = pv_up;
     }
-    __syncthreads();
   }
-  if (q >= H && q < H + TI && i >= 1) {
+  if (q >= H && q < 64 - H && i >= 1) {
     int ro = (j0 + H) * (n + 1) - ((j0 + H) * (j0 + H - 1)) / 2;
 #pragma unroll
-    for (int r = H; r < H + TJ; ++r) {
+    for (int r = H; r < H + TS; ++r) {
       const int j = j0 + r;
-      if (j >= 1 && i + j <= n - 1) uo[base + ro + i] = su[r * RW + q];
+      if (j >= 1 && i + j <= n - 1)
+        d_bstore(uom, (uint32_t)(ro + i) * (uint32_t)sizeof(T), ur[r]);
       ro += n + 1 - j;
     }
   }
-  __syncthreads();
 }
 
-// tile of (256 - 2C) columns x TJ rows, processed as SUB consecutive sub-tiles of TJ/SUB rows.
-// Reads u, writes the interior of uo: tiles overlap in their halos, so an in-place update
-// would let one tile read rows another tile has already written.
+// one wavefront per tile of (64 - 2C) columns x TJ rows, processed as SUB consecutive
+// sub-tiles of TJ/SUB rows.  Reads u, writes the interior of uo: tiles overlap in their
+// halos, so an in-place update would let one tile read rows another tile has already
+// written.  Blocks are spread over the XCDs in contiguous runs of tiles (block b runs on
+// XCD b mod 8), so neighbouring tiles share their halo rows in one L2.
 template <typename T, int C, int TJ, int SUB, bool FINE>
 __global__ void __launch_bounds__(256) k_gs2d_fused(LK lk, Tables tb, const T* __restrict__ u, T* __restrict__ uo,
                                                      const T* __restrict__ b,
                                                      const int32_t* __restrict__ tiles, int ntiles, int rb, double sA) {
-  constexpr int H = C, RW = 256, TI = RW - 2 * H, TS = TJ / SUB, RH = TS + 2 * H;
-  __shared__ T su[RH * RW];
-  const int m = blockIdx.x / ntiles;
-  const int tile = tiles[blockIdx.x - m * ntiles];
+  constexpr int H = C, TI = 64 - 2 * H, TS = TJ / SUB;
+  const int per_xcd = (int)(gridDim.x >> 3);   // gridDim.x is a multiple of 8
+  const int blk = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  // tile, macro and tile origin are uniform over the wavefront: keep them in scalar registers
+  const int gt = __builtin_amdgcn_readfirstlane(blk * 4 + (int)(threadIdx.x >> 6));
+  if (gt >= lk.nmacro * ntiles) return;
+  const int m = gt / ntiles;
+  const int tile = __builtin_amdgcn_readfirstlane(tiles[gt - m * ntiles]);
+  const int64_t base = (int64_t)m * lk.S;
+  const uint32_t bytes = (uint32_t)lk.Sraw * (uint32_t)sizeof(T);
   const int i0 = 1 + (tile & 0xffff) * TI - H;
   const double* W = tb.stiff + (size_t)m * kMaxMask * 7;
   const double ks = sA * tb.kappa[m];
@@ -483,7 +540,8 @@ __global__ void __launch_bounds__(256) k_gs2d_fused(LK lk, Tables tb, const T* _
   for (int sub = 0; sub < SUB; ++sub) {
     const int j0 = 1 + (tile >> 16) * TJ + sub * TS - H;
     if (j0 + H > lk.n - 2) break;
-    gs2d_subtile<T, C, TS, FINE>(lk, u, uo, b, su, m, i0, j0, rb, s1, s2, w1, w2, w3, w4, w5, w6, inv);
+    gs2d_wave_tile<T, C, TS, FINE>(lk.n, d_rsrc(u + base, bytes), d_rsrc(uo + base, bytes), d_rsrc(b + base, bytes), i0,
+                                   j0, rb, s1, s2, w1, w2, w3, w4, w5, w6, inv);
   }
 }
 
@@ -917,7 +975,7 @@ bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* 
   if (p1 || lk.NI <= 0) return false;
   if (dim == 2) {
     if (ntiles <= 0) return false;
-    const unsigned g = (unsigned)(lk.nmacro * ntiles);
+    const unsigned g = (unsigned)(((int64_t)lk.nmacro * ntiles + 31) / 32 * 8);   // 4 tiles per block, 8 XCDs
 #define HHG_F2(C, F) \
   k_gs2d_fused<T, C, kTileJ, sizeof(T) == 8 ? 2 : 1, F><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA)
     if (rb) { if (fine) HHG_F2(2, true); else HHG_F2(2, false); }

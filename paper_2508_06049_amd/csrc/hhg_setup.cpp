@@ -472,7 +472,7 @@ hhg_status build_colouring(hhg_ctx c) {
     lv.tiles.clear();
     lv.itab.clear();
     if (d == 2 && lv.NI > 0) {
-      const int TI = 256 - 2 * Cint;
+      const int TI = 64 - 2 * Cint;   // one wavefront per tile of the fused sweep
       for (int tj = 0; 1 + tj * kTileJ <= lv.n - 2; ++tj)
         for (int ti = 0; 1 + ti * TI + 1 + tj * kTileJ <= lv.n - 1; ++ti) lv.tiles.push_back(ti | (tj << 16));
     }
