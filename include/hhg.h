@@ -76,10 +76,13 @@ typedef struct {
   double jacobi_omega;        /* damping of the Jacobi smoother (0 selects 2/3)                */
   int flags;                  /* HHG_FLAG_NO_FUSED: sweep macro interiors one colour class per
                                  launch instead of all classes in one launch (same result up to
-                                 rounding; for checking the fused kernels)                    */
+                                 rounding; for checking the fused kernels).
+                                 HHG_FLAG_NO_LANE_IFACE: update interface DoFs one thread per
+                                 DoF instead of one lane per (DoF, macro) pair (same result up
+                                 to rounding; for checking the lane-parallel kernels)         */
 } hhg_options;
 
-enum { HHG_FLAG_NO_FUSED = 1 };
+enum { HHG_FLAG_NO_FUSED = 1, HHG_FLAG_NO_LANE_IFACE = 2 };
 
 typedef struct {
   int nu;                     /* V-cycles per FMG level (Algorithm 4's nu)                     */

@@ -22,6 +22,7 @@ HHG_GS_REDBLACK, HHG_GS_MULTICOLOR, HHG_JACOBI = 0, 1, 2
 HHG_FP64, HHG_FP32_REFINED = 0, 1
 HHG_OP_STIFFNESS, HHG_OP_MASS = 0, 1
 HHG_FLAG_NO_FUSED = 1
+HHG_FLAG_NO_LANE_IFACE = 2
 
 SMOOTHERS = {"redblack": HHG_GS_REDBLACK, "multicolour": HHG_GS_MULTICOLOR, "jacobi": HHG_JACOBI}
 PRECISIONS = {"fp64": HHG_FP64, "fp32_refined": HHG_FP32_REFINED}

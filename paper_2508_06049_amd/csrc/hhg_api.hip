@@ -155,7 +155,18 @@ hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
     else
       for (int col = 0; col < lv.interior_colours; ++col) interior_launch<T>(c, l, k, x, x, b, col, rb, 0);
     T* mir = twobuf ? x : (T*)nullptr;
-    if (lv.max_iface_class <= kIfaceOneGroup) {
+    if (lv.task_ok && !c->no_tasks) {
+      if (lv.max_class_waves <= kTaskOneGroupWaves) {
+        launch_iface_tasks_1wg<T>(c->dim, k, c->tab, lv.d_task_p, lv.d_task_q, lv.d_task_co, lv.d_task_seg,
+                                  lv.d_task_wmax, lv.d_task_woff, lv.interior_colours, lv.ncolours, y, x, y, mir, b,
+                                  sA(c, l), ST(c));
+      } else {
+        for (int col = lv.interior_colours; col < lv.ncolours; ++col)
+          launch_iface_tasks<T>(c->dim, k, c->tab, lv.d_task_p, lv.d_task_q, lv.d_task_co, lv.d_task_seg,
+                                lv.d_task_wmax, lv.task_woff[col], lv.task_woff[col + 1], y, x, y, mir, b, 0, 0.0,
+                                sA(c, l), ST(c));
+      }
+    } else if (lv.max_iface_class <= kIfaceOneGroup) {
       launch_iface_sweep_1wg<T>(c->dim, p1(c), k, c->tab, lv.d_colour_list, lv.d_colour_off, lv.interior_colours,
                                 lv.ncolours, y, x, y, mir, b, sA(c, l), lv.kn, ST(c));
     } else {
@@ -386,6 +397,7 @@ hhg_status hhg_setup(const hhg_mesh* mesh, int L, const hhg_options* opt, hhg_ct
   c->L = L;
   c->opt = *opt;
   c->no_fused = (opt->flags & HHG_FLAG_NO_FUSED) != 0;
+  c->no_tasks = (opt->flags & HHG_FLAG_NO_LANE_IFACE) != 0;
   c->nV = mesh->n_vertices;
   c->nC = mesh->n_cells;
   const int nv = c->dim + 1;
@@ -503,6 +515,18 @@ hhg_status hhg_bind_workspace(hhg_ctx c, void* ptr, size_t bytes, void* stream) 
     lv.b32 = (float*)(w + lv.off_b32);
     lv.d_colour_list = (int32_t*)(w + lv.off_cl);
     HIPCHK(up(lv.off_cl, lv.colour_list.data(), lv.colour_list.size() * 4));
+    lv.d_task_p = (int32_t*)(w + lv.off_tp);
+    HIPCHK(up(lv.off_tp, lv.task_p.data(), lv.task_p.size() * 4));
+    lv.d_task_q = (int32_t*)(w + lv.off_tq);
+    HIPCHK(up(lv.off_tq, lv.task_q.data(), lv.task_q.size() * 4));
+    lv.d_task_co = (int32_t*)(w + lv.off_tco);
+    HIPCHK(up(lv.off_tco, lv.task_co.data(), lv.task_co.size() * 4));
+    lv.d_task_seg = (int32_t*)(w + lv.off_tseg);
+    HIPCHK(up(lv.off_tseg, lv.task_seg.data(), lv.task_seg.size() * 4));
+    lv.d_task_wmax = (int32_t*)(w + lv.off_twmax);
+    HIPCHK(up(lv.off_twmax, lv.task_wmax.data(), lv.task_wmax.size() * 4));
+    lv.d_task_woff = (int32_t*)(w + lv.off_twoff);
+    HIPCHK(up(lv.off_twoff, lv.task_woff.data(), lv.task_woff.size() * 4));
     lv.d_colour_off = (int32_t*)(w + lv.off_coff);
     HIPCHK(up(lv.off_coff, lv.colour_off.data(), lv.colour_off.size() * 4));
     lv.d_tiles = (int32_t*)(w + lv.off_tiles);

@@ -31,6 +31,9 @@ constexpr int kMacroLdsN = 32;
 // levels whose largest interface colour class has at most this many DoFs sweep all interface
 // classes in one single-workgroup launch
 constexpr int kIfaceOneGroup = 4096;
+// lane-parallel interface sweeps: levels whose largest class spans at most this many
+// wavefronts sweep all classes in one workgroup of 16 wavefronts
+constexpr int kTaskOneGroupWaves = 32;
 
 // direction tables: index 0 is the centre, 1..H positive, H+1..2H negative
 constexpr int kDir3[7][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {-1, 1, 0}, {-1, 0, 1}, {0, -1, 1}, {1, -1, 1}};
@@ -88,6 +91,15 @@ struct Level {
   int32_t* d_colour_list = nullptr;
   int32_t* d_colour_off = nullptr;
   int max_iface_class = 0;
+  // lane-parallel interface sweep (Gauss-Seidel, per-macro coefficient): one lane per
+  // (interface DoF, incident macro), lanes of one DoF consecutive in a wavefront; arrays of
+  // 64 entries per wavefront, wavefronts of class c are task_woff[c] .. task_woff[c+1]-1
+  bool task_ok = false;
+  std::vector<int32_t> task_p, task_q, task_co, task_seg, task_wmax, task_woff;
+  int max_class_waves = 0;
+  int32_t *d_task_p = nullptr, *d_task_q = nullptr, *d_task_co = nullptr, *d_task_seg = nullptr,
+          *d_task_wmax = nullptr, *d_task_woff = nullptr;
+  int64_t off_tp = 0, off_tq = 0, off_tco = 0, off_tseg = 0, off_twmax = 0, off_twoff = 0;
   std::vector<int32_t> tiles;          // 2D: interior tiles (ti | tj << 16) of the fused sweep
   std::vector<uint32_t> itab;          // 3D, n <= kMacroLdsN: interior points (i | j << 10 | k << 20)
   int32_t* d_tiles = nullptr;
@@ -163,6 +175,7 @@ struct hhg_ctx_s {
   int prof_used = 0;
   bool prof_on = false;
   bool no_fused = false;            // force class-by-class interior launches (testing)
+  bool no_tasks = false;            // force the per-DoF interface kernels (testing)
   double prof_bytes = 0.0;
 
   std::string err;

@@ -27,6 +27,16 @@ bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* 
                      int ntiles, const uint32_t* itab, int rb, double sA, bool fine, hipStream_t st);
 // interface update of one colour class (xi: source of interior neighbours, xf: of interface
 // neighbours; umirror, if not NULL, receives the new values too)
+// lane-parallel interface update of the wavefronts w0..w1-1 (one colour class), or of all
+// classes c0..c1-1 in one workgroup
+template <typename T>
+void launch_iface_tasks(int dim, const LK& lk, const Tables& tb, const int32_t* tp, const int32_t* tq, const int32_t* tco,
+                        const int32_t* tseg, const int32_t* wmax, int w0, int w1, const T* xi, const T* xf, T* uout,
+                        T* umirror, const T* b, int jacobi, double omega, double sA, hipStream_t st);
+template <typename T>
+void launch_iface_tasks_1wg(int dim, const LK& lk, const Tables& tb, const int32_t* tp, const int32_t* tq,
+                            const int32_t* tco, const int32_t* tseg, const int32_t* wmax, const int32_t* woff, int c0,
+                            int c1, const T* xi, const T* xf, T* uout, T* umirror, const T* b, double sA, hipStream_t st);
 template <typename T>
 void launch_smooth_iface(int dim, bool p1, const LK& lk, const Tables& tb, const int32_t* list, int count, const T* xi,
                          const T* xf, T* uout, T* umirror, const T* b, int jacobi, double omega, double sA,

@@ -351,6 +351,108 @@ __global__ void __launch_bounds__(1024) k_iface_sweep_1wg(LK lk, Tables tb, cons
   }
 }
 
+// Lane-parallel interface update: one lane per (interface DoF, incident macro) pair, the lanes
+// of one DoF consecutive inside a wavefront (a segment).  Each lane computes its macro's
+// partial row (right-hand side, off-diagonal sum, diagonal) from the copy's closure
+// neighbours; every lane of a segment then sums the segment's partials in the same order
+// through lane shuffles, so all copies receive bitwise the same new value, which each lane
+// writes to its own copy.  The global loads of a DoF do not depend on one another, so the
+// update costs one table load and one gather round trip whatever the number of copies.
+// Task fields per lane: primitive p (-1 = padding lane), incidence q, coordinates along the
+// primitive's sorted vertices (co1 | co2 << 16; co0 = n - co1 - co2, a vertex has co = (n)),
+// segment (first lane | length << 8).  wmax[w]: longest segment of wavefront w.
+template <int D, typename T>
+__device__ __forceinline__ void iface_task_wave(const LK& lk, const Tables& tb, const int32_t* __restrict__ tp,
+                                                const int32_t* __restrict__ tq, const int32_t* __restrict__ tco,
+                                                const int32_t* __restrict__ tseg, int wmax, int w, const T* xi,
+                                                const T* xf, T* uout, T* umirror, const T* __restrict__ b, int jacobi,
+                                                double omega, double sA) {
+  const int lane = threadIdx.x & 63;
+  const int idx = w * 64 + lane;
+  const int p = tp[idx];
+  T rhs = (T)0, off = (T)0, diag = (T)0, uold = (T)0;
+  int64_t ix = 0;
+  bool dir = false;
+  if (p >= 0) {
+    const int q = tq[idx], cw = tco[idx];
+    const int np = p < tb.nV ? 1 : (p < tb.nV + tb.nE ? 2 : 3);
+    int co[3];
+    co[1] = cw & 0xffff;
+    co[2] = cw >> 16;
+    co[0] = np == 1 ? lk.n : lk.n - co[1] - co[2];
+    dir = tb.primdir[p] != 0;
+    const Inc in = tb.inc[q];
+    int lc[4] = {0, 0, 0, 0};
+    for (int r = 0; r < np; ++r) lc[in.slot[r]] = co[r];
+    const int i = lc[1], j = lc[2], k = lc[3];
+    const int64_t base = (int64_t)in.macro * lk.S;
+    ix = base + d_lin<D>(lk.n, i, j, k);
+    uold = xf[ix];
+    if (!dir) {
+      rhs = b[ix];
+      const double* W = tb.stiff + ((size_t)in.macro * kMaxMask + in.mask) * ndir<D>();
+      const uint32_t valid = tb.validdirs[in.mask];
+      const double scale = sA * tb.kappa[in.macro];
+#pragma unroll
+      for (int dd = 1; dd < ndir<D>(); ++dd) {
+        if (!((valid >> dd) & 1)) continue;
+        int a, b2, c;
+        d_off<D>(dd, a, b2, c);
+        const int i2 = i + a, j2 = j + b2, k2 = k + c;
+        off += (T)(scale * W[dd]) * (d_mask<D>(lk.n, i2, j2, k2) ? xf : xi)[base + d_lin<D>(lk.n, i2, j2, k2)];
+      }
+      diag = (T)(scale * W[0]);
+    }
+  }
+  // segment sums; every lane of the wavefront takes part in every shuffle
+  const int seg = tseg[idx];
+  const int lead = seg & 63, len = seg >> 8;
+  T srhs = (T)0, soff = (T)0, sdiag = (T)0;
+  for (int k = 0; k < wmax; ++k) {
+    const int src = min(lead + k, 63);
+    const T a = __shfl(rhs, src, 64), o = __shfl(off, src, 64), d = __shfl(diag, src, 64);
+    if (k < len) { srhs += a; soff += o; sdiag += d; }
+  }
+  if (p < 0) return;
+  T unew;
+  if (dir) unew = uold;
+  else if (jacobi) unew = uold + (T)omega * (srhs - soff - sdiag * uold) / sdiag;
+  else unew = (srhs - soff) / sdiag;
+  uout[ix] = unew;
+  if (umirror) umirror[ix] = unew;
+}
+
+// one interface colour class: wavefronts w0 .. w1-1, four per block
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_iface_tasks(LK lk, Tables tb, const int32_t* __restrict__ tp,
+                                                      const int32_t* __restrict__ tq, const int32_t* __restrict__ tco,
+                                                      const int32_t* __restrict__ tseg, const int32_t* __restrict__ wmax,
+                                                      int w0, int w1, const T* xi, const T* xf, T* uout, T* umirror,
+                                                      const T* __restrict__ b, int jacobi, double omega, double sA) {
+  const int w = __builtin_amdgcn_readfirstlane(w0 + (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+  if (w >= w1) return;
+  iface_task_wave<D, T>(lk, tb, tp, tq, tco, tseg, wmax[w], w, xi, xf, uout, umirror, b, jacobi, omega, sA);
+}
+
+// every interface class c0..c1-1 of one sweep in one workgroup of 16 wavefronts (small
+// levels), classes separated by barriers; woff[c] is the first wavefront of class c
+template <int D, typename T>
+__global__ void __launch_bounds__(1024) k_iface_tasks_1wg(LK lk, Tables tb, const int32_t* __restrict__ tp,
+                                                           const int32_t* __restrict__ tq, const int32_t* __restrict__ tco,
+                                                           const int32_t* __restrict__ tseg,
+                                                           const int32_t* __restrict__ wmax,
+                                                           const int32_t* __restrict__ woff, int c0, int c1, const T* xi,
+                                                           const T* xf, T* uout, T* umirror, const T* __restrict__ b,
+                                                           double sA) {
+  const int wave = (int)(threadIdx.x >> 6);
+  for (int c = c0; c < c1; ++c) {
+    const int e = woff[c + 1];
+    for (int w = woff[c] + wave; w < e; w += 16)
+      iface_task_wave<D, T>(lk, tb, tp, tq, tco, tseg, wmax[w], w, xi, xf, uout, umirror, b, 0, 0.0, sA);
+    __syncthreads();
+  }
+}
+
 // Assembled residual rows at interface DoFs: r = sum_m (b_m - A_m x) in Tin precision, stored
 // in the lowest-id copy (other copies 0, Dirichlet DoFs 0).  Used when a float64 residual is
 // handed to float32 cycles: the per-macro partial rows are one-sided differences that cancel
@@ -995,6 +1097,34 @@ bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* 
 }
 
 template <typename T>
+void launch_iface_tasks(int dim, const LK& lk, const Tables& tb, const int32_t* tp, const int32_t* tq, const int32_t* tco,
+                        const int32_t* tseg, const int32_t* wmax, int w0, int w1, const T* xi, const T* xf, T* uout,
+                        T* umirror, const T* b, int jacobi, double omega, double sA, hipStream_t st) {
+  if (w1 <= w0) return;
+  const unsigned g = (unsigned)((w1 - w0 + 3) / 4);
+  if (dim == 3)
+    k_iface_tasks<3, T><<<g, 256, 0, st>>>(lk, tb, tp, tq, tco, tseg, wmax, w0, w1, xi, xf, uout, umirror, b, jacobi,
+                                           omega, sA);
+  else
+    k_iface_tasks<2, T><<<g, 256, 0, st>>>(lk, tb, tp, tq, tco, tseg, wmax, w0, w1, xi, xf, uout, umirror, b, jacobi,
+                                           omega, sA);
+}
+
+template <typename T>
+void launch_iface_tasks_1wg(int dim, const LK& lk, const Tables& tb, const int32_t* tp, const int32_t* tq,
+                            const int32_t* tco, const int32_t* tseg, const int32_t* wmax, const int32_t* woff, int c0,
+                            int c1, const T* xi, const T* xf, T* uout, T* umirror, const T* b, double sA,
+                            hipStream_t st) {
+  if (c1 <= c0) return;
+  if (dim == 3)
+    k_iface_tasks_1wg<3, T><<<1, 1024, 0, st>>>(lk, tb, tp, tq, tco, tseg, wmax, woff, c0, c1, xi, xf, uout, umirror, b,
+                                                sA);
+  else
+    k_iface_tasks_1wg<2, T><<<1, 1024, 0, st>>>(lk, tb, tp, tq, tco, tseg, wmax, woff, c0, c1, xi, xf, uout, umirror, b,
+                                                sA);
+}
+
+template <typename T>
 void launch_smooth_iface(int dim, bool p1, const LK& lk, const Tables& tb, const int32_t* list, int count, const T* xi,
                          const T* xf, T* uout, T* umirror, const T* b, int jacobi, double omega, double sA,
                          const double* kn, hipStream_t st) {
@@ -1159,6 +1289,20 @@ template bool launch_gs_fused<double>(int, bool, const LK&, const Tables&, doubl
                                       const int32_t*, int, const uint32_t*, int, double, bool, hipStream_t);
 template bool launch_gs_fused<float>(int, bool, const LK&, const Tables&, float*, float*, const float*, const int32_t*,
                                      int, const uint32_t*, int, double, bool, hipStream_t);
+template void launch_iface_tasks<double>(int, const LK&, const Tables&, const int32_t*, const int32_t*, const int32_t*,
+                                         const int32_t*, const int32_t*, int, int, const double*, const double*, double*,
+                                         double*, const double*, int, double, double, hipStream_t);
+template void launch_iface_tasks<float>(int, const LK&, const Tables&, const int32_t*, const int32_t*, const int32_t*,
+                                        const int32_t*, const int32_t*, int, int, const float*, const float*, float*,
+                                        float*, const float*, int, double, double, hipStream_t);
+template void launch_iface_tasks_1wg<double>(int, const LK&, const Tables&, const int32_t*, const int32_t*,
+                                             const int32_t*, const int32_t*, const int32_t*, const int32_t*, int, int,
+                                             const double*, const double*, double*, double*, const double*, double,
+                                             hipStream_t);
+template void launch_iface_tasks_1wg<float>(int, const LK&, const Tables&, const int32_t*, const int32_t*,
+                                            const int32_t*, const int32_t*, const int32_t*, const int32_t*, int, int,
+                                            const float*, const float*, float*, float*, const float*, double,
+                                            hipStream_t);
 template void launch_smooth_iface<double>(int, bool, const LK&, const Tables&, const int32_t*, int, const double*,
                                           const double*, double*, double*, const double*, int, double, double,
                                           const double*, hipStream_t);

@@ -468,6 +468,51 @@ hhg_status build_colouring(hhg_ctx c) {
     std::vector<int32_t> fill(lv.colour_off.begin(), lv.colour_off.end() - 1);
     for (int64_t t = 0; t < lv.nIface; ++t)
       if (col[t] >= 0) lv.colour_list[fill[col[t]]++] = (int32_t)t;
+    // lane-parallel interface tasks (Gauss-Seidel with a per-macro coefficient): every
+    // non-empty interface class packed into wavefronts, a DoF's lanes never split
+    lv.task_ok = false;
+    lv.task_p.clear(); lv.task_q.clear(); lv.task_co.clear(); lv.task_seg.clear(); lv.task_wmax.clear();
+    lv.task_woff.assign(lv.ncolours + 1, 0);
+    lv.max_class_waves = 0;
+    if (c->opt.smoother != HHG_JACOBI && c->opt.coefficient == HHG_KAPPA_MACRO) {
+      bool ok = true;
+      auto pad_wave = [&]() {
+        while (lv.task_p.size() % 64) {
+          lv.task_p.push_back(-1); lv.task_q.push_back(0); lv.task_co.push_back(0); lv.task_seg.push_back(0);
+        }
+      };
+      for (int cc = 0; cc < lv.ncolours && ok; ++cc) {
+        lv.task_woff[cc] = (int32_t)(lv.task_p.size() / 64);
+        for (int32_t k = lv.colour_off[cc]; k < lv.colour_off[cc + 1]; ++k) {
+          int p, co[3];
+          iface_decode(c, lv, lv.colour_list[k], p, co);
+          const int q0 = c->inc_off[p], q1 = c->inc_off[p + 1], cnt = q1 - q0;
+          if (cnt < 1 || cnt > 64 || co[1] > 0xffff || co[2] > 0x7fff) { ok = false; break; }
+          if (lv.task_p.size() % 64 + cnt > 64) pad_wave();
+          const int lead = (int)(lv.task_p.size() % 64);
+          for (int q = q0; q < q1; ++q) {
+            lv.task_p.push_back(p);
+            lv.task_q.push_back(q);
+            lv.task_co.push_back(co[1] | (co[2] << 16));
+            lv.task_seg.push_back(lead | (cnt << 8));
+          }
+        }
+        pad_wave();
+      }
+      if (ok) {
+        lv.task_woff[lv.ncolours] = (int32_t)(lv.task_p.size() / 64);
+        const int nw = lv.task_woff[lv.ncolours];
+        lv.task_wmax.assign(nw, 0);
+        for (int w = 0; w < nw; ++w)
+          for (int q = 0; q < 64; ++q) lv.task_wmax[w] = std::max(lv.task_wmax[w], lv.task_seg[w * 64 + q] >> 8);
+        for (int cc = Cint; cc < lv.ncolours; ++cc)
+          lv.max_class_waves = std::max(lv.max_class_waves, lv.task_woff[cc + 1] - lv.task_woff[cc]);
+        lv.task_ok = true;
+      } else {
+        lv.task_p.clear(); lv.task_q.clear(); lv.task_co.clear(); lv.task_seg.clear();
+        lv.task_woff.assign(lv.ncolours + 1, 0);
+      }
+    }
     // tables of the fused interior sweeps
     lv.tiles.clear();
     lv.itab.clear();
@@ -612,6 +657,12 @@ void plan_workspace(hhg_ctx c) {
     lv.off_cl = take((int64_t)lv.colour_list.size() * 4);
     lv.off_tiles = take((int64_t)lv.tiles.size() * 4);
     lv.off_coff = take((int64_t)lv.colour_off.size() * 4);
+    lv.off_tp = take((int64_t)lv.task_p.size() * 4);
+    lv.off_tq = take((int64_t)lv.task_q.size() * 4);
+    lv.off_tco = take((int64_t)lv.task_co.size() * 4);
+    lv.off_tseg = take((int64_t)lv.task_seg.size() * 4);
+    lv.off_twmax = take((int64_t)lv.task_wmax.size() * 4);
+    lv.off_twoff = take((int64_t)lv.task_woff.size() * 4);
     lv.off_x2 = take(d == 2 ? nf * 8 : 0);
     lv.off_x2_32 = take(d == 2 ? nf * 4 : 0);
     lv.off_itab = take((int64_t)lv.itab.size() * 4);

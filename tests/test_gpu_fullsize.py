@@ -45,6 +45,33 @@ def test_fused_sweep_equals_class_by_class_full_size(lshape):
     assert rel_err(ra, to_host(ub)) < 1e-12
 
 
+@pytest.mark.parametrize("L", [5, 9])
+def test_lane_parallel_interface_equals_per_dof(lshape, L):
+    # the lane-parallel interface sweep (one lane per DoF copy, segment sums by shuffles)
+    # against the one-thread-per-DoF kernels on the workload mesh: L = 5 sweeps all classes in
+    # one workgroup, L = 9 launches one grid per class
+    import torch
+    from paper_2508_06049_amd import HHG
+    from paper_2508_06049_amd._lib import HHG_FLAG_NO_LANE_IFACE
+    w = lshape
+    _note("lane-parallel vs per-DoF interface", w.name, L)
+    a = HHG(w.mesh.coords, w.mesh.cells, L, smoother=w.smoother)
+    X = a.dof_coords().cpu().numpy()
+    rng = np.random.default_rng(1)
+    u0 = rng.standard_normal(len(X))
+    b = rng.standard_normal(len(X))
+    ua = to_dev(u0)
+    a.smooth(L, ua, to_dev(b), 3)
+    ra = to_host(ua)
+    a.close()
+    del a
+    torch.cuda.synchronize()
+    bb = HHG(w.mesh.coords, w.mesh.cells, L, smoother=w.smoother, flags=HHG_FLAG_NO_LANE_IFACE)
+    ub = to_dev(u0)
+    bb.smooth(L, ub, to_dev(b), 3)
+    assert rel_err(ra, to_host(ub)) < 1e-12
+
+
 def test_lshape_workload_mesh_parity_at_L7(lshape):
     from oracle import fmg
     from paper_2508_06049_amd import HHG
