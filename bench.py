@@ -32,9 +32,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 1 << 30          # plain copy used to scale the HBM byte counters
+# HBM bytes per launch of the finest-level float32 sweep on the L-shape workload (L = 9), from
+# FETCH_SIZE and WRITE_SIZE counter runs of `bench.py --kernel-only`, each scaled by the same
+# counter's reading for a 1 GiB device copy (fetch x2.000, write x1.000); valid for the kernel
+# as committed with profiles/k_gs2d_fused_lshape_L9_traffic.md, else reported as null
+TRAFFIC_BYTES = {("lshape_corner", 9, "k_gs2d_fused<float, 3, 30, 1, true>"): 228.3e6}
 # the finest-level interior smoother kernel per workload type (float32 sweeps)
 KERNEL_NAME = {
-    (2, "multicolour", "macro"): "k_gs2d_fused<float, 3, 32, 1, true>",
+    (2, "multicolour", "macro"): "k_gs2d_fused<float, 3, 30, 1, true>",
     (2, "redblack", "macro"): "k_gs2d_fused<float, 2, 32, 1, true>",
     (3, "multicolour", "macro"): "k_gs3d_macro<float, 4, true>",
     (3, "redblack", "macro"): "k_gs3d_macro<float, 2, true>",
@@ -108,6 +114,9 @@ def main():
     ap.add_argument("--L", type=int, default=None)
     ap.add_argument("--sweeps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="run only the smoother sweeps on level L and a plain device copy of known size "
+                         "(for hardware-counter runs; prints no JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the method runs on one GPU here); --gpus {args.gpus} is not "
@@ -129,6 +138,17 @@ def main():
     if w.kappa_nodal is not None:
         hh.set_kappa_nodal(torch.as_tensor(w.kappa_nodal(X), device="cuda:0"))
     log(f"N = {N} DoFs, workspace {hh.workspace_bytes / 2**30:.2f} GiB")
+    if args.kernel_only:
+        # counter calibration: a device-to-device copy of COPY_BYTES, then the float32 sweeps
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        b = hh.bench_smoother("fp32_refined", args.sweeps)
+        log(f"kernel-only: copy of {COPY_BYTES} B x3, {args.sweeps} float32 sweeps, interior launch "
+            f"{b['launch_ms'] * 1e3:.1f} us, {b['launch_bytes']:.0f} algorithmic bytes per launch")
+        return
 
     # reference discretisation error: converged float64 solve
     u_ref, st_ref = hh.fmg_solve(f, g, nu=w.nu, pre=w.pre, post=w.post, precision="fp64", rtol=1e-12, max_iter=200)
@@ -159,10 +179,10 @@ def main():
 
     k = sm["fp32_refined"]
     achieved = k["launch_bytes"] / (k["launch_ms"] * 1e-3) / 1e9
+    kname = KERNEL_NAME.get((w.mesh.dim, w.smoother, w.coefficient), "k_smooth_interior")
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                kernel=KERNEL_NAME.get((w.mesh.dim, w.smoother, w.coefficient), "k_smooth_interior"),
-                bytes_per_launch=k["launch_bytes"], avg_launch_us=round(k["launch_ms"] * 1e3, 2))
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=TRAFFIC_BYTES.get((w.name, w.L, kname)),
+                kernel=kname, bytes_per_launch=k["launch_bytes"], avg_launch_us=round(k["launch_ms"] * 1e3, 2))
 
     ms = res["fp32_refined"]["ms"]
     out = {

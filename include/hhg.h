@@ -141,7 +141,8 @@ hhg_status hhg_estimate(hhg_ctx ctx, int j, double* eta_cell_host, double* eta_j
                         double* norm_e);
 
 /* y = A x or y = M x on a level with the full (unconstrained) assembled matrix; x, y device
- * vectors in canonical order (op = HHG_OP_STIFFNESS | HHG_OP_MASS). */
+ * vectors in canonical order (op = HHG_OP_STIFFNESS | HHG_OP_MASS).  Leaves the state of the
+ * last hhg_fmg_solve intact (hhg_estimate may still follow). */
 hhg_status hhg_apply(hhg_ctx ctx, int level, int op, const double* x, double* y);
 
 /* y = M_L x (mass matrix on level L), device vectors; used for L2 goal functionals. */

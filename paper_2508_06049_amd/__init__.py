@@ -6,3 +6,4 @@ estimator (kl-refinement, Mann & Rude).
 * ``mesh``       -- host-side coarse-mesh marking and red-green refinement
 """
 from ._lib import HHG, HHGError, SolveStats, load, exported_symbols  # noqa: F401
+from .autograd import HHGSolve, hhg_solve  # noqa: F401

@@ -156,15 +156,23 @@ hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
       for (int col = 0; col < lv.interior_colours; ++col) interior_launch<T>(c, l, k, x, x, b, col, rb, 0);
     T* mir = twobuf ? x : (T*)nullptr;
     if (lv.task_ok && !c->no_tasks) {
-      if (lv.max_class_waves <= kTaskOneGroupWaves) {
-        launch_iface_tasks_1wg<T>(c->dim, k, c->tab, lv.d_task_p, lv.d_task_q, lv.d_task_co, lv.d_task_seg,
-                                  lv.d_task_wmax, lv.d_task_woff, lv.interior_colours, lv.ncolours, y, x, y, mir, b,
-                                  sA(c, l), ST(c));
-      } else {
-        for (int col = lv.interior_colours; col < lv.ncolours; ++col)
-          launch_iface_tasks<T>(c->dim, k, c->tab, lv.d_task_p, lv.d_task_q, lv.d_task_co, lv.d_task_seg,
+      // a class of more than kTaskOneGroupWaves wavefronts gets a grid of its own; runs of
+      // smaller consecutive classes share one single-workgroup launch
+      int col = lv.interior_colours;
+      while (col < lv.ncolours) {
+        auto waves = [&](int cc) { return lv.task_woff[cc + 1] - lv.task_woff[cc]; };
+        if (waves(col) > kTaskOneGroupWaves) {
+          launch_iface_tasks<T>(c->dim, k, c->tab, lv.d_task_copy, lv.d_task_info, lv.d_task_loc, lv.d_task_seg,
                                 lv.d_task_wmax, lv.task_woff[col], lv.task_woff[col + 1], y, x, y, mir, b, 0, 0.0,
                                 sA(c, l), ST(c));
+          ++col;
+          continue;
+        }
+        int c1 = col;
+        while (c1 < lv.ncolours && waves(c1) <= kTaskOneGroupWaves) ++c1;
+        launch_iface_tasks_1wg<T>(c->dim, k, c->tab, lv.d_task_copy, lv.d_task_info, lv.d_task_loc, lv.d_task_seg,
+                                  lv.d_task_wmax, lv.d_task_woff, col, c1, y, x, y, mir, b, sA(c, l), ST(c));
+        col = c1;
       }
     } else if (lv.max_iface_class <= kIfaceOneGroup) {
       launch_iface_sweep_1wg<T>(c->dim, p1(c), k, c->tab, lv.d_colour_list, lv.d_colour_off, lv.interior_colours,
@@ -207,8 +215,8 @@ hhg_status vcycle(hhg_ctx c, int l, const T* b, int pre, int post, bool x_is_zer
   TRY(smooth<T>(c, l, b, pre));
   launch_apply<T, T>(c->dim, p1(c), lk_of(c, l), c->tab, Arr<T>::x(lv), b, Arr<T>::t(lv), 0, sA(c, l), 1.0, -1.0, 1,
                      lv.kn, ST(c));
-  launch_restrict<T>(c->dim, lk_of(c, l), lk_of(c, l - 1), c->tab, Arr<T>::t(lv), Arr<T>::rc(lc), ST(c));
-  launch_fill<T>(Arr<T>::x(lc), lc.nfull, (T)0, ST(c));   // homogeneous correction, Dirichlet copies included
+  // restriction; the same launch clears the coarse correction (homogeneous, Dirichlet copies included)
+  launch_restrict<T>(c->dim, lk_of(c, l), lk_of(c, l - 1), c->tab, Arr<T>::t(lv), Arr<T>::rc(lc), ST(c), Arr<T>::x(lc));
   TRY(vcycle<T>(c, l - 1, Arr<T>::rc(lc), pre, post, true));
   launch_prolong<T>(c->dim, lk_of(c, l), lk_of(c, l - 1), c->tab, Arr<T>::x(lc), Arr<T>::x(lv), (T*)nullptr,
                     (const T*)nullptr, 0, ST(c));
@@ -515,12 +523,12 @@ hhg_status hhg_bind_workspace(hhg_ctx c, void* ptr, size_t bytes, void* stream) 
     lv.b32 = (float*)(w + lv.off_b32);
     lv.d_colour_list = (int32_t*)(w + lv.off_cl);
     HIPCHK(up(lv.off_cl, lv.colour_list.data(), lv.colour_list.size() * 4));
-    lv.d_task_p = (int32_t*)(w + lv.off_tp);
-    HIPCHK(up(lv.off_tp, lv.task_p.data(), lv.task_p.size() * 4));
-    lv.d_task_q = (int32_t*)(w + lv.off_tq);
-    HIPCHK(up(lv.off_tq, lv.task_q.data(), lv.task_q.size() * 4));
-    lv.d_task_co = (int32_t*)(w + lv.off_tco);
-    HIPCHK(up(lv.off_tco, lv.task_co.data(), lv.task_co.size() * 4));
+    lv.d_task_copy = (int32_t*)(w + lv.off_tcopy);
+    HIPCHK(up(lv.off_tcopy, lv.task_copy.data(), lv.task_copy.size() * 4));
+    lv.d_task_info = (int32_t*)(w + lv.off_tinfo);
+    HIPCHK(up(lv.off_tinfo, lv.task_info.data(), lv.task_info.size() * 4));
+    lv.d_task_loc = (int32_t*)(w + lv.off_tloc);
+    HIPCHK(up(lv.off_tloc, lv.task_loc.data(), lv.task_loc.size() * 4));
     lv.d_task_seg = (int32_t*)(w + lv.off_tseg);
     HIPCHK(up(lv.off_tseg, lv.task_seg.data(), lv.task_seg.size() * 4));
     lv.d_task_wmax = (int32_t*)(w + lv.off_twmax);
@@ -667,7 +675,8 @@ hhg_status hhg_apply(hhg_ctx c, int level, int op, const double* x, double* y) {
                                1.0, 0, lv.kn, ST(c));
   launch_full_to_canon(c->dim, lk_of(c, level), c->tab, lv.t, y, 1, ST(c));
   LAUNCHCHK();
-  c->solved = false;
+  // only the scratch vectors rc and t of the level are touched: the last solve's u and w stay
+  // valid for hhg_estimate
   return HHG_OK;
 }
 

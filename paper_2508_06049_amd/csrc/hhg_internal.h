@@ -27,6 +27,9 @@ constexpr int kNType3 = 6, kNType2 = 2;
 // fused interior sweeps: 2D core tile of (64 - 2 C) columns (one wavefront) x kTileJ rows
 // (C = interior colours), and the largest 3D macro level kept whole in LDS
 constexpr int kTileJ = 32;
+// multicolour (C = 3) tiles are 30 rows high, so every tile starts on a row = 1 (mod 3)
+constexpr int kTileJ3 = 30;
+constexpr int tile_rows(int C) { return C == 3 ? kTileJ3 : kTileJ; }
 constexpr int kMacroLdsN = 32;
 // levels whose largest interface colour class has at most this many DoFs sweep all interface
 // classes in one single-workgroup launch
@@ -34,6 +37,8 @@ constexpr int kIfaceOneGroup = 4096;
 // lane-parallel interface sweeps: levels whose largest class spans at most this many
 // wavefronts sweep all classes in one workgroup of 16 wavefronts
 constexpr int kTaskOneGroupWaves = 32;
+// blocks of the interior part of a squared norm (one partial each)
+constexpr int kNormBlocks = 8192;
 
 // direction tables: index 0 is the centre, 1..H positive, H+1..2H negative
 constexpr int kDir3[7][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {-1, 1, 0}, {-1, 0, 1}, {0, -1, 1}, {1, -1, 1}};
@@ -93,13 +98,15 @@ struct Level {
   int max_iface_class = 0;
   // lane-parallel interface sweep (Gauss-Seidel, per-macro coefficient): one lane per
   // (interface DoF, incident macro), lanes of one DoF consecutive in a wavefront; arrays of
-  // 64 entries per wavefront, wavefronts of class c are task_woff[c] .. task_woff[c+1]-1
+  // 64 entries per wavefront, wavefronts of class c are task_woff[c] .. task_woff[c+1]-1.
+  // Per lane: task_copy = level-vector index of the copy (-1: padding lane), task_info =
+  // macro | zero-set mask << 24 | Dirichlet << 28, task_loc = i | j << 11 | k << 22 (closure
+  // coordinates in the macro), task_seg = first lane of the DoF | lane count << 8.
   bool task_ok = false;
-  std::vector<int32_t> task_p, task_q, task_co, task_seg, task_wmax, task_woff;
-  int max_class_waves = 0;
-  int32_t *d_task_p = nullptr, *d_task_q = nullptr, *d_task_co = nullptr, *d_task_seg = nullptr,
+  std::vector<int32_t> task_copy, task_info, task_loc, task_seg, task_wmax, task_woff;
+  int32_t *d_task_copy = nullptr, *d_task_info = nullptr, *d_task_loc = nullptr, *d_task_seg = nullptr,
           *d_task_wmax = nullptr, *d_task_woff = nullptr;
-  int64_t off_tp = 0, off_tq = 0, off_tco = 0, off_tseg = 0, off_twmax = 0, off_twoff = 0;
+  int64_t off_tcopy = 0, off_tinfo = 0, off_tloc = 0, off_tseg = 0, off_twmax = 0, off_twoff = 0;
   std::vector<int32_t> tiles;          // 2D: interior tiles (ti | tj << 16) of the fused sweep
   std::vector<uint32_t> itab;          // 3D, n <= kMacroLdsN: interior points (i | j << 10 | k << 20)
   int32_t* d_tiles = nullptr;

@@ -53,7 +53,8 @@ template <typename Tin, typename Tout>
 void launch_iface_residual(int dim, bool p1, const LK& lk, const Tables& tb, const Tin* x, const Tin* b, Tout* y,
                            double sA, const double* kn, hipStream_t st);
 template <typename T>
-void launch_restrict(int dim, const LK& f, const LK& c, const Tables& tb, const T* rf, T* bc, hipStream_t st);
+void launch_restrict(int dim, const LK& f, const LK& c, const Tables& tb, const T* rf, T* bc, hipStream_t st,
+                     T* zc = nullptr);
 template <typename T>
 void launch_prolong(int dim, const LK& f, const LK& c, const Tables& tb, const T* ec, T* uf, T* w, const T* g, int mode,
                     hipStream_t st);

@@ -34,9 +34,11 @@ __device__ __forceinline__ int d_lin(int n, int i, int j, int k) {
   }
 }
 
+// row j of linear index s in a triangle of side n: a single-precision estimate from the
+// quadratic row-offset formula, then exact integer correction
 __device__ __forceinline__ void d_dec2(int n, int s, int& i, int& j) {
-  const double a = 2.0 * n + 3.0;
-  int jj = (int)floor(0.5 * (a - sqrt(fmax(a * a - 8.0 * s, 0.0))));
+  const float a = 2.0f * (float)n + 3.0f;
+  int jj = (int)floorf(0.5f * (a - sqrtf(fmaxf(a * a - 8.0f * (float)s, 0.0f))));
   jj = max(0, min(jj, n));
   while (jj < n && d_lin2(n, 0, jj + 1) <= s) ++jj;
   while (jj > 0 && d_lin2(n, 0, jj) > s) --jj;
@@ -51,7 +53,7 @@ __device__ __forceinline__ void d_dec(int n, int s, int& i, int& j, int& k) {
     d_dec2(n, s, i, j);
   } else {
     const int r = d_tet(n) - s;   // >= 1
-    int m = (int)cbrt(6.0 * r) - 2;
+    int m = (int)cbrtf(6.0f * (float)r) - 2;
     m = max(0, min(m, n));
     while (d_tet(m) < r) ++m;
     while (m > 0 && d_tet(m - 1) >= r) --m;
@@ -84,6 +86,26 @@ __device__ __forceinline__ void d_typeoff(int t, int v, int& a, int& b, int& c) 
   } else {
     a = kType2[t][v][0]; b = kType2[t][v][1]; c = 0;
   }
+}
+
+// raw buffer access to one block (a macro's, or a whole level vector): a descriptor plus a
+// 32-bit per-lane byte offset, so address arithmetic costs one VGPR per access.  The
+// descriptor's size bounds the access: loads past it return 0 and stores are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t d_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ void d_bload(__amdgpu_buffer_rsrc_t r, uint32_t off, float& v) {
+  v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void d_bload(__amdgpu_buffer_rsrc_t r, uint32_t off, double& v) {
+  v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void d_bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void d_bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v),
+                                        r, off, 0, 0);
 }
 
 template <int D> constexpr int ndir() { return D == 3 ? kNDir3 : kNDir2; }
@@ -356,89 +378,85 @@ __global__ void __launch_bounds__(1024) k_iface_sweep_1wg(LK lk, Tables tb, cons
 // partial row (right-hand side, off-diagonal sum, diagonal) from the copy's closure
 // neighbours; every lane of a segment then sums the segment's partials in the same order
 // through lane shuffles, so all copies receive bitwise the same new value, which each lane
-// writes to its own copy.  The global loads of a DoF do not depend on one another, so the
-// update costs one table load and one gather round trip whatever the number of copies.
-// Task fields per lane: primitive p (-1 = padding lane), incidence q, coordinates along the
-// primitive's sorted vertices (co1 | co2 << 16; co0 = n - co1 - co2, a vertex has co = (n)),
-// segment (first lane | length << 8).  wmax[w]: longest segment of wavefront w.
+// writes to its own copy.  A lane's task gives its copy's level-vector index, macro, zero-set
+// mask and closure coordinates directly, so the update is one table load and one gather,
+// whatever the number of copies.  Level vectors are accessed through buffer descriptors
+// bounded to the level (nfull entries).  wmax[w]: longest segment of wavefront w.
 template <int D, typename T>
-__device__ __forceinline__ void iface_task_wave(const LK& lk, const Tables& tb, const int32_t* __restrict__ tp,
-                                                const int32_t* __restrict__ tq, const int32_t* __restrict__ tco,
+__device__ __forceinline__ void iface_task_wave(const LK& lk, const Tables& tb, const int32_t* __restrict__ tcopy,
+                                                const int32_t* __restrict__ tinfo, const int32_t* __restrict__ tloc,
                                                 const int32_t* __restrict__ tseg, int wmax, int w, const T* xi,
                                                 const T* xf, T* uout, T* umirror, const T* __restrict__ b, int jacobi,
                                                 double omega, double sA) {
   const int lane = threadIdx.x & 63;
   const int idx = w * 64 + lane;
-  const int p = tp[idx];
+  const uint32_t vbytes = (uint32_t)((int64_t)lk.nmacro * lk.S) * (uint32_t)sizeof(T);
+  const __amdgpu_buffer_rsrc_t rxi = d_rsrc(xi, vbytes), rxf = d_rsrc(xf, vbytes), rb = d_rsrc(b, vbytes);
+  const int cp = tcopy[idx];
+  const int info = tinfo[idx], loc = tloc[idx], seg = tseg[idx];
   T rhs = (T)0, off = (T)0, diag = (T)0, uold = (T)0;
-  int64_t ix = 0;
-  bool dir = false;
-  if (p >= 0) {
-    const int q = tq[idx], cw = tco[idx];
-    const int np = p < tb.nV ? 1 : (p < tb.nV + tb.nE ? 2 : 3);
-    int co[3];
-    co[1] = cw & 0xffff;
-    co[2] = cw >> 16;
-    co[0] = np == 1 ? lk.n : lk.n - co[1] - co[2];
-    dir = tb.primdir[p] != 0;
-    const Inc in = tb.inc[q];
-    int lc[4] = {0, 0, 0, 0};
-    for (int r = 0; r < np; ++r) lc[in.slot[r]] = co[r];
-    const int i = lc[1], j = lc[2], k = lc[3];
-    const int64_t base = (int64_t)in.macro * lk.S;
-    ix = base + d_lin<D>(lk.n, i, j, k);
-    uold = xf[ix];
+  const bool live = cp >= 0;
+  const bool dir = (info >> 28) & 1;
+  if (live) {
+    const int m = info & 0xffffff, mask = (info >> 24) & 15;
+    const int i = loc & 2047, j = (loc >> 11) & 2047, k = loc >> 22;
+    const int64_t base = (int64_t)m * lk.S;
+    d_bload(rxf, (uint32_t)cp * (uint32_t)sizeof(T), uold);
     if (!dir) {
-      rhs = b[ix];
-      const double* W = tb.stiff + ((size_t)in.macro * kMaxMask + in.mask) * ndir<D>();
-      const uint32_t valid = tb.validdirs[in.mask];
-      const double scale = sA * tb.kappa[in.macro];
+      d_bload(rb, (uint32_t)cp * (uint32_t)sizeof(T), rhs);
+      const double* W = tb.stiff + ((size_t)m * kMaxMask + mask) * ndir<D>();
+      const uint32_t valid = tb.validdirs[mask];
+      const double scale = sA * tb.kappa[m];
 #pragma unroll
       for (int dd = 1; dd < ndir<D>(); ++dd) {
         if (!((valid >> dd) & 1)) continue;
         int a, b2, c;
         d_off<D>(dd, a, b2, c);
         const int i2 = i + a, j2 = j + b2, k2 = k + c;
-        off += (T)(scale * W[dd]) * (d_mask<D>(lk.n, i2, j2, k2) ? xf : xi)[base + d_lin<D>(lk.n, i2, j2, k2)];
+        const uint32_t o = (uint32_t)(base + d_lin<D>(lk.n, i2, j2, k2)) * (uint32_t)sizeof(T);
+        T v;
+        if (d_mask<D>(lk.n, i2, j2, k2)) d_bload(rxf, o, v);
+        else d_bload(rxi, o, v);
+        off += (T)(scale * W[dd]) * v;
       }
       diag = (T)(scale * W[0]);
     }
   }
   // segment sums; every lane of the wavefront takes part in every shuffle
-  const int seg = tseg[idx];
   const int lead = seg & 63, len = seg >> 8;
   T srhs = (T)0, soff = (T)0, sdiag = (T)0;
-  for (int k = 0; k < wmax; ++k) {
-    const int src = min(lead + k, 63);
+  for (int kq = 0; kq < wmax; ++kq) {
+    const int src = min(lead + kq, 63);
     const T a = __shfl(rhs, src, 64), o = __shfl(off, src, 64), d = __shfl(diag, src, 64);
-    if (k < len) { srhs += a; soff += o; sdiag += d; }
+    if (kq < len) { srhs += a; soff += o; sdiag += d; }
   }
-  if (p < 0) return;
+  if (!live) return;
   T unew;
   if (dir) unew = uold;
   else if (jacobi) unew = uold + (T)omega * (srhs - soff - sdiag * uold) / sdiag;
   else unew = (srhs - soff) / sdiag;
-  uout[ix] = unew;
-  if (umirror) umirror[ix] = unew;
+  const uint32_t oc = (uint32_t)cp * (uint32_t)sizeof(T);
+  d_bstore(d_rsrc(uout, vbytes), oc, unew);
+  if (umirror) d_bstore(d_rsrc(umirror, vbytes), oc, unew);
 }
 
 // one interface colour class: wavefronts w0 .. w1-1, four per block
 template <int D, typename T>
-__global__ void __launch_bounds__(256) k_iface_tasks(LK lk, Tables tb, const int32_t* __restrict__ tp,
-                                                      const int32_t* __restrict__ tq, const int32_t* __restrict__ tco,
+__global__ void __launch_bounds__(256) k_iface_tasks(LK lk, Tables tb, const int32_t* __restrict__ tcopy,
+                                                      const int32_t* __restrict__ tinfo, const int32_t* __restrict__ tloc,
                                                       const int32_t* __restrict__ tseg, const int32_t* __restrict__ wmax,
                                                       int w0, int w1, const T* xi, const T* xf, T* uout, T* umirror,
                                                       const T* __restrict__ b, int jacobi, double omega, double sA) {
   const int w = __builtin_amdgcn_readfirstlane(w0 + (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
   if (w >= w1) return;
-  iface_task_wave<D, T>(lk, tb, tp, tq, tco, tseg, wmax[w], w, xi, xf, uout, umirror, b, jacobi, omega, sA);
+  iface_task_wave<D, T>(lk, tb, tcopy, tinfo, tloc, tseg, wmax[w], w, xi, xf, uout, umirror, b, jacobi, omega, sA);
 }
 
 // every interface class c0..c1-1 of one sweep in one workgroup of 16 wavefronts (small
 // levels), classes separated by barriers; woff[c] is the first wavefront of class c
 template <int D, typename T>
-__global__ void __launch_bounds__(1024) k_iface_tasks_1wg(LK lk, Tables tb, const int32_t* __restrict__ tp,
-                                                           const int32_t* __restrict__ tq, const int32_t* __restrict__ tco,
+__global__ void __launch_bounds__(1024) k_iface_tasks_1wg(LK lk, Tables tb, const int32_t* __restrict__ tcopy,
+                                                           const int32_t* __restrict__ tinfo, const int32_t* __restrict__ tloc,
                                                            const int32_t* __restrict__ tseg,
                                                            const int32_t* __restrict__ wmax,
                                                            const int32_t* __restrict__ woff, int c0, int c1, const T* xi,
@@ -448,7 +466,7 @@ __global__ void __launch_bounds__(1024) k_iface_tasks_1wg(LK lk, Tables tb, cons
   for (int c = c0; c < c1; ++c) {
     const int e = woff[c + 1];
     for (int w = woff[c] + wave; w < e; w += 16)
-      iface_task_wave<D, T>(lk, tb, tp, tq, tco, tseg, wmax[w], w, xi, xf, uout, umirror, b, 0, 0.0, sA);
+      iface_task_wave<D, T>(lk, tb, tcopy, tinfo, tloc, tseg, wmax[w], w, xi, xf, uout, umirror, b, 0, 0.0, sA);
     __syncthreads();
   }
 }
@@ -495,26 +513,6 @@ __global__ void __launch_bounds__(256) k_iface_residual(LK lk, Tables tb, const 
 }
 
 // ------------------------------------------------------------------------------------------
-// raw buffer access to one macro's block: a wave-uniform descriptor (scalar registers) plus a
-// 32-bit per-lane byte offset, so address arithmetic costs one VGPR per access.  The
-// descriptor's size bounds the access: loads past it return 0 and stores are dropped.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t d_rsrc(const void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
-}
-__device__ __forceinline__ void d_bload(__amdgpu_buffer_rsrc_t r, uint32_t off, float& v) {
-  v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-__device__ __forceinline__ void d_bload(__amdgpu_buffer_rsrc_t r, uint32_t off, double& v) {
-  v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-__device__ __forceinline__ void d_bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
-}
-__device__ __forceinline__ void d_bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v),
-                                        r, off, 0, 0);
-}
-
 // value held by lane q+1 (from_next) or lane q-1 (from_prev) of the wavefront: full-wave DPP
 // shifts (wave_shl:1 / wave_shr:1).  The end lanes get their own value back; callers discard
 // them.
@@ -612,6 +610,83 @@ __device__ __forceinline__ void gs2d_wave_tile(int n, __amdgpu_buffer_rsrc_t um,
   }
 }
 
+// Multicolour (C = 3) form of the wavefront tile with every lane busy in every pass.  Node
+// (i, j) has colour (i + 2 j) mod 3, so a fixed row holds each colour in every third column
+// only.  Lane i instead keeps row j0 - 3 + (i mod 3) + s in slot s: the nodes of one colour
+// then sit in the same slots of all lanes (j0 = 1 mod 3 for every tile), and pass c updates
+// the slots s = 2c + 2 (mod 3) of every lane.  Row neighbours come from the adjacent lanes: a
+// lane offers, by its own column mod 3, the slot that holds the asking lane's row (right,
+// left, up-left, down-right neighbours), and DPP shifts deliver it.  The valid region
+// shrinks by one node per pass exactly as in the row-aligned form.
+template <typename T, int TS, bool FINE>
+__device__ __forceinline__ void gs2d_wave_tile_mc3(int n, __amdgpu_buffer_rsrc_t um, __amdgpu_buffer_rsrc_t uom,
+                                                   __amdgpu_buffer_rsrc_t bm, int i0, int j0, T w1, T w2, T w3, T w4,
+                                                   T w5, T w6, T inv) {
+  constexpr int H = 3, RH = TS + 2 * H, K = 3, RS = RH + K + 1;
+  const int q = threadIdx.x & 63;
+  const int i = i0 + q;
+  const int rho = ((i % 3) + 3) % 3;
+  // load rows j0 - K + t (t = 0 .. RS+1) aligned across lanes, so every load is one contiguous
+  // row segment, then rotate in registers: slot s takes aligned row s + (i mod 3)
+  T us[RS + 2], bs[RS + 2];
+  {
+    int j = j0 - K;
+    int roff = j * (n + 1) - (j * (j - 1)) / 2;
+#pragma unroll
+    for (int t = 0; t < RS + 2; ++t) {
+      const int r = t - K;   // row of the loaded region, 0 .. RH-1
+      const bool in = r >= 0 && r < RH && i >= 0 && j >= 0 && i + j <= n;
+      const uint32_t g = in ? (uint32_t)(roff + i) * (uint32_t)sizeof(T) : 0u;
+      d_bload(um, g, us[t]);
+      d_bload(bm, g, bs[t]);
+      roff += n + 1 - j;
+      ++j;
+    }
+    const bool p1 = rho == 1, p2 = rho == 2;
+#pragma unroll
+    for (int t = 0; t < RS; ++t) {
+      us[t] = p2 ? us[t + 2] : (p1 ? us[t + 1] : us[t]);
+      bs[t] = p2 ? bs[t + 2] : (p1 ? bs[t + 1] : bs[t]);
+    }
+  }
+  // node (i, j0 + r) is interior iff rlo <= r <= rhi
+  const int rhi = n - 1 - j0 - i, rlo = 1 - j0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const bool lok = q >= c + 1 && q <= 62 - c && i >= 1;
+    int rr = rho, hi = rhi, lo = rlo;
+    asm volatile("" : "+v"(rr), "+v"(hi), "+v"(lo));
+    const bool r0 = rr == 0, r2 = rr == 2;
+#pragma unroll
+    for (int s = 2; s <= RS - 3; ++s) {
+      if (s % 3 != (2 * c + 2) % 3) continue;
+      const int r = s - K + rr;
+      const T sR = r0 ? us[s + 2] : us[s - 1];
+      const T sL = r2 ? us[s - 2] : us[s + 1];
+      const T sUL = r2 ? us[s - 1] : us[s + 2];
+      const T sDR = r0 ? us[s + 1] : us[s - 2];
+      const T acc = w1 * from_next(sR) + w2 * us[s + 1] + w3 * from_prev(sUL) + w4 * from_prev(sL) + w5 * us[s - 1] +
+                    w6 * from_next(sDR);
+      const T v = (bs[s] - acc) * inv;
+      const bool act = lok && r >= c + 1 && r <= RH - 2 - c && r >= lo && r <= hi;
+      us[s] = act ? v : us[s];
+    }
+  }
+  if (q >= H && q < 64 - H && i >= 1) {
+    // rotate back: aligned row r sits in slot r + K - (i mod 3)
+    const bool p1 = rho == 1, p2 = rho == 2;
+    int j = j0 + H;
+    int roff = j * (n + 1) - (j * (j - 1)) / 2;
+#pragma unroll
+    for (int r = H; r < H + TS; ++r) {
+      const T v = p2 ? us[r + K - 2] : (p1 ? us[r + K - 1] : us[r + K]);
+      if (j >= 1 && i + j <= n - 1) d_bstore(uom, (uint32_t)(roff + i) * (uint32_t)sizeof(T), v);
+      roff += n + 1 - j;
+      ++j;
+    }
+  }
+}
+
 // one wavefront per tile of (64 - 2C) columns x TJ rows, processed as SUB consecutive
 // sub-tiles of TJ/SUB rows.  Reads u, writes the interior of uo: tiles overlap in their
 // halos, so an in-place update would let one tile read rows another tile has already
@@ -642,8 +717,12 @@ __global__ void __launch_bounds__(256) k_gs2d_fused(LK lk, Tables tb, const T* _
   for (int sub = 0; sub < SUB; ++sub) {
     const int j0 = 1 + (tile >> 16) * TJ + sub * TS - H;
     if (j0 + H > lk.n - 2) break;
-    gs2d_wave_tile<T, C, TS, FINE>(lk.n, d_rsrc(u + base, bytes), d_rsrc(uo + base, bytes), d_rsrc(b + base, bytes), i0,
-                                   j0, rb, s1, s2, w1, w2, w3, w4, w5, w6, inv);
+    if constexpr (C == 3 && TJ % 3 == 0 && TS % 3 == 0)
+      gs2d_wave_tile_mc3<T, TS, FINE>(lk.n, d_rsrc(u + base, bytes), d_rsrc(uo + base, bytes), d_rsrc(b + base, bytes),
+                                      i0, j0, w1, w2, w3, w4, w5, w6, inv);
+    else
+      gs2d_wave_tile<T, C, TS, FINE>(lk.n, d_rsrc(u + base, bytes), d_rsrc(uo + base, bytes), d_rsrc(b + base, bytes),
+                                     i0, j0, rb, s1, s2, w1, w2, w3, w4, w5, w6, inv);
   }
 }
 
@@ -723,17 +802,101 @@ __global__ void __launch_bounds__(256) k_apply(LK lk, Tables tb, const Tin* __re
   y[base + s] = (Tout)v;
 }
 
+// 2D y = alpha b + beta (A_m x) with a per-macro coefficient in two wavefront roles of one
+// launch.  Interior role (wavefronts 0 .. nint-1): a 64-node segment of kApplyRows rows of one
+// macro, lanes along i, the macro's full stencil with weights computed once per wavefront,
+// every load of the rows issued before the arithmetic; nodes on the macro boundary are left
+// to the other role.  Boundary role: one lane per boundary node (3n per macro: row j = 0,
+// column i = 0, the edge i + j = n) with its partial stencil.  x and y are accessed through
+// buffer descriptors bounded to the macro block.
+constexpr int kApplyRows = 4;
+template <typename Tin, typename Tout>
+__global__ void __launch_bounds__(256) k_apply2d_rows(LK lk, Tables tb, const Tin* __restrict__ x,
+                                                      const Tin* __restrict__ b, Tout* __restrict__ y, int op,
+                                                      double scale, double alpha, double beta, int zero_dir, int nseg,
+                                                      int nint) {
+  constexpr int R = kApplyRows;
+  const int n = lk.n;
+  const int nrb = (n + 1 + R - 1) / R;
+  const int wid = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+  const int lane = (int)(threadIdx.x & 63);
+  if (wid >= nint) {
+    // boundary role
+    const int64_t t = (int64_t)(wid - nint) * 64 + lane;
+    if (t >= (int64_t)lk.nmacro * 3 * n) return;
+    const int m = (int)(t / (3 * n));
+    const int q = (int)(t - (int64_t)m * 3 * n);
+    int i, j;
+    if (q <= n) { i = q; j = 0; }
+    else if (q <= 2 * n) { i = 0; j = q - n; }
+    else { j = q - 2 * n; i = n - j; }
+    const int mask = d_mask<2>(n, i, j, 0);
+    const int64_t base = (int64_t)m * lk.S;
+    const int s = d_lin2(n, i, j);
+    if (zero_dir && ((tb.dirbits[m] >> mask) & 1)) { y[base + s] = (Tout)0; return; }
+    Tin off, diag;
+    const double* W = (op == 0 ? tb.stiff : tb.mass) + ((size_t)m * kMaxMask + mask) * 7;
+    d_row_const<2, Tin>(lk, W, tb.validdirs[mask], op == 0 ? scale * tb.kappa[m] : scale, x, base, i, j, 0, off, diag);
+    Tin v = (Tin)beta * (off + diag * x[base + s]);
+    if (b) v += (Tin)alpha * b[base + s];
+    y[base + s] = (Tout)v;
+    return;
+  }
+  const int m = wid / (nrb * nseg);
+  const int rem = wid - m * nrb * nseg;
+  const int jb = rem / nseg, seg = rem - jb * nseg;
+  if (seg * 64 > n - jb * R) return;   // the segment starts beyond the first row's end
+  const int i = seg * 64 + lane;
+  const int64_t base = (int64_t)m * lk.S;
+  const __amdgpu_buffer_rsrc_t rx = d_rsrc(x + base, (uint32_t)lk.Sraw * (uint32_t)sizeof(Tin));
+  const __amdgpu_buffer_rsrc_t ry = d_rsrc(y + base, (uint32_t)lk.Sraw * (uint32_t)sizeof(Tout));
+  const double* Wt = (op == 0 ? tb.stiff : tb.mass) + (size_t)m * kMaxMask * 7;
+  const double sc = op == 0 ? scale * tb.kappa[m] : scale;
+  Tin w[7];
+#pragma unroll
+  for (int d = 0; d < 7; ++d) w[d] = (Tin)(sc * Wt[d]);
+  Tin xv[R][7], bv[R];
+  int ctr[R];
+  bool ok[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = jb * R + r;
+    const int rowlen = n + 1 - j;
+    ok[r] = j >= 1 && i >= 1 && i + j <= n - 1;
+    const int ro = d_lin2(n, 0, j), rup = ro + rowlen, rdn = ro - rowlen - 1;
+    const int od[7] = {ro + i, ro + i + 1, rup + i, rup + i - 1, ro + i - 1, rdn + i, rdn + i + 1};
+#pragma unroll
+    for (int d = 0; d < 7; ++d) d_bload(rx, ok[r] ? (uint32_t)od[d] * (uint32_t)sizeof(Tin) : 0u, xv[r][d]);
+    ctr[r] = ok[r] ? od[0] : 0;
+    bv[r] = (b && ok[r]) ? b[base + od[0]] : (Tin)0;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (!ok[r]) continue;
+    Tin off = (Tin)0;
+#pragma unroll
+    for (int d = 1; d < 7; ++d) off += w[d] * xv[r][d];
+    Tin v = (Tin)beta * (off + w[0] * xv[r][0]);
+    if (b) v += (Tin)alpha * bv[r];
+    d_bstore(ry, (uint32_t)ctr[r] * (uint32_t)sizeof(Tout), (Tout)v);
+  }
+}
+
 // r_c = P^T r_f per macro (dual in, dual out); zero on coarse Dirichlet nodes
 template <int D, typename T>
-__global__ void __launch_bounds__(256) k_restrict(LK f, LK c, Tables tb, const T* __restrict__ rf, T* __restrict__ bc) {
-  const int nchunk = (c.Sraw + 255) >> 8;
+__global__ void __launch_bounds__(256) k_restrict(LK f, LK c, Tables tb, const T* __restrict__ rf, T* __restrict__ bc,
+                                                   T* __restrict__ zc) {
+  // grid over the padded coarse block; zc (if given) is cleared over the whole block: the
+  // coarse correction of the next cycle starts from zero without a separate fill launch
+  const int nchunk = (int)((c.S + 255) >> 8);
   const int m = blockIdx.x / nchunk;
   const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
+  const int64_t cb = (int64_t)m * c.S, fb = (int64_t)m * f.S;
+  if (zc && s < c.S) zc[cb + s] = (T)0;
   if (s >= c.Sraw) return;
   int i, j, k;
   d_dec<D>(c.n, s, i, j, k);
   const int mask = d_mask<D>(c.n, i, j, k);
-  const int64_t cb = (int64_t)m * c.S, fb = (int64_t)m * f.S;
   if ((tb.dirbits[m] >> mask) & 1) { bc[cb + s] = (T)0; return; }
   const uint32_t valid = tb.validdirs[mask];
   const int fi = 2 * i, fj = 2 * j, fk = 2 * k;
@@ -768,6 +931,135 @@ __global__ void __launch_bounds__(256) k_prolong(LK f, LK c, Tables tb, const T*
   else {
     w[fb + s] = v;
     uf[fb + s] = dir ? g[fb + s] : v;
+  }
+}
+
+// 2D prolongation by rows (modes as k_prolong): each wavefront takes a 64-node segment of
+// kApplyRows consecutive fine rows of one macro; the coarse rows a fine row interpolates from
+// are scalar, lanes differ only in their column.  Accesses go through descriptors bounded to
+// the macro blocks.
+template <typename T>
+__global__ void __launch_bounds__(256) k_prolong2d_rows(LK f, LK c, Tables tb, const T* __restrict__ ec,
+                                                        T* __restrict__ uf, T* __restrict__ w, const T* __restrict__ g,
+                                                        int mode, int nseg) {
+  constexpr int R = kApplyRows;
+  const int n = f.n, nc = c.n;
+  const int nrb = (n + 1 + R - 1) / R;
+  const int wid = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+  const int m = wid / (nrb * nseg);
+  if (m >= f.nmacro) return;
+  const int rem = wid - m * nrb * nseg;
+  const int jb = rem / nseg, seg = rem - jb * nseg;
+  if (seg * 64 > n - jb * R) return;
+  const int i = seg * 64 + (int)(threadIdx.x & 63);
+  const int64_t fb = (int64_t)m * f.S, cb = (int64_t)m * c.S;
+  const __amdgpu_buffer_rsrc_t re = d_rsrc(ec + cb, (uint32_t)c.Sraw * (uint32_t)sizeof(T));
+  const __amdgpu_buffer_rsrc_t ru = d_rsrc(uf + fb, (uint32_t)f.Sraw * (uint32_t)sizeof(T));
+  const uint32_t dirb = tb.dirbits[m];
+  T lo[R], hi[R], u0[R];
+  int sidx[R];
+  bool ok[R], dir[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = jb * R + r;
+    ok[r] = j <= n && i < n + 1 - j;
+    // the two coarse nodes of the lattice direction whose endpoints have this parity pattern
+    // (one node, taken twice, when both fine indices are even)
+    int ilo, jlo, ihi, jhi;
+    if ((j & 1) == 0) {
+      jlo = jhi = j >> 1;
+      ilo = i >> 1;
+      ihi = (i + 1) >> 1;
+    } else if ((i & 1) == 0) {
+      ilo = ihi = i >> 1;
+      jlo = (j - 1) >> 1;
+      jhi = (j + 1) >> 1;
+    } else {
+      ilo = (i + 1) >> 1;
+      jlo = (j - 1) >> 1;
+      ihi = (i - 1) >> 1;
+      jhi = (j + 1) >> 1;
+    }
+    d_bload(re, ok[r] ? (uint32_t)d_lin2(nc, ilo, jlo) * (uint32_t)sizeof(T) : 0u, lo[r]);
+    d_bload(re, ok[r] ? (uint32_t)d_lin2(nc, ihi, jhi) * (uint32_t)sizeof(T) : 0u, hi[r]);
+    sidx[r] = ok[r] ? d_lin2(n, i, j) : 0;
+    dir[r] = ok[r] && ((dirb >> d_mask<2>(n, i, j, 0)) & 1);
+    if (mode == 0) d_bload(ru, (uint32_t)sidx[r] * (uint32_t)sizeof(T), u0[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (!ok[r]) continue;
+    const int j = jb * R + r;
+    const T v = ((i | j) & 1) ? (T)0.5 * (lo[r] + hi[r]) : lo[r];
+    const int s = sidx[r];
+    const uint32_t fo = (uint32_t)s * (uint32_t)sizeof(T);
+    if (mode == 0) {
+      if (!dir[r]) d_bstore(ru, fo, u0[r] + v);
+    } else if (mode == 1) {
+      d_bstore(ru, fo, v);
+    } else {
+      w[fb + s] = v;
+      d_bstore(ru, fo, dir[r] ? g[fb + s] : v);
+    }
+  }
+}
+
+// 2D restriction r_c = P^T r_f by rows of coarse nodes (as k_restrict, optional clearing of
+// zc over the coarse block done by the same launch)
+template <typename T>
+__global__ void __launch_bounds__(256) k_restrict2d_rows(LK f, LK c, Tables tb, const T* __restrict__ rf,
+                                                         T* __restrict__ bc, T* __restrict__ zc, int nseg) {
+  constexpr int R = kApplyRows;
+  const int n = c.n, nf = f.n;
+  const int nrb = (n + 1 + R - 1) / R;
+  const int wid = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+  const int m = wid / (nrb * nseg);
+  if (m >= c.nmacro) return;
+  const int rem = wid - m * nrb * nseg;
+  const int jb = rem / nseg, seg = rem - jb * nseg;
+  const int lane = (int)(threadIdx.x & 63);
+  const int i = seg * 64 + lane;
+  const int64_t fb = (int64_t)m * f.S, cb = (int64_t)m * c.S;
+  // the padding of the coarse block (beyond the closure) is cleared by the wavefronts of the
+  // first row block
+  if (zc && jb == 0)
+    for (int64_t s = c.Sraw + seg * 64 + lane; s < c.S; s += (int64_t)nseg * 64) zc[cb + s] = (T)0;
+  if (seg * 64 > n - jb * R) return;
+  const __amdgpu_buffer_rsrc_t rr = d_rsrc(rf + fb, (uint32_t)f.Sraw * (uint32_t)sizeof(T));
+  const __amdgpu_buffer_rsrc_t rc = d_rsrc(bc + cb, (uint32_t)c.Sraw * (uint32_t)sizeof(T));
+  const uint32_t dirb = tb.dirbits[m];
+  T xv[R][7];
+  int sidx[R], mk[R];
+  bool ok[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = jb * R + r;
+    ok[r] = j <= n && i < n + 1 - j;
+    mk[r] = ok[r] ? d_mask<2>(n, i, j, 0) : 0;
+    sidx[r] = ok[r] ? d_lin2(n, i, j) : 0;
+    const int fi = 2 * i, fj = 2 * j;
+#pragma unroll
+    for (int d = 0; d < 7; ++d) {
+      // fine neighbour inside the fine closure (the valid directions of this zero-set)
+      const int a = fi + kOff2[d][0], bb = fj + kOff2[d][1];
+      const bool use = ok[r] && a >= 0 && bb >= 0 && a + bb <= nf;
+      d_bload(rr, use ? (uint32_t)d_lin2(nf, a, bb) * (uint32_t)sizeof(T) : 0u, xv[r][d]);
+      xv[r][d] = use ? xv[r][d] : (T)0;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (!ok[r]) continue;
+    const uint32_t co = (uint32_t)sidx[r] * (uint32_t)sizeof(T);
+    if (zc) zc[cb + sidx[r]] = (T)0;
+    if ((dirb >> mk[r]) & 1) {
+      d_bstore(rc, co, (T)0);
+      continue;
+    }
+    T acc = (T)0;
+#pragma unroll
+    for (int d = 1; d < 7; ++d) acc += xv[r][d];
+    d_bstore(rc, co, xv[r][0] + (T)0.5 * acc);
   }
 }
 
@@ -825,16 +1117,34 @@ __global__ void __launch_bounds__(256) k_coarse(int n0, const int32_t* __restric
 // sum over macro-interior nodes of r^2 (per block partials)
 template <int D>
 __global__ void __launch_bounds__(256) k_sq_interior(LK lk, const double* __restrict__ r, double* __restrict__ partial) {
+  // one wavefront per interior row (lanes along i), a fixed grid striding over all rows of all
+  // macros, one partial per block: the sum order depends only on the sizes
   __shared__ double sh[4];
-  const int nchunk = (lk.NI + 255) >> 8;
-  const int m = blockIdx.x / nchunk;
-  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
+  const int n = lk.n;
+  const int64_t rows = (int64_t)lk.nmacro * (n + 1) * (D == 3 ? (n + 1) : 1);
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  const int lane = threadIdx.x & 63;
   double v = 0.0;
-  if (s < lk.NI) {
-    int i, j, k;
-    d_dec<D>(lk.n - D - 1, s, i, j, k);
-    const double x = r[(int64_t)m * lk.S + d_lin<D>(lk.n, i + 1, j + 1, k + (D == 3 ? 1 : 0))];
-    v = x * x;
+  for (int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); g < rows; g += nw) {
+    int64_t m;
+    int j, k = 0;
+    if constexpr (D == 2) {
+      m = g / (n + 1);
+      j = (int)(g - m * (n + 1));
+    } else {
+      const int64_t jk = g % ((int64_t)(n + 1) * (n + 1));
+      m = g / ((int64_t)(n + 1) * (n + 1));
+      k = (int)(jk / (n + 1));
+      j = (int)(jk - (int64_t)k * (n + 1));
+      if (k < 1) continue;
+    }
+    const int ilast = n - 1 - j - k;   // interior nodes i = 1 .. ilast
+    if (j < 1 || ilast < 1) continue;
+    const int64_t rb = m * lk.S + d_lin<D>(n, 0, j, k);
+    for (int i = 1 + lane; i <= ilast; i += 64) {
+      const double x = r[rb + i];
+      v += x * x;
+    }
   }
   v = block_sum(v, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = v;
@@ -1079,7 +1389,7 @@ bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* 
     if (ntiles <= 0) return false;
     const unsigned g = (unsigned)(((int64_t)lk.nmacro * ntiles + 31) / 32 * 8);   // 4 tiles per block, 8 XCDs
 #define HHG_F2(C, F) \
-  k_gs2d_fused<T, C, kTileJ, sizeof(T) == 8 ? 2 : 1, F><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA)
+  k_gs2d_fused<T, C, tile_rows(C), sizeof(T) == 8 ? 2 : 1, F><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA)
     if (rb) { if (fine) HHG_F2(2, true); else HHG_F2(2, false); }
     else { if (fine) HHG_F2(3, true); else HHG_F2(3, false); }
 #undef HHG_F2
@@ -1158,6 +1468,14 @@ void launch_iface_sweep_1wg(int dim, bool p1, const LK& lk, const Tables& tb, co
 template <typename Tin, typename Tout>
 void launch_apply(int dim, bool p1, const LK& lk, const Tables& tb, const Tin* x, const Tin* b, Tout* y, int op,
                   double scale, double alpha, double beta, int zero_dir, const double* kn, hipStream_t st) {
+  if (dim == 2 && !(p1 && op == 0)) {
+    const int nseg = (lk.n + 1 + 63) / 64, nrb = (lk.n + 1 + kApplyRows - 1) / kApplyRows;
+    const int nint = lk.nmacro * nrb * nseg;
+    const int nbnd = (int)(((int64_t)lk.nmacro * 3 * lk.n + 63) / 64);
+    const unsigned gw = (unsigned)(((int64_t)nint + nbnd + 3) / 4);
+    k_apply2d_rows<Tin, Tout><<<gw, 256, 0, st>>>(lk, tb, x, b, y, op, scale, alpha, beta, zero_dir, nseg, nint);
+    return;
+  }
   const unsigned g = (unsigned)(lk.nmacro * ((lk.Sraw + 255) / 256));
   if (dim == 3) {
     if (p1) k_apply<3, Tin, Tout, true><<<g, 256, 0, st>>>(lk, tb, x, b, y, op, scale, alpha, beta, zero_dir, kn);
@@ -1183,15 +1501,27 @@ void launch_iface_residual(int dim, bool p1, const LK& lk, const Tables& tb, con
 }
 
 template <typename T>
-void launch_restrict(int dim, const LK& f, const LK& c, const Tables& tb, const T* rf, T* bc, hipStream_t st) {
-  const unsigned g = (unsigned)(c.nmacro * ((c.Sraw + 255) / 256));
-  if (dim == 3) k_restrict<3, T><<<g, 256, 0, st>>>(f, c, tb, rf, bc);
-  else k_restrict<2, T><<<g, 256, 0, st>>>(f, c, tb, rf, bc);
+void launch_restrict(int dim, const LK& f, const LK& c, const Tables& tb, const T* rf, T* bc, hipStream_t st, T* zc) {
+  if (dim == 2) {
+    const int nseg = (c.n + 1 + 63) / 64, nrb = (c.n + 1 + kApplyRows - 1) / kApplyRows;
+    const unsigned gw = (unsigned)(((int64_t)c.nmacro * nrb * nseg + 3) / 4);
+    k_restrict2d_rows<T><<<gw, 256, 0, st>>>(f, c, tb, rf, bc, zc, nseg);
+    return;
+  }
+  const unsigned g = (unsigned)(c.nmacro * ((c.S + 255) / 256));
+  if (dim == 3) k_restrict<3, T><<<g, 256, 0, st>>>(f, c, tb, rf, bc, zc);
+  else k_restrict<2, T><<<g, 256, 0, st>>>(f, c, tb, rf, bc, zc);
 }
 
 template <typename T>
 void launch_prolong(int dim, const LK& f, const LK& c, const Tables& tb, const T* ec, T* uf, T* w, const T* g, int mode,
                     hipStream_t st) {
+  if (dim == 2) {
+    const int nseg = (f.n + 1 + 63) / 64, nrb = (f.n + 1 + kApplyRows - 1) / kApplyRows;
+    const unsigned gw = (unsigned)(((int64_t)f.nmacro * nrb * nseg + 3) / 4);
+    k_prolong2d_rows<T><<<gw, 256, 0, st>>>(f, c, tb, ec, uf, w, g, mode, nseg);
+    return;
+  }
   const unsigned gr = (unsigned)(f.nmacro * ((f.Sraw + 255) / 256));
   if (dim == 3) k_prolong<3, T><<<gr, 256, 0, st>>>(f, c, tb, ec, uf, w, g, mode);
   else k_prolong<2, T><<<gr, 256, 0, st>>>(f, c, tb, ec, uf, w, g, mode);
@@ -1219,7 +1549,8 @@ void launch_coarse(int n0, const int32_t* coff, const int64_t* copy, const doubl
 }
 
 void launch_sqnorm(int dim, const LK& lk, const Tables& tb, const double* r, double* partial, double* out, hipStream_t st) {
-  const unsigned g1 = (unsigned)(lk.NI > 0 ? lk.nmacro * ((lk.NI + 255) / 256) : 0);
+  const int64_t rows = (int64_t)lk.nmacro * (lk.n + 1) * (dim == 3 ? (lk.n + 1) : 1);
+  const unsigned g1 = (unsigned)(lk.NI > 0 ? std::min<int64_t>(kNormBlocks, (rows + 3) / 4) : 0);
   const unsigned g2 = nblk(lk.nIface);
   if (g1) {
     if (dim == 3) k_sq_interior<3><<<g1, 256, 0, st>>>(lk, r, partial);
@@ -1325,8 +1656,9 @@ template void launch_iface_residual<double, float>(int, bool, const LK&, const T
                                                   float*, double, const double*, hipStream_t);
 template void launch_iface_residual<double, double>(int, bool, const LK&, const Tables&, const double*, const double*,
                                                    double*, double, const double*, hipStream_t);
-template void launch_restrict<double>(int, const LK&, const LK&, const Tables&, const double*, double*, hipStream_t);
-template void launch_restrict<float>(int, const LK&, const LK&, const Tables&, const float*, float*, hipStream_t);
+template void launch_restrict<double>(int, const LK&, const LK&, const Tables&, const double*, double*, hipStream_t,
+                                      double*);
+template void launch_restrict<float>(int, const LK&, const LK&, const Tables&, const float*, float*, hipStream_t, float*);
 template void launch_prolong<double>(int, const LK&, const LK&, const Tables&, const double*, double*, double*,
                                      const double*, int, hipStream_t);
 template void launch_prolong<float>(int, const LK&, const LK&, const Tables&, const float*, float*, float*, const float*,

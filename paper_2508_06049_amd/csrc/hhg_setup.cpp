@@ -469,47 +469,59 @@ hhg_status build_colouring(hhg_ctx c) {
     for (int64_t t = 0; t < lv.nIface; ++t)
       if (col[t] >= 0) lv.colour_list[fill[col[t]]++] = (int32_t)t;
     // lane-parallel interface tasks (Gauss-Seidel with a per-macro coefficient): every
-    // non-empty interface class packed into wavefronts, a DoF's lanes never split
+    // non-empty interface class packed into wavefronts, a DoF's lanes never split; every
+    // entry is checked here (copy index inside the level vector, coordinates inside the
+    // closure), so the kernel only follows validated indices
     lv.task_ok = false;
-    lv.task_p.clear(); lv.task_q.clear(); lv.task_co.clear(); lv.task_seg.clear(); lv.task_wmax.clear();
+    lv.task_copy.clear(); lv.task_info.clear(); lv.task_loc.clear(); lv.task_seg.clear(); lv.task_wmax.clear();
     lv.task_woff.assign(lv.ncolours + 1, 0);
-    lv.max_class_waves = 0;
-    if (c->opt.smoother != HHG_JACOBI && c->opt.coefficient == HHG_KAPPA_MACRO) {
+    if (c->opt.smoother != HHG_JACOBI && c->opt.coefficient == HHG_KAPPA_MACRO && lv.nfull < (int64_t)1 << 29 &&
+        c->nC < (1 << 24) && lv.n < 2048) {
       bool ok = true;
       auto pad_wave = [&]() {
-        while (lv.task_p.size() % 64) {
-          lv.task_p.push_back(-1); lv.task_q.push_back(0); lv.task_co.push_back(0); lv.task_seg.push_back(0);
+        while (lv.task_copy.size() % 64) {
+          lv.task_copy.push_back(-1); lv.task_info.push_back(0); lv.task_loc.push_back(0); lv.task_seg.push_back(0);
         }
       };
+      const int np_of[3] = {1, 2, 3};
       for (int cc = 0; cc < lv.ncolours && ok; ++cc) {
-        lv.task_woff[cc] = (int32_t)(lv.task_p.size() / 64);
-        for (int32_t k = lv.colour_off[cc]; k < lv.colour_off[cc + 1]; ++k) {
+        lv.task_woff[cc] = (int32_t)(lv.task_copy.size() / 64);
+        for (int32_t kk = lv.colour_off[cc]; kk < lv.colour_off[cc + 1] && ok; ++kk) {
           int p, co[3];
-          iface_decode(c, lv, lv.colour_list[k], p, co);
+          iface_decode(c, lv, lv.colour_list[kk], p, co);
           const int q0 = c->inc_off[p], q1 = c->inc_off[p + 1], cnt = q1 - q0;
-          if (cnt < 1 || cnt > 64 || co[1] > 0xffff || co[2] > 0x7fff) { ok = false; break; }
-          if (lv.task_p.size() % 64 + cnt > 64) pad_wave();
-          const int lead = (int)(lv.task_p.size() % 64);
+          if (cnt < 1 || cnt > 64) { ok = false; break; }
+          const int np = np_of[p < c->nV ? 0 : (p < c->nV + c->nE ? 1 : 2)];
+          if (lv.task_copy.size() % 64 + cnt > 64) pad_wave();
+          const int lead = (int)(lv.task_copy.size() % 64);
           for (int q = q0; q < q1; ++q) {
-            lv.task_p.push_back(p);
-            lv.task_q.push_back(q);
-            lv.task_co.push_back(co[1] | (co[2] << 16));
+            const Inc& in = c->inc[q];
+            int lc[4] = {0, 0, 0, 0};
+            for (int r = 0; r < np; ++r) lc[in.slot[r]] = co[r];
+            const int i = lc[1], j = lc[2], k = lc[3];
+            const int64_t loc = lin_closure(d, lv.n, i, j, k);
+            if (i < 0 || j < 0 || k < 0 || i + j + k > lv.n || loc < 0 || loc >= lv.Sraw || in.macro < 0 ||
+                in.macro >= c->nC || in.mask >= kMaxMask || zero_mask(d, lv.n, i, j, k) != in.mask) {
+              ok = false;
+              break;
+            }
+            lv.task_copy.push_back((int32_t)(in.macro * lv.S + loc));
+            lv.task_info.push_back(in.macro | (in.mask << 24) | ((c->primdir[p] ? 1 : 0) << 28));
+            lv.task_loc.push_back(i | (j << 11) | (k << 22));
             lv.task_seg.push_back(lead | (cnt << 8));
           }
         }
         pad_wave();
       }
       if (ok) {
-        lv.task_woff[lv.ncolours] = (int32_t)(lv.task_p.size() / 64);
+        lv.task_woff[lv.ncolours] = (int32_t)(lv.task_copy.size() / 64);
         const int nw = lv.task_woff[lv.ncolours];
         lv.task_wmax.assign(nw, 0);
         for (int w = 0; w < nw; ++w)
           for (int q = 0; q < 64; ++q) lv.task_wmax[w] = std::max(lv.task_wmax[w], lv.task_seg[w * 64 + q] >> 8);
-        for (int cc = Cint; cc < lv.ncolours; ++cc)
-          lv.max_class_waves = std::max(lv.max_class_waves, lv.task_woff[cc + 1] - lv.task_woff[cc]);
         lv.task_ok = true;
       } else {
-        lv.task_p.clear(); lv.task_q.clear(); lv.task_co.clear(); lv.task_seg.clear();
+        lv.task_copy.clear(); lv.task_info.clear(); lv.task_loc.clear(); lv.task_seg.clear();
         lv.task_woff.assign(lv.ncolours + 1, 0);
       }
     }
@@ -518,8 +530,9 @@ hhg_status build_colouring(hhg_ctx c) {
     lv.itab.clear();
     if (d == 2 && lv.NI > 0) {
       const int TI = 64 - 2 * Cint;   // one wavefront per tile of the fused sweep
-      for (int tj = 0; 1 + tj * kTileJ <= lv.n - 2; ++tj)
-        for (int ti = 0; 1 + ti * TI + 1 + tj * kTileJ <= lv.n - 1; ++ti) lv.tiles.push_back(ti | (tj << 16));
+      const int TJ = tile_rows(Cint);
+      for (int tj = 0; 1 + tj * TJ <= lv.n - 2; ++tj)
+        for (int ti = 0; 1 + ti * TI + 1 + tj * TJ <= lv.n - 1; ++ti) lv.tiles.push_back(ti | (tj << 16));
     }
     if (d == 3 && lv.NI > 0 && lv.n <= kMacroLdsN) {
       const int n = lv.n;
@@ -636,7 +649,7 @@ void plan_workspace(hhg_ctx c) {
   const Level& lt = c->lev[c->L];
   int64_t bpm = (lt.Sraw + 255) / 256;
   int64_t nblk_norm = nC * ((lt.NI + 255) / 256) + (lt.nIface + 255) / 256 + 16;
-  c->red_capacity = std::max<int64_t>(nC * bpm * 4, nblk_norm) + 1024;
+  c->red_capacity = std::max<int64_t>(std::max<int64_t>(nC * bpm * 4, nblk_norm), kNormBlocks + (lt.nIface + 255) / 256) + 1024;
   c->o_red = take(c->red_capacity * 8);
   c->o_scal = take(64 * 8);
   c->o_mxyz = take(nC * nv * d * 8);
@@ -657,9 +670,9 @@ void plan_workspace(hhg_ctx c) {
     lv.off_cl = take((int64_t)lv.colour_list.size() * 4);
     lv.off_tiles = take((int64_t)lv.tiles.size() * 4);
     lv.off_coff = take((int64_t)lv.colour_off.size() * 4);
-    lv.off_tp = take((int64_t)lv.task_p.size() * 4);
-    lv.off_tq = take((int64_t)lv.task_q.size() * 4);
-    lv.off_tco = take((int64_t)lv.task_co.size() * 4);
+    lv.off_tcopy = take((int64_t)lv.task_copy.size() * 4);
+    lv.off_tinfo = take((int64_t)lv.task_info.size() * 4);
+    lv.off_tloc = take((int64_t)lv.task_loc.size() * 4);
     lv.off_tseg = take((int64_t)lv.task_seg.size() * 4);
     lv.off_twmax = take((int64_t)lv.task_wmax.size() * 4);
     lv.off_twoff = take((int64_t)lv.task_woff.size() * 4);

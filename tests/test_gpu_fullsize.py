@@ -130,3 +130,106 @@ def test_full_size_solve_converges_and_estimates(lshape):
     assert abs(float(np.sum(est["eta_T"] ** 2)) - est["norm_e"] ** 2) <= 1e-12 * est["norm_e"] ** 2
     # the estimate is of the size of the error (effectivity in the range the paper reports)
     assert 0.2 < est["eta_j"] / err < 5.0
+
+
+def test_lshape_estimator_drives_one_more_k_step():
+    # one kl step on the L-shape workload: solve at L = 9, mark the 10 % of macros with the
+    # largest eta_T, red-green refine, set up again and solve; the L2 error against the exact
+    # solution drops
+    import torch
+    from paper_2508_06049_amd import HHG, mesh as hostmesh
+    from workloads.meshes import lshape_6tri
+    from workloads import problems
+    rg = hostmesh.RedGreen2D(lshape_6tri())
+    for _ in range(6):
+        cells, _ = rg.conforming()
+        origin = [v for v, q in enumerate(rg.X) if q == (0.0, 0.0)][0]
+        rg.refine([i for i, c in enumerate(cells) if origin in c])
+    L = 9
+    errs, sizes = [], []
+    marked = None
+    for step in range(2):
+        m = rg.mesh(f"kstep{step}")
+        _note("k-step", step, m.n_cells)
+        hh = HHG(m.coords, m.cells, L, smoother="multicolour")
+        X = hh.dof_coords().cpu().numpy()
+        g = to_dev(problems.lshape_u(X))
+        f = to_dev(np.zeros(len(X)))
+        u, st = hh.fmg_solve(f, g, nu=1, rtol=1e-10, max_iter=60)
+        e = to_dev(problems.lshape_u(X)) - u
+        errs.append(float(torch.dot(e, hh.mass_apply(e))) ** 0.5)
+        sizes.append(m.n_cells)
+        if step == 0:
+            est = hh.estimate(1)
+            eta = est["eta_T"]
+            assert np.all(np.isfinite(eta)) and np.all(eta >= 0)
+            marked = hostmesh.mark_fraction(eta, 0.10)
+            assert len(marked) == int(np.ceil(0.1 * m.n_cells))
+            assert np.min(eta[marked]) >= np.max(np.delete(eta, marked))
+            rg.conforming()
+            rg.refine(marked)
+        hh.close()
+        del hh
+        torch.cuda.synchronize()
+    assert sizes[1] > sizes[0]
+    assert errs[1] < errs[0]
+
+
+def test_cube_corner_workload_solves_and_estimates():
+    # workload 4 at full size (4334 macros, L = 5): the float64 and float32-refined solves
+    # agree, the error against |x|^(1/4) is small, sum_T eta_T^2 = ||e~_{L-1}||^2
+    import torch
+    from paper_2508_06049_amd import HHG, configs
+    w = configs.config(4)
+    _note("workload 4", w.mesh.n_cells, w.L)
+    hh = HHG(w.mesh.coords, w.mesh.cells, w.L, smoother=w.smoother)
+    X = hh.dof_coords().cpu().numpy()
+    f, g = to_dev(w.f(X)), to_dev(w.g(X))
+    u64, s64 = hh.fmg_solve(f, g, nu=1, rtol=1e-11, max_iter=60)
+    est = hh.estimate(1)
+    u32, s32 = hh.fmg_solve(f, g, nu=1, precision="fp32_refined", rtol=1e-11, max_iter=60)
+    assert s64.final_rel_residual <= 1e-11 and s32.final_rel_residual <= 1e-11
+    assert rel_err(to_host(u32), to_host(u64)) < 1e-6
+    e = to_dev(w.u_exact(X)) - u64
+    err = float(torch.dot(e, hh.mass_apply(e))) ** 0.5
+    assert err < 1e-3
+    assert abs(float(np.sum(est["eta_T"] ** 2)) - est["norm_e"] ** 2) <= 1e-10 * est["norm_e"] ** 2
+    assert 0.0 < est["theta"] < 1.0
+
+
+def test_adjoint_workload_gradient_full_size():
+    # workload 5 at full size (384 macros, L = 6, 257^3 DoFs): autograd through the adjoint
+    # FMG against central finite differences in two macro coefficients and along one
+    # right-hand-side direction
+    import torch
+    from paper_2508_06049_amd import HHG, configs, hhg_solve
+    from workloads import problems
+    w = configs.config(5)
+    _note("workload 5 adjoint", w.mesh.n_cells, w.L)
+    hh = HHG(w.mesh.coords, w.mesh.cells, w.L, smoother=w.smoother, kappa_cell=w.kappa_cell)
+    X = hh.dof_coords().cpu().numpy()
+    f0 = to_dev(w.f(X))
+    g = to_dev(np.zeros(len(X)))
+    wM = hh.mass_apply(to_dev(w.goal_weight(X)))
+    opts = dict(nu=1, rtol=1e-12, max_iter=60)
+    ft = f0.clone().requires_grad_(True)
+    kt = torch.tensor(w.kappa_cell, dtype=torch.float64, requires_grad=True)
+    torch.dot(wM, hhg_solve(hh, ft, g, kappa=kt, **opts)).backward()
+    k0 = torch.tensor(w.kappa_cell, dtype=torch.float64)
+
+    def J(fv, kv):
+        with torch.no_grad():
+            return float(torch.dot(wM, hhg_solve(hh, fv, g, kappa=kv, **opts)))
+
+    gk = kt.grad.numpy()
+    for e in (int(np.argmax(np.abs(gk))), 100):
+        he = 1e-4 * w.kappa_cell[e]
+        kp, km = k0.clone(), k0.clone()
+        kp[e] += he
+        km[e] -= he
+        fd = (J(f0, kp) - J(f0, km)) / (2 * he)
+        assert abs(fd - gk[e]) <= 1e-5 * np.abs(gk).max()
+    d = to_dev(np.random.default_rng(4).standard_normal(len(X)))
+    fd = (J(f0 + 1e-2 * d, k0) - J(f0 - 1e-2 * d, k0)) / 2e-2
+    an = float(torch.dot(ft.grad, d))
+    assert abs(fd - an) <= 1e-6 * abs(an)

@@ -205,6 +205,18 @@ def test_estimate_requires_solve():
     hh = hip_context(m, 3, "redblack")
     with pytest.raises(HHGError):
         hh.estimate(1)
+    # operator applications keep the solve's state, a smoother call on the iterate drops it
+    h, perms = oracle_hierarchy(m, 3)
+    X = h.levels[3].X
+    f, g = _rhs("square", X, 2)
+    u, _ = hh.fmg_solve(to_dev(f[perms[3]]), to_dev(g[perms[3]]), nu=1)
+    e1 = hh.estimate(1)
+    hh.mass_apply(u)
+    hh.apply(3, "stiffness", u)
+    assert hh.estimate(1)["eta_j"] == e1["eta_j"]
+    hh.smooth(3, u, u, 1)
+    with pytest.raises(HHGError):
+        hh.estimate(1)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
