@@ -79,10 +79,12 @@ typedef struct {
                                  rounding; for checking the fused kernels).
                                  HHG_FLAG_NO_LANE_IFACE: update interface DoFs one thread per
                                  DoF instead of one lane per (DoF, macro) pair (same result up
-                                 to rounding; for checking the lane-parallel kernels)         */
+                                 to rounding; for checking the lane-parallel kernels).
+                                 HHG_FLAG_NO_GRAPH: launch every kernel of a solve directly
+                                 instead of replaying recorded HIP graphs (same result)       */
 } hhg_options;
 
-enum { HHG_FLAG_NO_FUSED = 1, HHG_FLAG_NO_LANE_IFACE = 2 };
+enum { HHG_FLAG_NO_FUSED = 1, HHG_FLAG_NO_LANE_IFACE = 2, HHG_FLAG_NO_GRAPH = 4 };
 
 typedef struct {
   int nu;                     /* V-cycles per FMG level (Algorithm 4's nu)                     */

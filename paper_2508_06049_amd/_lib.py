@@ -23,6 +23,7 @@ HHG_FP64, HHG_FP32_REFINED = 0, 1
 HHG_OP_STIFFNESS, HHG_OP_MASS = 0, 1
 HHG_FLAG_NO_FUSED = 1
 HHG_FLAG_NO_LANE_IFACE = 2
+HHG_FLAG_NO_GRAPH = 4
 
 SMOOTHERS = {"redblack": HHG_GS_REDBLACK, "multicolour": HHG_GS_MULTICOLOR, "jacobi": HHG_JACOBI}
 PRECISIONS = {"fp64": HHG_FP64, "fp32_refined": HHG_FP32_REFINED}

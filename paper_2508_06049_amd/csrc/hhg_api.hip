@@ -51,7 +51,7 @@ thread_local std::string g_err;
     if (s_ != HHG_OK) return s_;     \
   } while (0)
 
-inline hipStream_t ST(hhg_ctx c) { return (hipStream_t)c->stream; }
+inline hipStream_t ST(hhg_ctx c) { return (hipStream_t)(c->capturing ? c->cap_stream : c->stream); }
 
 LK lk_of(hhg_ctx c, int l) {
   const Level& lv = c->lev[l];
@@ -225,15 +225,22 @@ hhg_status vcycle(hhg_ctx c, int l, const T* b, int pre, int post, bool x_is_zer
   return HHG_OK;
 }
 
-// one cycle on level l of the selected precision for x_l (float64) and rhs bf_l
-hhg_status cycle(hhg_ctx c, int l, const double* b, const hhg_solve_params& p) {
+// float64 residual of level l rounded to the float32 right-hand side b32_l of the correction
+// equation; interface rows are summed over their copies in float64 before rounding and kept
+// in the owner copy only
+void residual_f32(hhg_ctx c, int l, const double* b) {
   Level& lv = c->lev[l];
-  if (p.precision == HHG_FP64) return vcycle<double>(c, l, b, p.pre, p.post, false);
-  // residual in float64, stored as float32 right-hand side of the correction equation
   launch_apply<double, float>(c->dim, p1(c), lk_of(c, l), c->tab, lv.x, b, lv.b32, 0, sA(c, l), 1.0, -1.0, 1, lv.kn,
                               ST(c));
-  // interface rows: sum the per-macro partials in float64 before rounding (owner copy only)
   launch_iface_residual<double, float>(c->dim, p1(c), lk_of(c, l), c->tab, lv.x, b, lv.b32, sA(c, l), lv.kn, ST(c));
+}
+
+// one cycle on level l of the selected precision for x_l (float64) and rhs bf_l; with
+// rhs_ready the float32 right-hand side b32_l already holds the current residual
+hhg_status cycle(hhg_ctx c, int l, const double* b, const hhg_solve_params& p, bool rhs_ready = false) {
+  Level& lv = c->lev[l];
+  if (p.precision == HHG_FP64) return vcycle<double>(c, l, b, p.pre, p.post, false);
+  if (!rhs_ready) residual_f32(c, l, b);
   launch_fill<float>(lv.x32, lv.nfull, 0.0f, ST(c));
   TRY(vcycle<float>(c, l, lv.b32, p.pre, p.post, l == 0));
   launch_add_f32(lv.x, lv.x32, lv.nfull, ST(c));
@@ -254,19 +261,72 @@ hhg_status residual_norm(hhg_ctx c, int l, const double* x, const double* b, dou
   return HHG_OK;
 }
 
+void drop_graphs(hhg_ctx c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy((hipGraphExec_t)kv.second);
+  c->graphs.clear();
+}
+
+// Run body() on the caller's stream, through a recorded HIP graph when possible: the first
+// call with a key records body() on the private capture stream (nothing executes while
+// recording), later calls replay it.  body() must only launch kernels (no copies, no
+// synchronisation) and must leave the host-side buffer roles as it found them; the callers
+// guarantee the latter by using graphs only for even pre- and post-smoothing counts (each
+// 2D sweep swaps the two iterate buffers).
+template <class F>
+hhg_status run_recorded(hhg_ctx c, int64_t key, F&& body) {
+  if (c->no_graph || c->prof_on || c->capturing) return body();
+  hipGraphExec_t ex = nullptr;
+  for (auto& kv : c->graphs)
+    if (kv.first == key) ex = (hipGraphExec_t)kv.second;
+  if (!ex) {
+    if (!c->cap_stream) {
+      hipStream_t cs;
+      HIPCHK(hipStreamCreate(&cs));
+      c->cap_stream = cs;
+    }
+    HIPCHK(hipStreamBeginCapture((hipStream_t)c->cap_stream, hipStreamCaptureModeThreadLocal));
+    c->capturing = true;
+    const hhg_status s = body();
+    c->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture((hipStream_t)c->cap_stream, &g);
+    if (s != HHG_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess || !g) { c->err = std::string("HIP graph capture: ") + hipGetErrorString(e); return HHG_EHIP; }
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) { c->err = std::string("HIP graph instantiation: ") + hipGetErrorString(ei); return HHG_EHIP; }
+    c->graphs.push_back({key, (void*)ex});
+  }
+  HIPCHK(hipGraphLaunch(ex, (hipStream_t)c->stream));
+  return HHG_OK;
+}
+
+int64_t graph_key(int kind, const hhg_solve_params& p) {
+  return (int64_t)kind | ((int64_t)p.nu << 4) | ((int64_t)p.pre << 12) | ((int64_t)p.post << 20) |
+         ((int64_t)p.precision << 28);
+}
+
 // FMG given bf_l and g_l on all levels; result in lev[L].x, w_l in lev[l+1].w
 hhg_status fmg_core(hhg_ctx c, const hhg_solve_params& p, hhg_solve_stats* stats) {
   const int L = c->L;
-  int vcycles = 0;
-  Level& l0 = c->lev[0];
-  launch_init_dirichlet(c->dim, lk_of(c, 0), c->tab, l0.g, l0.x, 0.0, ST(c));
-  TRY(coarse_step<double>(c, l0.bf, false));
-  for (int l = 1; l <= L; ++l) {
-    Level& lv = c->lev[l];
-    launch_prolong<double>(c->dim, lk_of(c, l), lk_of(c, l - 1), c->tab, c->lev[l - 1].x, lv.x, lv.w, lv.g, 2, ST(c));
-    for (int it = 0; it < p.nu; ++it) { TRY(cycle(c, l, lv.bf, p)); ++vcycles; }
-  }
-  LAUNCHCHK();
+  const bool rec = p.pre % 2 == 0 && p.post % 2 == 0;
+  auto body = [&]() -> hhg_status {
+    Level& l0 = c->lev[0];
+    launch_init_dirichlet(c->dim, lk_of(c, 0), c->tab, l0.g, l0.x, 0.0, ST(c));
+    TRY(coarse_step<double>(c, l0.bf, false));
+    for (int l = 1; l <= L; ++l) {
+      Level& lv = c->lev[l];
+      launch_prolong<double>(c->dim, lk_of(c, l), lk_of(c, l - 1), c->tab, c->lev[l - 1].x, lv.x, lv.w, lv.g, 2, ST(c));
+      for (int it = 0; it < p.nu; ++it) TRY(cycle(c, l, lv.bf, p));
+    }
+    LAUNCHCHK();
+    return HHG_OK;
+  };
+  TRY(rec ? run_recorded(c, graph_key(1, p), body) : body());
+  int vcycles = p.nu * L;
   int extra = 0;
   double rel = 0.0;
   if (p.max_iter > 0) {
@@ -279,10 +339,31 @@ hhg_status fmg_core(hhg_ctx c, const hhg_solve_params& p, hhg_solve_stats* stats
     rel = r0 > 0 ? r / r0 : 0.0;
     c->res_hist.clear();
     while (extra < p.max_iter && rel > p.rtol) {
-      TRY(cycle(c, L, lL.bf, p));
+      // one cycle and the residual it leaves, then the norm to the host.  In the float32-refined
+      // form the residual is the rounded, interface-assembled right-hand side of the next
+      // cycle's correction equation (its norm is exact to float32 rounding of the entries),
+      // so the next cycle does not recompute it
+      const bool f32 = p.precision == HHG_FP32_REFINED, ready = f32 && extra > 0;
+      auto step = [&]() -> hhg_status {
+        TRY(cycle(c, L, lL.bf, p, ready));
+        if (f32) {
+          residual_f32(c, L, lL.bf);
+          launch_sqnorm_closure<float>(c->dim, lk_of(c, L), lL.b32, c->d_red, c->d_scal, ST(c));
+        } else {
+          launch_apply<double, double>(c->dim, p1(c), lk_of(c, L), c->tab, lL.x, lL.bf, lL.t, 0, sA(c, L), 1.0, -1.0, 1,
+                                       lL.kn, ST(c));
+          launch_sqnorm(c->dim, lk_of(c, L), c->tab, lL.t, c->d_red, c->d_scal, ST(c));
+        }
+        LAUNCHCHK();
+        return HHG_OK;
+      };
+      TRY(rec ? run_recorded(c, graph_key(ready ? 3 : 2, p), step) : step());
       ++extra;
       ++vcycles;
-      TRY(residual_norm(c, L, lL.x, lL.bf, &r));
+      double h = 0;
+      HIPCHK(hipMemcpyAsync(&h, c->d_scal, sizeof(double), hipMemcpyDeviceToHost, ST(c)));
+      HIPCHK(hipStreamSynchronize(ST(c)));
+      r = std::sqrt(h);
       rel = r0 > 0 ? r / r0 : 0.0;
       c->res_hist.push_back(rel);
       if (!std::isfinite(rel)) { c->err = "residual is not finite"; return HHG_ENOTCONV; }
@@ -406,6 +487,7 @@ hhg_status hhg_setup(const hhg_mesh* mesh, int L, const hhg_options* opt, hhg_ct
   c->opt = *opt;
   c->no_fused = (opt->flags & HHG_FLAG_NO_FUSED) != 0;
   c->no_tasks = (opt->flags & HHG_FLAG_NO_LANE_IFACE) != 0;
+  c->no_graph = (opt->flags & HHG_FLAG_NO_GRAPH) != 0;
   c->nV = mesh->n_vertices;
   c->nC = mesh->n_cells;
   const int nv = c->dim + 1;
@@ -549,6 +631,7 @@ hhg_status hhg_bind_workspace(hhg_ctx c, void* ptr, size_t bytes, void* stream) 
     c->ev0 = a;
     c->ev1 = b;
   }
+  drop_graphs(c);   // recorded launches refer to the previous workspace and stream
   c->bound = true;
   c->solved = false;
   return upload_coarse(c);
@@ -815,6 +898,8 @@ hhg_status hhg_residual_history(hhg_ctx c, double* out, int capacity, int* count
 
 void hhg_destroy(hhg_ctx c) {
   if (!c) return;
+  drop_graphs(c);
+  if (c->cap_stream) (void)hipStreamDestroy((hipStream_t)c->cap_stream);
   for (void* e : c->prof_ev) (void)hipEventDestroy((hipEvent_t)e);
   if (c->ev0) (void)hipEventDestroy((hipEvent_t)c->ev0);
   if (c->ev1) (void)hipEventDestroy((hipEvent_t)c->ev1);

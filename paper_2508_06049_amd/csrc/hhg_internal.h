@@ -183,6 +183,13 @@ struct hhg_ctx_s {
   bool prof_on = false;
   bool no_fused = false;            // force class-by-class interior launches (testing)
   bool no_tasks = false;            // force the per-DoF interface kernels (testing)
+  // HIP graphs of the launch-bound sequences (FMG body; one extra cycle with its residual
+  // norm), recorded once per parameter set on a private capture stream and replayed on the
+  // caller's stream; key = kind | nu << 4 | pre << 12 | post << 20 | precision << 28
+  bool no_graph = false;            // run every launch eagerly (testing)
+  void* cap_stream = nullptr;       // hipStream_t used only while recording
+  bool capturing = false;
+  std::vector<std::pair<int64_t, void*>> graphs;   // (key, hipGraphExec_t)
   double prof_bytes = 0.0;
 
   std::string err;

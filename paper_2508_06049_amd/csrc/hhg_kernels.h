@@ -65,6 +65,9 @@ template <typename T>
 void launch_coarse(int n0, const int32_t* coff, const int64_t* copy, const double* Ainv, const T* rhs, T* x, int accumulate,
                    hipStream_t st);
 void launch_sqnorm(int dim, const LK& lk, const Tables& tb, const double* r, double* partial, double* out, hipStream_t st);
+// sum of squares of every closure entry (interface rows assembled in one copy)
+template <typename T>
+void launch_sqnorm_closure(int dim, const LK& lk, const T* r, double* partial, double* out, hipStream_t st);
 void launch_estimate(int dim, const LK& f, const LK& c, const Tables& tb, const double* u, const double* a,
                      const double* bc, double* partial, double* out, double sM, hipStream_t st);
 void launch_bilinear(int dim, const LK& lk, const Tables& tb, const double* x, const double* y, double* partial,

@@ -1150,6 +1150,41 @@ __global__ void __launch_bounds__(256) k_sq_interior(LK lk, const double* __rest
   if (threadIdx.x == 0) partial[blockIdx.x] = v;
 }
 
+// sum of squares over every closure entry (a vector whose interface rows are already
+// assembled in one copy, all other copies and Dirichlet rows 0), accumulated in float64; row
+// wavefronts on a fixed grid as k_sq_interior
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_sq_closure(LK lk, const T* __restrict__ r, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const int n = lk.n;
+  const int64_t rows = (int64_t)lk.nmacro * (n + 1) * (D == 3 ? (n + 1) : 1);
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  const int lane = threadIdx.x & 63;
+  double v = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); g < rows; g += nw) {
+    int64_t m;
+    int j, k = 0;
+    if constexpr (D == 2) {
+      m = g / (n + 1);
+      j = (int)(g - m * (n + 1));
+    } else {
+      const int64_t jk = g % ((int64_t)(n + 1) * (n + 1));
+      m = g / ((int64_t)(n + 1) * (n + 1));
+      k = (int)(jk / (n + 1));
+      j = (int)(jk - (int64_t)k * (n + 1));
+    }
+    const int ilast = n - j - k;   // closure nodes i = 0 .. ilast
+    if (ilast < 0) continue;
+    const int64_t rb = m * lk.S + d_lin<D>(n, 0, j, k);
+    for (int i = lane; i <= ilast; i += 64) {
+      const double x = (double)r[rb + i];
+      v += x * x;
+    }
+  }
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = v;
+}
+
 // sum over non-Dirichlet interface DoFs of (sum of copies)^2 (dual vector)
 template <int D>
 __global__ void __launch_bounds__(256) k_sq_iface(LK lk, Tables tb, const double* __restrict__ r, double* __restrict__ partial) {
@@ -1562,6 +1597,16 @@ void launch_sqnorm(int dim, const LK& lk, const Tables& tb, const double* r, dou
   }
   k_sum<<<1, 256, 0, st>>>(partial, (int)(g1 + g2), out);
 }
+
+template <typename T>
+void launch_sqnorm_closure(int dim, const LK& lk, const T* r, double* partial, double* out, hipStream_t st) {
+  const int64_t rows = (int64_t)lk.nmacro * (lk.n + 1) * (dim == 3 ? (lk.n + 1) : 1);
+  const unsigned g1 = (unsigned)std::min<int64_t>(kNormBlocks, (rows + 3) / 4);
+  if (dim == 3) k_sq_closure<3, T><<<g1, 256, 0, st>>>(lk, r, partial);
+  else k_sq_closure<2, T><<<g1, 256, 0, st>>>(lk, r, partial);
+  k_sum<<<1, 256, 0, st>>>(partial, (int)g1, out);
+}
+template void launch_sqnorm_closure<float>(int, const LK&, const float*, double*, double*, hipStream_t);
 
 void launch_estimate(int dim, const LK& f, const LK& c, const Tables& tb, const double* u, const double* a,
                      const double* bc, double* partial, double* out, double sM, hipStream_t st) {

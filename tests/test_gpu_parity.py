@@ -283,3 +283,35 @@ def test_mixed_precision_reaches_fp64_solution(name):
     ug, st = hh.fmg_solve(to_dev(f[p]), to_dev(g[p]), nu=1, precision="fp32_refined", rtol=1e-12, max_iter=60)
     assert st.final_rel_residual <= 1e-12
     assert np.abs(to_host(ug) - ud[p]).max() <= 1e-9 * np.abs(ud).max()
+
+
+@pytest.mark.parametrize("name,precision", [("lshape", "fp64"), ("lshape", "fp32_refined"), ("kuhn2", "fp64")])
+def test_recorded_graphs_replay_equal_eager(name, precision):
+    # the solve replays recorded HIP graphs (FMG body, extra cycles with their norms); every
+    # replay, with eager library work and synchronisations in between, must reproduce the
+    # eager launches bit for bit
+    import torch
+    from paper_2508_06049_amd import HHG
+    from paper_2508_06049_amd._lib import HHG_FLAG_NO_GRAPH
+    mk, L, sm = MESHES[name]
+    _note("graphs", name, precision)
+    m = mk()
+    X = None
+    ref = None
+    hh_e = HHG(m.coords, m.cells, L, smoother=sm, flags=HHG_FLAG_NO_GRAPH)
+    X = hh_e.dof_coords().cpu().numpy()
+    f, g = _rhs(name, X, m.dim)
+    fd, gd = to_dev(f), to_dev(g)
+    kw = dict(nu=1, precision=precision, rtol=1e-10, max_iter=30)
+    ue, se = hh_e.fmg_solve(fd, gd, **kw)
+    ee = hh_e.estimate(1)
+    ref = to_host(ue)
+    hh = HHG(m.coords, m.cells, L, smoother=sm)
+    for rep in range(3):
+        u, s = hh.fmg_solve(fd, gd, **kw)
+        assert s.vcycles == se.vcycles and s.ir_steps == se.ir_steps
+        assert np.array_equal(to_host(u), ref)
+        assert hh.estimate(1)["eta_j"] == ee["eta_j"]
+        # eager work between replays
+        hh.apply(L, "stiffness", u)
+        torch.cuda.synchronize()
