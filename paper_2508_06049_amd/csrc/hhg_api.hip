@@ -107,7 +107,8 @@ void interior_launch(hhg_ctx c, int l, const LK& k, const T* x, T* y, const T* b
   if (rec) (void)hipEventRecord((hipEvent_t)c->prof_ev[c->prof_used], ST(c));
   int64_t npts;
   if (col < 0) {   // all interior colours fused in one launch
-    launch_gs_fused<T>(c->dim, p1(c), k, c->tab, const_cast<T*>(x), y, b, lv.d_tiles, (int)lv.tiles.size(), lv.d_itab, rb,
+    launch_gs_fused<T>(c->dim, p1(c), k, c->tab, const_cast<T*>(x), y, b, lv.d_tiles, (int)lv.tiles.size(), lv.d_itab,
+                       lv.d_itab_off, rb,
                        sA(c, l), fine, ST(c));
     npts = lv.NI * c->nC;
   } else {
@@ -623,6 +624,8 @@ hhg_status hhg_bind_workspace(hhg_ctx c, void* ptr, size_t bytes, void* stream) 
     HIPCHK(up(lv.off_tiles, lv.tiles.data(), lv.tiles.size() * 4));
     lv.d_itab = (uint32_t*)(w + lv.off_itab);
     HIPCHK(up(lv.off_itab, lv.itab.data(), lv.itab.size() * 4));
+    lv.d_itab_off = (int32_t*)(w + lv.off_itoff);
+    HIPCHK(up(lv.off_itoff, lv.itab_off.data(), lv.itab_off.size() * 4));
   }
   if (!c->ev0) {
     hipEvent_t a, b;

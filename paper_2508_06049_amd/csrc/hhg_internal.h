@@ -29,7 +29,11 @@ constexpr int kNType3 = 6, kNType2 = 2;
 constexpr int kTileJ = 32;
 // multicolour (C = 3) tiles are 30 rows high, so every tile starts on a row = 1 (mod 3)
 constexpr int kTileJ3 = 30;
-constexpr int tile_rows(int C) { return C == 3 ? kTileJ3 : kTileJ; }
+// tile height by level: small levels (n <= 16) use short tiles, which shortens the per-tile
+// chain of the fused sweep; multicolour heights stay multiples of 3 (and of 3 per half tile)
+constexpr int tile_rows(int C, int n) {
+  return C == 3 ? (n <= 8 ? 6 : (n <= 16 ? 18 : kTileJ3)) : (n <= 8 ? 8 : (n <= 16 ? 16 : kTileJ));
+}
 constexpr int kMacroLdsN = 32;
 // levels whose largest interface colour class has at most this many DoFs sweep all interface
 // classes in one single-workgroup launch
@@ -111,6 +115,9 @@ struct Level {
   std::vector<uint32_t> itab;          // 3D, n <= kMacroLdsN: interior points (i | j << 10 | k << 20)
   int32_t* d_tiles = nullptr;
   uint32_t* d_itab = nullptr;
+  std::vector<int32_t> itab_off;       // 3D: colour offsets of itab per parity pattern
+  int32_t* d_itab_off = nullptr;
+  int64_t off_itoff = 0;
   int64_t off_x = 0, off_t = 0, off_bf = 0, off_rc = 0, off_g = 0, off_w = 0, off_kn = -1, off_x32 = 0, off_t32 = 0,
           off_b32 = 0, off_cl = 0, off_tiles = 0, off_itab = 0, off_x2 = 0, off_x2_32 = 0, off_coff = 0;
 };

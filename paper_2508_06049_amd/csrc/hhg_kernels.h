@@ -24,7 +24,8 @@ void launch_smooth_interior(int dim, bool p1, const LK& lk, const Tables& tb, co
 // (2D reads u and writes the interior of uo; 3D updates u in place and ignores uo)
 template <typename T>
 bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* uo, const T* b, const int32_t* tiles,
-                     int ntiles, const uint32_t* itab, int rb, double sA, bool fine, hipStream_t st);
+                     int ntiles, const uint32_t* itab, const int32_t* itab_off, int rb, double sA, bool fine,
+                     hipStream_t st);
 // interface update of one colour class (xi: source of interior neighbours, xf: of interface
 // neighbours; umirror, if not NULL, receives the new values too)
 // lane-parallel interface update of the wavefronts w0..w1-1 (one colour class), or of all

@@ -392,6 +392,7 @@ __device__ __forceinline__ void iface_task_wave(const LK& lk, const Tables& tb, 
   const int idx = w * 64 + lane;
   const uint32_t vbytes = (uint32_t)((int64_t)lk.nmacro * lk.S) * (uint32_t)sizeof(T);
   const __amdgpu_buffer_rsrc_t rxi = d_rsrc(xi, vbytes), rxf = d_rsrc(xf, vbytes), rb = d_rsrc(b, vbytes);
+  const bool same = xi == xf;
   const int cp = tcopy[idx];
   const int info = tinfo[idx], loc = tloc[idx], seg = tseg[idx];
   T rhs = (T)0, off = (T)0, diag = (T)0, uold = (T)0;
@@ -415,26 +416,36 @@ __device__ __forceinline__ void iface_task_wave(const LK& lk, const Tables& tb, 
         const int i2 = i + a, j2 = j + b2, k2 = k + c;
         const uint32_t o = (uint32_t)(base + d_lin<D>(lk.n, i2, j2, k2)) * (uint32_t)sizeof(T);
         T v;
-        if (d_mask<D>(lk.n, i2, j2, k2)) d_bload(rxf, o, v);
-        else d_bload(rxi, o, v);
+        if (same) {
+          d_bload(rxf, o, v);
+        } else {
+          // interface neighbours from xf, interior ones from xi: both loads, one select (the
+          // descriptors stay uniform)
+          T vi, vf;
+          d_bload(rxi, o, vi);
+          d_bload(rxf, o, vf);
+          v = d_mask<D>(lk.n, i2, j2, k2) ? vf : vi;
+        }
         off += (T)(scale * W[dd]) * v;
       }
       diag = (T)(scale * W[0]);
     }
   }
-  // segment sums; every lane of the wavefront takes part in every shuffle
+  // segment sums of (rhs - off) and diag; every lane of the wavefront takes part in every
+  // shuffle
   const int lead = seg & 63, len = seg >> 8;
-  T srhs = (T)0, soff = (T)0, sdiag = (T)0;
+  const T num = rhs - off;
+  T snum = (T)0, sdiag = (T)0;
   for (int kq = 0; kq < wmax; ++kq) {
     const int src = min(lead + kq, 63);
-    const T a = __shfl(rhs, src, 64), o = __shfl(off, src, 64), d = __shfl(diag, src, 64);
-    if (kq < len) { srhs += a; soff += o; sdiag += d; }
+    const T a = __shfl(num, src, 64), d = __shfl(diag, src, 64);
+    if (kq < len) { snum += a; sdiag += d; }
   }
   if (!live) return;
   T unew;
   if (dir) unew = uold;
-  else if (jacobi) unew = uold + (T)omega * (srhs - soff - sdiag * uold) / sdiag;
-  else unew = (srhs - soff) / sdiag;
+  else if (jacobi) unew = uold + (T)omega * (snum - sdiag * uold) / sdiag;
+  else unew = snum / sdiag;
   const uint32_t oc = (uint32_t)cp * (uint32_t)sizeof(T);
   d_bstore(d_rsrc(uout, vbytes), oc, unew);
   if (umirror) d_bstore(d_rsrc(umirror, vbytes), oc, unew);
@@ -731,7 +742,8 @@ __global__ void __launch_bounds__(256) k_gs2d_fused(LK lk, Tables tb, const T* _
 // update from global memory.
 template <typename T, int C, bool FINE>
 __global__ void __launch_bounds__(1024) k_gs3d_macro(LK lk, Tables tb, T* __restrict__ u, const T* __restrict__ b,
-                                                      const uint32_t* __restrict__ itab, int rb, double sA) {
+                                                      const uint32_t* __restrict__ itab_all,
+                                                      const int32_t* __restrict__ itab_off, int rb, double sA) {
   extern __shared__ unsigned char smem_raw[];
   T* su = reinterpret_cast<T*>(smem_raw);
   const int m = blockIdx.x;
@@ -744,14 +756,15 @@ __global__ void __launch_bounds__(1024) k_gs3d_macro(LK lk, Tables tb, T* __rest
   T w[15];
 #pragma unroll
   for (int q = 0; q < 15; ++q) w[q] = (T)(ks * W[q]);
+  // the interior points of this macro's parity pattern, sorted by colour
   const int* rp = tb.rbpar + m * 4;
-  const int s1 = rb ? rp[1] : 0, s2 = rb ? rp[2] : 0, s3 = rb ? rp[3] : 0;
+  const int pat = rb ? ((rp[1] & 1) | ((rp[2] & 1) << 1) | ((rp[3] & 1) << 2)) : 0;
+  const uint32_t* itab = itab_all + (size_t)pat * lk.NI;
+  const int32_t* off = itab_off + pat * (C + 1);
   for (int c = 0; c < C; ++c) {
-    for (int t = threadIdx.x; t < lk.NI; t += blockDim.x) {
+    for (int t = off[c] + (int)threadIdx.x; t < off[c + 1]; t += blockDim.x) {
       const uint32_t pk = itab[t];
       const int i = pk & 1023, j = (pk >> 10) & 1023, k = pk >> 20;
-      const int col = rb ? ((i * s1 + j * s2 + k * s3) & 1) : (i + 2 * j + 3 * k) % 4;
-      if (col != c) continue;
       T acc = (T)0;
 #pragma unroll
       for (int q = 1; q < 15; ++q) acc += w[q] * su[d_lin<3>(n, i + kOff3[q][0], j + kOff3[q][1], k + kOff3[q][2])];
@@ -1117,10 +1130,31 @@ __global__ void __launch_bounds__(256) k_coarse(int n0, const int32_t* __restric
 // sum over macro-interior nodes of r^2 (per block partials)
 template <int D>
 __global__ void __launch_bounds__(256) k_sq_interior(LK lk, const double* __restrict__ r, double* __restrict__ partial) {
-  // one wavefront per interior row (lanes along i), a fixed grid striding over all rows of all
-  // macros, one partial per block: the sum order depends only on the sizes
+  // 2D: one wavefront per interior row (lanes along i); 3D (short rows): 256-entry chunks of
+  // the contiguous macro blocks with a decode.  A fixed grid strides over all of them, one
+  // partial per block: the sum order depends only on the sizes
   __shared__ double sh[4];
   const int n = lk.n;
+  if constexpr (D == 3) {
+    const int nch = (lk.Sraw + 255) >> 8;
+    const int64_t nchunks = (int64_t)lk.nmacro * nch;
+    double v3 = 0.0;
+    for (int64_t g = blockIdx.x; g < nchunks; g += gridDim.x) {
+      const int64_t m = g / nch;
+      const int s = (int)(g - m * nch) * 256 + (int)threadIdx.x;
+      if (s < lk.Sraw) {
+        int i, j, k;
+        d_dec<3>(n, s, i, j, k);
+        if (d_mask<3>(n, i, j, k) == 0) {
+          const double x = r[m * lk.S + s];
+          v3 += x * x;
+        }
+      }
+    }
+    v3 = block_sum(v3, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = v3;
+    return;
+  }
   const int64_t rows = (int64_t)lk.nmacro * (n + 1) * (D == 3 ? (n + 1) : 1);
   const int64_t nw = (int64_t)gridDim.x * 4;
   const int lane = threadIdx.x & 63;
@@ -1151,33 +1185,20 @@ __global__ void __launch_bounds__(256) k_sq_interior(LK lk, const double* __rest
 }
 
 // sum of squares over every closure entry (a vector whose interface rows are already
-// assembled in one copy, all other copies and Dirichlet rows 0), accumulated in float64; row
-// wavefronts on a fixed grid as k_sq_interior
+// assembled in one copy, all other copies and Dirichlet rows 0), accumulated in float64.  The
+// closure of a macro is contiguous, so blocks stride over 256-entry chunks of the macro blocks
+// (fixed grid, one partial per block).
 template <int D, typename T>
 __global__ void __launch_bounds__(256) k_sq_closure(LK lk, const T* __restrict__ r, double* __restrict__ partial) {
   __shared__ double sh[4];
-  const int n = lk.n;
-  const int64_t rows = (int64_t)lk.nmacro * (n + 1) * (D == 3 ? (n + 1) : 1);
-  const int64_t nw = (int64_t)gridDim.x * 4;
-  const int lane = threadIdx.x & 63;
+  const int nch = (lk.Sraw + 255) >> 8;
+  const int64_t nchunks = (int64_t)lk.nmacro * nch;
   double v = 0.0;
-  for (int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); g < rows; g += nw) {
-    int64_t m;
-    int j, k = 0;
-    if constexpr (D == 2) {
-      m = g / (n + 1);
-      j = (int)(g - m * (n + 1));
-    } else {
-      const int64_t jk = g % ((int64_t)(n + 1) * (n + 1));
-      m = g / ((int64_t)(n + 1) * (n + 1));
-      k = (int)(jk / (n + 1));
-      j = (int)(jk - (int64_t)k * (n + 1));
-    }
-    const int ilast = n - j - k;   // closure nodes i = 0 .. ilast
-    if (ilast < 0) continue;
-    const int64_t rb = m * lk.S + d_lin<D>(n, 0, j, k);
-    for (int i = lane; i <= ilast; i += 64) {
-      const double x = (double)r[rb + i];
+  for (int64_t g = blockIdx.x; g < nchunks; g += gridDim.x) {
+    const int64_t m = g / nch;
+    const int s = (int)(g - m * nch) * 256 + (int)threadIdx.x;
+    if (s < lk.Sraw) {
+      const double x = (double)r[m * lk.S + s];
       v += x * x;
     }
   }
@@ -1418,15 +1439,24 @@ void launch_smooth_interior(int dim, bool p1, const LK& lk, const Tables& tb, co
 
 template <typename T>
 bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* uo, const T* b, const int32_t* tiles,
-                     int ntiles, const uint32_t* itab, int rb, double sA, bool fine, hipStream_t st) {
+                     int ntiles, const uint32_t* itab, const int32_t* itab_off, int rb, double sA, bool fine,
+                     hipStream_t st) {
   if (p1 || lk.NI <= 0) return false;
   if (dim == 2) {
     if (ntiles <= 0) return false;
     const unsigned g = (unsigned)(((int64_t)lk.nmacro * ntiles + 31) / 32 * 8);   // 4 tiles per block, 8 XCDs
-#define HHG_F2(C, F) \
-  k_gs2d_fused<T, C, tile_rows(C), sizeof(T) == 8 ? 2 : 1, F><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA)
-    if (rb) { if (fine) HHG_F2(2, true); else HHG_F2(2, false); }
-    else { if (fine) HHG_F2(3, true); else HHG_F2(3, false); }
+#define HHG_F2(C, N, F)                                                                                          \
+  k_gs2d_fused<T, C, tile_rows(C, N), (sizeof(T) == 8 && tile_rows(C, N) > 18) ? 2 : 1, F><<<g, 256, 0, st>>>(       \
+      lk, tb, u, uo, b, tiles, ntiles, rb, sA)
+#define HHG_F2N(C, F)                                       \
+  do {                                                      \
+    if (lk.n <= 8) HHG_F2(C, 8, F);                         \
+    else if (lk.n <= 16) HHG_F2(C, 16, F);                  \
+    else HHG_F2(C, 32, F);                                  \
+  } while (0)
+    if (rb) { if (fine) HHG_F2N(2, true); else HHG_F2N(2, false); }
+    else { if (fine) HHG_F2N(3, true); else HHG_F2N(3, false); }
+#undef HHG_F2N
 #undef HHG_F2
     return true;
   }
@@ -1434,7 +1464,7 @@ bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* 
   const size_t shm = (size_t)lk.Sraw * sizeof(T);
   if (shm > 64 * 1024) return false;
   const unsigned blk = lk.NI >= 512 ? 1024 : 256;
-#define HHG_F3(C, F) k_gs3d_macro<T, C, F><<<(unsigned)lk.nmacro, blk, shm, st>>>(lk, tb, u, b, itab, rb, sA)
+#define HHG_F3(C, F) k_gs3d_macro<T, C, F><<<(unsigned)lk.nmacro, blk, shm, st>>>(lk, tb, u, b, itab, itab_off, rb, sA)
   if (rb) { if (fine) HHG_F3(2, true); else HHG_F3(2, false); }
   else { if (fine) HHG_F3(4, true); else HHG_F3(4, false); }
 #undef HHG_F3
@@ -1584,8 +1614,9 @@ void launch_coarse(int n0, const int32_t* coff, const int64_t* copy, const doubl
 }
 
 void launch_sqnorm(int dim, const LK& lk, const Tables& tb, const double* r, double* partial, double* out, hipStream_t st) {
-  const int64_t rows = (int64_t)lk.nmacro * (lk.n + 1) * (dim == 3 ? (lk.n + 1) : 1);
-  const unsigned g1 = (unsigned)(lk.NI > 0 ? std::min<int64_t>(kNormBlocks, (rows + 3) / 4) : 0);
+  // 2D: one wavefront per row; 3D: one block per 256-entry chunk of a macro block
+  const int64_t units = dim == 3 ? (int64_t)lk.nmacro * ((lk.Sraw + 255) / 256) : ((int64_t)lk.nmacro * (lk.n + 1) + 3) / 4;
+  const unsigned g1 = (unsigned)(lk.NI > 0 ? std::min<int64_t>(kNormBlocks, units) : 0);
   const unsigned g2 = nblk(lk.nIface);
   if (g1) {
     if (dim == 3) k_sq_interior<3><<<g1, 256, 0, st>>>(lk, r, partial);
@@ -1600,8 +1631,8 @@ void launch_sqnorm(int dim, const LK& lk, const Tables& tb, const double* r, dou
 
 template <typename T>
 void launch_sqnorm_closure(int dim, const LK& lk, const T* r, double* partial, double* out, hipStream_t st) {
-  const int64_t rows = (int64_t)lk.nmacro * (lk.n + 1) * (dim == 3 ? (lk.n + 1) : 1);
-  const unsigned g1 = (unsigned)std::min<int64_t>(kNormBlocks, (rows + 3) / 4);
+  const int64_t chunks = (int64_t)lk.nmacro * ((lk.Sraw + 255) / 256);
+  const unsigned g1 = (unsigned)std::min<int64_t>(kNormBlocks, chunks);
   if (dim == 3) k_sq_closure<3, T><<<g1, 256, 0, st>>>(lk, r, partial);
   else k_sq_closure<2, T><<<g1, 256, 0, st>>>(lk, r, partial);
   k_sum<<<1, 256, 0, st>>>(partial, (int)g1, out);
@@ -1662,9 +1693,9 @@ template void launch_smooth_interior<double>(int, bool, const LK&, const Tables&
 template void launch_smooth_interior<float>(int, bool, const LK&, const Tables&, const float*, float*, const float*, int,
                                             int, int, double, double, const double*, bool, hipStream_t);
 template bool launch_gs_fused<double>(int, bool, const LK&, const Tables&, double*, double*, const double*,
-                                      const int32_t*, int, const uint32_t*, int, double, bool, hipStream_t);
+                                      const int32_t*, int, const uint32_t*, const int32_t*, int, double, bool, hipStream_t);
 template bool launch_gs_fused<float>(int, bool, const LK&, const Tables&, float*, float*, const float*, const int32_t*,
-                                     int, const uint32_t*, int, double, bool, hipStream_t);
+                                     int, const uint32_t*, const int32_t*, int, double, bool, hipStream_t);
 template void launch_iface_tasks<double>(int, const LK&, const Tables&, const int32_t*, const int32_t*, const int32_t*,
                                          const int32_t*, const int32_t*, int, int, const double*, const double*, double*,
                                          double*, const double*, int, double, double, hipStream_t);

@@ -530,15 +530,34 @@ hhg_status build_colouring(hhg_ctx c) {
     lv.itab.clear();
     if (d == 2 && lv.NI > 0) {
       const int TI = 64 - 2 * Cint;   // one wavefront per tile of the fused sweep
-      const int TJ = tile_rows(Cint);
+      const int TJ = tile_rows(Cint, lv.n);
       for (int tj = 0; 1 + tj * TJ <= lv.n - 2; ++tj)
         for (int ti = 0; 1 + ti * TI + 1 + tj * TJ <= lv.n - 1; ++ti) lv.tiles.push_back(ti | (tj << 16));
     }
+    lv.itab_off.clear();
     if (d == 3 && lv.NI > 0 && lv.n <= kMacroLdsN) {
+      // interior points sorted by colour, one list per red-black parity pattern (s1, s2, s3)
+      // of a macro (multicolour: one list); itab_off[p * (Cint + 1) + c] starts colour c
       const int n = lv.n;
-      for (int k = 1; k <= n - 3; ++k)
-        for (int j = 1; j <= n - 2 - k; ++j)
-          for (int i = 1; i <= n - 1 - j - k; ++i) lv.itab.push_back((uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20));
+      const bool rbs = c->opt.smoother == HHG_GS_REDBLACK;
+      const int npat = rbs ? 8 : 1;
+      for (int pat = 0; pat < npat; ++pat) {
+        std::vector<std::vector<uint32_t>> bycol(Cint);
+        for (int k = 1; k <= n - 3; ++k)
+          for (int j = 1; j <= n - 2 - k; ++j)
+            for (int i = 1; i <= n - 1 - j - k; ++i) {
+              const int col = rbs ? ((i * (pat & 1) + j * ((pat >> 1) & 1) + k * ((pat >> 2) & 1)) & 1)
+                                  : (Cint == 4 ? (i + 2 * j + 3 * k) % 4 : 0);
+              bycol[col].push_back((uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20));
+            }
+        int32_t o = 0;
+        for (int cc = 0; cc < Cint; ++cc) {
+          lv.itab_off.push_back(o);
+          lv.itab.insert(lv.itab.end(), bycol[cc].begin(), bycol[cc].end());
+          o += (int32_t)bycol[cc].size();
+        }
+        lv.itab_off.push_back(o);
+      }
     }
   }
   return HHG_OK;
@@ -679,6 +698,7 @@ void plan_workspace(hhg_ctx c) {
     lv.off_x2 = take(d == 2 ? nf * 8 : 0);
     lv.off_x2_32 = take(d == 2 ? nf * 4 : 0);
     lv.off_itab = take((int64_t)lv.itab.size() * 4);
+    lv.off_itoff = take((int64_t)lv.itab_off.size() * 4);
   }
   c->ws_bytes = (size_t)off;
 }
