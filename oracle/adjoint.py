@@ -1,6 +1,6 @@
 """Gradient of a goal functional of the converged discrete solution.
 
-The paper only mentions goal-oriented (semi-)norms (remark on norm choices in Section 4.5);
+The paper only mentions goal-oriented (semi-)norms (remark on norm choices in Section 4.4);
 the reading here: for J(u_h) with u_h = A^{-1} b, b = M f on inner rows and u_h = g on the
 Dirichlet boundary,
     adjoint:   A_II lambda_I = (dJ/du)_I,   lambda = 0 on Dirichlet nodes

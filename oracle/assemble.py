@@ -1,4 +1,4 @@
-"""Element-by-element assembly of the level matrices (Section 4.5, the per-level linear
+"""Element-by-element assembly of the level matrices (Section 4.4, the per-level linear
 system A_l u_l = b_l, and Section 5, the Poisson form a(u,v) = int grad v . grad u,
 b(v) = int v f).
 

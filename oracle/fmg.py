@@ -51,6 +51,8 @@ class FMGSolver:
                  omega=2.0 / 3.0, nu1=2, nu2=2):
         self.h = h
         self.L = h.L
+        self.kappa_cell = kappa_cell
+        self.kappa_nodal = kappa_nodal
         self.smoother = smoother
         self.omega = omega
         self.nu1, self.nu2 = nu1, nu2

@@ -80,3 +80,75 @@ def test_general_j_uses_prolongated_coarse_solutions():
     # j=2's e~_{l} is j=1's e~_{l-1}
     assert abs(e2["norm_e_l"] - e1["norm_e_lm1"]) < 1e-14
     assert np.allclose(e2["eta_T"], e1["eta_T"])
+
+
+def test_energy_norm_matches_gradient_quadrature():
+    # per macro, e^T A_T e with the macro coefficients equals int_T kappa |grad e_h|^2 computed
+    # from element gradients solved directly from the nodal values; the sum is e^T A_L e
+    m = meshes.lshape_6tri()
+    L = 4
+    h = refine.Hierarchy(m.coords, m.cells, L)
+    kap = np.random.default_rng(21).uniform(0.5, 2.0, m.n_cells)
+    S = fmg.FMGSolver(h, kappa_cell=kap, smoother="multicolour")
+    X = h.levels[L].X
+    e = np.random.default_rng(22).standard_normal(len(X))
+    sq = estimate.per_macro_sq_norms(h, e, estimate.element_norm_matrices(S, "energy"))
+    lv = h.levels[L]
+    q = estimate.quadrature_energy(h, e, None, kappa_el=kap[lv.emacro], per_macro=True)
+    assert np.allclose(sq, q, rtol=1e-12, atol=0)
+    A = S.sys[L].A
+    assert abs(sq.sum() - e @ (A @ e)) <= 1e-12 * sq.sum()
+
+
+def test_lumped_norm_is_row_sum_diagonal_and_equivalent_to_l2():
+    # lumped: sum_T ||v||_T^2 = sum_i (M 1)_i v_i^2, |Omega| for v = 1, and per macro
+    # v^T M_T v <= v^T D_T v <= (d+2) v^T M_T v (eigenvalues of the P1 element mass matrix)
+    for mk, L in ((meshes.lshape_6tri, 4), (lambda: meshes.kuhn_cube(1), 3)):
+        m = mk()
+        h = refine.Hierarchy(m.coords, m.cells, L)
+        S = fmg.FMGSolver(h, smoother="redblack" if m.dim == 3 else "multicolour")
+        X = h.levels[L].X
+        v = np.random.default_rng(23).standard_normal(len(X))
+        lum = estimate.per_macro_sq_norms(h, v, estimate.element_norm_matrices(S, "lumped"))
+        con = estimate.per_macro_sq_norms(h, v, estimate.element_norm_matrices(S, "l2"))
+        M = S.sys[L].M
+        assert abs(lum.sum() - np.asarray(M.sum(axis=1)).ravel() @ (v * v)) <= 1e-12 * lum.sum()
+        ones = estimate.per_macro_sq_norms(h, np.ones(len(X)), estimate.element_norm_matrices(S, "lumped"))
+        vol = estimate.per_macro_sq_norms(h, np.ones(len(X)))
+        assert np.allclose(ones, vol, rtol=1e-13)
+        d = m.dim
+        assert np.all(con <= lum * (1 + 1e-12)) and np.all(lum <= (d + 2) * con * (1 + 1e-12))
+
+
+def test_energy_estimate_follows_galerkin_orthogonality():
+    # For nested P1 spaces the energy error splits as ||e_{l}||^2 = ||e_L||^2 + ||u_L - u_l||^2
+    # (Galerkin orthogonality), and P1 converges at first order in energy, ||e_l|| ~ 2^(L-l)
+    # ||e_L||.  Hence ||e~_{L-1}|| / ||e_L|| -> sqrt(4 - 1) and theta~ -> sqrt(3 / 15) = 1/sqrt5
+    # (not the q = 1 value 1/2: e~ of the coarser level spans two levels).  The effectivity
+    # lies within the theorem's bounds for theta = 1/2.
+    h, S, u, w, b, g = _solve(meshes.unit_square_2tri, 6, problems.sine2d_f, problems.zero, 2, "redblack")
+    est = estimate.error_estimate(S, u, w, 1, norm="energy")
+    err = estimate.quadrature_energy(h, u, problems.sine2d_grad, m=4)
+    assert abs(est["theta"] - 5 ** -0.5) < 0.01
+    assert abs(est["norm_e_l"] / err - 3 ** 0.5) < 0.02
+    C1, C2 = estimate.effectivity_bounds(0.5, 0.0, 1)
+    assert C1 <= est["eta_j"] / err <= C2
+    # the L2 and lumped estimates of the same solve see second-order convergence
+    assert abs(estimate.error_estimate(S, u, w, 1, norm="l2")["theta"] - 0.25) < 0.06
+    assert abs(estimate.error_estimate(S, u, w, 1, norm="lumped")["theta"] - 0.25) < 0.06
+
+
+@pytest.mark.parametrize("norm", ["l2", "energy", "lumped"])
+def test_local_indicators_consistent_across_j(norm):
+    # eta'_{j+1,T} = ||e~_{L-j-1}||_T is the denominator of theta~_{L-j,T}, so the scaled
+    # indicator of j is (eta'_j / eta'_{j+1})^j eta'_j from two separate calls; the unscaled
+    # indicators square-sum to ||e~_{L-j}||^2, and eta_T does not depend on j
+    h, S, u, w, b, g = _solve(meshes.lshape_6tri, 5, problems.zero, problems.lshape_u, 1, "multicolour")
+    for j in (1, 2, 3):
+        a = estimate.error_estimate(S, u, w, j, norm=norm)
+        c = estimate.error_estimate(S, u, w, j + 1, norm=norm)
+        assert np.allclose(a["eta_jT"], (a["eta_prime_jT"] / c["eta_prime_jT"]) ** j * a["eta_prime_jT"],
+                           rtol=1e-12, atol=0)
+        assert abs(np.sum(a["eta_prime_jT"] ** 2) - a["norm_e_l"] ** 2) <= 1e-12 * a["norm_e_l"] ** 2
+        assert abs(c["norm_e_l"] - a["norm_e_lm1"]) <= 1e-13 * a["norm_e_lm1"]
+        assert np.allclose(a["eta_T"], estimate.error_estimate(S, u, w, 1, norm=norm)["eta_T"], rtol=1e-13)

@@ -20,6 +20,12 @@ def sine2d_f(x):
     return 2.0 * PI * PI * sine2d_u(x)
 
 
+def sine2d_grad(x):
+    """(N, 2) gradient of sine2d_u."""
+    return np.stack([PI * np.cos(PI * x[:, 0]) * np.sin(PI * x[:, 1]),
+                     PI * np.sin(PI * x[:, 0]) * np.cos(PI * x[:, 1])], axis=1)
+
+
 # --- L-shape corner singularity: u = r^(2/3) sin(2 phi / 3), phi in [0, 2 pi) ---------------
 def lshape_u(x):
     r = np.hypot(x[:, 0], x[:, 1])
