@@ -54,6 +54,15 @@ enum { HHG_KAPPA_MACRO = 0, HHG_KAPPA_P1 = 1 };
 enum { HHG_GS_REDBLACK = 0, HHG_GS_MULTICOLOR = 1, HHG_JACOBI = 2 };
 enum { HHG_FP64 = 0, HHG_FP32_REFINED = 1 };
 enum { HHG_OP_STIFFNESS = 0, HHG_OP_MASS = 1 };
+/* Norm of the error estimate (remark on the choice of norm, Section 4.4): the consistent mass
+ * matrix M_L (L2, the paper's choice), the stiffness matrix A_L with the context's per-macro
+ * coefficients (energy), or the row-sum lumped mass matrix. */
+enum { HHG_NORM_L2 = 0, HHG_NORM_ENERGY = 1, HHG_NORM_LUMPED = 2 };
+/* Local indicator (Section 4.3): ||e~_{L-1}||_T for every j (what the paper implements for
+ * P1), the unscaled eta'_{j,T} = ||e~_{L-j}||_T, or the scaled eta_{j,T} =
+ * theta~_{L-j,T}^j ||e~_{L-j}||_T with the per-macro factor
+ * theta~_{L-j,T} = ||e~_{L-j}||_T / ||e~_{L-j-1}||_T. */
+enum { HHG_LOCAL_L1 = 0, HHG_LOCAL_UNSCALED = 1, HHG_LOCAL_SCALED = 2 };
 
 /* Coarse macro mesh T_0.  All arrays are host memory and are copied by hhg_setup. */
 typedef struct {
@@ -127,7 +136,7 @@ hhg_status hhg_set_kappa_cell(hhg_ctx ctx, const double* host_kappa);
  * Coarser levels use its values at their nodes. */
 hhg_status hhg_set_kappa_nodal(hhg_ctx ctx, const double* device_kappa);
 
-/* Full multigrid solve of A_L u = b_L (equation of the per-level linear system, Section 4.5)
+/* Full multigrid solve of A_L u = b_L (equation of the per-level linear system, Section 4.4)
  * with b_l = M_l f_l on every level l (f_l = nodal values of f) and u = g on Dirichlet DoFs,
  * following procedure FMG of Algorithm 4, then optional extra cycles.  f_nodal, g_nodal and
  * u_out are device vectors on level L.  The prolongated level solutions w_l are kept for
@@ -141,6 +150,16 @@ hhg_status hhg_fmg_solve(hhg_ctx ctx, const double* f_nodal, const double* g_nod
  * *norm_e = ||e~_{L-j}||.  Any output pointer may be NULL.  Synchronises the stream. */
 hhg_status hhg_estimate(hhg_ctx ctx, int j, double* eta_cell_host, double* eta_j, double* theta_est,
                         double* norm_e);
+
+/* hhg_estimate with a choice of norm (HHG_NORM_*) and of local indicator (HHG_LOCAL_*):
+ * every norm below is the chosen one.  eta_cell_host[T] receives the chosen local indicator;
+ * a scaled indicator whose ||e~_{L-j-1}||_T is zero is reported as 0.  *eta_j, *theta_est and
+ * *norm_e are as for hhg_estimate (equations of the global estimate eta_j and of theta~).
+ * HHG_NORM_ENERGY needs HHG_KAPPA_MACRO (HHG_EINVAL otherwise); unknown norm or indicator
+ * values give HHG_EINVAL.  hhg_estimate(ctx, j, ...) equals
+ * hhg_estimate_ex(ctx, j, HHG_NORM_L2, HHG_LOCAL_L1, ...).  Synchronises the stream. */
+hhg_status hhg_estimate_ex(hhg_ctx ctx, int j, int norm, int local, double* eta_cell_host, double* eta_j,
+                           double* theta_est, double* norm_e);
 
 /* y = A x or y = M x on a level with the full (unconstrained) assembled matrix; x, y device
  * vectors in canonical order (op = HHG_OP_STIFFNESS | HHG_OP_MASS).  Leaves the state of the

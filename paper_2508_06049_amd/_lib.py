@@ -21,6 +21,10 @@ HHG_KAPPA_MACRO, HHG_KAPPA_P1 = 0, 1
 HHG_GS_REDBLACK, HHG_GS_MULTICOLOR, HHG_JACOBI = 0, 1, 2
 HHG_FP64, HHG_FP32_REFINED = 0, 1
 HHG_OP_STIFFNESS, HHG_OP_MASS = 0, 1
+HHG_NORM_L2, HHG_NORM_ENERGY, HHG_NORM_LUMPED = 0, 1, 2
+HHG_LOCAL_L1, HHG_LOCAL_UNSCALED, HHG_LOCAL_SCALED = 0, 1, 2
+_NORMS = {"l2": HHG_NORM_L2, "energy": HHG_NORM_ENERGY, "lumped": HHG_NORM_LUMPED}
+_LOCALS = {"l1": HHG_LOCAL_L1, "unscaled": HHG_LOCAL_UNSCALED, "scaled": HHG_LOCAL_SCALED}
 HHG_FLAG_NO_FUSED = 1
 HHG_FLAG_NO_LANE_IFACE = 2
 HHG_FLAG_NO_GRAPH = 4
@@ -62,6 +66,8 @@ _SIGS = {
     "hhg_fmg_solve": (C.c_int, [_ctx, _dp, _dp, _dp, C.POINTER(hhg_solve_params), C.POINTER(hhg_solve_stats)]),
     "hhg_estimate": (C.c_int, [_ctx, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "hhg_estimate_ex": (C.c_int, [_ctx, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "hhg_apply": (C.c_int, [_ctx, C.c_int, C.c_int, _dp, _dp]),
     "hhg_mass_apply": (C.c_int, [_ctx, _dp, _dp]),
     "hhg_smooth": (C.c_int, [_ctx, C.c_int, _dp, _dp, C.c_int]),
@@ -229,10 +235,17 @@ class HHG:
         _check(self.lib.hhg_residual_history(self.ctx, _dbl(out), n.value, C.byref(n)), self.ctx)
         return out[:n.value]
 
-    def estimate(self, j: int = 1) -> dict:
+    def estimate(self, j: int = 1, norm: str | None = None, local: str | None = None) -> dict:
+        """hhg_estimate; with ``norm`` ("l2", "energy", "lumped") or ``local`` ("l1",
+        "unscaled", "scaled") given, hhg_estimate_ex."""
         eta = np.zeros(self.n_cells)
         ej, th, ne = C.c_double(), C.c_double(), C.c_double()
-        _check(self.lib.hhg_estimate(self.ctx, j, _dbl(eta), C.byref(ej), C.byref(th), C.byref(ne)), self.ctx)
+        if norm is None and local is None:
+            st = self.lib.hhg_estimate(self.ctx, j, _dbl(eta), C.byref(ej), C.byref(th), C.byref(ne))
+        else:
+            st = self.lib.hhg_estimate_ex(self.ctx, j, _NORMS[norm or "l2"], _LOCALS[local or "l1"], _dbl(eta),
+                                          C.byref(ej), C.byref(th), C.byref(ne))
+        _check(st, self.ctx)
         return dict(eta_T=eta, eta_j=ej.value, theta=th.value, norm_e=ne.value)
 
     def apply(self, level: int, op: str, x):

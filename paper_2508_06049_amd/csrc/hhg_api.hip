@@ -434,11 +434,13 @@ const double* prolong_chain(hhg_ctx c, const double* v, int from, int to, bool u
   return v;
 }
 
-// per-macro [||u - a||_T^2, ||u - P b||_T^2] into host vectors
-hhg_status estimate_pair(hhg_ctx c, const double* a, const double* bc, std::vector<double>& s1, std::vector<double>& s2) {
+// per-macro [||u - a||_T^2, ||u - P b||_T^2] in the given norm into host vectors
+hhg_status estimate_pair(hhg_ctx c, int norm, const double* a, const double* bc, std::vector<double>& s1,
+                         std::vector<double>& s2) {
   const int L = c->L;
   double* out = c->d_red + (c->red_capacity - 2 * c->nC - 8);
-  launch_estimate(c->dim, lk_of(c, L), lk_of(c, L - 1), c->tab, c->lev[L].x, a, bc, c->d_red, out, sM(c, L), ST(c));
+  launch_estimate(c->dim, norm, lk_of(c, L), lk_of(c, L - 1), c->tab, c->lev[L].x, a, bc, c->d_red, out,
+                  norm == HHG_NORM_ENERGY ? sA(c, L) : sM(c, L), ST(c));
   LAUNCHCHK();
   std::vector<double> h(2 * c->nC);
   HIPCHK(hipMemcpyAsync(h.data(), out, h.size() * 8, hipMemcpyDeviceToHost, ST(c)));
@@ -715,37 +717,65 @@ hhg_status hhg_fmg_solve(hhg_ctx c, const double* f, const double* g, double* u_
   return s;
 }
 
-hhg_status hhg_estimate(hhg_ctx c, int j, double* eta_cell, double* eta_j, double* theta_est, double* norm_e) {
+hhg_status hhg_estimate_ex(hhg_ctx c, int j, int norm, int local, double* eta_cell, double* eta_j, double* theta_est,
+                           double* norm_e) {
   TRY(check_ready(c));
   if (!c->solved) { c->err = "hhg_estimate needs a preceding successful hhg_fmg_solve"; return HHG_ESTATE; }
   const int L = c->L;
   if (j < 1 || j >= L) { c->err = "need 0 < j < L"; return HHG_EINVAL; }
+  if (norm != HHG_NORM_L2 && norm != HHG_NORM_ENERGY && norm != HHG_NORM_LUMPED) {
+    c->err = "unknown norm";
+    return HHG_EINVAL;
+  }
+  if (local != HHG_LOCAL_L1 && local != HHG_LOCAL_UNSCALED && local != HHG_LOCAL_SCALED) {
+    c->err = "unknown local indicator";
+    return HHG_EINVAL;
+  }
+  if (norm == HHG_NORM_ENERGY && p1(c)) {
+    c->err = "the energy norm is implemented for per-macro coefficients only";
+    return HHG_EINVAL;
+  }
   const int l = L - j;
-  // w_k is stored on level k+1 (lev[k+1].w)
-  std::vector<double> a1, a2;
-  // j = 1 pair: (w_{L-1} on L, w_{L-2} on L-1) -> eta_T and, for j = 1, the global estimate
-  const double* wL1 = c->lev[L].w;
-  const double* wL2 = c->lev[L - 1].w;
-  if (L - 1 == 0) { c->err = "L >= 2 required for the estimate"; return HHG_EINVAL; }
-  TRY(estimate_pair(c, wL1, wL2, a1, a2));
-  std::vector<double> s_l = a1, s_lm1 = a2;
-  if (j > 1) {
+  // w_k is stored on level k+1 (lev[k+1].w).  s_l[T] = ||e~_l||_T^2, s_lm1[T] = ||e~_{l-1}||_T^2.
+  std::vector<double> s_l, s_lm1, a1;
+  if (j == 1) {
+    TRY(estimate_pair(c, norm, c->lev[L].w, c->lev[L - 1].w, s_l, s_lm1));
+  } else {
     // e~_l = u_L - I_{l+1}^L w_l,  e~_{l-1} = u_L - I_l^L w_{l-1} (last prolongation fused)
     const double* A = prolong_chain(c, c->lev[l + 1].w, l + 1, L, true);
     const double* B = prolong_chain(c, c->lev[l].w, l, L - 1, false);
-    TRY(estimate_pair(c, A, B, s_l, s_lm1));
+    TRY(estimate_pair(c, norm, A, B, s_l, s_lm1));
+  }
+  if (eta_cell && local == HHG_LOCAL_L1 && j > 1) {
+    std::vector<double> unused;
+    TRY(estimate_pair(c, norm, c->lev[L].w, c->lev[L - 1].w, a1, unused));
   }
   double n1 = 0, n2 = 0;
   for (int64_t m = 0; m < c->nC; ++m) { n1 += s_l[m]; n2 += s_lm1[m]; }
   n1 = std::sqrt(std::max(n1, 0.0));
   n2 = std::sqrt(std::max(n2, 0.0));
   const double theta = n2 > 0 ? n1 / n2 : 0.0;
-  if (eta_cell)
-    for (int64_t m = 0; m < c->nC; ++m) eta_cell[m] = std::sqrt(std::max(a1[m], 0.0));
+  if (eta_cell) {
+    for (int64_t m = 0; m < c->nC; ++m) {
+      const double el = std::sqrt(std::max(s_l[m], 0.0));
+      if (local == HHG_LOCAL_L1) {
+        eta_cell[m] = std::sqrt(std::max(j == 1 ? s_l[m] : a1[m], 0.0));
+      } else if (local == HHG_LOCAL_UNSCALED) {
+        eta_cell[m] = el;
+      } else {
+        const double elm1 = std::sqrt(std::max(s_lm1[m], 0.0));
+        eta_cell[m] = elm1 > 0 ? std::pow(el / elm1, j) * el : 0.0;
+      }
+    }
+  }
   if (eta_j) *eta_j = std::pow(theta, j) * n1;
   if (theta_est) *theta_est = theta;
   if (norm_e) *norm_e = n1;
   return HHG_OK;
+}
+
+hhg_status hhg_estimate(hhg_ctx c, int j, double* eta_cell, double* eta_j, double* theta_est, double* norm_e) {
+  return hhg_estimate_ex(c, j, HHG_NORM_L2, HHG_LOCAL_L1, eta_cell, eta_j, theta_est, norm_e);
 }
 
 hhg_status hhg_apply(hhg_ctx c, int level, int op, const double* x, double* y) {

@@ -8,7 +8,7 @@
 //        assembled value (each macro contributes the rows of its own micro elements).
 // With this split the residual, the restriction P^T, the prolongation P and the mass/stiffness
 // products are purely macro-local; only the smoother's interface update and the norms sum
-// over the copies of a DoF (additive collection from the adjacent volume macros, Section 4.5).
+// over the copies of a DoF (additive collection from the adjacent volume macros, Section 4.4).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -1238,13 +1238,15 @@ __global__ void __launch_bounds__(256) k_sum(const double* __restrict__ partial,
   if (threadIdx.x == 0) *out = v;
 }
 
-// Estimator: per macro T, sum over the closure nodes q of T of e(q) (M_T e)(q) for
-// e1 = u - a (a on level L) and e2 = u - P bc (bc on level L-1), M_T the mass matrix of T's
-// own micro elements.  Per-block partials [macro][chunk][2].
-template <int D>
+// Estimator: per macro T, sum over the closure nodes q of T of e(q) (N_T e)(q) for
+// e1 = u - a (a on level L) and e2 = u - P bc (bc on level L-1), N_T the matrix of T's own
+// micro elements for the chosen norm: NORM 0 the consistent mass matrix (L2), NORM 1 the
+// stiffness matrix with the macro's coefficient (energy), NORM 2 the row-sum lumped mass
+// matrix.  Per-block partials [macro][chunk][2].
+template <int D, int NORM>
 __global__ void __launch_bounds__(256) k_estimate(LK f, LK c, Tables tb, const double* __restrict__ u,
                                                    const double* __restrict__ a, const double* __restrict__ bc,
-                                                   double* __restrict__ partial, double sM) {
+                                                   double* __restrict__ partial, double scale) {
   __shared__ double sh[4];
   const int nchunk = (f.Sraw + 255) >> 8;
   const int m = blockIdx.x / nchunk;
@@ -1256,25 +1258,37 @@ __global__ void __launch_bounds__(256) k_estimate(LK f, LK c, Tables tb, const d
     d_dec<D>(f.n, s, i, j, k);
     const int mask = d_mask<D>(f.n, i, j, k);
     const int64_t fb = (int64_t)m * f.S, cb = (int64_t)m * c.S;
-    const double* W = tb.mass + ((size_t)m * kMaxMask + mask) * ndir<D>();
+    const double* W = (NORM == 1 ? tb.stiff : tb.mass) + ((size_t)m * kMaxMask + mask) * ndir<D>();
     const uint32_t valid = tb.validdirs[mask];
-    double m1 = 0.0, m2 = 0.0;
-#pragma unroll
-    for (int q = 0; q < ndir<D>(); ++q) {
-      if (q && !((valid >> q) & 1)) continue;
-      int o0, o1, o2;
-      d_off<D>(q, o0, o1, o2);
-      const int ii = i + o0, jj = j + o1, kk = k + o2;
-      const int lq = d_lin<D>(f.n, ii, jj, kk);
-      const double uq = u[fb + lq];
-      const double e1 = uq - a[fb + lq];
-      const double e2 = uq - d_prolong_val<D, double>(c.n, bc, cb, ii, jj, kk);
-      m1 += W[q] * e1;
-      m2 += W[q] * e2;
-    }
+    const double sc = NORM == 1 ? scale * tb.kappa[m] : scale;
     const double uc = u[fb + s];
-    v1 = (uc - a[fb + s]) * m1 * sM;
-    v2 = (uc - d_prolong_val<D, double>(c.n, bc, cb, i, j, k)) * m2 * sM;
+    const double e1c = uc - a[fb + s];
+    const double e2c = uc - d_prolong_val<D, double>(c.n, bc, cb, i, j, k);
+    double m1 = 0.0, m2 = 0.0;
+    if constexpr (NORM == 2) {
+      double rs = 0.0;
+#pragma unroll
+      for (int q = 0; q < ndir<D>(); ++q)
+        if (!q || ((valid >> q) & 1)) rs += W[q];
+      m1 = rs * e1c;
+      m2 = rs * e2c;
+    } else {
+#pragma unroll
+      for (int q = 0; q < ndir<D>(); ++q) {
+        if (q && !((valid >> q) & 1)) continue;
+        int o0, o1, o2;
+        d_off<D>(q, o0, o1, o2);
+        const int ii = i + o0, jj = j + o1, kk = k + o2;
+        const int lq = d_lin<D>(f.n, ii, jj, kk);
+        const double uq = u[fb + lq];
+        const double e1 = uq - a[fb + lq];
+        const double e2 = uq - d_prolong_val<D, double>(c.n, bc, cb, ii, jj, kk);
+        m1 += W[q] * e1;
+        m2 += W[q] * e2;
+      }
+    }
+    v1 = e1c * m1 * sc;
+    v2 = e2c * m2 * sc;
   }
   v1 = block_sum(v1, sh);
   v2 = block_sum(v2, sh);
@@ -1639,12 +1653,17 @@ void launch_sqnorm_closure(int dim, const LK& lk, const T* r, double* partial, d
 }
 template void launch_sqnorm_closure<float>(int, const LK&, const float*, double*, double*, hipStream_t);
 
-void launch_estimate(int dim, const LK& f, const LK& c, const Tables& tb, const double* u, const double* a,
-                     const double* bc, double* partial, double* out, double sM, hipStream_t st) {
+void launch_estimate(int dim, int norm, const LK& f, const LK& c, const Tables& tb, const double* u, const double* a,
+                     const double* bc, double* partial, double* out, double scale, hipStream_t st) {
   const int nchunk = (int)((f.Sraw + 255) / 256);
   const unsigned g = (unsigned)(f.nmacro * nchunk);
-  if (dim == 3) k_estimate<3><<<g, 256, 0, st>>>(f, c, tb, u, a, bc, partial, sM);
-  else k_estimate<2><<<g, 256, 0, st>>>(f, c, tb, u, a, bc, partial, sM);
+#define HHG_EST(D, N) k_estimate<D, N><<<g, 256, 0, st>>>(f, c, tb, u, a, bc, partial, scale)
+  if (dim == 3) {
+    if (norm == 1) HHG_EST(3, 1); else if (norm == 2) HHG_EST(3, 2); else HHG_EST(3, 0);
+  } else {
+    if (norm == 1) HHG_EST(2, 1); else if (norm == 2) HHG_EST(2, 2); else HHG_EST(2, 0);
+  }
+#undef HHG_EST
   k_macro_sum<<<nblk((int64_t)f.nmacro * 2), 256, 0, st>>>(partial, f.nmacro, nchunk, 2, out);
 }
 

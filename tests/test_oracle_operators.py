@@ -1,5 +1,5 @@
 """Pins for the oracle's level operators: stiffness, mass, prolongation, right-hand side and
-colouring (Section 4.5 linear systems; Section 5 Poisson form)."""
+colouring (Section 4.4 linear systems; Section 5 Poisson form)."""
 import numpy as np
 import pytest
 
