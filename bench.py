@@ -105,6 +105,58 @@ def cpu_baseline(w, rtol, min_seconds=10.0, L=7):
                        f"(assembly excluded; scipy sparse, single thread)")
 
 
+# convergence studies of Section 5 (coarse mesh, f, g, u, criterion): the waves problem on the
+# 32-triangle unit square (Section 5.1) and the L-shape on 24 triangles (Section 5.2), both
+# refined by the actual local errors, 10 % of the macros per step
+KL_CASES = {
+    "waves": ("unit_square_grid4", "waves_f", "zero", "waves_u"),
+    "lshape24": ("lshape_24tri", "zero", "lshape_u", "lshape_u"),
+}
+
+
+def run_kl(args):
+    from paper_2508_06049_amd import kl
+    from workloads import meshes, problems
+
+    mname, fn, gn, un = KL_CASES[args.kl]
+    coarse = meshes.unit_square_grid(4) if mname == "unit_square_grid4" else getattr(meshes, mname)()
+    f, g, u = getattr(problems, fn), getattr(problems, gn), getattr(problems, un)
+    K, L = args.kl_K, args.kl_L
+    log(f"kl loop {args.kl}: {coarse.n_cells} macros, K={K}, L={L}")
+
+    def show(s):
+        log(f"k={s.k}: {s.n_macros} macros, {s.n_dofs} DoFs, error {s.err:.4e}, level-0 error {s.err_level0:.4e}, "
+            f"{s.vcycles} V-cycles ({s.extra['solves']} solves, rel. residual {s.extra['final_rel_residual']:.1e}), "
+            f"setup {s.t_setup:.2f} s, solve {s.t_solve * 1e3:.1f} ms, local norms "
+            f"{s.t_local * 1e3:.1f} ms, mark+refine {s.t_refine * 1e3:.1f} ms")
+
+    t0 = time.perf_counter()
+    steps = kl.kl_refine(coarse, L, K, f, g, u, criterion="error", nu=2, rtol=1e-6, max_iter=100, callback=show)
+    t_loop = time.perf_counter() - t0
+    rho = kl.error_ratio(steps)
+    # uniform refinement of T_0^0 (levels 1..L), same solver and stopping rule
+    H = kl.mean_width(coarse, 0)
+    uni = []
+    for l in range(1, L + 1):
+        s = kl.kl_refine(coarse, l, 0, f, g, u, criterion="error", nu=2, rtol=1e-6, max_iter=100)[0]
+        uni.append(dict(L=l, dofs=s.n_dofs, error=s.err, rho=H * H * s.err / (s.hbar * s.hbar * steps[0].err_level0)))
+        log(f"uniform L={l}: {s.n_dofs} DoFs, error {s.err:.4e}, rho {uni[-1]['rho']:.3f}")
+    out = {
+        "metric": "kl-refinement loop: error ratio rho and time per k-step",
+        "value": rho[-1], "unit": "rho on T_L^K", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+        "config": {"workload": f"kl_{args.kl}", "coarse_macros": coarse.n_cells, "K": K, "L": L,
+                   "marking": "10 % largest local L2 errors, red-green", "smoother": "multicolour", "fmg_nu": 2,
+                   "vcycle": [2, 2], "rtol": "1e-6, lowered 100-fold until the error's first two digits are stable"},
+        "loop_seconds": round(t_loop, 3),
+        "steps": [dict(k=s.k, macros=s.n_macros, dofs=s.n_dofs, error=s.err, level0_error=s.err_level0,
+                       rho=r, eta_1=s.eta_1, vcycles=s.vcycles, solves=s.extra["solves"], setup_s=round(s.t_setup, 4),
+                       solve_ms=round(s.t_solve * 1e3, 3), local_ms=round(s.t_local * 1e3, 3),
+                       refine_ms=round(s.t_refine * 1e3, 3)) for s, r in zip(steps, rho)],
+        "uniform": uni,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,11 +169,20 @@ def main():
     ap.add_argument("--kernel-only", action="store_true",
                     help="run only the smoother sweeps on level L and a plain device copy of known size "
                          "(for hardware-counter runs; prints no JSON line)")
+    ap.add_argument("--kl", choices=sorted(KL_CASES), default=None,
+                    help="run the kl-refinement loop (Section 3) on one of the convergence-study problems of "
+                         "Section 5 instead of the solve benchmark, with a uniform-refinement baseline; prints "
+                         "one JSON line")
+    ap.add_argument("--kl-K", type=int, default=10)
+    ap.add_argument("--kl-L", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the method runs on one GPU here); --gpus {args.gpus} is not "
               f"supported", file=sys.stderr)
         sys.exit(2)
+    if args.kl:
+        run_kl(args)
+        return
 
     import numpy as np
     import torch

@@ -161,6 +161,20 @@ hhg_status hhg_estimate(hhg_ctx ctx, int j, double* eta_cell_host, double* eta_j
 hhg_status hhg_estimate_ex(hhg_ctx ctx, int j, int norm, int local, double* eta_cell_host, double* eta_j,
                            double* theta_est, double* norm_e);
 
+/* Per-macro squared norms on level L (norm = HHG_NORM_*; the local norms of Section 4.3):
+ * sq_host[T] = ||d||_T^2 over the fine elements of macro T, T = 0..n_cells-1 (host array),
+ * where, with x a device vector on level L in canonical order (NULL: u_L of the last solve),
+ *   level = -1:          d = x                  (x must not be NULL),
+ *   0 <= level < L:      d = x - I_{level+1}^L w_level   (w_level: the stored prolongation
+ *                                                         of the FMG solution of that level),
+ *   level = L:           d = x - u_L.
+ * With x the nodal interpolant of an exact solution this gives the local errors of u_L
+ * (level = L) or of a coarser FMG solution (level < L), the criterion of the convergence
+ * studies of Section 5; with x = NULL and level = L-j it gives ||e~_{L-j}||_T.  level >= 0 or
+ * x = NULL needs a preceding hhg_fmg_solve (HHG_ESTATE).  HHG_NORM_ENERGY needs
+ * HHG_KAPPA_MACRO.  Leaves the state of the last solve intact.  Synchronises the stream. */
+hhg_status hhg_macro_norms(hhg_ctx ctx, const double* x, int level, int norm, double* sq_host);
+
 /* y = A x or y = M x on a level with the full (unconstrained) assembled matrix; x, y device
  * vectors in canonical order (op = HHG_OP_STIFFNESS | HHG_OP_MASS).  Leaves the state of the
  * last hhg_fmg_solve intact (hhg_estimate may still follow). */

@@ -68,6 +68,7 @@ _SIGS = {
                                C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "hhg_estimate_ex": (C.c_int, [_ctx, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
                                   C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "hhg_macro_norms": (C.c_int, [_ctx, _dp, C.c_int, C.c_int, C.POINTER(C.c_double)]),
     "hhg_apply": (C.c_int, [_ctx, C.c_int, C.c_int, _dp, _dp]),
     "hhg_mass_apply": (C.c_int, [_ctx, _dp, _dp]),
     "hhg_smooth": (C.c_int, [_ctx, C.c_int, _dp, _dp, C.c_int]),
@@ -117,12 +118,16 @@ def _check(status: int, ctx=None):
         raise HHGError(status, msg or lib.hhg_status_string(status).decode())
 
 
-def _dptr(t) -> int:
+def _dptr(t, n: int | None = None) -> int:
+    """Device address of a contiguous float64 CUDA tensor; with n, its length must be n (the
+    C entry points take raw pointers and cannot check sizes themselves)."""
     import torch
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
         raise TypeError("device tensor expected")
     if t.dtype != torch.float64 or not t.is_contiguous():
         raise TypeError("contiguous float64 tensor expected")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"vector of length {n} expected, got {t.numel()}")
     return t.data_ptr()
 
 
@@ -198,6 +203,14 @@ class HHG:
         _check(self.lib.hhg_num_dofs(self.ctx, self.L if level is None else level, C.byref(n)), self.ctx)
         return int(n.value)
 
+    def _nd(self, level: int | None = None) -> int:
+        lvl = self.L if level is None else level
+        if not 0 <= lvl <= self.L:
+            raise HHGError(HHG_EINVAL, f"level {lvl} outside 0..{self.L}")
+        if not hasattr(self, "_ndofs"):
+            self._ndofs = [self.num_dofs(l) for l in range(self.L + 1)]
+        return self._ndofs[lvl]
+
     def dof_coords(self, level: int | None = None):
         import torch
         lvl = self.L if level is None else level
@@ -210,7 +223,7 @@ class HHG:
         _check(self.lib.hhg_set_kappa_cell(self.ctx, _dbl(k)), self.ctx)
 
     def set_kappa_nodal(self, kappa):
-        _check(self.lib.hhg_set_kappa_nodal(self.ctx, _dptr(kappa)), self.ctx)
+        _check(self.lib.hhg_set_kappa_nodal(self.ctx, _dptr(kappa, self._nd())), self.ctx)
 
     @staticmethod
     def params(nu=1, pre=2, post=2, precision="fp64", rtol=0.0, max_iter=0) -> hhg_solve_params:
@@ -225,7 +238,9 @@ class HHG:
         p = self.params(**kw)
         u = torch.empty_like(f) if u_out is None else u_out
         st = hhg_solve_stats()
-        _check(self.lib.hhg_fmg_solve(self.ctx, _dptr(f), _dptr(g), _dptr(u), C.byref(p), C.byref(st)), self.ctx)
+        n = self._nd()
+        _check(self.lib.hhg_fmg_solve(self.ctx, _dptr(f, n), _dptr(g, n), _dptr(u, n), C.byref(p), C.byref(st)),
+               self.ctx)
         return u, SolveStats(st.vcycles, st.ir_steps, st.final_rel_residual, st.ms_total)
 
     def residual_history(self) -> np.ndarray:
@@ -248,33 +263,42 @@ class HHG:
         _check(st, self.ctx)
         return dict(eta_T=eta, eta_j=ej.value, theta=th.value, norm_e=ne.value)
 
+    def macro_norms(self, x=None, level: int = -1, norm: str = "l2") -> np.ndarray:
+        """hhg_macro_norms: per-macro squared norms of x (level -1), x - u_L (level L) or
+        x - I w_level (0 <= level < L); x None means u_L of the last solve."""
+        out = np.zeros(self.n_cells)
+        _check(self.lib.hhg_macro_norms(self.ctx, None if x is None else _dptr(x, self._nd()), level, _NORMS[norm], _dbl(out)),
+               self.ctx)
+        return out
+
     def apply(self, level: int, op: str, x):
         import torch
         y = torch.empty_like(x)
         _check(self.lib.hhg_apply(self.ctx, level, HHG_OP_MASS if op == "mass" else HHG_OP_STIFFNESS,
-                                  _dptr(x), _dptr(y)), self.ctx)
+                                  _dptr(x, self._nd(level)), _dptr(y)), self.ctx)
         return y
 
     def mass_apply(self, x):
         import torch
         y = torch.empty_like(x)
-        _check(self.lib.hhg_mass_apply(self.ctx, _dptr(x), _dptr(y)), self.ctx)
+        _check(self.lib.hhg_mass_apply(self.ctx, _dptr(x, self._nd()), _dptr(y)), self.ctx)
         return y
 
     def smooth(self, level: int, u, b, sweeps: int = 1):
-        _check(self.lib.hhg_smooth(self.ctx, level, _dptr(u), _dptr(b), sweeps), self.ctx)
+        _check(self.lib.hhg_smooth(self.ctx, level, _dptr(u, self._nd(level)), _dptr(b, self._nd(level)), sweeps),
+               self.ctx)
         return u
 
     def restrict(self, level: int, r_fine):
         import torch
         out = torch.empty(self.num_dofs(level - 1), dtype=torch.float64, device=self.device)
-        _check(self.lib.hhg_restrict(self.ctx, level, _dptr(r_fine), _dptr(out)), self.ctx)
+        _check(self.lib.hhg_restrict(self.ctx, level, _dptr(r_fine, self._nd(level)), _dptr(out)), self.ctx)
         return out
 
     def prolongate(self, level: int, e_coarse):
         import torch
         out = torch.empty(self.num_dofs(level), dtype=torch.float64, device=self.device)
-        _check(self.lib.hhg_prolongate(self.ctx, level, _dptr(e_coarse), _dptr(out)), self.ctx)
+        _check(self.lib.hhg_prolongate(self.ctx, level, _dptr(e_coarse, self._nd(level - 1)), _dptr(out)), self.ctx)
         return out
 
     def adjoint(self, f, g, dJdu, **kw):
@@ -282,7 +306,9 @@ class HHG:
         p = self.params(**kw)
         dJdf = torch.empty_like(f)
         dJdk = np.zeros(self.n_cells)
-        _check(self.lib.hhg_adjoint(self.ctx, _dptr(f), _dptr(g), _dptr(dJdu), _dptr(dJdf), _dbl(dJdk), C.byref(p)),
+        n = self._nd()
+        _check(self.lib.hhg_adjoint(self.ctx, _dptr(f, n), _dptr(g, n), _dptr(dJdu, n), _dptr(dJdf, n), _dbl(dJdk),
+                                    C.byref(p)),
                self.ctx)
         return dJdf, dJdk
 

@@ -434,12 +434,13 @@ const double* prolong_chain(hhg_ctx c, const double* v, int from, int to, bool u
   return v;
 }
 
-// per-macro [||u - a||_T^2, ||u - P b||_T^2] in the given norm into host vectors
+// per-macro [||u - a||_T^2, ||u - P b||_T^2] in the given norm into host vectors (u: level-L
+// closure vector, the last solve's u_L unless given)
 hhg_status estimate_pair(hhg_ctx c, int norm, const double* a, const double* bc, std::vector<double>& s1,
-                         std::vector<double>& s2) {
+                         std::vector<double>& s2, const double* u = nullptr) {
   const int L = c->L;
   double* out = c->d_red + (c->red_capacity - 2 * c->nC - 8);
-  launch_estimate(c->dim, norm, lk_of(c, L), lk_of(c, L - 1), c->tab, c->lev[L].x, a, bc, c->d_red, out,
+  launch_estimate(c->dim, norm, lk_of(c, L), lk_of(c, L - 1), c->tab, u ? u : c->lev[L].x, a, bc, c->d_red, out,
                   norm == HHG_NORM_ENERGY ? sA(c, L) : sM(c, L), ST(c));
   LAUNCHCHK();
   std::vector<double> h(2 * c->nC);
@@ -771,6 +772,48 @@ hhg_status hhg_estimate_ex(hhg_ctx c, int j, int norm, int local, double* eta_ce
   if (eta_j) *eta_j = std::pow(theta, j) * n1;
   if (theta_est) *theta_est = theta;
   if (norm_e) *norm_e = n1;
+  return HHG_OK;
+}
+
+hhg_status hhg_macro_norms(hhg_ctx c, const double* x, int level, int norm, double* sq) {
+  TRY(check_ready(c));
+  const int L = c->L;
+  if (!sq || level < -1 || level > L || (level == -1 && !x) ||
+      (norm != HHG_NORM_L2 && norm != HHG_NORM_ENERGY && norm != HHG_NORM_LUMPED)) {
+    c->err = "invalid argument";
+    return HHG_EINVAL;
+  }
+  if (norm == HHG_NORM_ENERGY && p1(c)) {
+    c->err = "the energy norm is implemented for per-macro coefficients only";
+    return HHG_EINVAL;
+  }
+  if ((level >= 0 || !x) && !c->solved) {
+    c->err = "hhg_macro_norms with level >= 0 or x = NULL needs a preceding successful hhg_fmg_solve";
+    return HHG_ESTATE;
+  }
+  // only the scratch vectors rc and t are written: the last solve's u and w stay valid
+  Level& lL = c->lev[L];
+  const double* u = lL.x;
+  if (x) {
+    launch_canon_to_full(c->dim, lk_of(c, L), c->tab, x, lL.rc, 0, ST(c));
+    u = lL.rc;
+  }
+  const double* a;
+  if (level == -1) {
+    launch_fill<double>(lL.t, lL.nfull, 0.0, ST(c));
+    a = lL.t;
+  } else if (level == L) {
+    a = lL.x;
+  } else if (level == L - 1) {
+    a = lL.w;
+  } else {
+    a = prolong_chain(c, c->lev[level + 1].w, level + 1, L, false);
+  }
+  LAUNCHCHK();
+  std::vector<double> s1, s2;
+  // the kernel's second norm (against a level L-1 vector) is not used here
+  TRY(estimate_pair(c, norm, a, c->lev[L - 1].x, s1, s2, u));
+  for (int64_t m = 0; m < c->nC; ++m) sq[m] = s1[m];
   return HHG_OK;
 }
 

@@ -104,3 +104,54 @@ def test_green_types_3d_only_three():
     for t in rg.tets:
         he = rg._hanging_edges(t)
         assert len(he) in (0, 1, 2, 3)
+
+
+def test_lshape_24tri_is_conforming_and_symmetric():
+    m = meshes.lshape_24tri()
+    assert m.n_cells == 24 and m.n_vertices == 21
+    _check_conforming(m, 3.0)
+    # symmetric about y = -x: the mirror image of every cell is a cell
+    key = lambda pts: tuple(sorted(tuple(np.round(p, 12)) for p in pts))
+    cells = {key(m.coords[c]) for c in m.cells}
+    mirror = {key(-m.coords[c][:, ::-1]) for c in m.cells}
+    assert cells == mirror
+
+
+def test_waves_right_hand_side_is_minus_laplacian():
+    # f = -Laplace(u) for the waves solution of Section 5.1, checked by a fourth-order
+    # central difference; u vanishes on the boundary of the unit square
+    from workloads import problems
+    rng = np.random.default_rng(41)
+    X = rng.uniform(0.05, 0.95, (200, 2))
+    h = 2e-4
+    lap = np.zeros(len(X))
+    for d in range(2):
+        e = np.zeros(2); e[d] = h
+        u = lambda Y: problems.waves_u(Y)
+        lap += (-u(X + 2 * e) + 16 * u(X + e) - 30 * u(X) + 16 * u(X - e) - u(X - 2 * e)) / (12 * h * h)
+    f = problems.waves_f(X)
+    assert np.max(np.abs(-lap - f)) <= 1e-5 * np.max(np.abs(f))
+    t = np.linspace(0, 1, 11)
+    B = np.concatenate([np.stack([t, 0 * t], 1), np.stack([t, 1 + 0 * t], 1), np.stack([0 * t, t], 1),
+                        np.stack([1 + 0 * t, t], 1)])
+    assert np.max(np.abs(problems.waves_u(B))) < 1e-12
+
+
+def test_error_ratio_and_mean_width():
+    # rho = Hbar^2 e_h / (hbar^2 e_H): an error sequence e = C hbar^2 through the coarse-grid
+    # error gives rho = 1 on every step, a sequence at half that error gives 1/2
+    from paper_2508_06049_amd import kl
+    m0 = meshes.unit_square_grid(4)
+    assert abs(kl.domain_measure(m0) - 1.0) < 1e-15
+    assert abs(kl.domain_measure(meshes.lshape_24tri()) - 3.0) < 1e-15
+    assert abs(kl.mean_width(m0, 0) - (1 / 32) ** 0.5) < 1e-15
+    assert abs(kl.mean_width(m0, 3) - (1 / (32 * 64)) ** 0.5) < 1e-15
+    H = kl.mean_width(m0, 0)
+    eH = 0.3
+    steps = []
+    for k, L in enumerate((2, 4, 6)):
+        hb = kl.mean_width(m0, L)
+        steps.append(kl.KStep(k, m0, 0, hb, (0.5 if k else 1.0) * eH * (hb / H) ** 2, eH, 0.0, 0.0,
+                              np.zeros(32), None, 0, 0, 0, 0, 0))
+    rho = kl.error_ratio(steps)
+    assert abs(rho[0] - 1.0) < 1e-12 and abs(rho[1] - 0.5) < 1e-12 and abs(rho[2] - 0.5) < 1e-12

@@ -76,6 +76,35 @@ def lshape_6tri() -> CoarseMesh:
     return CoarseMesh(coords, cells, "lshape_6tri")
 
 
+def lshape_24tri() -> CoarseMesh:
+    """The L-shaped domain of lshape_6tri as 12 squares of side 1/2, each split into two
+    triangles by the diagonal whose line passes nearest the re-entrant corner ((1,1)
+    direction in quadrants I and III, (-1,1) in quadrant II): 24 triangles, symmetric about
+    the line y = -x."""
+    pts = {}
+    cells = []
+
+    def vid(x, y):
+        key = (round(2 * x), round(2 * y))
+        if key not in pts:
+            pts[key] = len(pts)
+        return pts[key]
+
+    for qx, qy in ((0.0, 0.0), (-1.0, 0.0), (-1.0, -1.0)):
+        for i in range(2):
+            for j in range(2):
+                x0, y0 = qx + 0.5 * i, qy + 0.5 * j
+                a, b, c, d = vid(x0, y0), vid(x0 + 0.5, y0), vid(x0 + 0.5, y0 + 0.5), vid(x0, y0 + 0.5)
+                if qx < 0 <= qy:            # quadrant II: diagonal b-d
+                    cells += [[a, b, d], [b, c, d]]
+                else:                       # quadrants I and III: diagonal a-c
+                    cells += [[a, b, c], [a, c, d]]
+    coords = np.zeros((len(pts), 2))
+    for (kx, ky), v in pts.items():
+        coords[v] = (0.5 * kx, 0.5 * ky)
+    return CoarseMesh(coords, np.array(cells, dtype=np.int32), "lshape_24tri")
+
+
 def kuhn_cube(ns: int, lo: float = 0.0, hi: float = 1.0) -> CoarseMesh:
     """[lo,hi]^3 as ns^3 subcubes, each split into the 6 Kuhn tetrahedra (path order)."""
     g = np.linspace(lo, hi, ns + 1)
