@@ -90,10 +90,13 @@ typedef struct {
                                  DoF instead of one lane per (DoF, macro) pair (same result up
                                  to rounding; for checking the lane-parallel kernels).
                                  HHG_FLAG_NO_GRAPH: launch every kernel of a solve directly
-                                 instead of replaying recorded HIP graphs (same result)       */
+                                 instead of replaying recorded HIP graphs (same result).
+                                 HHG_FLAG_NO_PRELOAD: in the single-workgroup interface sweep,
+                                 load every row in its own class instead of loading the
+                                 sweep-invariant part of all rows first (same result)       */
 } hhg_options;
 
-enum { HHG_FLAG_NO_FUSED = 1, HHG_FLAG_NO_LANE_IFACE = 2, HHG_FLAG_NO_GRAPH = 4 };
+enum { HHG_FLAG_NO_FUSED = 1, HHG_FLAG_NO_LANE_IFACE = 2, HHG_FLAG_NO_GRAPH = 4, HHG_FLAG_NO_PRELOAD = 8 };
 
 typedef struct {
   int nu;                     /* V-cycles per FMG level (Algorithm 4's nu)                     */

@@ -170,9 +170,13 @@ hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
           continue;
         }
         int c1 = col;
-        while (c1 < lv.ncolours && waves(c1) <= kTaskOneGroupWaves) ++c1;
+        bool pre = !c->no_preload;
+        while (c1 < lv.ncolours && waves(c1) <= kTaskOneGroupWaves) {
+          if (waves(c1) > 16) pre = false;
+          ++c1;
+        }
         launch_iface_tasks_1wg<T>(c->dim, k, c->tab, lv.d_task_copy, lv.d_task_info, lv.d_task_loc, lv.d_task_seg,
-                                  lv.d_task_wmax, lv.d_task_woff, col, c1, y, x, y, mir, b, sA(c, l), ST(c));
+                                  lv.d_task_wmax, lv.d_task_woff, col, c1, y, x, y, mir, b, sA(c, l), pre, ST(c));
         col = c1;
       }
     } else if (lv.max_iface_class <= kIfaceOneGroup) {
@@ -492,6 +496,7 @@ hhg_status hhg_setup(const hhg_mesh* mesh, int L, const hhg_options* opt, hhg_ct
   c->no_fused = (opt->flags & HHG_FLAG_NO_FUSED) != 0;
   c->no_tasks = (opt->flags & HHG_FLAG_NO_LANE_IFACE) != 0;
   c->no_graph = (opt->flags & HHG_FLAG_NO_GRAPH) != 0;
+  c->no_preload = (opt->flags & HHG_FLAG_NO_PRELOAD) != 0;
   c->nV = mesh->n_vertices;
   c->nC = mesh->n_cells;
   const int nv = c->dim + 1;

@@ -194,6 +194,7 @@ struct hhg_ctx_s {
   // norm), recorded once per parameter set on a private capture stream and replayed on the
   // caller's stream; key = kind | nu << 4 | pre << 12 | post << 20 | precision << 28
   bool no_graph = false;            // run every launch eagerly (testing)
+  bool no_preload = false;          // single-workgroup interface sweep without preloading (testing)
   void* cap_stream = nullptr;       // hipStream_t used only while recording
   bool capturing = false;
   std::vector<std::pair<int64_t, void*>> graphs;   // (key, hipGraphExec_t)

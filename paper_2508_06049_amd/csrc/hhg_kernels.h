@@ -37,7 +37,10 @@ void launch_iface_tasks(int dim, const LK& lk, const Tables& tb, const int32_t* 
 template <typename T>
 void launch_iface_tasks_1wg(int dim, const LK& lk, const Tables& tb, const int32_t* tp, const int32_t* tq,
                             const int32_t* tco, const int32_t* tseg, const int32_t* wmax, const int32_t* woff, int c0,
-                            int c1, const T* xi, const T* xf, T* uout, T* umirror, const T* b, double sA, hipStream_t st);
+                            int c1, const T* xi, const T* xf, T* uout, T* umirror, const T* b, double sA, bool pre,
+                            hipStream_t st);
+// classes the preloading single-workgroup interface form holds at once
+int iface_pre_classes(int dim, bool dbl);
 template <typename T>
 void launch_smooth_iface(int dim, bool p1, const LK& lk, const Tables& tb, const int32_t* list, int count, const T* xi,
                          const T* xf, T* uout, T* umirror, const T* b, int jacobi, double omega, double sA,

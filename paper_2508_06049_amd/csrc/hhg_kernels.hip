@@ -482,6 +482,136 @@ __global__ void __launch_bounds__(1024) k_iface_tasks_1wg(LK lk, Tables tb, cons
   }
 }
 
+// The same classes in one workgroup with the sweep-invariant part of every row loaded before
+// the first class: task records, right-hand side, stencil weights, and the values of interior
+// neighbours (final once the macro interiors are swept).  Each class then reloads only its
+// interface neighbours, so a class costs one dependent memory round trip instead of two.
+// Wave v takes wavefront woff[c] + v of class c0 + k for k < P (the host launches this form
+// only when every class has at most 16 wavefronts and c1 - c0 <= P).  Rows are summed in the
+// same order as iface_task_wave, so both forms give identical results.
+template <int D, typename T>
+struct TaskPre {
+  int cp, seg, wmax, info;
+  uint32_t valid, ifm;
+  T rhs, diag, uold;
+  T coef[ndir<D>() - 1], v[ndir<D>() - 1];
+  uint32_t o[ndir<D>() - 1];
+};
+
+template <int D, typename T>
+__device__ __forceinline__ void task_pre_load(const LK& lk, const Tables& tb, const int32_t* __restrict__ tcopy,
+                                              const int32_t* __restrict__ tinfo, const int32_t* __restrict__ tloc,
+                                              const int32_t* __restrict__ tseg, int w,
+                                              const __amdgpu_buffer_rsrc_t& rxi, const __amdgpu_buffer_rsrc_t& rxf,
+                                              const __amdgpu_buffer_rsrc_t& rb, double sA, TaskPre<D, T>& q) {
+  const int idx = w * 64 + (int)(threadIdx.x & 63);
+  q.cp = tcopy[idx];
+  q.info = tinfo[idx];
+  q.seg = tseg[idx];
+  const int loc = tloc[idx];
+  q.valid = 0;
+  q.ifm = 0;
+  q.rhs = (T)0;
+  q.diag = (T)0;
+  q.uold = (T)0;
+#pragma unroll
+  for (int dd = 0; dd < ndir<D>() - 1; ++dd) { q.coef[dd] = (T)0; q.v[dd] = (T)0; q.o[dd] = 0; }
+  if (q.cp < 0) return;
+  const bool dir = (q.info >> 28) & 1;
+  const int m = q.info & 0xffffff, mask = (q.info >> 24) & 15;
+  const int i = loc & 2047, j = (loc >> 11) & 2047, k = loc >> 22;
+  const int64_t base = (int64_t)m * lk.S;
+  d_bload(rxf, (uint32_t)q.cp * (uint32_t)sizeof(T), q.uold);
+  if (dir) return;
+  d_bload(rb, (uint32_t)q.cp * (uint32_t)sizeof(T), q.rhs);
+  const double* W = tb.stiff + ((size_t)m * kMaxMask + mask) * ndir<D>();
+  q.valid = tb.validdirs[mask];
+  const double scale = sA * tb.kappa[m];
+#pragma unroll
+  for (int dd = 1; dd < ndir<D>(); ++dd) {
+    if (!((q.valid >> dd) & 1)) continue;
+    int a, b2, c;
+    d_off<D>(dd, a, b2, c);
+    const int i2 = i + a, j2 = j + b2, k2 = k + c;
+    q.o[dd - 1] = (uint32_t)(base + d_lin<D>(lk.n, i2, j2, k2)) * (uint32_t)sizeof(T);
+    q.coef[dd - 1] = (T)(scale * W[dd]);
+    if (d_mask<D>(lk.n, i2, j2, k2)) q.ifm |= 1u << dd;
+    else d_bload(rxi, q.o[dd - 1], q.v[dd - 1]);
+  }
+  q.diag = (T)(scale * W[0]);
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void task_pre_finish(const __amdgpu_buffer_rsrc_t& rxf, TaskPre<D, T>& q, T* uout,
+                                                T* umirror, uint32_t vbytes) {
+  const bool live = q.cp >= 0;
+  const bool dir = (q.info >> 28) & 1;
+  T off = (T)0;
+  if (live && !dir) {
+#pragma unroll
+    for (int dd = 1; dd < ndir<D>(); ++dd) {
+      if (!((q.valid >> dd) & 1)) continue;
+      if ((q.ifm >> dd) & 1) d_bload(rxf, q.o[dd - 1], q.v[dd - 1]);
+      off += q.coef[dd - 1] * q.v[dd - 1];
+    }
+  }
+  const int lead = q.seg & 63, len = q.seg >> 8;
+  const T num = q.rhs - off, diag = q.diag;
+  T snum = (T)0, sdiag = (T)0;
+  for (int kq = 0; kq < q.wmax; ++kq) {
+    const int src = min(lead + kq, 63);
+    const T a = __shfl(num, src, 64), d = __shfl(diag, src, 64);
+    if (kq < len) { snum += a; sdiag += d; }
+  }
+  if (!live) return;
+  const T unew = dir ? q.uold : snum / sdiag;
+  const uint32_t oc = (uint32_t)q.cp * (uint32_t)sizeof(T);
+  d_bstore(d_rsrc(uout, vbytes), oc, unew);
+  if (umirror) d_bstore(d_rsrc(umirror, vbytes), oc, unew);
+}
+
+// classes held in registers at once within the register budget of a 1024-thread workgroup:
+// four float rows in 2D, two double rows in 2D or float rows in 3D; double rows in 3D (14
+// neighbours) do not fit and use the plain form
+template <int D, typename T>
+constexpr int pre_classes() { return D == 2 ? (sizeof(T) == 4 ? 4 : 2) : (sizeof(T) == 4 ? 2 : 0); }
+
+int iface_pre_classes(int dim, bool dbl) {
+  return dim == 2 ? (dbl ? pre_classes<2, double>() : pre_classes<2, float>())
+                  : (dbl ? pre_classes<3, double>() : pre_classes<3, float>());
+}
+
+template <int D, typename T, int P>
+__global__ void __launch_bounds__(1024) k_iface_tasks_1wg_pre(LK lk, Tables tb, const int32_t* __restrict__ tcopy,
+                                                               const int32_t* __restrict__ tinfo,
+                                                               const int32_t* __restrict__ tloc,
+                                                               const int32_t* __restrict__ tseg,
+                                                               const int32_t* __restrict__ wmax,
+                                                               const int32_t* __restrict__ woff, int c0, int c1,
+                                                               const T* xi, const T* xf, T* uout, T* umirror,
+                                                               const T* __restrict__ b, double sA) {
+  const int wave = (int)(threadIdx.x >> 6);
+  const uint32_t vbytes = (uint32_t)((int64_t)lk.nmacro * lk.S) * (uint32_t)sizeof(T);
+  const __amdgpu_buffer_rsrc_t rxi = d_rsrc(xi, vbytes), rxf = d_rsrc(xf, vbytes), rb = d_rsrc(b, vbytes);
+  TaskPre<D, T> q[P];
+  bool has[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const int c = c0 + k;
+    const int w = c < c1 ? __builtin_amdgcn_readfirstlane(woff[c] + wave) : 0;
+    has[k] = c < c1 && w < woff[c + 1];
+    q[k].wmax = has[k] ? wmax[w] : 0;
+    if (has[k]) task_pre_load<D, T>(lk, tb, tcopy, tinfo, tloc, tseg, w, rxi, rxf, rb, sA, q[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    if (k < c1 - c0) {
+      if (has[k]) task_pre_finish<D, T>(rxf, q[k], uout, umirror, vbytes);
+      __syncthreads();
+    }
+  }
+}
+
 // Assembled residual rows at interface DoFs: r = sum_m (b_m - A_m x) in Tin precision, stored
 // in the lowest-id copy (other copies 0, Dirichlet DoFs 0).  Used when a float64 residual is
 // handed to float32 cycles: the per-macro partial rows are one-sided differences that cancel
@@ -1502,9 +1632,21 @@ void launch_iface_tasks(int dim, const LK& lk, const Tables& tb, const int32_t* 
 template <typename T>
 void launch_iface_tasks_1wg(int dim, const LK& lk, const Tables& tb, const int32_t* tp, const int32_t* tq,
                             const int32_t* tco, const int32_t* tseg, const int32_t* wmax, const int32_t* woff, int c0,
-                            int c1, const T* xi, const T* xf, T* uout, T* umirror, const T* b, double sA,
+                            int c1, const T* xi, const T* xf, T* uout, T* umirror, const T* b, double sA, bool pre,
                             hipStream_t st) {
   if (c1 <= c0) return;
+  // preloading form: the caller has checked that every class has at most 16 wavefronts
+  if (pre && c1 - c0 <= iface_pre_classes(dim, sizeof(T) == 8)) {
+    if (dim == 3) {
+      if constexpr (pre_classes<3, T>() > 0)
+        k_iface_tasks_1wg_pre<3, T, pre_classes<3, T>()><<<1, 1024, 0, st>>>(lk, tb, tp, tq, tco, tseg, wmax, woff, c0,
+                                                                             c1, xi, xf, uout, umirror, b, sA);
+    } else {
+      k_iface_tasks_1wg_pre<2, T, pre_classes<2, T>()><<<1, 1024, 0, st>>>(lk, tb, tp, tq, tco, tseg, wmax, woff, c0,
+                                                                           c1, xi, xf, uout, umirror, b, sA);
+    }
+    return;
+  }
   if (dim == 3)
     k_iface_tasks_1wg<3, T><<<1, 1024, 0, st>>>(lk, tb, tp, tq, tco, tseg, wmax, woff, c0, c1, xi, xf, uout, umirror, b,
                                                 sA);
@@ -1723,11 +1865,11 @@ template void launch_iface_tasks<float>(int, const LK&, const Tables&, const int
                                         float*, const float*, int, double, double, hipStream_t);
 template void launch_iface_tasks_1wg<double>(int, const LK&, const Tables&, const int32_t*, const int32_t*,
                                              const int32_t*, const int32_t*, const int32_t*, const int32_t*, int, int,
-                                             const double*, const double*, double*, double*, const double*, double,
+                                             const double*, const double*, double*, double*, const double*, double, bool,
                                              hipStream_t);
 template void launch_iface_tasks_1wg<float>(int, const LK&, const Tables&, const int32_t*, const int32_t*,
                                             const int32_t*, const int32_t*, const int32_t*, const int32_t*, int, int,
-                                            const float*, const float*, float*, float*, const float*, double,
+                                            const float*, const float*, float*, float*, const float*, double, bool,
                                             hipStream_t);
 template void launch_smooth_iface<double>(int, bool, const LK&, const Tables&, const int32_t*, int, const double*,
                                           const double*, double*, double*, const double*, int, double, double,

@@ -72,6 +72,29 @@ def test_lane_parallel_interface_equals_per_dof(lshape, L):
     assert rel_err(ra, to_host(ub)) < 1e-12
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_preloaded_interface_sweep_identical(lshape, precision):
+    # the single-workgroup interface sweep that loads the sweep-invariant part of its rows
+    # first sums every row in the same order as the plain form: identical solves on the
+    # workload at L = 9 (small classes at every level, all classes at the coarse levels)
+    import torch
+    from paper_2508_06049_amd import HHG
+    from paper_2508_06049_amd._lib import HHG_FLAG_NO_PRELOAD
+    w = lshape
+    _note("preloaded interface sweep", w.name, precision)
+    out = []
+    for flags in (0, HHG_FLAG_NO_PRELOAD):
+        hh = HHG(w.mesh.coords, w.mesh.cells, w.L, smoother=w.smoother, flags=flags)
+        X = hh.dof_coords().cpu().numpy()
+        u, st = hh.fmg_solve(to_dev(w.f(X)), to_dev(w.g(X)), nu=1, precision=precision, rtol=1e-6, max_iter=20)
+        out.append((to_host(u), st.vcycles))
+        hh.close()
+        del hh
+        torch.cuda.synchronize()
+    assert out[0][1] == out[1][1]
+    assert np.array_equal(out[0][0], out[1][0])
+
+
 def test_lshape_workload_mesh_parity_at_L7(lshape):
     from oracle import fmg
     from paper_2508_06049_amd import HHG
