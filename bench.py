@@ -241,6 +241,9 @@ def main():
     k = sm["fp32_refined"]
     achieved = k["launch_bytes"] / (k["launch_ms"] * 1e-3) / 1e9
     kname = KERNEL_NAME.get((w.mesh.dim, w.smoother, w.coefficient), "k_smooth_interior")
+    if w.mesh.dim == 3 and 2 ** w.L > 32:
+        # 3D levels above n = 32 are swept class by class (the macro does not fit in LDS)
+        kname = "k_gs3d_rows<float, true>"
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=TRAFFIC_BYTES.get((w.name, w.L, kname)),
                 kernel=kname, bytes_per_launch=k["launch_bytes"], avg_launch_us=round(k["launch_ms"] * 1e3, 2))

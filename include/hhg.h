@@ -93,10 +93,20 @@ typedef struct {
                                  instead of replaying recorded HIP graphs (same result).
                                  HHG_FLAG_NO_PRELOAD: in the single-workgroup interface sweep,
                                  load every row in its own class instead of loading the
-                                 sweep-invariant part of all rows first (same result)       */
+                                 sweep-invariant part of all rows first (same result).
+                                 HHG_FLAG_ROWS3D: use the 3D kernels that take one wavefront
+                                 per lattice row (operator application; class-by-class
+                                 interior sweep) on every level, not only from n = 128 on
+                                 (same result; for checking them on small levels)            */
 } hhg_options;
 
-enum { HHG_FLAG_NO_FUSED = 1, HHG_FLAG_NO_LANE_IFACE = 2, HHG_FLAG_NO_GRAPH = 4, HHG_FLAG_NO_PRELOAD = 8 };
+enum {
+  HHG_FLAG_NO_FUSED = 1,
+  HHG_FLAG_NO_LANE_IFACE = 2,
+  HHG_FLAG_NO_GRAPH = 4,
+  HHG_FLAG_NO_PRELOAD = 8,
+  HHG_FLAG_ROWS3D = 16
+};
 
 typedef struct {
   int nu;                     /* V-cycles per FMG level (Algorithm 4's nu)                     */

@@ -15,6 +15,8 @@ All data are analytic or seeded (no dataset exists for this method):
   5  cube of 4^3 Kuhn cubes (384 tets), L=6 (257^3 DoFs), kappa_e ~ U[0.5, 2] (seed 55),
      Fourier right-hand side (seed 5), goal J(u) = int w u with a Gaussian w (centre
      (1/2,1/2,1/2), sigma 0.1), adjoint gradients.
+  6  the mesh and right-hand side of 3 with kappa = 1 per macro, red-black GS: the size scan of
+     the smoother bandwidth at L = 8 (257^3) and L = 9 (513^3 DoFs, 135 M).
 """
 from __future__ import annotations
 
@@ -83,4 +85,8 @@ def config(i: int, L: Optional[int] = None) -> Workload:
                         lambda X: problems.fourier3d(X, amp), problems.zero, None,
                         kappa_cell=problems.kappa_cells_uniform(55, m.n_cells),
                         goal_weight=problems.gaussian3d)
+    if i == 6:
+        amp = problems.fourier_amplitudes(0)
+        return Workload("cube_uniform", meshes.kuhn_cube(1), L or 8, "redblack",
+                        lambda X: problems.fourier3d(X, amp), problems.zero, None)
     raise ValueError(i)

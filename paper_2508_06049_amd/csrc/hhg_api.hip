@@ -66,6 +66,9 @@ LK lk_of(hhg_ctx c, int l) {
   k.nIface = lv.nIface;
   k.ndof = lv.ndof;
   k.nmacro = (int)c->nC;
+  // one wavefront per 3D lattice row pays off once rows are long (below n = 128 most lanes of
+  // a wavefront would idle and the one-thread-per-point kernels are used)
+  k.rows3d_min = c->force_rows3d ? 1 : 128;
   return k;
 }
 
@@ -497,6 +500,7 @@ hhg_status hhg_setup(const hhg_mesh* mesh, int L, const hhg_options* opt, hhg_ct
   c->no_tasks = (opt->flags & HHG_FLAG_NO_LANE_IFACE) != 0;
   c->no_graph = (opt->flags & HHG_FLAG_NO_GRAPH) != 0;
   c->no_preload = (opt->flags & HHG_FLAG_NO_PRELOAD) != 0;
+  c->force_rows3d = (opt->flags & HHG_FLAG_ROWS3D) != 0;
   c->nV = mesh->n_vertices;
   c->nC = mesh->n_cells;
   const int nv = c->dim + 1;

@@ -195,6 +195,7 @@ struct hhg_ctx_s {
   // caller's stream; key = kind | nu << 4 | pre << 12 | post << 20 | precision << 28
   bool no_graph = false;            // run every launch eagerly (testing)
   bool no_preload = false;          // single-workgroup interface sweep without preloading (testing)
+  bool force_rows3d = false;        // 3D row kernels at every level (testing)
   void* cap_stream = nullptr;       // hipStream_t used only while recording
   bool capturing = false;
   std::vector<std::pair<int64_t, void*>> graphs;   // (key, hipGraphExec_t)

@@ -15,6 +15,7 @@ struct LK {
   int Sraw = 0, NI = 0, nEd = 0, nFd = 0;
   int64_t nIface = 0, ndof = 0;
   int nmacro = 0;
+  int rows3d_min = 128;   // 3D levels with n >= this use the row kernels
 };
 
 template <typename T>

@@ -267,6 +267,75 @@ __global__ void __launch_bounds__(256) k_smooth_interior(LK lk, Tables tb, const
   }
 }
 
+// 3D interior Gauss-Seidel of one colour class by rows: one wavefront per interior row (j, k)
+// of one macro (j, k >= 1, j + k <= n - 2), lanes along i in segments of 64.  The macro, the
+// row and the offsets of the 14 neighbour rows are wave-uniform and computed once; stencil
+// weights that vanish (the 7-point stencils of Kuhn macros) are skipped for the whole wave.
+// Rows are numbered plane by plane (k, then j), so the neighbour rows of a wavefront are
+// swept by wavefronts close to it in time; blocks are spread over the XCDs in contiguous runs
+// (block b runs on XCD b mod 8).  Same update, in the same order, as k_smooth_interior.
+template <typename T, bool FINE>
+__global__ void __launch_bounds__(256) k_gs3d_rows(LK lk, Tables tb, T* __restrict__ u, const T* __restrict__ b,
+                                                    int colour, int rb, double sA, int nrows) {
+  const int per_xcd = (int)(gridDim.x >> 3);   // gridDim.x is a multiple of 8
+  const int blk = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  const int wid = __builtin_amdgcn_readfirstlane(blk * 4 + (int)(threadIdx.x >> 6));
+  if (wid >= lk.nmacro * nrows) return;
+  const int n = lk.n;
+  const int m = wid / nrows;
+  const int r = wid - m * nrows;
+  // plane k holds the rows j = 1 .. n - 2 - k: r = sum_{k' < k} (n - 2 - k') + (j - 1)
+  const float a = 2.0f * (float)n - 5.0f;
+  int k = 1 + (int)floorf(0.5f * (a - sqrtf(fmaxf(a * a - 8.0f * (float)r, 0.0f))));
+  k = max(1, min(k, n - 3));
+  auto first = [&](int kk) { return (kk - 1) * (n - 2) - ((kk - 1) * kk) / 2; };
+  while (k < n - 3 && first(k + 1) <= r) ++k;
+  while (k > 1 && first(k) > r) --k;
+  const int j = 1 + r - first(k);
+  const int64_t base = (int64_t)m * lk.S;
+  auto row = [&](int jj, int kk) { return d_tet(n) - d_tet(n - kk) + jj * (n - kk + 1) - (jj * (jj - 1)) / 2; };
+  const double* W = tb.stiff + (size_t)m * kMaxMask * 15;
+  const double ks = sA * tb.kappa[m];
+  const T diag = (T)(ks * W[0]);
+  const int len = n - 1 - j - k;   // interior points i = 1 .. len
+  const int ctr0 = row(j, k);
+  // the points of this colour along the row: i = i1, i1 + P, ... (period P in i)
+  int i1, P;
+  if (rb) {
+    const int* rp = tb.rbpar + m * 4;
+    const int c1 = (rp[1] + j * rp[2] + k * rp[3]) & 1;
+    if (rp[1] & 1) {
+      P = 2;
+      i1 = c1 == colour ? 1 : 2;
+    } else {
+      if (c1 != colour) return;
+      P = 1;
+      i1 = 1;
+    }
+  } else {
+    P = 4;
+    i1 = 1 + ((colour - (1 + 2 * j + 3 * k)) % 4 + 4) % 4;
+  }
+  T cq[15];
+  int64_t ro[15];
+#pragma unroll
+  for (int q = 1; q < 15; ++q) {
+    cq[q] = (T)(ks * W[q]);
+    ro[q] = base + row(j + kOff3[q][1], k + kOff3[q][2]) + kOff3[q][0];
+  }
+  const int lane = (int)(threadIdx.x & 63);
+  for (int i = i1 + P * lane; i <= len; i += 64 * P) {
+    T off = (T)0;
+#pragma unroll
+    for (int q = 1; q < 15; ++q) {
+      if (W[q] == 0.0) continue;
+      off += cq[q] * u[ro[q] + i];
+    }
+    const int64_t ctr = base + ctr0 + i;
+    u[ctr] = (b[ctr] - off) / diag;
+  }
+}
+
 // Gauss-Seidel (or Jacobi) update of one interface DoF t: the assembled row is the sum of the
 // partial rows of all macros containing it.  Interior neighbours are read from xi, interface
 // neighbours (and the DoF's own old value) from xf; the new value goes to every copy in uout
@@ -945,6 +1014,67 @@ __global__ void __launch_bounds__(256) k_apply(LK lk, Tables tb, const Tin* __re
   y[base + s] = (Tout)v;
 }
 
+// 3D y = alpha b + beta (A_m x) per macro by rows: one wavefront per closure row (j, k) of one
+// macro, lanes along i in segments of 64.  Interior points take the macro's full stencil
+// through wave-uniform neighbour-row offsets; points on the macro boundary take the partial
+// stencil of their zero-set.  Same arithmetic, in the same order, as k_apply.
+template <typename Tin, typename Tout>
+__global__ void __launch_bounds__(256) k_apply3d_rows(LK lk, Tables tb, const Tin* __restrict__ x,
+                                                       const Tin* __restrict__ b, Tout* __restrict__ y, int op,
+                                                       double scale, double alpha, double beta, int zero_dir,
+                                                       int nrows) {
+  const int per_xcd = (int)(gridDim.x >> 3);   // gridDim.x is a multiple of 8
+  const int blk = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  const int wid = __builtin_amdgcn_readfirstlane(blk * 4 + (int)(threadIdx.x >> 6));
+  if (wid >= lk.nmacro * nrows) return;
+  const int n = lk.n;
+  const int m = wid / nrows;
+  const int r = wid - m * nrows;
+  // plane k holds the rows j = 0 .. n - k: r = sum_{k' < k} (n + 1 - k') + j
+  const float a = 2.0f * (float)n + 3.0f;
+  int k = (int)floorf(0.5f * (a - sqrtf(fmaxf(a * a - 8.0f * (float)r, 0.0f))));
+  k = max(0, min(k, n));
+  auto first = [&](int kk) { return kk * (n + 1) - (kk * (kk - 1)) / 2; };
+  while (k < n && first(k + 1) <= r) ++k;
+  while (k > 0 && first(k) > r) --k;
+  const int j = r - first(k);
+  const int64_t base = (int64_t)m * lk.S;
+  auto row = [&](int jj, int kk) { return d_tet(n) - d_tet(n - kk) + jj * (n - kk + 1) - (jj * (jj - 1)) / 2; };
+  const double* Wt = (op == 0 ? tb.stiff : tb.mass) + (size_t)m * kMaxMask * 15;
+  const double sc = op == 0 ? scale * tb.kappa[m] : scale;
+  Tin cq[15];
+  int64_t ro[15];
+  const bool inner_row = j >= 1 && k >= 1 && j + k <= n - 2;
+#pragma unroll
+  for (int q = 0; q < 15; ++q) {
+    cq[q] = (Tin)(sc * Wt[q]);
+    ro[q] = inner_row ? base + row(j + kOff3[q][1], k + kOff3[q][2]) + kOff3[q][0] : 0;
+  }
+  const int64_t r0 = base + row(j, k);
+  const int len = n - j - k;   // points i = 0 .. len
+  const uint32_t dirb = tb.dirbits[m];
+  const int lane = (int)(threadIdx.x & 63);
+  for (int i = lane; i <= len; i += 64) {
+    const int mask = d_mask<3>(n, i, j, k);
+    const int64_t ctr = r0 + i;
+    if (zero_dir && ((dirb >> mask) & 1)) { y[ctr] = (Tout)0; continue; }
+    Tin off, diag;
+    if (mask == 0) {
+      Tin acc = (Tin)0;
+#pragma unroll
+      for (int q = 1; q < 15; ++q) acc += cq[q] * x[ro[q] + i];
+      off = acc;
+      diag = cq[0];
+    } else {
+      d_row_const<3, Tin>(lk, Wt + (size_t)mask * 15, tb.validdirs[mask], sc, x, base, i, j, k, off, diag);
+    }
+    const Tin ax = off + diag * x[ctr];
+    Tin v = (Tin)beta * ax;
+    if (b) v += (Tin)alpha * b[ctr];
+    y[ctr] = (Tout)v;
+  }
+}
+
 // 2D y = alpha b + beta (A_m x) with a per-macro coefficient in two wavefront roles of one
 // launch.  Interior role (wavefronts 0 .. nint-1): a 64-node segment of kApplyRows rows of one
 // macro, lanes along i, the macro's full stencil with weights computed once per wavefront,
@@ -1453,14 +1583,16 @@ __global__ void __launch_bounds__(256) k_bilinear(LK lk, Tables tb, const double
 }
 
 // out[m * nval + v] = sum over chunks (fixed order)
+// one block per output (macro m, value v): the chunk partials of the macro summed by the block
 __global__ void __launch_bounds__(256) k_macro_sum(const double* __restrict__ partial, int nmacro, int nchunk, int nval,
                                                    double* __restrict__ out) {
-  const int id = blockIdx.x * 256 + threadIdx.x;
-  if (id >= nmacro * nval) return;
+  __shared__ double sh[4];
+  const int id = blockIdx.x;
   const int m = id / nval, v = id - m * nval;
   double s = 0.0;
-  for (int q = 0; q < nchunk; ++q) s += partial[((size_t)m * nchunk + q) * nval + v];
-  out[id] = s;
+  for (int q = (int)threadIdx.x; q < nchunk; q += 256) s += partial[((size_t)m * nchunk + q) * nval + v];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[id] = s;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1569,6 +1701,15 @@ template <typename T>
 void launch_smooth_interior(int dim, bool p1, const LK& lk, const Tables& tb, const T* uin, T* uout, const T* b, int colour,
                             int rb, int jacobi, double omega, double sA, const double* kn, bool fine, hipStream_t st) {
   if (lk.NI <= 0) return;
+  if (dim == 3 && !p1 && !jacobi && uin == uout && lk.n >= max(lk.rows3d_min, 4)) {
+    // Gauss-Seidel in place with a per-macro coefficient: by rows
+    const int nrows = (lk.n - 3) * (lk.n - 2) / 2;
+    const int64_t waves = (int64_t)lk.nmacro * nrows;
+    const unsigned g = (unsigned)((waves + 31) / 32 * 8);   // 4 rows per block, a multiple of 8 blocks
+    if (fine) k_gs3d_rows<T, true><<<g, 256, 0, st>>>(lk, tb, uout, b, colour, rb, sA, nrows);
+    else k_gs3d_rows<T, false><<<g, 256, 0, st>>>(lk, tb, uout, b, colour, rb, sA, nrows);
+    return;
+  }
   const unsigned g = (unsigned)(lk.nmacro * ((lk.NI + 255) / 256));
 #define HHG_SI(D, P, F) k_smooth_interior<D, T, P, F><<<g, 256, 0, st>>>(lk, tb, uin, uout, b, colour, rb, jacobi, omega, sA, kn)
   if (dim == 3) {
@@ -1697,6 +1838,13 @@ void launch_apply(int dim, bool p1, const LK& lk, const Tables& tb, const Tin* x
     k_apply2d_rows<Tin, Tout><<<gw, 256, 0, st>>>(lk, tb, x, b, y, op, scale, alpha, beta, zero_dir, nseg, nint);
     return;
   }
+  if (dim == 3 && !(p1 && op == 0) && lk.n >= lk.rows3d_min) {
+    const int nrows = (lk.n + 1) * (lk.n + 2) / 2;
+    const int64_t waves = (int64_t)lk.nmacro * nrows;
+    const unsigned gw = (unsigned)((waves + 31) / 32 * 8);   // 4 rows per block, a multiple of 8 blocks
+    k_apply3d_rows<Tin, Tout><<<gw, 256, 0, st>>>(lk, tb, x, b, y, op, scale, alpha, beta, zero_dir, nrows);
+    return;
+  }
   const unsigned g = (unsigned)(lk.nmacro * ((lk.Sraw + 255) / 256));
   if (dim == 3) {
     if (p1) k_apply<3, Tin, Tout, true><<<g, 256, 0, st>>>(lk, tb, x, b, y, op, scale, alpha, beta, zero_dir, kn);
@@ -1806,7 +1954,7 @@ void launch_estimate(int dim, int norm, const LK& f, const LK& c, const Tables& 
     if (norm == 1) HHG_EST(2, 1); else if (norm == 2) HHG_EST(2, 2); else HHG_EST(2, 0);
   }
 #undef HHG_EST
-  k_macro_sum<<<nblk((int64_t)f.nmacro * 2), 256, 0, st>>>(partial, f.nmacro, nchunk, 2, out);
+  k_macro_sum<<<(unsigned)(f.nmacro * 2), 256, 0, st>>>(partial, f.nmacro, nchunk, 2, out);
 }
 
 void launch_bilinear(int dim, const LK& lk, const Tables& tb, const double* x, const double* y, double* partial,
@@ -1815,7 +1963,7 @@ void launch_bilinear(int dim, const LK& lk, const Tables& tb, const double* x, c
   const unsigned g = (unsigned)(lk.nmacro * nchunk);
   if (dim == 3) k_bilinear<3><<<g, 256, 0, st>>>(lk, tb, x, y, partial, sA);
   else k_bilinear<2><<<g, 256, 0, st>>>(lk, tb, x, y, partial, sA);
-  k_macro_sum<<<nblk(lk.nmacro), 256, 0, st>>>(partial, lk.nmacro, nchunk, 1, out);
+  k_macro_sum<<<(unsigned)lk.nmacro, 256, 0, st>>>(partial, lk.nmacro, nchunk, 1, out);
 }
 
 void launch_canon_to_full(int dim, const LK& lk, const Tables& tb, const double* canon, double* full, int mode,

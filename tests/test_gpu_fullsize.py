@@ -256,3 +256,51 @@ def test_adjoint_workload_gradient_full_size():
     fd = (J(f0 + 1e-2 * d, k0) - J(f0 - 1e-2 * d, k0)) / 2e-2
     an = float(torch.dot(ft.grad, d))
     assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+def test_largest_2d_level():
+    # L = 10, the largest 2D level the library sets up (n = 1024; closure coordinates take 11
+    # bits), on the L-shape workload mesh: 75.5 M DoFs.  The float32-refined solve converges,
+    # agrees with float64, and its error against r^(2/3) sin(2 phi/3) falls from L = 9 at
+    # least as fast as the O(h) of the corner singularity
+    import torch
+    from paper_2508_06049_amd import HHG, configs
+    w = configs.config(2)
+    errs = []
+    for L in (9, 10):
+        _note("largest 2D level", L)
+        hh = HHG(w.mesh.coords, w.mesh.cells, L, smoother=w.smoother)
+        X = hh.dof_coords().cpu().numpy()
+        f, g, ue = to_dev(w.f(X)), to_dev(w.g(X)), to_dev(w.u_exact(X))
+        u32, s32 = hh.fmg_solve(f, g, nu=1, precision="fp32_refined", rtol=1e-10, max_iter=60)
+        assert s32.final_rel_residual <= 1e-10
+        if L == 10:
+            assert hh.num_dofs() == 75_510_785
+            u64, s64 = hh.fmg_solve(f, g, nu=1, rtol=1e-10, max_iter=60)
+            assert rel_err(to_host(u32), to_host(u64)) < 1e-7
+        e = ue - u32
+        errs.append(float(torch.dot(e, hh.mass_apply(e))) ** 0.5)
+        hh.close()
+        del hh
+        torch.cuda.synchronize()
+    assert errs[1] < 0.55 * errs[0]
+
+
+def test_largest_3d_level():
+    # L = 9 on the unit cube of 6 Kuhn tetrahedra: 513^3 = 135 M DoFs, the class-by-class 3D
+    # sweep at n = 512.  The solve converges in both precisions to the same solution and the
+    # estimator's local values square-sum to its global norm
+    import torch
+    from paper_2508_06049_amd import HHG, configs
+    w = configs.config(6, 9)
+    _note("largest 3D level", w.mesh.n_cells, w.L)
+    hh = HHG(w.mesh.coords, w.mesh.cells, w.L, smoother=w.smoother)
+    assert hh.num_dofs() == 513 ** 3
+    X = hh.dof_coords().cpu().numpy()
+    f, g = to_dev(w.f(X)), to_dev(w.g(X))
+    u32, s32 = hh.fmg_solve(f, g, nu=1, precision="fp32_refined", rtol=1e-8, max_iter=60)
+    assert s32.final_rel_residual <= 1e-8
+    est = hh.estimate(1)
+    assert abs(float(np.sum(est["eta_T"] ** 2)) - est["norm_e"] ** 2) <= 1e-10 * est["norm_e"] ** 2
+    u64, s64 = hh.fmg_solve(f, g, nu=1, rtol=1e-8, max_iter=60)
+    assert rel_err(to_host(u32), to_host(u64)) < 1e-6

@@ -133,6 +133,39 @@ def test_smoother_matches(name, smoother):
     assert rel_err(to_host(ug), uo[p]) < 1e-12
 
 
+@pytest.mark.parametrize("name,smoother", [("kuhn1_5", "redblack"), ("kuhn2", "multicolour"), ("tet", "multicolour"),
+                                           ("twotets", "multicolour")])
+def test_3d_row_sweep_matches(name, smoother):
+    # the 3D kernels with one wavefront per lattice row (class-by-class interior sweep and
+    # operator application, used from n = 128 on; forced here on small levels with
+    # HHG_FLAG_NO_FUSED | HHG_FLAG_ROWS3D) against the oracle's smoother and operator: Kuhn
+    # (7-point) and generic (15-point) macros, per-macro coefficients
+    from paper_2508_06049_amd import HHG
+    from paper_2508_06049_amd._lib import HHG_FLAG_NO_FUSED, HHG_FLAG_ROWS3D
+    mk, L, _ = MESHES[name]
+    _note("3d row sweep", name, smoother, L)
+    m = mk()
+    h, perms = oracle_hierarchy(m, L)
+    kc = problems.kappa_cells_uniform(6, m.n_cells)
+    hh = HHG(m.coords, m.cells, L, smoother=smoother, kappa_cell=kc, flags=HHG_FLAG_NO_FUSED | HHG_FLAG_ROWS3D)
+    S = fmg.FMGSolver(h, kappa_cell=kc, smoother=smoother)
+    rng = np.random.default_rng(12)
+    p = perms[L]
+    u = rng.standard_normal(h.levels[L].n)
+    b = rng.standard_normal(h.levels[L].n)
+    uo = u.copy()
+    S.smooth(L, uo, b, 2)
+    ug = to_dev(u[p])
+    hh.smooth(L, ug, to_dev(b[p]), 2)
+    assert rel_err(to_host(ug), uo[p]) < 1e-12
+    A, M = S.sys[L].A, S.sys[L].M
+    assert rel_err(to_host(hh.apply(L, "stiffness", to_dev(u[p]))), (A @ u)[p]) < 1e-13
+    assert rel_err(to_host(hh.apply(L, "mass", to_dev(u[p]))), (M @ u)[p]) < 1e-13
+    uf, _ = S.fmg(S.rhs_levels(b), np.zeros(len(b)), nu=1)
+    ugf, _ = hh.fmg_solve(to_dev(b[p]), to_dev(np.zeros(len(b))), nu=1)
+    assert np.abs(to_host(ugf) - uf[p]).max() <= 1e-12 * np.abs(uf).max()
+
+
 def _rhs(name, X, dim):
     if name.startswith("square"):
         return problems.sine2d_f(X), np.zeros(len(X))
@@ -256,6 +289,30 @@ def test_estimate_variant_arguments_checked():
     for j in (0, 3):
         with pytest.raises(HHGError):
             hh.estimate(j, norm="energy")
+
+
+@pytest.mark.parametrize("L", [1, 2])
+def test_single_macro_smallest_levels(L):
+    # one macro triangle: at L = 1 every DoF is a Dirichlet DoF (the solve returns g, with and
+    # without extra cycles, and no inner DoF exists); at L = 2 there is one interior DoF and
+    # the FMG solve is the oracle's
+    m = meshes.CoarseMesh(np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]]), np.array([[0, 1, 2]], dtype=np.int32),
+                          "one_triangle")
+    _note("single macro", L)
+    h, perms = oracle_hierarchy(m, L)
+    X = h.levels[L].X
+    f, g = problems.sine2d_f(X), 0.3 + X[:, 0] * X[:, 1]
+    hh = hip_context(m, L, "multicolour")
+    p = perms[L]
+    for kw in (dict(), dict(rtol=1e-12, max_iter=10)):
+        ug, st = hh.fmg_solve(to_dev(f[p]), to_dev(g[p]), nu=1, **kw)
+        S = fmg.FMGSolver(h, smoother="multicolour")
+        uo, _ = S.fmg(S.rhs_levels(f), g, nu=1)
+        if kw:
+            S.extra_cycles(uo, S.rhs_levels(f)[L], g, rtol=1e-12, max_iter=10)
+        assert np.abs(to_host(ug) - uo[p]).max() <= 1e-12 * np.abs(uo).max()
+    if L == 1:
+        assert np.array_equal(to_host(ug), g[p])
 
 
 def test_estimate_requires_solve():
