@@ -43,6 +43,8 @@ constexpr int kIfaceOneGroup = 4096;
 constexpr int kTaskOneGroupWaves = 32;
 // blocks of the interior part of a squared norm (one partial each)
 constexpr int kNormBlocks = 8192;
+// interior rows per wavefront of the 2D row estimator
+constexpr int kEstRows = 4;
 
 // direction tables: index 0 is the centre, 1..H positive, H+1..2H negative
 constexpr int kDir3[7][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {-1, 1, 0}, {-1, 0, 1}, {0, -1, 1}, {1, -1, 1}};

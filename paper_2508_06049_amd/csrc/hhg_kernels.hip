@@ -1498,6 +1498,102 @@ __global__ void __launch_bounds__(256) k_sum(const double* __restrict__ partial,
   if (threadIdx.x == 0) *out = v;
 }
 
+// 2D L2 estimator by rows: per macro T the two sums of k_estimate<2, 0> (e1 = u - a on level
+// L, e2 = u - P bc with bc on level L-1, each against T's mass matrix).  Interior role: one
+// wavefront per block of kEstRows interior rows and 62 columns of one macro; every lane forms
+// e1 and e2 at its column on the block's rows and the rows above and below (P bc evaluated once
+// per node), and takes the values of columns i - 1 and i + 1 from its neighbour lanes.
+// Boundary role: one lane per macro-boundary node with its partial mass stencil.  Every
+// wavefront writes the two sums of its nodes to partial[(m * per-macro wavefronts + w) * 2 + v].
+__global__ void __launch_bounds__(256) k_estimate2d_rows(LK f, LK c, Tables tb, const double* __restrict__ u,
+                                                          const double* __restrict__ a,
+                                                          const double* __restrict__ bc,
+                                                          double* __restrict__ partial, double sM, int nrb, int nseg,
+                                                          int nbw) {
+  constexpr int R = kEstRows;
+  const int wpm = nrb * nseg + nbw;
+  const int wid = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+  if (wid >= f.nmacro * wpm) return;
+  const int m = wid / wpm;
+  const int w = wid - m * wpm;
+  const int n = f.n;
+  const int lane = (int)(threadIdx.x & 63);
+  const int64_t fb = (int64_t)m * f.S, cb = (int64_t)m * c.S;
+  double s1 = 0.0, s2 = 0.0;
+  if (w < nrb * nseg) {
+    const int jb = w / nseg, seg = w - jb * nseg;
+    const int j0 = 1 + jb * R;
+    const int i = seg * 62 + lane;   // lanes 1 .. 62 produce; lanes 0 and 63 are halo
+    const double* W = tb.mass + (size_t)m * kMaxMask * 7;
+    double w7[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) w7[q] = W[q];
+    double e1[R + 2], e2[R + 2];
+#pragma unroll
+    for (int t = 0; t < R + 2; ++t) {
+      const int r = j0 - 1 + t;
+      const bool in = r <= n && i <= n - r;
+      double v1 = 0.0, v2 = 0.0;
+      if (in) {
+        const int q = d_lin2(n, i, r);
+        const double uq = u[fb + q];
+        v1 = uq - a[fb + q];
+        v2 = uq - d_prolong_val<2, double>(c.n, bc, cb, i, r, 0);
+      }
+      e1[t] = v1;
+      e2[t] = v2;
+    }
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      const int j = j0 + rr;
+      // neighbours in the order of the 2D directions: (1,0) (0,1) (-1,1) (-1,0) (0,-1) (1,-1)
+      const double a1 = w7[0] * e1[rr + 1] + w7[1] * from_next(e1[rr + 1]) + w7[2] * e1[rr + 2] +
+                        w7[3] * from_prev(e1[rr + 2]) + w7[4] * from_prev(e1[rr + 1]) + w7[5] * e1[rr] +
+                        w7[6] * from_next(e1[rr]);
+      const double a2 = w7[0] * e2[rr + 1] + w7[1] * from_next(e2[rr + 1]) + w7[2] * e2[rr + 2] +
+                        w7[3] * from_prev(e2[rr + 2]) + w7[4] * from_prev(e2[rr + 1]) + w7[5] * e2[rr] +
+                        w7[6] * from_next(e2[rr]);
+      if (lane >= 1 && lane <= 62 && i >= 1 && j <= n - 2 && i + j <= n - 1) {
+        s1 += e1[rr + 1] * a1;
+        s2 += e2[rr + 1] * a2;
+      }
+    }
+  } else {
+    const int q = (w - nrb * nseg) * 64 + lane;
+    if (q < 3 * n) {
+      int i, j;
+      if (q <= n) { i = q; j = 0; }
+      else if (q <= 2 * n) { i = 0; j = q - n; }
+      else { j = q - 2 * n; i = n - j; }
+      const int mask = d_mask<2>(n, i, j, 0);
+      const double* W = tb.mass + ((size_t)m * kMaxMask + mask) * 7;
+      const uint32_t valid = tb.validdirs[mask];
+      double m1 = 0.0, m2 = 0.0;
+      for (int d = 0; d < 7; ++d) {
+        if (d && !((valid >> d) & 1)) continue;
+        const int ii = i + kOff2[d][0], jj = j + kOff2[d][1];
+        const int lq = d_lin2(n, ii, jj);
+        const double uq = u[fb + lq];
+        m1 += W[d] * (uq - a[fb + lq]);
+        m2 += W[d] * (uq - d_prolong_val<2, double>(c.n, bc, cb, ii, jj, 0));
+      }
+      const int s = d_lin2(n, i, j);
+      const double uc = u[fb + s];
+      s1 = (uc - a[fb + s]) * m1;
+      s2 = (uc - d_prolong_val<2, double>(c.n, bc, cb, i, j, 0)) * m2;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    s1 += __shfl_xor(s1, o, 64);
+    s2 += __shfl_xor(s2, o, 64);
+  }
+  if (lane == 0) {
+    partial[((size_t)m * wpm + w) * 2 + 0] = s1 * sM;
+    partial[((size_t)m * wpm + w) * 2 + 1] = s2 * sM;
+  }
+}
+
 // Estimator: per macro T, sum over the closure nodes q of T of e(q) (N_T e)(q) for
 // e1 = u - a (a on level L) and e2 = u - P bc (bc on level L-1), N_T the matrix of T's own
 // micro elements for the chosen norm: NORM 0 the consistent mass matrix (L2), NORM 1 the
@@ -1945,6 +2041,14 @@ template void launch_sqnorm_closure<float>(int, const LK&, const float*, double*
 
 void launch_estimate(int dim, int norm, const LK& f, const LK& c, const Tables& tb, const double* u, const double* a,
                      const double* bc, double* partial, double* out, double scale, hipStream_t st) {
+  if (dim == 2 && norm == 0 && f.n >= 4) {
+    const int nrb = (f.n - 2 + kEstRows - 1) / kEstRows, nseg = (f.n - 2 + 61) / 62, nbw = (3 * f.n + 63) / 64;
+    const int wpm = nrb * nseg + nbw;
+    const unsigned g = (unsigned)(((int64_t)f.nmacro * wpm + 3) / 4);
+    k_estimate2d_rows<<<g, 256, 0, st>>>(f, c, tb, u, a, bc, partial, scale, nrb, nseg, nbw);
+    k_macro_sum<<<(unsigned)(f.nmacro * 2), 256, 0, st>>>(partial, f.nmacro, wpm, 2, out);
+    return;
+  }
   const int nchunk = (int)((f.Sraw + 255) / 256);
   const unsigned g = (unsigned)(f.nmacro * nchunk);
 #define HHG_EST(D, N) k_estimate<D, N><<<g, 256, 0, st>>>(f, c, tb, u, a, bc, partial, scale)

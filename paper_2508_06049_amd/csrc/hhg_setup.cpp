@@ -669,6 +669,13 @@ void plan_workspace(hhg_ctx c) {
   int64_t bpm = (lt.Sraw + 255) / 256;
   int64_t nblk_norm = nC * ((lt.NI + 255) / 256) + (lt.nIface + 255) / 256 + 16;
   c->red_capacity = std::max<int64_t>(std::max<int64_t>(nC * bpm * 4, nblk_norm), kNormBlocks + (lt.nIface + 255) / 256) + 1024;
+  if (d == 2) {
+    // the 2D row estimator: two sums per wavefront, kEstRows x 62 interior nodes or 64
+    // boundary nodes of one macro per wavefront; its per-macro results follow the partials
+    const int64_t n = lt.n;
+    const int64_t wpm = ((n - 2 + kEstRows - 1) / kEstRows) * ((n - 2 + 61) / 62) + (3 * n + 63) / 64;
+    c->red_capacity = std::max<int64_t>(c->red_capacity, nC * wpm * 2 + 2 * nC + 1024);
+  }
   c->o_red = take(c->red_capacity * 8);
   c->o_scal = take(64 * 8);
   c->o_mxyz = take(nC * nv * d * 8);
