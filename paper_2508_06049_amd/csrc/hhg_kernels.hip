@@ -488,12 +488,9 @@ __device__ __forceinline__ void iface_task_wave(const LK& lk, const Tables& tb, 
         if (same) {
           d_bload(rxf, o, v);
         } else {
-          // interface neighbours from xf, interior ones from xi: both loads, one select (the
-          // descriptors stay uniform)
-          T vi, vf;
-          d_bload(rxi, o, vi);
-          d_bload(rxf, o, vf);
-          v = d_mask<D>(lk.n, i2, j2, k2) ? vf : vi;
+          // interface neighbours from xf, interior ones from xi: one load through a per-lane
+          // address (a buffer descriptor must be wave-uniform)
+          v = (d_mask<D>(lk.n, i2, j2, k2) ? xf : xi)[(uint32_t)(base + d_lin<D>(lk.n, i2, j2, k2))];
         }
         off += (T)(scale * W[dd]) * v;
       }
