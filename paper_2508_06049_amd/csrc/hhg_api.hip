@@ -240,7 +240,15 @@ void residual_f32(hhg_ctx c, int l, const double* b) {
   Level& lv = c->lev[l];
   launch_apply<double, float>(c->dim, p1(c), lk_of(c, l), c->tab, lv.x, b, lv.b32, 0, sA(c, l), 1.0, -1.0, 1, lv.kn,
                               ST(c));
-  launch_iface_residual<double, float>(c->dim, p1(c), lk_of(c, l), c->tab, lv.x, b, lv.b32, sA(c, l), lv.kn, ST(c));
+  // by lanes in 2D (two or a few copies per DoF); in 3D, where edge and vertex DoFs have many
+  // copies, the one-thread-per-DoF kernel measured faster
+  if (c->dim == 2 && lv.task_ok && !c->no_tasks)
+    launch_iface_residual_tasks<double, float>(c->dim, lk_of(c, l), c->tab, lv.d_task_copy, lv.d_task_info,
+                                               lv.d_task_loc, lv.d_task_seg, lv.d_task_wmax,
+                                               lv.task_woff[lv.interior_colours], lv.task_woff[lv.ncolours], lv.x, b,
+                                               lv.b32, sA(c, l), ST(c));
+  else
+    launch_iface_residual<double, float>(c->dim, p1(c), lk_of(c, l), c->tab, lv.x, b, lv.b32, sA(c, l), lv.kn, ST(c));
 }
 
 // one cycle on level l of the selected precision for x_l (float64) and rhs bf_l; with

@@ -54,6 +54,11 @@ void launch_iface_sweep_1wg(int dim, bool p1, const LK& lk, const Tables& tb, co
 template <typename Tin, typename Tout>
 void launch_apply(int dim, bool p1, const LK& lk, const Tables& tb, const Tin* x, const Tin* b, Tout* y, int op,
                   double scale, double alpha, double beta, int zero_dir, const double* kn, hipStream_t st);
+// interface residual rows from the interface tasks (wavefronts w0..w1-1 of all classes)
+template <typename Tin, typename Tout>
+void launch_iface_residual_tasks(int dim, const LK& lk, const Tables& tb, const int32_t* tp, const int32_t* tq,
+                                 const int32_t* tco, const int32_t* tseg, const int32_t* wmax, int w0, int w1,
+                                 const Tin* x, const Tin* b, Tout* y, double sA, hipStream_t st);
 template <typename Tin, typename Tout>
 void launch_iface_residual(int dim, bool p1, const LK& lk, const Tables& tb, const Tin* x, const Tin* b, Tout* y,
                            double sA, const double* kn, hipStream_t st);

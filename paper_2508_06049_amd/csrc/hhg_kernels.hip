@@ -678,6 +678,46 @@ __global__ void __launch_bounds__(1024) k_iface_tasks_1wg_pre(LK lk, Tables tb, 
   }
 }
 
+// The same assembled residual rows from the interface tasks: one lane per (DoF, incident
+// macro) pair forms its macro's term b_m - A_m x, the lanes of a DoF sum the terms in
+// incidence order through shuffles, and the first lane (the lowest-id copy) stores the sum;
+// the other copies, and every copy of a Dirichlet DoF, get 0.  Identical to k_iface_residual.
+template <int D, typename Tin, typename Tout>
+__global__ void __launch_bounds__(256) k_iface_residual_tasks(LK lk, Tables tb, const int32_t* __restrict__ tcopy,
+                                                               const int32_t* __restrict__ tinfo,
+                                                               const int32_t* __restrict__ tloc,
+                                                               const int32_t* __restrict__ tseg,
+                                                               const int32_t* __restrict__ wmax, int w0, int w1,
+                                                               const Tin* __restrict__ x, const Tin* __restrict__ b,
+                                                               Tout* __restrict__ y, double sA) {
+  const int w = __builtin_amdgcn_readfirstlane(w0 + (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+  if (w >= w1) return;
+  const int lane = (int)(threadIdx.x & 63);
+  const int idx = w * 64 + lane;
+  const int cp = tcopy[idx];
+  const int info = tinfo[idx], loc = tloc[idx], seg = tseg[idx];
+  const bool live = cp >= 0;
+  const bool dir = (info >> 28) & 1;
+  Tin term = (Tin)0;
+  if (live && !dir) {
+    const int m = info & 0xffffff, mask = (info >> 24) & 15;
+    const int i = loc & 2047, j = (loc >> 11) & 2047, k = loc >> 22;
+    const int64_t base = (int64_t)m * lk.S;
+    Tin o, dg;
+    d_row_const<D, Tin>(lk, tb.stiff + ((size_t)m * kMaxMask + mask) * ndir<D>(), tb.validdirs[mask],
+                        sA * tb.kappa[m], x, base, i, j, k, o, dg);
+    term = b[cp] - o - dg * x[cp];
+  }
+  const int lead = seg & 63, len = seg >> 8;
+  Tin r = (Tin)0;
+  const int wm = wmax[w];
+  for (int kq = 0; kq < wm; ++kq) {
+    const Tin t = __shfl(term, min(lead + kq, 63), 64);
+    if (kq < len) r += t;
+  }
+  if (live) y[cp] = (Tout)(lane == lead ? r : (Tin)0);
+}
+
 // Assembled residual rows at interface DoFs: r = sum_m (b_m - A_m x) in Tin precision, stored
 // in the lowest-id copy (other copies 0, Dirichlet DoFs 0).  Used when a float64 residual is
 // handed to float32 cycles: the per-macro partial rows are one-sided differences that cancel
@@ -1947,6 +1987,21 @@ void launch_apply(int dim, bool p1, const LK& lk, const Tables& tb, const Tin* x
     else k_apply<2, Tin, Tout, false><<<g, 256, 0, st>>>(lk, tb, x, b, y, op, scale, alpha, beta, zero_dir, kn);
   }
 }
+
+template <typename Tin, typename Tout>
+void launch_iface_residual_tasks(int dim, const LK& lk, const Tables& tb, const int32_t* tp, const int32_t* tq,
+                                 const int32_t* tco, const int32_t* tseg, const int32_t* wmax, int w0, int w1,
+                                 const Tin* x, const Tin* b, Tout* y, double sA, hipStream_t st) {
+  if (w1 <= w0) return;
+  const unsigned g = (unsigned)((w1 - w0 + 3) / 4);
+  if (dim == 3)
+    k_iface_residual_tasks<3, Tin, Tout><<<g, 256, 0, st>>>(lk, tb, tp, tq, tco, tseg, wmax, w0, w1, x, b, y, sA);
+  else
+    k_iface_residual_tasks<2, Tin, Tout><<<g, 256, 0, st>>>(lk, tb, tp, tq, tco, tseg, wmax, w0, w1, x, b, y, sA);
+}
+template void launch_iface_residual_tasks<double, float>(int, const LK&, const Tables&, const int32_t*, const int32_t*,
+                                                         const int32_t*, const int32_t*, const int32_t*, int, int,
+                                                         const double*, const double*, float*, double, hipStream_t);
 
 template <typename Tin, typename Tout>
 void launch_iface_residual(int dim, bool p1, const LK& lk, const Tables& tb, const Tin* x, const Tin* b, Tout* y,
