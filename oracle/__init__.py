@@ -15,12 +15,15 @@ Parity status per function (what pins it is listed in the tests):
   fmg.*         pinned: direct sparse solve, MMS O(h^2) rates, linearity of MG
   estimate.*    pinned: brute-force quadrature, affine special case, effectivity bounds
                 (Theorem on eta_j bounds, closed forms reproduced from Tables 1-2)
+  estimate.*    (norm variants) pinned: gradient quadrature of the energy norm, mass-matrix
+                row sums, Galerkin orthogonality of the energy estimate
   adjoint.*     pinned: duality J = g^T u = lambda^T b, finite differences
+  transfer.*    pinned: affine functions exact, nested transfer equals the prolongation
   The float32-refined form of the solve has no oracle function: the library's result is
   compared with the float64 direct solution it converges to (its fixed point); the float32
   V-cycle inside it is parity unpinned.
 """
 from .refine import Hierarchy, build_hierarchy
-from . import assemble, colour, fmg, estimate, adjoint
+from . import assemble, colour, fmg, estimate, adjoint, transfer
 
-__all__ = ["Hierarchy", "build_hierarchy", "assemble", "colour", "fmg", "estimate", "adjoint"]
+__all__ = ["Hierarchy", "build_hierarchy", "assemble", "colour", "fmg", "estimate", "adjoint", "transfer"]
