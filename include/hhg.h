@@ -157,6 +157,27 @@ hhg_status hhg_set_kappa_nodal(hhg_ctx ctx, const double* device_kappa);
 hhg_status hhg_fmg_solve(hhg_ctx ctx, const double* f_nodal, const double* g_nodal, double* u_out,
                          const hhg_solve_params* params, hhg_solve_stats* stats);
 
+/* V-cycles on level L for the system of hhg_fmg_solve, started from the iterate u_inout
+ * (device, canonical order of level L; its Dirichlet values are replaced by g) instead of the
+ * FMG pass: cycles of V(pre, post) until the residual norm is at most params->rtol times that
+ * of the zero iterate (g on Dirichlet DoFs, 0 elsewhere), at most params->max_iter >= 1 cycles
+ * (params->nu is not used).  A warm start, e.g. from hhg_transfer after a k-step.  The result
+ * overwrites u_inout.  Afterwards hhg_macro_norms may use u_L; hhg_estimate, which needs the
+ * FMG level solutions, returns HHG_ESTATE.  Stagnation gives HHG_ENOTCONV (u_inout still
+ * holds the last iterate). */
+hhg_status hhg_cycle_solve(hhg_ctx ctx, const double* f_nodal, const double* g_nodal, double* u_inout,
+                           const hhg_solve_params* params, hhg_solve_stats* stats);
+
+/* Transfer of a level-L vector between two contexts on the same 2D domain: the solution
+ * transfer from the fine level of one macro mesh to that of the next one in a kl-loop, which
+ * the conclusion (Section 6) lists as missing.  u_new[i] is the P1 function with nodal values
+ * u_old (device, canonical order of ctx_old's level L) evaluated at the coordinates of DoF i of
+ * ctx_new's level L (device, canonical order).  Both contexts are bound on one device; the
+ * work runs on ctx_new's stream and uses scratch vectors of both contexts (the state of their
+ * last solves is kept); ctx_old must not be in use meanwhile.  A DoF outside every macro of
+ * ctx_old gets NaN.  Triangle meshes only (HHG_EINVAL otherwise).  Synchronises the stream. */
+hhg_status hhg_transfer(hhg_ctx ctx_new, hhg_ctx ctx_old, const double* u_old, double* u_new);
+
 /* Error estimate of procedure ErrorEstimate (Algorithm 4) from the last hhg_fmg_solve, for
  * 0 < j < L: eta_cell_host[T] = ||u_L - w_{L-1}||_{L2(T)} for every macro T (host, n_cells),
  * *eta_j = theta^j ||e~_{L-j}||, *theta_est = ||e~_{L-j}|| / ||e~_{L-j-1}||,

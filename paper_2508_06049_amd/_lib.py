@@ -71,6 +71,8 @@ _SIGS = {
     "hhg_estimate_ex": (C.c_int, [_ctx, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
                                   C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "hhg_macro_norms": (C.c_int, [_ctx, _dp, C.c_int, C.c_int, C.POINTER(C.c_double)]),
+    "hhg_cycle_solve": (C.c_int, [_ctx, _dp, _dp, _dp, C.POINTER(hhg_solve_params), C.POINTER(hhg_solve_stats)]),
+    "hhg_transfer": (C.c_int, [_ctx, _ctx, _dp, _dp]),
     "hhg_apply": (C.c_int, [_ctx, C.c_int, C.c_int, _dp, _dp]),
     "hhg_mass_apply": (C.c_int, [_ctx, _dp, _dp]),
     "hhg_smooth": (C.c_int, [_ctx, C.c_int, _dp, _dp, C.c_int]),
@@ -244,6 +246,23 @@ class HHG:
         _check(self.lib.hhg_fmg_solve(self.ctx, _dptr(f, n), _dptr(g, n), _dptr(u, n), C.byref(p), C.byref(st)),
                self.ctx)
         return u, SolveStats(st.vcycles, st.ir_steps, st.final_rel_residual, st.ms_total)
+
+    def cycle_solve(self, f, g, u0, **kw):
+        """hhg_cycle_solve: V-cycles from the iterate u0 (copied); returns (u, stats)."""
+        p = self.params(**kw)
+        u = u0.clone()
+        st = hhg_solve_stats()
+        n = self._nd()
+        _check(self.lib.hhg_cycle_solve(self.ctx, _dptr(f, n), _dptr(g, n), _dptr(u, n), C.byref(p), C.byref(st)),
+               self.ctx)
+        return u, SolveStats(st.vcycles, st.ir_steps, st.final_rel_residual, st.ms_total)
+
+    def transfer_from(self, old: "HHG", u_old):
+        """hhg_transfer: u_old on old's level L evaluated at this context's level-L DoFs."""
+        import torch
+        out = torch.empty(self._nd(), dtype=torch.float64, device=self.device)
+        _check(self.lib.hhg_transfer(self.ctx, old.ctx, _dptr(u_old, old._nd()), _dptr(out)), self.ctx)
+        return out
 
     def residual_history(self) -> np.ndarray:
         n = C.c_int()

@@ -326,7 +326,7 @@ int64_t graph_key(int kind, const hhg_solve_params& p) {
 }
 
 // FMG given bf_l and g_l on all levels; result in lev[L].x, w_l in lev[l+1].w
-hhg_status fmg_core(hhg_ctx c, const hhg_solve_params& p, hhg_solve_stats* stats) {
+hhg_status fmg_core(hhg_ctx c, const hhg_solve_params& p, hhg_solve_stats* stats, bool warm = false) {
   const int L = c->L;
   const bool rec = p.pre % 2 == 0 && p.post % 2 == 0;
   auto body = [&]() -> hhg_status {
@@ -341,8 +341,9 @@ hhg_status fmg_core(hhg_ctx c, const hhg_solve_params& p, hhg_solve_stats* stats
     LAUNCHCHK();
     return HHG_OK;
   };
-  TRY(rec ? run_recorded(c, graph_key(1, p), body) : body());
-  int vcycles = p.nu * L;
+  // warm: the iterate on level L is given; only the cycles below run
+  if (!warm) TRY(rec ? run_recorded(c, graph_key(1, p), body) : body());
+  int vcycles = warm ? 0 : p.nu * L;
   int extra = 0;
   double rel = 0.0;
   if (p.max_iter > 0) {
@@ -657,6 +658,7 @@ hhg_status hhg_bind_workspace(hhg_ctx c, void* ptr, size_t bytes, void* stream) 
   drop_graphs(c);   // recorded launches refer to the previous workspace and stream
   c->bound = true;
   c->solved = false;
+  c->have_u = false;
   return upload_coarse(c);
 }
 
@@ -687,6 +689,7 @@ hhg_status hhg_set_kappa_cell(hhg_ctx c, const double* kappa) {
     TRY(upload_coarse(c));
   }
   c->solved = false;
+  c->have_u = false;
   return HHG_OK;
 }
 
@@ -707,6 +710,7 @@ hhg_status hhg_set_kappa_nodal(hhg_ctx c, const double* kappa) {
   TRY(upload_coarse(c));
   c->kappa_nodal_set = true;
   c->solved = false;
+  c->have_u = false;
   return HHG_OK;
 }
 
@@ -731,8 +735,95 @@ hhg_status hhg_fmg_solve(hhg_ctx c, const double* f, const double* g, double* u_
     *stats = st;
   }
   c->solved = (s == HHG_OK);
+  c->have_u = c->solved;
   c->last_nu = p->nu;
   return s;
+}
+
+hhg_status hhg_cycle_solve(hhg_ctx c, const double* f, const double* g, double* u, const hhg_solve_params* p,
+                           hhg_solve_stats* stats) {
+  TRY(check_ready(c));
+  TRY(validate_params(c, p));
+  if (!f || !g || !u) { c->err = "NULL vector"; return HHG_EINVAL; }
+  if (p->max_iter < 1) { c->err = "hhg_cycle_solve needs max_iter >= 1"; return HHG_EINVAL; }
+  c->solved = c->have_u = false;
+  HIPCHK(hipEventRecord((hipEvent_t)c->ev0, ST(c)));
+  TRY(setup_rhs(c, f, g));
+  const int L = c->L;
+  Level& lL = c->lev[L];
+  launch_canon_to_full(c->dim, lk_of(c, L), c->tab, u, lL.x, 0, ST(c));
+  launch_impose_dirichlet(c->dim, lk_of(c, L), c->tab, lL.g, lL.x, ST(c));
+  LAUNCHCHK();
+  hhg_solve_stats st{};
+  hhg_status s = fmg_core(c, *p, &st, true);
+  if (s != HHG_OK && s != HHG_ENOTCONV) return s;
+  launch_full_to_canon(c->dim, lk_of(c, L), c->tab, lL.x, u, 0, ST(c));
+  LAUNCHCHK();
+  HIPCHK(hipEventRecord((hipEvent_t)c->ev1, ST(c)));
+  if (stats) {
+    HIPCHK(hipEventSynchronize((hipEvent_t)c->ev1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, (hipEvent_t)c->ev0, (hipEvent_t)c->ev1));
+    st.ms_total = ms;
+    *stats = st;
+  }
+  c->have_u = (s == HHG_OK);
+  return s;
+}
+
+hhg_status hhg_transfer(hhg_ctx c, hhg_ctx old, const double* u_old, double* u_new) {
+  TRY(check_ready(c));
+  if (!old || !old->bound) { c->err = "the old context has no workspace bound"; return HHG_ESTATE; }
+  if (c->dim != 2 || old->dim != 2) { c->err = "hhg_transfer is implemented for triangle meshes"; return HHG_EINVAL; }
+  if (!u_old || !u_new) { c->err = "NULL vector"; return HHG_EINVAL; }
+  // candidate old macros of every new macro: those whose bounding boxes meet its own
+  auto box = [](hhg_ctx k, int64_t m, double* b) {
+    b[0] = b[2] = 1e300;
+    b[1] = b[3] = -1e300;
+    for (int a = 0; a < 3; ++a) {
+      const int v = k->cells[m * 3 + a];
+      for (int q = 0; q < 2; ++q) {
+        b[2 * q] = std::min(b[2 * q], k->coords[v * 2 + q]);
+        b[2 * q + 1] = std::max(b[2 * q + 1], k->coords[v * 2 + q]);
+      }
+    }
+  };
+  std::vector<double> bo(old->nC * 4);
+  double ext = 0.0;
+  for (int64_t m = 0; m < old->nC; ++m) {
+    box(old, m, &bo[m * 4]);
+    ext = std::max(ext, std::max(bo[m * 4 + 1] - bo[m * 4], bo[m * 4 + 3] - bo[m * 4 + 2]));
+  }
+  const double tol = 1e-9 * ext;
+  std::vector<int32_t> off(c->nC + 1, 0), cand;
+  for (int64_t m = 0; m < c->nC; ++m) {
+    double b[4];
+    box(c, m, b);
+    for (int64_t M = 0; M < old->nC; ++M) {
+      const double* q = &bo[M * 4];
+      if (q[0] <= b[1] + tol && b[0] <= q[1] + tol && q[2] <= b[3] + tol && b[2] <= q[3] + tol)
+        cand.push_back((int32_t)M);
+    }
+    off[m + 1] = (int32_t)cand.size();
+  }
+  const int L = c->L;
+  Level& ln = c->lev[L];
+  Level& lo = old->lev[old->L];
+  const size_t bytes = (off.size() + cand.size()) * sizeof(int32_t);
+  if (bytes > (size_t)ln.nfull * sizeof(double)) { c->err = "too many candidate macros"; return HHG_EINVAL; }
+  int32_t* d_off = reinterpret_cast<int32_t*>(c->d_aux1);
+  int32_t* d_cand = d_off + off.size();
+  HIPCHK(hipMemcpyAsync(d_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice, ST(c)));
+  if (!cand.empty())
+    HIPCHK(hipMemcpyAsync(d_cand, cand.data(), cand.size() * sizeof(int32_t), hipMemcpyHostToDevice, ST(c)));
+  // the old vector into the old context's closure scratch, interpolated into the new one's
+  launch_canon_to_full(2, lk_of(old, old->L), old->tab, u_old, lo.rc, 0, ST(c));
+  launch_transfer2d(lk_of(c, L), (const double*)(c->ws + c->o_mxyz), lk_of(old, old->L),
+                    (const double*)(old->ws + old->o_mxyz), d_off, d_cand, lo.rc, ln.t, ST(c));
+  launch_full_to_canon(2, lk_of(c, L), c->tab, ln.t, u_new, 0, ST(c));
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(ST(c)));
+  return HHG_OK;
 }
 
 hhg_status hhg_estimate_ex(hhg_ctx c, int j, int norm, int local, double* eta_cell, double* eta_j, double* theta_est,
@@ -804,8 +895,12 @@ hhg_status hhg_macro_norms(hhg_ctx c, const double* x, int level, int norm, doub
     c->err = "the energy norm is implemented for per-macro coefficients only";
     return HHG_EINVAL;
   }
-  if ((level >= 0 || !x) && !c->solved) {
-    c->err = "hhg_macro_norms with level >= 0 or x = NULL needs a preceding successful hhg_fmg_solve";
+  if (level >= 0 && level < L && !c->solved) {
+    c->err = "hhg_macro_norms with level < L needs a preceding successful hhg_fmg_solve";
+    return HHG_ESTATE;
+  }
+  if ((level == L || !x) && !c->have_u) {
+    c->err = "hhg_macro_norms needs u_L of a preceding successful solve";
     return HHG_ESTATE;
   }
   // only the scratch vectors rc and t are written: the last solve's u and w stay valid
@@ -872,6 +967,7 @@ hhg_status hhg_smooth(hhg_ctx c, int level, double* u, const double* b, int swee
   launch_full_to_canon(c->dim, lk_of(c, level), c->tab, lv.x, u, 0, ST(c));
   LAUNCHCHK();
   c->solved = false;
+  c->have_u = false;
   return HHG_OK;
 }
 
@@ -885,6 +981,7 @@ hhg_status hhg_restrict(hhg_ctx c, int level, const double* rf, double* rcn) {
   launch_full_to_canon(c->dim, lk_of(c, level - 1), c->tab, lc.rc, rcn, 1, ST(c));
   LAUNCHCHK();
   c->solved = false;
+  c->have_u = false;
   return HHG_OK;
 }
 
@@ -899,6 +996,7 @@ hhg_status hhg_prolongate(hhg_ctx c, int level, const double* ec, double* ef) {
   launch_full_to_canon(c->dim, lk_of(c, level), c->tab, lf.t, ef, 0, ST(c));
   LAUNCHCHK();
   c->solved = false;
+  c->have_u = false;
   return HHG_OK;
 }
 
@@ -938,6 +1036,7 @@ hhg_status hhg_adjoint(hhg_ctx c, const double* f, const double* g, const double
   }
   LAUNCHCHK();
   c->solved = false;
+  c->have_u = false;
   return HHG_OK;
 }
 
@@ -978,6 +1077,7 @@ hhg_status hhg_bench_smoother(hhg_ctx c, int precision, int sweeps, double* ms, 
   if (launch_ms) *launch_ms = pairs ? tot / pairs : 0.0;
   if (launch_bytes) *launch_bytes = pairs ? c->prof_bytes / pairs : 0.0;
   c->solved = false;
+  c->have_u = false;
   return HHG_OK;
 }
 

@@ -167,7 +167,8 @@ struct hhg_ctx_s {
   char* ws = nullptr;
   void* stream = nullptr;
   bool bound = false;
-  bool solved = false;
+  bool solved = false;              // the FMG level solutions of the last solve are valid
+  bool have_u = false;              // u_L of the last solve is valid (FMG or cycles)
   bool kappa_nodal_set = false;
   // workspace offsets of tables
   int64_t o_stiff = 0, o_mass = 0, o_elemK = 0, o_kappa = 0, o_subprim = 0, o_suborder = 0, o_dirbits = 0,

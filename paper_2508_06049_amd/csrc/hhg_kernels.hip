@@ -1400,6 +1400,64 @@ __global__ void __launch_bounds__(256) k_init_dirichlet(LK lk, Tables tb, const 
   x[base + s] = ((tb.dirbits[m] >> d_mask<D>(lk.n, i, j, k)) & 1) ? g[base + s] : inner;
 }
 
+// x = g on Dirichlet nodes, unchanged elsewhere
+template <int D>
+__global__ void __launch_bounds__(256) k_impose_dirichlet(LK lk, Tables tb, const double* __restrict__ g,
+                                                           double* __restrict__ x) {
+  const int nchunk = (lk.Sraw + 255) >> 8;
+  const int m = blockIdx.x / nchunk;
+  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
+  if (s >= lk.Sraw) return;
+  int i, j, k;
+  d_dec<D>(lk.n, s, i, j, k);
+  const int64_t base = (int64_t)m * lk.S;
+  if ((tb.dirbits[m] >> d_mask<D>(lk.n, i, j, k)) & 1) x[base + s] = g[base + s];
+}
+
+// 2D transfer of a level vector between two macro meshes of one domain: every closure node of
+// the new mesh (coordinates as in k_dof_coords) is located in one of the candidate old macros
+// of its macro (barycentric coordinates >= -1e-10), then in the old macro's lattice of side
+// no, and gets the P1 interpolant of the old closure values on that micro triangle (NaN if no
+// candidate contains it)
+__global__ void __launch_bounds__(256) k_transfer2d(LK fn, const double* __restrict__ mxyz_new, LK fo,
+                                                     const double* __restrict__ mxyz_old, const int32_t* __restrict__ coff,
+                                                     const int32_t* __restrict__ cand, const double* __restrict__ uold,
+                                                     double* __restrict__ unew) {
+  const int nchunk = (fn.Sraw + 255) >> 8;
+  const int m = blockIdx.x / nchunk;
+  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
+  if (s >= fn.Sraw) return;
+  int i, j;
+  d_dec2(fn.n, s, i, j);
+  const double* X = mxyz_new + (size_t)m * 6;
+  const double inv = 1.0 / fn.n;
+  double x[2];
+  for (int q = 0; q < 2; ++q) x[q] = X[q] + (i * inv) * (X[2 + q] - X[q]) + (j * inv) * (X[4 + q] - X[q]);
+  double v = __builtin_nan("");
+  for (int q = coff[m]; q < coff[m + 1]; ++q) {
+    const int M = cand[q];
+    const double* Y = mxyz_old + (size_t)M * 6;
+    const double e1x = Y[2] - Y[0], e1y = Y[3] - Y[1], e2x = Y[4] - Y[0], e2y = Y[5] - Y[1];
+    const double rx = x[0] - Y[0], ry = x[1] - Y[1];
+    const double det = e1x * e2y - e1y * e2x;
+    const double l1 = (rx * e2y - ry * e2x) / det, l2 = (e1x * ry - e1y * rx) / det;
+    if (l1 < -1e-10 || l2 < -1e-10 || 1.0 - l1 - l2 < -1e-10) continue;
+    const int no = fo.n;
+    const double xi1 = l1 * no, xi2 = l2 * no;
+    const int i0 = min(max((int)floor(xi1), 0), no - 1);
+    const int j0 = min(max((int)floor(xi2), 0), no - 1 - i0);
+    const double f1 = xi1 - i0, f2 = xi2 - j0;
+    const double* U = uold + (int64_t)M * fo.S;
+    if (f1 + f2 <= 1.0 || i0 + j0 + 2 > no)
+      v = (1.0 - f1 - f2) * U[d_lin2(no, i0, j0)] + f1 * U[d_lin2(no, i0 + 1, j0)] + f2 * U[d_lin2(no, i0, j0 + 1)];
+    else
+      v = (f1 + f2 - 1.0) * U[d_lin2(no, i0 + 1, j0 + 1)] + (1.0 - f2) * U[d_lin2(no, i0 + 1, j0)] +
+          (1.0 - f1) * U[d_lin2(no, i0, j0 + 1)];
+    break;
+  }
+  unew[(int64_t)m * fn.S + s] = v;
+}
+
 // level 0: x (+)= A_II^{-1} (assembled rhs) on the inner coarse vertices; one thread per row
 template <typename T>
 __global__ void __launch_bounds__(256) k_coarse(int n0, const int32_t* __restrict__ coff, const int64_t* __restrict__ copy,
@@ -2210,5 +2268,17 @@ template void launch_coarse<float>(int, const int32_t*, const int64_t*, const do
                                    hipStream_t);
 template void launch_fill<double>(double*, int64_t, double, hipStream_t);
 template void launch_fill<float>(float*, int64_t, float, hipStream_t);
+
+void launch_impose_dirichlet(int dim, const LK& lk, const Tables& tb, const double* g, double* x, hipStream_t st) {
+  const unsigned gr = (unsigned)(lk.nmacro * ((lk.Sraw + 255) / 256));
+  if (dim == 3) k_impose_dirichlet<3><<<gr, 256, 0, st>>>(lk, tb, g, x);
+  else k_impose_dirichlet<2><<<gr, 256, 0, st>>>(lk, tb, g, x);
+}
+
+void launch_transfer2d(const LK& fn, const double* mxyz_new, const LK& fo, const double* mxyz_old, const int32_t* coff,
+                       const int32_t* cand, const double* uold, double* unew, hipStream_t st) {
+  const unsigned gr = (unsigned)(fn.nmacro * ((fn.Sraw + 255) / 256));
+  k_transfer2d<<<gr, 256, 0, st>>>(fn, mxyz_new, fo, mxyz_old, coff, cand, uold, unew);
+}
 
 }  // namespace hhg

@@ -1,0 +1,95 @@
+"""Solution transfer between kl-steps (the transfer from T_L^k to T_L^(k+1) that the
+conclusion lists as missing) and the warm-started V-cycle solve it feeds, on the GPU against
+the oracle."""
+import numpy as np
+import pytest
+
+from gpu_common import oracle_hierarchy, rel_err, to_dev, to_host
+from oracle import fmg, transfer
+from paper_2508_06049_amd import mesh as hostmesh
+from workloads import meshes, problems
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(*a):
+    print("[case]", *a, flush=True)
+
+
+def _two_steps():
+    # the L-shape on 24 triangles and the mesh after one kl-step that marks the quarter of
+    # the macros nearest the re-entrant corner (red-green refinement with green closure)
+    m0 = meshes.lshape_24tri()
+    rg = hostmesh.RedGreen2D(m0)
+    cen = m0.coords[m0.cells].mean(axis=1)
+    rg.refine(hostmesh.mark_fraction(-np.hypot(cen[:, 0], cen[:, 1]), 0.25))
+    return m0, rg.mesh("lshape24_k1")
+
+
+@pytest.mark.parametrize("L", [2, 4])
+def test_transfer_matches_oracle(L):
+    from paper_2508_06049_amd import HHG
+    m0, m1 = _two_steps()
+    _note("transfer", m0.n_cells, "->", m1.n_cells, L)
+    h0, p0 = oracle_hierarchy(m0, L)
+    h1, p1 = oracle_hierarchy(m1, L)
+    a = HHG(m0.coords, m0.cells, L, smoother="multicolour")
+    b = HHG(m1.coords, m1.cells, L, smoother="multicolour")
+    u0 = np.random.default_rng(5).standard_normal(h0.levels[L].n)
+    ref = transfer.transfer(h0, u0, h1.levels[L].X)
+    got = to_host(b.transfer_from(a, to_dev(u0[p0[L]])))
+    assert np.all(np.isfinite(got))
+    assert np.abs(got - ref[p1[L]]).max() <= 1e-12 * np.abs(u0).max()
+    aff = lambda X: 0.3 - 1.7 * X[:, 0] + 0.6 * X[:, 1]
+    got = to_host(b.transfer_from(a, to_dev(aff(h0.levels[L].X)[p0[L]])))
+    assert np.abs(got - aff(h1.levels[L].X)[p1[L]]).max() < 1e-13
+
+
+def test_warm_started_cycles_reach_the_fmg_solution():
+    # V-cycles from the transferred solution of the previous k-step converge to the discrete
+    # solution of the new mesh, and need fewer cycles than from zero
+    from paper_2508_06049_amd import HHG
+    L = 5
+    m0, m1 = _two_steps()
+    _note("warm start", L)
+    a = HHG(m0.coords, m0.cells, L, smoother="multicolour")
+    b = HHG(m1.coords, m1.cells, L, smoother="multicolour")
+    Xa, Xb = a.dof_coords().cpu().numpy(), b.dof_coords().cpu().numpy()
+    ua, _ = a.fmg_solve(to_dev(np.zeros(len(Xa))), to_dev(problems.lshape_u(Xa)), nu=1, rtol=1e-12, max_iter=60)
+    fb, gb = to_dev(np.zeros(len(Xb))), to_dev(problems.lshape_u(Xb))
+    ref, _ = b.fmg_solve(fb, gb, nu=1, rtol=1e-13, max_iter=80)
+    warm = b.transfer_from(a, ua)
+    uw, sw = b.cycle_solve(fb, gb, warm, rtol=1e-11, max_iter=80)
+    uz, sz = b.cycle_solve(fb, gb, warm * 0, rtol=1e-11, max_iter=80)
+    assert sw.final_rel_residual <= 1e-11 and sz.final_rel_residual <= 1e-11
+    assert rel_err(to_host(uw), to_host(ref)) < 1e-9
+    assert rel_err(to_host(uz), to_host(ref)) < 1e-9
+    assert sw.vcycles < sz.vcycles
+    # the macro norms of the cycle solve's result need no FMG levels; the estimate does
+    from paper_2508_06049_amd import HHGError
+    assert np.all(np.isfinite(b.macro_norms(to_dev(problems.lshape_u(Xb)), L)))
+    with pytest.raises(HHGError):
+        b.estimate(1)
+
+
+def test_cycle_solve_matches_oracle_cycles():
+    # the warm-started solve is the oracle's extra V-cycles from the same iterate
+    from paper_2508_06049_amd import HHG
+    m = meshes.lshape_6tri()
+    L = 4
+    _note("cycle solve parity", L)
+    h, perms = oracle_hierarchy(m, L)
+    p = perms[L]
+    X = h.levels[L].X
+    S = fmg.FMGSolver(h, smoother="multicolour")
+    f, g = np.zeros(len(X)), problems.lshape_u(X)
+    u0 = np.random.default_rng(8).standard_normal(len(X))
+    hh = HHG(m.coords, m.cells, L, smoother="multicolour")
+    ug, st = hh.cycle_solve(to_dev(f[p]), to_dev(g[p]), to_dev(u0[p]), rtol=1e-30, max_iter=3)
+    assert st.vcycles == 3
+    b = S.rhs_levels(f)
+    uo = u0.copy()
+    uo[S.sys[L].bnd] = g[S.sys[L].bnd]
+    for _ in range(3):
+        S.vcycle(L, uo, b[L])
+    assert np.abs(to_host(ug) - uo[p]).max() <= 1e-12 * np.abs(uo).max()
