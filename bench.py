@@ -125,13 +125,16 @@ def run_kl(args):
     log(f"kl loop {args.kl}: {coarse.n_cells} macros, K={K}, L={L}")
 
     def show(s):
-        log(f"k={s.k}: {s.n_macros} macros, {s.n_dofs} DoFs, error {s.err:.4e}, level-0 error {s.err_level0:.4e}, "
-            f"{s.vcycles} V-cycles ({s.extra['solves']} solves, rel. residual {s.extra['final_rel_residual']:.1e}), "
+        e0 = "-" if s.err_level0 is None else f"{s.err_level0:.4e}"
+        log(f"k={s.k}: {s.n_macros} macros, {s.n_dofs} DoFs, error {s.err:.4e}, level-0 error {e0}, "
+            f"transfer {s.extra['transfer_s'] * 1e3:.1f} ms, {s.vcycles} V-cycles ({s.extra['solves']} solves, "
+            f"rel. residual {s.extra['final_rel_residual']:.1e}), "
             f"setup {s.t_setup:.2f} s, solve {s.t_solve * 1e3:.1f} ms, local norms "
             f"{s.t_local * 1e3:.1f} ms, mark+refine {s.t_refine * 1e3:.1f} ms")
 
     t0 = time.perf_counter()
-    steps = kl.kl_refine(coarse, L, K, f, g, u, criterion="error", nu=2, rtol=1e-6, max_iter=100, callback=show)
+    steps = kl.kl_refine(coarse, L, K, f, g, u, criterion="error", nu=2, rtol=1e-6, max_iter=100, callback=show,
+                         warm=args.kl_warm)
     t_loop = time.perf_counter() - t0
     rho = kl.error_ratio(steps)
     # uniform refinement of T_0^0 (levels 1..L), same solver and stopping rule
@@ -145,13 +148,15 @@ def run_kl(args):
         "metric": "kl-refinement loop: error ratio rho and time per k-step",
         "value": rho[-1], "unit": "rho on T_L^K", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
         "config": {"workload": f"kl_{args.kl}", "coarse_macros": coarse.n_cells, "K": K, "L": L,
+                   "start": "transferred solution + V-cycles" if args.kl_warm else "FMG",
                    "marking": "10 % largest local L2 errors, red-green", "smoother": "multicolour", "fmg_nu": 2,
                    "vcycle": [2, 2], "rtol": "1e-6, lowered 100-fold until the error's first two digits are stable"},
         "loop_seconds": round(t_loop, 3),
         "steps": [dict(k=s.k, macros=s.n_macros, dofs=s.n_dofs, error=s.err, level0_error=s.err_level0,
                        rho=r, eta_1=s.eta_1, vcycles=s.vcycles, solves=s.extra["solves"], setup_s=round(s.t_setup, 4),
                        solve_ms=round(s.t_solve * 1e3, 3), local_ms=round(s.t_local * 1e3, 3),
-                       refine_ms=round(s.t_refine * 1e3, 3)) for s, r in zip(steps, rho)],
+                       refine_ms=round(s.t_refine * 1e3, 3), transfer_ms=round(s.extra["transfer_s"] * 1e3, 3))
+                  for s, r in zip(steps, rho)],
         "uniform": uni,
     }
     print(json.dumps(out), flush=True)
@@ -175,6 +180,9 @@ def main():
                          "one JSON line")
     ap.add_argument("--kl-K", type=int, default=10)
     ap.add_argument("--kl-L", type=int, default=8)
+    ap.add_argument("--kl-warm", action="store_true",
+                    help="kl loop: start each step after the first from the transferred solution of the "
+                         "previous step (hhg_transfer + hhg_cycle_solve) instead of an FMG solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the method runs on one GPU here); --gpus {args.gpus} is not "

@@ -13,7 +13,15 @@ Refinement criterion (one value per macro T):
 
 Every fine-grid step (setup tables, solve, local norms, estimate) runs in the HIP library; the
 macro mesh is small, so marking and red-green refinement run serially on the host, as in the
-paper.  Errors are discrete L2 norms (mass matrix of level L).
+paper.  Errors are discrete L2 norms (mass matrix of level L).  The data callables f, g and u
+receive the level-L DoF coordinates as a device tensor and return nodal values (numpy results
+are copied to the device).
+
+Warm start (``warm=True``, the solution transfer the conclusion of the paper lists as future
+work): from the second step on, the solution on T_L^k is evaluated at the DoFs of T_L^(k+1)
+(``hhg_transfer``) and V-cycles run from there (``hhg_cycle_solve``) instead of an FMG solve.
+No FMG levels exist then, so these steps carry neither eta_T nor a level-0 error, and the
+criterion must be ``"error"``.
 
 Mesh-quality metric (Section 5.1, equation of the error ratio): with hbar = (|Omega| / #T)^(1/d)
 the mean mesh width of T_L^k, Hbar that of T_0^0, e_hbar the error on T_L^k and e_Hbar the error
@@ -86,23 +94,25 @@ def error_ratio(steps: List[KStep]) -> List[float]:
 
 
 def _solve_until_stable(hh, fd, gd, ud, L, nu, precision, rtol, max_iter, tighten):
+    """FMG solves, each from scratch, with the tolerance lowered until the error is stable.
+    Returns (stats of the last solve, per-macro squared errors, number of solves, u_L)."""
     from ._lib import HHG_ENOTCONV, HHGError
-    prev = sq = st = None
+    prev = sq = st = u = None
     n = 0
     for t in range(tighten + 1):
         try:
-            _, st_t = hh.fmg_solve(fd, gd, nu=nu, precision=precision, rtol=rtol * 100.0 ** (-t), max_iter=max_iter)
+            u_t, st_t = hh.fmg_solve(fd, gd, nu=nu, precision=precision, rtol=rtol * 100.0 ** (-t), max_iter=max_iter)
         except HHGError as e:
             if e.status != HHG_ENOTCONV or st is None:
                 raise
             # the tighter tolerance is below what float64 reaches: repeat the last solve
-            _, st = hh.fmg_solve(fd, gd, nu=nu, precision=precision, rtol=rtol * 100.0 ** (1 - t), max_iter=max_iter)
+            u, st = hh.fmg_solve(fd, gd, nu=nu, precision=precision, rtol=rtol * 100.0 ** (1 - t), max_iter=max_iter)
             n += 1
             if ud is not None:
                 sq = hh.macro_norms(ud, L)
             break
         n += 1
-        st = st_t
+        u, st = u_t, st_t
         if ud is None:
             break
         sq = hh.macro_norms(ud, L)
@@ -110,13 +120,44 @@ def _solve_until_stable(hh, fd, gd, ud, L, nu, precision, rtol, max_iter, tighte
         if err == prev:
             break
         prev = err
-    return st, sq, n
+    return st, sq, n, u
+
+
+def _cycles_until_stable(hh, fd, gd, u, ud, L, precision, rtol, max_iter, tighten):
+    """V-cycles from the iterate u, continued with the tolerance lowered until the error is
+    stable.  Returns (stats with the V-cycles of all rounds, squared errors, rounds, u_L)."""
+    from ._lib import HHG_ENOTCONV, HHGError, SolveStats
+    prev = sq = st = None
+    n = cycles = 0
+    for t in range(tighten + 1):
+        try:
+            u_t, st_t = hh.cycle_solve(fd, gd, u, precision=precision, rtol=rtol * 100.0 ** (-t), max_iter=max_iter)
+        except HHGError as e:
+            if e.status != HHG_ENOTCONV or st is None:
+                raise
+            break                      # the last iterate and its errors stand
+        n += 1
+        cycles += st_t.vcycles
+        u, st = u_t, st_t
+        if ud is None:
+            break
+        sq = hh.macro_norms(ud, L)
+        err = f"{math.sqrt(float(sq.sum())):.1e}"
+        if err == prev:
+            break
+        prev = err
+    return SolveStats(cycles, st.ir_steps, st.final_rel_residual, st.ms_total), sq, n, u
+
+
+def _nodal(fn, X, device):
+    import torch
+    return torch.as_tensor(fn(X), dtype=torch.float64, device=device).contiguous()
 
 
 def kl_refine(coarse: CoarseMesh, L: int, K: int, f: Callable, g: Callable,
               u_exact: Optional[Callable] = None, criterion: str = "error", fraction: float = 0.1,
               smoother: str = "multicolour", nu: int = 2, rtol: float = 1e-10, max_iter: int = 100,
-              precision: str = "fp64", device: str = "cuda:0", tighten: int = 3,
+              precision: str = "fp64", device: str = "cuda:0", tighten: int = 3, warm: bool = False,
               callback: Optional[Callable[[KStep], None]] = None) -> List[KStep]:
     """Run K kl-steps and the final solve; returns one record per solved mesh (K + 1).
 
@@ -133,30 +174,44 @@ def kl_refine(coarse: CoarseMesh, L: int, K: int, f: Callable, g: Callable,
         raise ValueError("the 'error' criterion needs u_exact")
     if criterion == "estimate" and L < 2:
         raise ValueError("the estimate needs L >= 2")
+    if warm and criterion != "error":
+        raise ValueError("warm-started steps have no FMG levels, hence no estimate: use criterion 'error'")
     if coarse.dim == 2:
         rg = hostmesh.RedGreen2D(coarse)
     else:
         rg = hostmesh.RedGreen3D(coarse)
     measure = domain_measure(coarse)
     steps: List[KStep] = []
+    prev = None                                    # (context, u_L) of the last step, for the warm start
     for k in range(K + 1):
         m = rg.mesh(f"{coarse.name}_k{k}")          # macro order = conforming-cell order
         t0 = time.perf_counter()
         hh = HHG(m.coords, m.cells, L, smoother=smoother, device=device)
-        X = hh.dof_coords().cpu().numpy()
-        fd = torch.as_tensor(f(X), device=hh.device)
-        gd = torch.as_tensor(g(X), device=hh.device)
-        ud = None if u_exact is None else torch.as_tensor(u_exact(X), device=hh.device)
+        X = hh.dof_coords()
+        fd, gd = _nodal(f, X, hh.device), _nodal(g, X, hh.device)
+        ud = None if u_exact is None else _nodal(u_exact, X, hh.device)
+        del X
         torch.cuda.synchronize(hh.device)
         t1 = time.perf_counter()
-        st, sq, n_solves = _solve_until_stable(hh, fd, gd, ud, L, nu, precision, rtol, max_iter, tighten)
+        t_transfer = 0.0
+        if warm and prev is not None:
+            u0 = hh.transfer_from(prev[0], prev[1])
+            torch.cuda.synchronize(hh.device)
+            t_transfer = time.perf_counter() - t1
+            prev[0].close()
+            prev = None
+            st, sq, n_solves, u = _cycles_until_stable(hh, fd, gd, u0, ud, L, precision, rtol, max_iter, tighten)
+        else:
+            st, sq, n_solves, u = _solve_until_stable(hh, fd, gd, ud, L, nu, precision, rtol, max_iter, tighten)
         torch.cuda.synchronize(hh.device)
         t2 = time.perf_counter()
-        est = hh.estimate(1) if L >= 2 else dict(eta_j=math.nan, theta=math.nan, eta_T=None)
+        fmg_levels = not (warm and k > 0)
+        est = hh.estimate(1) if L >= 2 and fmg_levels else dict(eta_j=math.nan, theta=math.nan, eta_T=None)
         err = err0 = None
         if ud is not None:
             err = math.sqrt(float(sq.sum()))
-            err0 = math.sqrt(float(hh.macro_norms(ud, 0).sum()))
+            if fmg_levels:
+                err0 = math.sqrt(float(hh.macro_norms(ud, 0).sum()))
         local = np.sqrt(sq) if criterion == "error" else est["eta_T"]
         t3 = time.perf_counter()
         marked = None
@@ -166,10 +221,14 @@ def kl_refine(coarse: CoarseMesh, L: int, K: int, f: Callable, g: Callable,
         t4 = time.perf_counter()
         s = KStep(k, m, hh.num_dofs(), mean_width(m, L, measure), err, err0, est["eta_j"], est["theta"], local,
                   marked, st.vcycles, t1 - t0, t2 - t1, t3 - t2, t4 - t3,
-                  dict(solves=n_solves, final_rel_residual=st.final_rel_residual))
+                  dict(solves=n_solves, final_rel_residual=st.final_rel_residual, transfer_s=t_transfer))
         steps.append(s)
         if callback is not None:
             callback(s)
-        hh.close()
-        del hh
+        del fd, gd, ud
+        if warm and k < K:
+            prev = (hh, u)
+        else:
+            hh.close()
+        del hh, u
     return steps

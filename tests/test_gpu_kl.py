@@ -42,13 +42,15 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("name", ["waves", "lshape24"])
-def test_kl_loop_matches_oracle(name):
+@pytest.mark.parametrize("name,warm", [("waves", False), ("lshape24", False), ("waves", True)])
+def test_kl_loop_matches_oracle(name, warm):
+    # warm: steps after the first start from the transferred solution of the previous step
     from paper_2508_06049_amd import kl
     coarse, f, g, u, crit = CASES[name]
     L, K, nu = 4, 3, 2
-    _note("kl loop", name, crit, L, K)
-    steps = kl.kl_refine(coarse, L, K, f, g, u, criterion=crit, nu=nu, rtol=1e-13, max_iter=200, tighten=0)
+    _note("kl loop", name, crit, L, K, "warm" if warm else "fmg")
+    steps = kl.kl_refine(coarse, L, K, f, g, u, criterion=crit, nu=nu, rtol=1e-13, max_iter=200, tighten=0,
+                         warm=warm)
     assert len(steps) == K + 1
     for s in steps:
         sq, sq0, eta_T, scale = _oracle(s.mesh, L, f, g, u, nu, "multicolour")
@@ -56,7 +58,10 @@ def test_kl_loop_matches_oracle(name):
         ref = np.sqrt(sq) if crit == "error" else eta_T
         assert np.all(np.abs(s.local - ref) <= tol)
         assert abs(s.err - math.sqrt(sq.sum())) <= tol
-        assert abs(s.err_level0 - math.sqrt(sq0.sum())) <= tol
+        if warm and s.k > 0:
+            assert s.err_level0 is None and s.extra["transfer_s"] > 0
+        else:
+            assert abs(s.err_level0 - math.sqrt(sq0.sum())) <= tol
         if s.marked is None:
             continue
         n = s.n_macros

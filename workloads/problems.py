@@ -2,7 +2,10 @@
 random parameters for the workloads.
 
 Every function takes an (N, dim) array of points and returns (N,) float64.  These are
-*inputs*: they are evaluated at node coordinates by whoever needs nodal values.
+*inputs*: they are evaluated at node coordinates by whoever needs nodal values.  The 2D
+functions of the convergence studies (sine, L-shape, waves, zero, one) also take a torch tensor
+of points and then evaluate where the tensor lives, so that nodal data of a large level is made
+on the device instead of on the host.
 """
 from __future__ import annotations
 
@@ -11,9 +14,18 @@ import numpy as np
 PI = np.pi
 
 
+def _xp(x):
+    """The array namespace of x: torch for tensors, numpy otherwise."""
+    if type(x).__module__.startswith("torch"):
+        import torch
+        return torch
+    return np
+
+
 # --- manufactured 2D solution on the unit square: u = sin(pi x) sin(pi y) -------------------
 def sine2d_u(x):
-    return np.sin(PI * x[:, 0]) * np.sin(PI * x[:, 1])
+    xp = _xp(x)
+    return xp.sin(PI * x[:, 0]) * xp.sin(PI * x[:, 1])
 
 
 def sine2d_f(x):
@@ -28,18 +40,19 @@ def sine2d_grad(x):
 
 # --- L-shape corner singularity: u = r^(2/3) sin(2 phi / 3), phi in [0, 2 pi) ---------------
 def lshape_u(x):
-    r = np.hypot(x[:, 0], x[:, 1])
-    phi = np.arctan2(x[:, 1], x[:, 0])
-    phi = np.where(phi < 0.0, phi + 2.0 * PI, phi)
-    return np.where(r > 0.0, r ** (2.0 / 3.0) * np.sin(2.0 * phi / 3.0), 0.0)
+    xp = _xp(x)
+    r = xp.hypot(x[:, 0], x[:, 1])
+    phi = xp.arctan2(x[:, 1], x[:, 0])
+    phi = xp.where(phi < 0.0, phi + 2.0 * PI, phi)
+    return xp.where(r > 0.0, r ** (2.0 / 3.0) * xp.sin(2.0 * phi / 3.0), 0.0)
 
 
 def zero(x):
-    return np.zeros(x.shape[0])
+    return _xp(x).zeros_like(x[:, 0])
 
 
 def one(x):
-    return np.ones(x.shape[0])
+    return _xp(x).ones_like(x[:, 0])
 
 
 # --- 3D variable coefficient and seeded Fourier right-hand side ------------------------------
@@ -94,31 +107,36 @@ def kappa_cells_uniform(seed: int, n: int, lo: float = 0.5, hi: float = 2.0) -> 
 
 # --- 2D "waves" problem: u = w(x) w(y), w(t) = 1 - cos(exp(a (t-1)) om t) ---------------------
 def waves_w(t, om=16 * PI, a=10.0):
-    return 1.0 - np.cos(np.exp(a * (t - 1.0)) * om * t)
+    xp = _xp(t)
+    return 1.0 - xp.cos(xp.exp(a * (t - 1.0)) * om * t)
 
 
 def waves_w2(t, om=16 * PI, a=10.0):
     """Second derivative of w."""
-    e = np.exp(a * (t - 1.0))
+    xp = _xp(t)
+    e = xp.exp(a * (t - 1.0))
     th = e * om * t
     th1 = om * e * (1.0 + a * t)
     th2 = om * e * a * (2.0 + a * t)
-    return np.cos(th) * th1 * th1 + np.sin(th) * th2
+    return xp.cos(th) * th1 * th1 + xp.sin(th) * th2
 
 
 def waves_u(x, om=16 * PI, a=10.0):
-    return np.prod([waves_w(x[:, i], om, a) for i in range(x.shape[1])], axis=0)
+    u = waves_w(x[:, 0], om, a)
+    for i in range(1, x.shape[1]):
+        u = u * waves_w(x[:, i], om, a)
+    return u
 
 
 def waves_f(x, om=16 * PI, a=10.0):
     d = x.shape[1]
     w = [waves_w(x[:, i], om, a) for i in range(d)]
     w2 = [waves_w2(x[:, i], om, a) for i in range(d)]
-    f = np.zeros(x.shape[0])
+    f = zero(x)
     for i in range(d):
-        t = w2[i].copy()
+        t = w2[i]
         for k in range(d):
             if k != i:
-                t *= w[k]
-        f -= t
+                t = t * w[k]
+        f = f - t
     return f
