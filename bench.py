@@ -162,6 +162,47 @@ def run_kl(args):
     print(json.dumps(out), flush=True)
 
 
+def run_kl_study(args):
+    """Section 5.3: effectivity gamma_j = eta_j / ||e|| (j = 1..4) over the kl sequence refined
+    by local errors, with nu = 6, 2, 1 V-cycles per FMG level (worst case over k per j); then
+    the kl loop refined by eta_T computed with nu = 1, 2, 6, against refinement by the errors."""
+    from paper_2508_06049_amd import kl
+    from workloads import meshes, problems
+
+    mname, fn, gn, un = KL_CASES[args.kl]
+    coarse = meshes.unit_square_grid(4) if mname == "unit_square_grid4" else getattr(meshes, mname)()
+    f, g, u = getattr(problems, fn), getattr(problems, gn), getattr(problems, un)
+    K, L = args.kl_K, args.kl_L
+    js = [j for j in (1, 2, 3, 4) if j < L]
+    out = {"metric": "estimator effectivity eta_j/||e|| and kl refinement by eta_T, per nu",
+           "unit": "ratio", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": f"kl_{args.kl}", "coarse_macros": coarse.n_cells, "K": K, "L": L,
+                      "smoother": "multicolour", "vcycle": [2, 2], "marking": "10 %, red-green"},
+           "effectivity": {}, "indicator": {}}
+    t0 = time.perf_counter()
+    for nu in (6, 2, 1):
+        steps = kl.kl_refine(coarse, L, K, f, g, u, criterion="error", nu=nu, rtol=1e-6, max_iter=100,
+                             estimate_js=js)
+        worst = {j: kl.worst_effectivity(steps, j) for j in js}
+        out["effectivity"][f"nu{nu}"] = {
+            "gamma": {j: kl.effectivity(steps, j) for j in js},
+            "worst": {j: dict(k=k, gamma=gm) for j, (k, gm) in worst.items()}}
+        log(f"nu={nu}: worst effectivity " + ", ".join(f"j={j}: {gm:.2f} (k={k})" for j, (k, gm) in worst.items()))
+    ref = None
+    for nu in ("error", 1, 2, 6):
+        crit = "error" if nu == "error" else "estimate"
+        steps = kl.kl_refine(coarse, L, K, f, g, u, criterion=crit, nu=2 if nu == "error" else nu, rtol=1e-6,
+                             max_iter=100)
+        rho = kl.error_ratio(steps)
+        out["indicator"]["errors" if nu == "error" else f"eta_T_nu{nu}"] = dict(
+            macros=[s.n_macros for s in steps], dofs=[s.n_dofs for s in steps], error=[s.err for s in steps],
+            rho=rho)
+        log(f"refined by {'local errors' if nu == 'error' else f'eta_T with nu={nu}'}: final error "
+            f"{steps[-1].err:.3e}, rho {rho[-1]:.2f}, {steps[-1].n_macros} macros")
+    out["seconds"] = round(time.perf_counter() - t0, 2)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,6 +221,9 @@ def main():
                          "one JSON line")
     ap.add_argument("--kl-K", type=int, default=10)
     ap.add_argument("--kl-L", type=int, default=8)
+    ap.add_argument("--kl-study", action="store_true",
+                    help="with --kl: the estimator study of Section 5.3 (effectivity of eta_j for nu = 6, 2, 1 "
+                         "and refinement by eta_T for nu = 1, 2, 6); prints one JSON line")
     ap.add_argument("--kl-warm", action="store_true",
                     help="kl loop: start each step after the first from the transferred solution of the "
                          "previous step (hhg_transfer + hhg_cycle_solve) instead of an FMG solve")
@@ -189,7 +233,7 @@ def main():
               f"supported", file=sys.stderr)
         sys.exit(2)
     if args.kl:
-        run_kl(args)
+        run_kl_study(args) if args.kl_study else run_kl(args)
         return
 
     import numpy as np

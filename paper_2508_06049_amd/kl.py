@@ -36,7 +36,7 @@ from __future__ import annotations
 import math
 import time
 from dataclasses import dataclass, field
-from typing import Callable, List, Optional
+from typing import Callable, List, Optional, Sequence
 
 import numpy as np
 
@@ -91,6 +91,18 @@ def error_ratio(steps: List[KStep]) -> List[float]:
     H = mean_width(m0, 0)
     eH = steps[0].err_level0
     return [(H * H * s.err) / (s.hbar * s.hbar * eH) for s in steps]
+
+
+def effectivity(steps: List[KStep], j: int) -> List[float]:
+    """gamma_j = eta_j / ||e_L|| per step (Section 5.3); needs ``estimate_js`` to hold j."""
+    return [s.extra["eta"][j] / s.err for s in steps]
+
+
+def worst_effectivity(steps: List[KStep], j: int):
+    """(k, gamma_j) of the step whose |log gamma_j| is largest: the worst case of Section 5.3."""
+    g = effectivity(steps, j)
+    k = max(range(len(g)), key=lambda i: abs(math.log(g[i])))
+    return steps[k].k, g[k]
 
 
 def _solve_until_stable(hh, fd, gd, ud, L, nu, precision, rtol, max_iter, tighten):
@@ -158,13 +170,15 @@ def kl_refine(coarse: CoarseMesh, L: int, K: int, f: Callable, g: Callable,
               u_exact: Optional[Callable] = None, criterion: str = "error", fraction: float = 0.1,
               smoother: str = "multicolour", nu: int = 2, rtol: float = 1e-10, max_iter: int = 100,
               precision: str = "fp64", device: str = "cuda:0", tighten: int = 3, warm: bool = False,
+              estimate_js: Sequence[int] = (),
               callback: Optional[Callable[[KStep], None]] = None) -> List[KStep]:
     """Run K kl-steps and the final solve; returns one record per solved mesh (K + 1).
 
     Each solve is FMG plus extra V-cycles to the relative residual ``rtol``; with a known
     solution it is repeated with the tolerance lowered 100-fold (at most ``tighten`` times)
     until the first two significant digits of the error no longer change, the stopping rule
-    of the experiments in Section 5."""
+    of the experiments in Section 5.  For every j in ``estimate_js`` (1 <= j < L) each FMG step
+    also records the global estimate eta_j in ``extra["eta"][j]``."""
     import torch
     from ._lib import HHG
 
@@ -174,6 +188,9 @@ def kl_refine(coarse: CoarseMesh, L: int, K: int, f: Callable, g: Callable,
         raise ValueError("the 'error' criterion needs u_exact")
     if criterion == "estimate" and L < 2:
         raise ValueError("the estimate needs L >= 2")
+    for j in estimate_js:
+        if not 1 <= j < L:
+            raise ValueError(f"eta_{j} needs 1 <= j < L = {L}")
     if warm and criterion != "error":
         raise ValueError("warm-started steps have no FMG levels, hence no estimate: use criterion 'error'")
     if coarse.dim == 2:
@@ -207,6 +224,10 @@ def kl_refine(coarse: CoarseMesh, L: int, K: int, f: Callable, g: Callable,
         t2 = time.perf_counter()
         fmg_levels = not (warm and k > 0)
         est = hh.estimate(1) if L >= 2 and fmg_levels else dict(eta_j=math.nan, theta=math.nan, eta_T=None)
+        eta = {}
+        if fmg_levels:
+            for j in estimate_js:
+                eta[j] = est["eta_j"] if j == 1 else hh.estimate(j)["eta_j"]
         err = err0 = None
         if ud is not None:
             err = math.sqrt(float(sq.sum()))
@@ -221,7 +242,7 @@ def kl_refine(coarse: CoarseMesh, L: int, K: int, f: Callable, g: Callable,
         t4 = time.perf_counter()
         s = KStep(k, m, hh.num_dofs(), mean_width(m, L, measure), err, err0, est["eta_j"], est["theta"], local,
                   marked, st.vcycles, t1 - t0, t2 - t1, t3 - t2, t4 - t3,
-                  dict(solves=n_solves, final_rel_residual=st.final_rel_residual, transfer_s=t_transfer))
+                  dict(solves=n_solves, final_rel_residual=st.final_rel_residual, transfer_s=t_transfer, eta=eta))
         steps.append(s)
         if callback is not None:
             callback(s)

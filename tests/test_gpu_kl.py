@@ -30,8 +30,9 @@ def _oracle(mesh, L, f, g, u, nu, smoother):
     sq = estimate.per_macro_sq_norms(h, ue - uo)
     sq0 = estimate.per_macro_sq_norms(h, ue - estimate.prolongate_to(S, wo[0], 1, L))
     eta_T = estimate.error_estimate(S, uo, wo, 1)["eta_T"]
+    eta = {j: estimate.error_estimate(S, uo, wo, j)["eta_j"] for j in range(1, L)}
     scale = math.sqrt(uo @ (S.sys[L].M @ uo))
-    return sq, sq0, eta_T, scale
+    return sq, sq0, eta_T, eta, scale
 
 
 CASES = {
@@ -50,18 +51,21 @@ def test_kl_loop_matches_oracle(name, warm):
     L, K, nu = 4, 3, 2
     _note("kl loop", name, crit, L, K, "warm" if warm else "fmg")
     steps = kl.kl_refine(coarse, L, K, f, g, u, criterion=crit, nu=nu, rtol=1e-13, max_iter=200, tighten=0,
-                         warm=warm)
+                         warm=warm, estimate_js=(1, 2, 3))
     assert len(steps) == K + 1
     for s in steps:
-        sq, sq0, eta_T, scale = _oracle(s.mesh, L, f, g, u, nu, "multicolour")
+        sq, sq0, eta_T, eta, scale = _oracle(s.mesh, L, f, g, u, nu, "multicolour")
         tol = 1e-12 * scale
         ref = np.sqrt(sq) if crit == "error" else eta_T
         assert np.all(np.abs(s.local - ref) <= tol)
         assert abs(s.err - math.sqrt(sq.sum())) <= tol
         if warm and s.k > 0:
-            assert s.err_level0 is None and s.extra["transfer_s"] > 0
+            assert s.err_level0 is None and s.extra["transfer_s"] > 0 and not s.extra["eta"]
         else:
             assert abs(s.err_level0 - math.sqrt(sq0.sum())) <= tol
+            assert sorted(s.extra["eta"]) == [1, 2, 3]
+            for j in (1, 2, 3):
+                assert abs(s.extra["eta"][j] - eta[j]) <= tol
         if s.marked is None:
             continue
         n = s.n_macros
