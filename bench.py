@@ -215,6 +215,10 @@ def main():
     ap.add_argument("--kernel-only", action="store_true",
                     help="run only the smoother sweeps on level L and a plain device copy of known size "
                          "(for hardware-counter runs; prints no JSON line)")
+    ap.add_argument("--flags", type=int, default=0,
+                    help="hhg_options.flags of the context (e.g. 1: class-by-class interior sweeps) for A/B timing")
+    ap.add_argument("--kernel-only-fp64", action="store_true",
+                    help="with --kernel-only: also time float64 sweeps")
     ap.add_argument("--kl", choices=sorted(KL_CASES), default=None,
                     help="run the kl-refinement loop (Section 3) on one of the convergence-study problems of "
                          "Section 5 instead of the solve benchmark, with a uniform-refinement baseline; prints "
@@ -243,11 +247,9 @@ def main():
     w = configs.config(args.config, args.L)
     log(f"workload {w.name}: {w.mesh.n_cells} macros, L={w.L}, smoother {w.smoother}")
     hh = HHG(w.mesh.coords, w.mesh.cells, w.L, smoother=w.smoother, coefficient=w.coefficient,
-             kappa_cell=w.kappa_cell)
+             kappa_cell=w.kappa_cell, flags=args.flags)
     N = hh.num_dofs()
     X = hh.dof_coords().cpu().numpy()
-    f = torch.as_tensor(w.f(X), device="cuda:0")
-    g = torch.as_tensor(w.g(X), device="cuda:0")
     if w.kappa_nodal is not None:
         hh.set_kappa_nodal(torch.as_tensor(w.kappa_nodal(X), device="cuda:0"))
     log(f"N = {N} DoFs, workspace {hh.workspace_bytes / 2**30:.2f} GiB")
@@ -258,11 +260,20 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+        hh.bench_smoother("fp32_refined", 2)   # first touch of the level's pages
         b = hh.bench_smoother("fp32_refined", args.sweeps)
         log(f"kernel-only: copy of {COPY_BYTES} B x3, {args.sweeps} float32 sweeps, interior launch "
-            f"{b['launch_ms'] * 1e3:.1f} us, {b['launch_bytes']:.0f} algorithmic bytes per launch")
+            f"{b['launch_ms'] * 1e3:.1f} us, {b['launch_bytes']:.0f} algorithmic bytes per launch "
+            f"({b['launch_bytes'] / (b['launch_ms'] * 1e-3) / 1e9:.0f} GB/s)")
+        if args.kernel_only_fp64:
+            hh.bench_smoother("fp64", 2)
+            b = hh.bench_smoother("fp64", args.sweeps)
+            log(f"kernel-only: {args.sweeps} float64 sweeps, interior launch {b['launch_ms'] * 1e3:.1f} us "
+                f"({b['launch_bytes'] / (b['launch_ms'] * 1e-3) / 1e9:.0f} GB/s)")
         return
 
+    f = torch.as_tensor(w.f(X), device="cuda:0")
+    g = torch.as_tensor(w.g(X), device="cuda:0")
     # reference discretisation error: converged float64 solve
     u_ref, st_ref = hh.fmg_solve(f, g, nu=w.nu, pre=w.pre, post=w.post, precision="fp64", rtol=1e-12, max_iter=200)
     if w.u_exact is not None:
@@ -294,8 +305,13 @@ def main():
     achieved = k["launch_bytes"] / (k["launch_ms"] * 1e-3) / 1e9
     kname = KERNEL_NAME.get((w.mesh.dim, w.smoother, w.coefficient), "k_smooth_interior")
     if w.mesh.dim == 3 and 2 ** w.L > 32:
-        # 3D levels above n = 32 are swept class by class (the macro does not fit in LDS)
-        kname = "k_gs3d_rows<float, true>"
+        # 3D levels above n = 32 (the macro does not fit in LDS): red-black with a per-macro
+        # coefficient streams planes (both colours in one launch) from n = 256 on, other
+        # smoothers and smaller levels go class by class
+        if w.smoother == "redblack" and w.coefficient == "macro" and 2 ** w.L >= 256:
+            kname = "k_gs3d_stream<float, true>"
+        else:
+            kname = "k_gs3d_rows<float, true>" if 2 ** w.L >= 128 else "k_smooth_interior"
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=TRAFFIC_BYTES.get((w.name, w.L, kname)),
                 kernel=kname, bytes_per_launch=k["launch_bytes"], avg_launch_us=round(k["launch_ms"] * 1e3, 2))

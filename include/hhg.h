@@ -97,7 +97,11 @@ typedef struct {
                                  HHG_FLAG_ROWS3D: use the 3D kernels that take one wavefront
                                  per lattice row (operator application; class-by-class
                                  interior sweep) on every level, not only from n = 128 on
-                                 (same result; for checking them on small levels)            */
+                                 (same result; for checking them on small levels).
+                                 HHG_FLAG_STREAM3D: with the red-black smoother and a per-macro
+                                 coefficient, use the plane-streaming 3D interior sweep (float32
+                                 sweeps) on every level with n >= 4, not only from n = 256 on
+                                 (same result; for checking it on small levels)               */
 } hhg_options;
 
 enum {
@@ -105,7 +109,8 @@ enum {
   HHG_FLAG_NO_LANE_IFACE = 2,
   HHG_FLAG_NO_GRAPH = 4,
   HHG_FLAG_NO_PRELOAD = 8,
-  HHG_FLAG_ROWS3D = 16
+  HHG_FLAG_ROWS3D = 16,
+  HHG_FLAG_STREAM3D = 32
 };
 
 typedef struct {

@@ -30,6 +30,7 @@ HHG_FLAG_NO_LANE_IFACE = 2
 HHG_FLAG_NO_GRAPH = 4
 HHG_FLAG_NO_PRELOAD = 8
 HHG_FLAG_ROWS3D = 16
+HHG_FLAG_STREAM3D = 32
 
 SMOOTHERS = {"redblack": HHG_GS_REDBLACK, "multicolour": HHG_GS_MULTICOLOR, "jacobi": HHG_JACOBI}
 PRECISIONS = {"fp64": HHG_FP64, "fp32_refined": HHG_FP32_REFINED}

@@ -130,6 +130,9 @@ bool fused_available(hhg_ctx c, int l, size_t tsize) {
   const Level& lv = c->lev[l];
   if (p1(c) || lv.NI <= 0 || c->opt.smoother == HHG_JACOBI || c->no_fused) return false;
   if (c->dim == 2) return !lv.tiles.empty();
+  // the plane-streaming 3D sweep runs in float32; float64 sweeps stay class by class (with
+  // twice the LDS per tile the float64 form holds one workgroup per CU and was measured slower)
+  if (!lv.tiles.empty()) return tsize == 4;
   return !lv.itab.empty() && (size_t)lv.Sraw * tsize <= 64 * 1024;
 }
 
@@ -140,7 +143,8 @@ hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
   const bool jac = c->opt.smoother == HHG_JACOBI;
   const int rb = c->opt.smoother == HHG_GS_REDBLACK ? 1 : 0;
   const bool fused = fused_available(c, l, sizeof(T));
-  const bool twobuf = fused && c->dim == 2;   // out-of-place interior sweep, see k_gs2d_fused
+  // out-of-place interior sweep (k_gs2d_fused, k_gs3d_stream)
+  const bool twobuf = fused && (c->dim == 2 || !lv.tiles.empty());
   for (int s = 0; s < sweeps; ++s) {
     T* x = Arr<T>::x(lv);
     if (jac) {
@@ -149,6 +153,7 @@ hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
       launch_smooth_iface<T>(c->dim, p1(c), k, c->tab, nullptr, (int)lv.nIface, x, x, y, (T*)nullptr, b, 1, omega(c),
                              sA(c, l), lv.kn, ST(c));
       std::swap(Arr<T>::x(lv), Arr<T>::t(lv));
+      c->xswap ^= 1u << (l + (sizeof(T) == 4 ? 16 : 0));
       continue;
     }
     // macro interiors first (all colours), then the interface colour classes; with two buffers
@@ -192,7 +197,10 @@ hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
                                0.0, sA(c, l), lv.kn, ST(c));
       }
     }
-    if (twobuf) std::swap(Arr<T>::x(lv), Arr<T>::x2(lv));
+    if (twobuf) {
+      std::swap(Arr<T>::x(lv), Arr<T>::x2(lv));
+      c->xswap ^= 1u << (l + (sizeof(T) == 4 ? 16 : 0));
+    }
   }
   LAUNCHCHK();
   return HHG_OK;
@@ -287,7 +295,7 @@ void drop_graphs(hhg_ctx c) {
 // recording), later calls replay it.  body() must only launch kernels (no copies, no
 // synchronisation) and must leave the host-side buffer roles as it found them; the callers
 // guarantee the latter by using graphs only for even pre- and post-smoothing counts (each
-// 2D sweep swaps the two iterate buffers).
+// out-of-place sweep swaps the two iterate buffers).
 template <class F>
 hhg_status run_recorded(hhg_ctx c, int64_t key, F&& body) {
   if (c->no_graph || c->prof_on || c->capturing) return body();
@@ -320,9 +328,12 @@ hhg_status run_recorded(hhg_ctx c, int64_t key, F&& body) {
   return HHG_OK;
 }
 
-int64_t graph_key(int kind, const hhg_solve_params& p) {
+// recorded launches refer to the iterate buffers by address, so the key includes which buffer
+// of each level currently holds the iterate (an odd number of sweeps through hhg_smooth or
+// hhg_bench_smoother leaves them exchanged)
+int64_t graph_key(hhg_ctx c, int kind, const hhg_solve_params& p) {
   return (int64_t)kind | ((int64_t)p.nu << 4) | ((int64_t)p.pre << 12) | ((int64_t)p.post << 20) |
-         ((int64_t)p.precision << 28);
+         ((int64_t)p.precision << 28) | ((int64_t)c->xswap << 32);
 }
 
 // FMG given bf_l and g_l on all levels; result in lev[L].x, w_l in lev[l+1].w
@@ -342,7 +353,7 @@ hhg_status fmg_core(hhg_ctx c, const hhg_solve_params& p, hhg_solve_stats* stats
     return HHG_OK;
   };
   // warm: the iterate on level L is given; only the cycles below run
-  if (!warm) TRY(rec ? run_recorded(c, graph_key(1, p), body) : body());
+  if (!warm) TRY(rec ? run_recorded(c, graph_key(c, 1, p), body) : body());
   int vcycles = warm ? 0 : p.nu * L;
   int extra = 0;
   double rel = 0.0;
@@ -374,7 +385,7 @@ hhg_status fmg_core(hhg_ctx c, const hhg_solve_params& p, hhg_solve_stats* stats
         LAUNCHCHK();
         return HHG_OK;
       };
-      TRY(rec ? run_recorded(c, graph_key(ready ? 3 : 2, p), step) : step());
+      TRY(rec ? run_recorded(c, graph_key(c, ready ? 3 : 2, p), step) : step());
       ++extra;
       ++vcycles;
       double h = 0;
@@ -510,6 +521,7 @@ hhg_status hhg_setup(const hhg_mesh* mesh, int L, const hhg_options* opt, hhg_ct
   c->no_graph = (opt->flags & HHG_FLAG_NO_GRAPH) != 0;
   c->no_preload = (opt->flags & HHG_FLAG_NO_PRELOAD) != 0;
   c->force_rows3d = (opt->flags & HHG_FLAG_ROWS3D) != 0;
+  c->force_stream3d = (opt->flags & HHG_FLAG_STREAM3D) != 0;
   c->nV = mesh->n_vertices;
   c->nC = mesh->n_cells;
   const int nv = c->dim + 1;

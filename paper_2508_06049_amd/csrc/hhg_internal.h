@@ -35,6 +35,10 @@ constexpr int tile_rows(int C, int n) {
   return C == 3 ? (n <= 8 ? 6 : (n <= 16 ? 18 : kTileJ3)) : (n <= 8 ? 8 : (n <= 16 ? 16 : kTileJ));
 }
 constexpr int kMacroLdsN = 32;
+// plane-streaming 3D red-black sweep: a tile holds kS3I x kS3J interior points of a plane and
+// streams kS3K planes; LDS planes are 64 x (kS3J + 4) points (two-point halo in i and j)
+constexpr int kS3I = 60, kS3J = 28, kS3K = 32;
+constexpr int kStream3dMinN = 256;  // levels with n >= this use it (red-black, per-macro coefficient)
 // levels whose largest interface colour class has at most this many DoFs sweep all interface
 // classes in one single-workgroup launch
 constexpr int kIfaceOneGroup = 4096;
@@ -199,6 +203,8 @@ struct hhg_ctx_s {
   bool no_graph = false;            // run every launch eagerly (testing)
   bool no_preload = false;          // single-workgroup interface sweep without preloading (testing)
   bool force_rows3d = false;        // 3D row kernels at every level (testing)
+  bool force_stream3d = false;      // 3D plane-streaming sweep from n = 4 on (testing)
+  uint32_t xswap = 0;               // bit l (+16 for float32): level l's iterate is in its second buffer
   void* cap_stream = nullptr;       // hipStream_t used only while recording
   bool capturing = false;
   std::vector<std::pair<int64_t, void*>> graphs;   // (key, hipGraphExec_t)

@@ -22,7 +22,8 @@ template <typename T>
 void launch_smooth_interior(int dim, bool p1, const LK& lk, const Tables& tb, const T* uin, T* uout, const T* b, int colour,
                             int rb, int jacobi, double omega, double sA, const double* kn, bool fine, hipStream_t st);
 // fused interior Gauss-Seidel sweep (all interior colours); false if not available for the level
-// (2D reads u and writes the interior of uo; 3D updates u in place and ignores uo)
+// (2D, and 3D with streaming tiles: reads u and writes the interior of uo; the 3D LDS macro
+// sweep updates u in place and ignores uo)
 template <typename T>
 bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* uo, const T* b, const int32_t* tiles,
                      int ntiles, const uint32_t* itab, const int32_t* itab_off, int rb, double sA, bool fine,

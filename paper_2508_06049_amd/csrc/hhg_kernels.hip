@@ -336,6 +336,169 @@ __global__ void __launch_bounds__(256) k_gs3d_rows(LK lk, Tables tb, T* __restri
   }
 }
 
+// Red-black Gauss-Seidel sweep of all macro interiors of a 3D level, both colours in one
+// launch, out of place: reads u, writes the interior of uo.  One workgroup takes a tile of
+// kS3I x kS3J points in (i, j) and streams the planes k0 .. k1-1 of one macro.  Per plane p it
+// loads u on the tile plus a two-point halo into LDS, updates the red points of plane p-1 on the
+// tile plus a one-point halo from the old values (red values at halo points are recomputed
+// here, identically to the tile that owns them, since all inputs are old values), then the
+// black points of plane p-2 on the tile from the new red values, and writes both colours of
+// plane p-2.  Per point this moves u and b once in and u once out (plus the halos, mostly
+// served by L2).  Same updates, in the same order within each point, as the class-by-class
+// sweep: red (parity 0) first, then black; interface points are left to the interface sweep.
+template <typename T, bool FINE>
+__global__ void __launch_bounds__(256) k_gs3d_stream(LK lk, Tables tb, const T* __restrict__ u, T* __restrict__ uo,
+                                                     const T* __restrict__ b, const int32_t* __restrict__ tiles,
+                                                     int ntiles, double sA) {
+  constexpr int W = 64, H = kS3J + 4, NP = W * H / 256;
+  static_assert(kS3I + 4 == W, "one wavefront per LDS row");
+  __shared__ T sU[3][H * W];
+  __shared__ T sR[3][H * W];
+  const int per_xcd = (int)(gridDim.x >> 3);   // gridDim.x is a multiple of 8
+  const int blk = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (blk >= lk.nmacro * ntiles) return;
+  const int m = blk / ntiles;
+  const int tile = tiles[blk - m * ntiles];
+  const int n = lk.n;
+  const int i0 = 1 + (tile & 1023) * kS3I, j0 = 1 + ((tile >> 10) & 1023) * kS3J, k0 = 1 + (tile >> 20) * kS3K;
+  const int k1 = min(k0 + kS3K, n - i0 - j0);   // interior points with i >= i0, j >= j0 have k < n - i0 - j0
+  // the macro's closure as buffer resources: 32-bit offsets, every access below stays inside
+  const int64_t base = (int64_t)m * lk.S;
+  const uint32_t mbytes = (uint32_t)(lk.S * (int64_t)sizeof(T));
+  const __amdgpu_buffer_rsrc_t ru = d_rsrc(u + base, mbytes), rb = d_rsrc(b + base, mbytes),
+                               ro = d_rsrc(uo + base, mbytes);
+  const double* Wt = tb.stiff + (size_t)m * kMaxMask * 15;
+  const double ks = sA * tb.kappa[m];
+  const T diag = (T)(ks * Wt[0]);
+  // all 14 neighbours are read and weighted, vanishing weights included: adding the exact zero
+  // products leaves every sum bitwise as it is, and unconditional LDS reads keep in flight
+  T cq[15];
+#pragma unroll
+  for (int q = 1; q < 15; ++q) cq[q] = (T)(ks * Wt[q]);
+  const int* rp = tb.rbpar + m * 4;
+  const int s1 = rp[1], s2 = rp[2], s3 = rp[3];
+  // a wavefront holds one LDS row (64 points along i) per step s: the row's j, its offset in a
+  // plane and the membership of the row in the halo regions are wave-uniform
+  const int lane = (int)(threadIdx.x & 63), w4 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int i = i0 - 2 + lane;
+  const bool lane1 = lane >= 1 && lane < W - 1, lane2 = lane >= 2 && lane < W - 2;
+  const int ipar = (i * s1) & 1;
+  const int dn = d_tet(n);
+  // offset of point (i, j, k) in the closure: plane(k) + rowin(j, k) + i
+  auto plane = [&](int k) { return dn - d_tet(n - k); };
+  auto rowin = [&](int s, int k) {
+    const int j = j0 - 2 + w4 + 4 * s;
+    return j * (n - k + 1) - (j * (j - 1)) / 2;
+  };
+  auto slot = [](int k) { return (k + 3) % 3; };
+  // global loads run one plane ahead: u of plane p + 1 and b of plane p are in flight while
+  // plane p is processed (the barriers wait for LDS only).  Points outside the closure (or
+  // outside the interior, for b) load offset 0 and are then replaced by zero.
+  T ureg[NP], bnext[NP], bcur[NP], bprev[NP];
+  auto load_u = [&](int p) {
+    const int pk = plane(p);
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+      const int j = j0 - 2 + w4 + 4 * s;
+      const bool ok = p >= 0 && i >= 0 && j >= 0 && i + j + p <= n;
+      T v;
+      d_bload(ru, ok ? (uint32_t)(pk + rowin(s, p) + i) * (uint32_t)sizeof(T) : 0u, v);
+      ureg[s] = ok ? v : (T)0;
+    }
+  };
+  auto load_b = [&](int q) {   // b at the interior points of the one-point halo region of plane q
+    const int pk = plane(q);
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+      const int jj = w4 + 4 * s, j = j0 - 2 + jj;
+      const bool ok = jj >= 1 && jj < H - 1 && lane1 && i >= 1 && j >= 1 && q >= 1 && i + j + q <= n - 1;
+      T v;
+      d_bload(rb, ok ? (uint32_t)(pk + rowin(s, q) + i) * (uint32_t)sizeof(T) : 0u, v);
+      bnext[s] = ok ? v : (T)0;
+    }
+  };
+#pragma unroll
+  for (int s = 0; s < NP; ++s) bnext[s] = bcur[s] = bprev[s] = (T)0;
+  load_u(k0 - 2);
+  for (int p = k0 - 2; p <= k1 + 1; ++p) {
+    // u of plane p on the tile and its two-point halo
+    {
+      T* U = sU[slot(p)];
+#pragma unroll
+      for (int s = 0; s < NP; ++s) U[(w4 + 4 * s) * W + lane] = ureg[s];
+    }
+    if (p + 1 <= k1 + 1) load_u(p + 1);
+    if (p >= k0 - 1 && p <= k1) load_b(p);
+    __syncthreads();
+    const int q = p - 1;   // red points of plane q on the tile and a one-point halo
+    if (q >= k0 - 1 && q <= k1) {
+      const T* Um = sU[slot(q - 1)];
+      const T* U0 = sU[slot(q)];
+      const T* Up = sU[slot(q + 1)];
+      T* R = sR[slot(q)];
+      const int qpar = (q * s3) & 1;
+#pragma unroll
+      for (int s = 0; s < NP; ++s) {
+        const int jj = w4 + 4 * s;
+        if (jj < 1 || jj >= H - 1) continue;   // wave-uniform
+        const int j = j0 - 2 + jj;
+        const int idx = jj * W + lane;
+        if (!lane1) continue;
+        T r = U0[idx];
+        if (i >= 1 && j >= 1 && q >= 1 && i + j + q <= n - 1 && (ipar ^ ((j * s2) & 1) ^ qpar) == 0) {
+          T nb[15];
+#pragma unroll
+          for (int c = 1; c < 15; ++c) {
+            const T* P = kOff3[c][2] < 0 ? Um : (kOff3[c][2] > 0 ? Up : U0);
+            nb[c] = P[idx + kOff3[c][1] * W + kOff3[c][0]];
+          }
+          T off = (T)0;
+#pragma unroll
+          for (int c = 1; c < 15; ++c) off += cq[c] * nb[c];
+          r = (bcur[s] - off) / diag;
+        }
+        R[idx] = r;
+      }
+    }
+    __syncthreads();
+    const int qb = p - 2;   // black points of plane qb on the tile; both colours written
+    if (qb >= k0 && qb < k1) {
+      const T* Rm = sR[slot(qb - 1)];
+      const T* R0 = sR[slot(qb)];
+      const T* Rp = sR[slot(qb + 1)];
+      const int pk = plane(qb);
+      const int qpar = (qb * s3) & 1;
+#pragma unroll
+      for (int s = 0; s < NP; ++s) {
+        const int jj = w4 + 4 * s;
+        if (jj < 2 || jj >= H - 2) continue;   // wave-uniform
+        const int j = j0 - 2 + jj;
+        if (!lane2 || i + j + qb > n - 1) continue;   // i, j, qb >= 1 on the tile
+        const int idx = jj * W + lane;
+        T v = R0[idx];
+        if ((ipar ^ ((j * s2) & 1) ^ qpar) != 0) {
+          T nb[15];
+#pragma unroll
+          for (int c = 1; c < 15; ++c) {
+            const T* P = kOff3[c][2] < 0 ? Rm : (kOff3[c][2] > 0 ? Rp : R0);
+            nb[c] = P[idx + kOff3[c][1] * W + kOff3[c][0]];
+          }
+          T off = (T)0;
+#pragma unroll
+          for (int c = 1; c < 15; ++c) off += cq[c] * nb[c];
+          v = (bprev[s] - off) / diag;
+        }
+        d_bstore(ro, (uint32_t)(pk + rowin(s, qb) + i) * (uint32_t)sizeof(T), v);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+      bprev[s] = bcur[s];
+      bcur[s] = bnext[s];
+    }
+  }
+}
+
 // Gauss-Seidel (or Jacobi) update of one interface DoF t: the assembled row is the sum of the
 // partial rows of all macros containing it.  Interior neighbours are read from xi, interface
 // neighbours (and the DoF's own old value) from xf; the new value goes to every copy in uout
@@ -1935,6 +2098,19 @@ bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* 
 #undef HHG_F2N
 #undef HHG_F2
     return true;
+  }
+  if (ntiles > 0) {
+    // red-black with per-macro coefficient on a level with the plane-streaming tile table
+    // (float32 only: float64 sweeps of these levels go class by class)
+    if constexpr (sizeof(T) == 4) {
+      if (!rb) return false;
+      const unsigned g = (unsigned)(((int64_t)lk.nmacro * ntiles + 7) / 8 * 8);   // a multiple of 8 blocks (XCDs)
+      if (fine) k_gs3d_stream<T, true><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, sA);
+      else k_gs3d_stream<T, false><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, sA);
+      return true;
+    } else {
+      return false;
+    }
   }
   if (!itab || lk.n > kMacroLdsN) return false;
   const size_t shm = (size_t)lk.Sraw * sizeof(T);

@@ -534,8 +534,20 @@ hhg_status build_colouring(hhg_ctx c) {
       for (int tj = 0; 1 + tj * TJ <= lv.n - 2; ++tj)
         for (int ti = 0; 1 + ti * TI + 1 + tj * TJ <= lv.n - 1; ++ti) lv.tiles.push_back(ti | (tj << 16));
     }
+    // 3D red-black with a per-macro coefficient: plane-streaming tiles (i0, j0, k0 in units of
+    // kS3I, kS3J, kS3K) of the levels with n >= kStream3dMinN, or of all levels with n >= 4
+    // under HHG_FLAG_STREAM3D
+    const bool stream3d = d == 3 && lv.NI > 0 && c->opt.smoother == HHG_GS_REDBLACK &&
+                          c->opt.coefficient == HHG_KAPPA_MACRO &&
+                          (lv.n >= kStream3dMinN || (c->force_stream3d && lv.n >= 4));
+    if (stream3d) {
+      for (int tk = 0; 1 + tk * kS3K <= lv.n - 3; ++tk)
+        for (int tj = 0; 1 + tj * kS3J + 1 + tk * kS3K <= lv.n - 2; ++tj)
+          for (int ti = 0; 1 + ti * kS3I + 1 + tj * kS3J + 1 + tk * kS3K <= lv.n - 1; ++ti)
+            lv.tiles.push_back(ti | (tj << 10) | (tk << 20));
+    }
     lv.itab_off.clear();
-    if (d == 3 && lv.NI > 0 && lv.n <= kMacroLdsN) {
+    if (d == 3 && lv.NI > 0 && lv.n <= kMacroLdsN && !stream3d) {
       // interior points sorted by colour, one list per red-black parity pattern (s1, s2, s3)
       // of a macro (multicolour: one list); itab_off[p * (Cint + 1) + c] starts colour c
       const int n = lv.n;
@@ -702,8 +714,9 @@ void plan_workspace(hhg_ctx c) {
     lv.off_tseg = take((int64_t)lv.task_seg.size() * 4);
     lv.off_twmax = take((int64_t)lv.task_wmax.size() * 4);
     lv.off_twoff = take((int64_t)lv.task_woff.size() * 4);
+    // second iterate buffers of the out-of-place fused sweeps (2D; 3D streaming tiles: float32)
     lv.off_x2 = take(d == 2 ? nf * 8 : 0);
-    lv.off_x2_32 = take(d == 2 ? nf * 4 : 0);
+    lv.off_x2_32 = take(d == 2 || !lv.tiles.empty() ? nf * 4 : 0);
     lv.off_itab = take((int64_t)lv.itab.size() * 4);
     lv.off_itoff = take((int64_t)lv.itab_off.size() * 4);
   }

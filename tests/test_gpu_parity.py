@@ -166,6 +166,38 @@ def test_3d_row_sweep_matches(name, smoother):
     assert np.abs(to_host(ugf) - uf[p]).max() <= 1e-12 * np.abs(uf).max()
 
 
+@pytest.mark.parametrize("name,L", [("kuhn1", 5), ("kuhn2", 4), ("kuhn1", 6)])
+def test_3d_stream_sweep_matches(name, L):
+    # the plane-streaming red-black 3D sweep (both colours in one out-of-place float32 launch,
+    # used from n = 256 on; forced here from n = 4 on with HHG_FLAG_STREAM3D) runs in the
+    # float32 cycles of the float32-refined solve: bit for bit the same iterates as the
+    # class-by-class row sweep, over odd and even smoothing counts (odd counts leave the two
+    # iterate buffers exchanged), and the oracle's solution at convergence
+    from paper_2508_06049_amd import HHG
+    from paper_2508_06049_amd._lib import HHG_FLAG_NO_FUSED, HHG_FLAG_ROWS3D, HHG_FLAG_STREAM3D
+    _note("3d stream sweep", name, L)
+    m = meshes.kuhn_cube(1 if name == "kuhn1" else 2)
+    h, perms = oracle_hierarchy(m, L)
+    kc = problems.kappa_cells_uniform(7, m.n_cells)
+    hs = HHG(m.coords, m.cells, L, smoother="redblack", kappa_cell=kc, flags=HHG_FLAG_STREAM3D)
+    hr = HHG(m.coords, m.cells, L, smoother="redblack", kappa_cell=kc, flags=HHG_FLAG_NO_FUSED | HHG_FLAG_ROWS3D)
+    S = fmg.FMGSolver(h, kappa_cell=kc, smoother="redblack")
+    p = perms[L]
+    X = h.levels[L].X
+    f = problems.fourier3d(X, problems.fourier_amplitudes(0))
+    g = 0.1 * X[:, 0] - 0.2 * X[:, 2]
+    fd, gd = to_dev(f[p]), to_dev(g[p])
+    for pre, post, iters in ((2, 2, 3), (1, 2, 2), (3, 1, 4)):
+        us, ss = hs.fmg_solve(fd, gd, nu=1, pre=pre, post=post, precision="fp32_refined", rtol=1e-30, max_iter=iters)
+        ur, sr = hr.fmg_solve(fd, gd, nu=1, pre=pre, post=post, precision="fp32_refined", rtol=1e-30, max_iter=iters)
+        assert ss.vcycles == sr.vcycles == L + iters
+        assert np.array_equal(to_host(us), to_host(ur))
+    if L <= 5:   # sparse direct solve of the oracle's system
+        ref = S.direct(L, S.rhs_levels(f)[L], g)
+        us, st = hs.fmg_solve(fd, gd, nu=1, precision="fp32_refined", rtol=1e-12, max_iter=80)
+        assert np.abs(to_host(us) - ref[p]).max() <= 1e-9 * np.abs(ref).max()
+
+
 def _rhs(name, X, dim):
     if name.startswith("square"):
         return problems.sine2d_f(X), np.zeros(len(X))
