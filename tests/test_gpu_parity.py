@@ -198,6 +198,28 @@ def test_3d_stream_sweep_matches(name, L):
         assert np.abs(to_host(us) - ref[p]).max() <= 1e-9 * np.abs(ref).max()
 
 
+def test_graph_replay_after_odd_smoothing():
+    # an odd number of out-of-place sweeps through hhg_smooth leaves a level's two iterate
+    # buffers exchanged; solves recorded as HIP graphs before must not replay stale addresses
+    from paper_2508_06049_amd import HHG
+    m = meshes.lshape_6tri()
+    L = 6
+    _note("graph replay after odd smoothing", L)
+    hh = HHG(m.coords, m.cells, L, smoother="multicolour")
+    X = hh.dof_coords().cpu().numpy()
+    f, g = to_dev(np.ones(len(X))), to_dev(problems.lshape_u(X))
+    kw = dict(nu=1, rtol=1e-30, max_iter=3)
+    u1, _ = hh.fmg_solve(f, g, **kw)
+    u2, _ = hh.fmg_solve(f, g, precision="fp32_refined", **kw)
+    for lvl in (L, L - 2):
+        x = to_dev(np.random.default_rng(lvl).standard_normal(hh.num_dofs(lvl)))
+        hh.smooth(lvl, x, x * 0, 1)
+    v1, _ = hh.fmg_solve(f, g, **kw)
+    v2, _ = hh.fmg_solve(f, g, precision="fp32_refined", **kw)
+    assert np.array_equal(to_host(u1), to_host(v1))
+    assert np.array_equal(to_host(u2), to_host(v2))
+
+
 def _rhs(name, X, dim):
     if name.startswith("square"):
         return problems.sine2d_f(X), np.zeros(len(X))
