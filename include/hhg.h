@@ -173,14 +173,15 @@ hhg_status hhg_fmg_solve(hhg_ctx ctx, const double* f_nodal, const double* g_nod
 hhg_status hhg_cycle_solve(hhg_ctx ctx, const double* f_nodal, const double* g_nodal, double* u_inout,
                            const hhg_solve_params* params, hhg_solve_stats* stats);
 
-/* Transfer of a level-L vector between two contexts on the same 2D domain: the solution
+/* Transfer of a level-L vector between two contexts on the same domain: the solution
  * transfer from the fine level of one macro mesh to that of the next one in a kl-loop, which
  * the conclusion (Section 6) lists as missing.  u_new[i] is the P1 function with nodal values
  * u_old (device, canonical order of ctx_old's level L) evaluated at the coordinates of DoF i of
  * ctx_new's level L (device, canonical order).  Both contexts are bound on one device; the
  * work runs on ctx_new's stream and uses scratch vectors of both contexts (the state of their
  * last solves is kept); ctx_old must not be in use meanwhile.  A DoF outside every macro of
- * ctx_old gets NaN.  Triangle meshes only (HHG_EINVAL otherwise).  Synchronises the stream. */
+ * ctx_old gets NaN.  Triangle or tetrahedral meshes, both of the same dimension (HHG_EINVAL
+ * otherwise).  Synchronises the stream. */
 hhg_status hhg_transfer(hhg_ctx ctx_new, hhg_ctx ctx_old, const double* u_old, double* u_new);
 
 /* Error estimate of procedure ErrorEstimate (Algorithm 4) from the last hhg_fmg_solve, for

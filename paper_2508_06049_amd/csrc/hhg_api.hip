@@ -786,35 +786,39 @@ hhg_status hhg_cycle_solve(hhg_ctx c, const double* f, const double* g, double* 
 hhg_status hhg_transfer(hhg_ctx c, hhg_ctx old, const double* u_old, double* u_new) {
   TRY(check_ready(c));
   if (!old || !old->bound) { c->err = "the old context has no workspace bound"; return HHG_ESTATE; }
-  if (c->dim != 2 || old->dim != 2) { c->err = "hhg_transfer is implemented for triangle meshes"; return HHG_EINVAL; }
+  if (c->dim != old->dim) { c->err = "the two meshes differ in dimension"; return HHG_EINVAL; }
   if (!u_old || !u_new) { c->err = "NULL vector"; return HHG_EINVAL; }
+  const int d = c->dim, nv = d + 1;
   // candidate old macros of every new macro: those whose bounding boxes meet its own
-  auto box = [](hhg_ctx k, int64_t m, double* b) {
-    b[0] = b[2] = 1e300;
-    b[1] = b[3] = -1e300;
-    for (int a = 0; a < 3; ++a) {
-      const int v = k->cells[m * 3 + a];
-      for (int q = 0; q < 2; ++q) {
-        b[2 * q] = std::min(b[2 * q], k->coords[v * 2 + q]);
-        b[2 * q + 1] = std::max(b[2 * q + 1], k->coords[v * 2 + q]);
+  auto box = [d, nv](hhg_ctx k, int64_t m, double* b) {
+    for (int q = 0; q < d; ++q) {
+      b[2 * q] = 1e300;
+      b[2 * q + 1] = -1e300;
+    }
+    for (int a = 0; a < nv; ++a) {
+      const int v = k->cells[m * nv + a];
+      for (int q = 0; q < d; ++q) {
+        b[2 * q] = std::min(b[2 * q], k->coords[v * d + q]);
+        b[2 * q + 1] = std::max(b[2 * q + 1], k->coords[v * d + q]);
       }
     }
   };
-  std::vector<double> bo(old->nC * 4);
+  std::vector<double> bo(old->nC * 6);
   double ext = 0.0;
   for (int64_t m = 0; m < old->nC; ++m) {
-    box(old, m, &bo[m * 4]);
-    ext = std::max(ext, std::max(bo[m * 4 + 1] - bo[m * 4], bo[m * 4 + 3] - bo[m * 4 + 2]));
+    box(old, m, &bo[m * 6]);
+    for (int q = 0; q < d; ++q) ext = std::max(ext, bo[m * 6 + 2 * q + 1] - bo[m * 6 + 2 * q]);
   }
   const double tol = 1e-9 * ext;
   std::vector<int32_t> off(c->nC + 1, 0), cand;
   for (int64_t m = 0; m < c->nC; ++m) {
-    double b[4];
+    double b[6];
     box(c, m, b);
     for (int64_t M = 0; M < old->nC; ++M) {
-      const double* q = &bo[M * 4];
-      if (q[0] <= b[1] + tol && b[0] <= q[1] + tol && q[2] <= b[3] + tol && b[2] <= q[3] + tol)
-        cand.push_back((int32_t)M);
+      const double* q = &bo[M * 6];
+      bool meet = true;
+      for (int a = 0; a < d; ++a) meet = meet && q[2 * a] <= b[2 * a + 1] + tol && b[2 * a] <= q[2 * a + 1] + tol;
+      if (meet) cand.push_back((int32_t)M);
     }
     off[m + 1] = (int32_t)cand.size();
   }
@@ -829,10 +833,10 @@ hhg_status hhg_transfer(hhg_ctx c, hhg_ctx old, const double* u_old, double* u_n
   if (!cand.empty())
     HIPCHK(hipMemcpyAsync(d_cand, cand.data(), cand.size() * sizeof(int32_t), hipMemcpyHostToDevice, ST(c)));
   // the old vector into the old context's closure scratch, interpolated into the new one's
-  launch_canon_to_full(2, lk_of(old, old->L), old->tab, u_old, lo.rc, 0, ST(c));
-  launch_transfer2d(lk_of(c, L), (const double*)(c->ws + c->o_mxyz), lk_of(old, old->L),
-                    (const double*)(old->ws + old->o_mxyz), d_off, d_cand, lo.rc, ln.t, ST(c));
-  launch_full_to_canon(2, lk_of(c, L), c->tab, ln.t, u_new, 0, ST(c));
+  launch_canon_to_full(d, lk_of(old, old->L), old->tab, u_old, lo.rc, 0, ST(c));
+  launch_transfer(d, lk_of(c, L), (const double*)(c->ws + c->o_mxyz), lk_of(old, old->L),
+                  (const double*)(old->ws + old->o_mxyz), d_off, d_cand, lo.rc, ln.t, ST(c));
+  launch_full_to_canon(d, lk_of(c, L), c->tab, ln.t, u_new, 0, ST(c));
   LAUNCHCHK();
   HIPCHK(hipStreamSynchronize(ST(c)));
   return HHG_OK;

@@ -100,7 +100,7 @@ void launch_copy(double* dst, const double* src, int64_t n, hipStream_t st);
 void launch_impose_dirichlet(int dim, const LK& lk, const Tables& tb, const double* g, double* x, hipStream_t st);
 // 2D transfer of a level vector (closure layout) from old macros to the closure nodes of new
 // macros; candidate old macros of new macro m: cand[coff[m] .. coff[m+1]-1]
-void launch_transfer2d(const LK& fn, const double* mxyz_new, const LK& fo, const double* mxyz_old, const int32_t* coff,
-                       const int32_t* cand, const double* uold, double* unew, hipStream_t st);
+void launch_transfer(int dim, const LK& fn, const double* mxyz_new, const LK& fo, const double* mxyz_old,
+                     const int32_t* coff, const int32_t* cand, const double* uold, double* unew, hipStream_t st);
 
 }  // namespace hhg

@@ -1621,6 +1621,87 @@ __global__ void __launch_bounds__(256) k_transfer2d(LK fn, const double* __restr
   unew[(int64_t)m * fn.S + s] = v;
 }
 
+// 3D transfer, one thread per closure node of the new level.  In a candidate old macro the
+// point's barycentric coordinates (l1, l2, l3) (negative round-off clamped to zero) give lattice
+// coordinates xi = no (l1, l2, l3); in cumulative form y = (xi1, xi1 + xi2, xi1 + xi2 + xi3),
+// which is non-decreasing and at most no, the six micro-tetrahedron types of the lattice are
+// the six Kuhn simplices of each unit cube base + [0,1]^3 (base = floor(y) clamped to 0..no-1).
+// The point lies in the simplex that leaves base along the coordinates in order of decreasing
+// fractional part f (ties: the later coordinate first, so every vertex stays non-decreasing and
+// inside the closure), with P1 weights 1 - f_s0, f_s0 - f_s1, f_s1 - f_s2, f_s2.
+__global__ void __launch_bounds__(256) k_transfer3d(LK fn, const double* __restrict__ mxyz_new, LK fo,
+                                                     const double* __restrict__ mxyz_old, const int32_t* __restrict__ coff,
+                                                     const int32_t* __restrict__ cand, const double* __restrict__ uold,
+                                                     double* __restrict__ unew) {
+  const int nchunk = (fn.Sraw + 255) >> 8;
+  const int m = blockIdx.x / nchunk;
+  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
+  if (s >= fn.Sraw) return;
+  int i, j, k;
+  d_dec<3>(fn.n, s, i, j, k);
+  const double* X = mxyz_new + (size_t)m * 12;
+  const double inv = 1.0 / fn.n;
+  double x[3];
+  for (int q = 0; q < 3; ++q)
+    x[q] = X[q] + (i * inv) * (X[3 + q] - X[q]) + (j * inv) * (X[6 + q] - X[q]) + (k * inv) * (X[9 + q] - X[q]);
+  auto det3 = [](const double* a, const double* b, const double* c) {
+    return a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) + a[2] * (b[0] * c[1] - b[1] * c[0]);
+  };
+  double v = __builtin_nan("");
+  for (int q = coff[m]; q < coff[m + 1]; ++q) {
+    const int M = cand[q];
+    const double* Y = mxyz_old + (size_t)M * 12;
+    double e1[3], e2[3], e3[3], r[3];
+    for (int a = 0; a < 3; ++a) {
+      e1[a] = Y[3 + a] - Y[a];
+      e2[a] = Y[6 + a] - Y[a];
+      e3[a] = Y[9 + a] - Y[a];
+      r[a] = x[a] - Y[a];
+    }
+    const double det = det3(e1, e2, e3);
+    double l1 = det3(r, e2, e3) / det, l2 = det3(e1, r, e3) / det, l3 = det3(e1, e2, r) / det;
+    if (l1 < -1e-10 || l2 < -1e-10 || l3 < -1e-10 || 1.0 - l1 - l2 - l3 < -1e-10) continue;
+    l1 = fmax(l1, 0.0);
+    l2 = fmax(l2, 0.0);
+    l3 = fmax(l3, 0.0);
+    const double ls = l1 + l2 + l3;
+    if (ls > 1.0) {
+      l1 /= ls;
+      l2 /= ls;
+      l3 /= ls;
+    }
+    const int no = fo.n;
+    const double y[3] = {l1 * no, (l1 + l2) * no, fmin((l1 + l2 + l3) * no, (double)no)};
+    int base[3], o[3] = {2, 1, 0};
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+      base[a] = min(max((int)floor(y[a]), 0), no - 1);
+      f[a] = y[a] - base[a];
+    }
+    // stable sort of (c, b, a) by decreasing fractional part
+    for (int a = 1; a < 3; ++a)
+      for (int b2 = a; b2 > 0 && f[o[b2]] > f[o[b2 - 1]]; --b2) {
+        const int t = o[b2];
+        o[b2] = o[b2 - 1];
+        o[b2 - 1] = t;
+      }
+    const double w[4] = {1.0 - f[o[0]], f[o[0]] - f[o[1]], f[o[1]] - f[o[2]], f[o[2]]};
+    const double* U = uold + (int64_t)M * fo.S;
+    int cur[3] = {base[0], base[1], base[2]};
+    double acc = 0.0;
+    for (int t = 0; t < 4; ++t) {
+      if (t > 0) ++cur[o[t - 1]];
+      const int ii = min(max(cur[0], 0), no);
+      const int jj = min(max(cur[1] - cur[0], 0), no - ii);
+      const int kk = min(max(cur[2] - cur[1], 0), no - ii - jj);
+      acc += w[t] * U[d_lin<3>(no, ii, jj, kk)];
+    }
+    v = acc;
+    break;
+  }
+  unew[(int64_t)m * fn.S + s] = v;
+}
+
 // level 0: x (+)= A_II^{-1} (assembled rhs) on the inner coarse vertices; one thread per row
 template <typename T>
 __global__ void __launch_bounds__(256) k_coarse(int n0, const int32_t* __restrict__ coff, const int64_t* __restrict__ copy,
@@ -2451,10 +2532,11 @@ void launch_impose_dirichlet(int dim, const LK& lk, const Tables& tb, const doub
   else k_impose_dirichlet<2><<<gr, 256, 0, st>>>(lk, tb, g, x);
 }
 
-void launch_transfer2d(const LK& fn, const double* mxyz_new, const LK& fo, const double* mxyz_old, const int32_t* coff,
-                       const int32_t* cand, const double* uold, double* unew, hipStream_t st) {
+void launch_transfer(int dim, const LK& fn, const double* mxyz_new, const LK& fo, const double* mxyz_old,
+                     const int32_t* coff, const int32_t* cand, const double* uold, double* unew, hipStream_t st) {
   const unsigned gr = (unsigned)(fn.nmacro * ((fn.Sraw + 255) / 256));
-  k_transfer2d<<<gr, 256, 0, st>>>(fn, mxyz_new, fo, mxyz_old, coff, cand, uold, unew);
+  if (dim == 3) k_transfer3d<<<gr, 256, 0, st>>>(fn, mxyz_new, fo, mxyz_old, coff, cand, uold, unew);
+  else k_transfer2d<<<gr, 256, 0, st>>>(fn, mxyz_new, fo, mxyz_old, coff, cand, uold, unew);
 }
 
 }  // namespace hhg

@@ -28,6 +28,7 @@ def _two_steps():
 
 @pytest.mark.parametrize("L", [2, 4])
 def test_transfer_matches_oracle(L):
+    # triangles
     from paper_2508_06049_amd import HHG
     m0, m1 = _two_steps()
     _note("transfer", m0.n_cells, "->", m1.n_cells, L)
@@ -45,13 +46,43 @@ def test_transfer_matches_oracle(L):
     assert np.abs(got - aff(h1.levels[L].X)[p1[L]]).max() < 1e-13
 
 
-def test_warm_started_cycles_reach_the_fmg_solution():
+def _two_steps_3d():
+    # the 6-tetrahedron cube and the mesh after one kl-step that marks the third of the macros
+    # nearest the origin (red-green refinement of tetrahedra)
+    m0 = meshes.kuhn_cube(1)
+    rg = hostmesh.RedGreen3D(m0)
+    cen = m0.coords[m0.cells].mean(axis=1)
+    rg.refine(hostmesh.mark_fraction(-np.linalg.norm(cen, axis=1), 0.34))
+    return m0, rg.mesh("kuhn1_k1")
+
+
+def test_transfer_matches_oracle_3d():
+    from paper_2508_06049_amd import HHG
+    m0, m1 = _two_steps_3d()
+    L = 3
+    _note("transfer 3d", m0.n_cells, "->", m1.n_cells, L)
+    h0, p0 = oracle_hierarchy(m0, L)
+    h1, p1 = oracle_hierarchy(m1, L)
+    a = HHG(m0.coords, m0.cells, L, smoother="multicolour")
+    b = HHG(m1.coords, m1.cells, L, smoother="multicolour")
+    u0 = np.random.default_rng(6).standard_normal(h0.levels[L].n)
+    ref = transfer.transfer(h0, u0, h1.levels[L].X)
+    got = to_host(b.transfer_from(a, to_dev(u0[p0[L]])))
+    assert np.all(np.isfinite(got))
+    assert np.abs(got - ref[p1[L]]).max() <= 1e-12 * np.abs(u0).max()
+    aff = lambda X: 0.3 - 1.7 * X[:, 0] + 0.6 * X[:, 1] + 0.45 * X[:, 2]
+    got = to_host(b.transfer_from(a, to_dev(aff(h0.levels[L].X)[p0[L]])))
+    assert np.abs(got - aff(h1.levels[L].X)[p1[L]]).max() < 1e-13
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_warm_started_cycles_reach_the_fmg_solution(dim):
     # V-cycles from the transferred solution of the previous k-step converge to the discrete
     # solution of the new mesh, and need fewer cycles than from zero
     from paper_2508_06049_amd import HHG
-    L = 5
-    m0, m1 = _two_steps()
-    _note("warm start", L)
+    L = 5 if dim == 2 else 4
+    m0, m1 = _two_steps() if dim == 2 else _two_steps_3d()
+    _note("warm start", dim, L)
     a = HHG(m0.coords, m0.cells, L, smoother="multicolour")
     b = HHG(m1.coords, m1.cells, L, smoother="multicolour")
     Xa, Xb = a.dof_coords().cpu().numpy(), b.dof_coords().cpu().numpy()

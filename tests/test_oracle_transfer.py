@@ -41,3 +41,21 @@ def test_identity_on_the_same_mesh_and_nan_outside():
     assert np.abs(transfer.transfer(h, u, X) - u).max() < 1e-14
     out = transfer.evaluate_p1(X, h.levels[2].E, u, np.array([[1.5, 0.5], [-0.1, 0.2]]))
     assert np.all(np.isnan(out))
+
+
+def test_affine_and_nested_transfer_in_3d():
+    # tetrahedra: affine functions are reproduced across a red-green step of the Kuhn cube, and
+    # from level 1 to level 2 of one hierarchy (Bey's children) the transfer is P_1
+    m0 = meshes.kuhn_cube(1)
+    rg = hostmesh.RedGreen3D(m0)
+    rg.refine([0, 3])
+    m1 = rg.mesh()
+    h0 = refine.Hierarchy(m0.coords, m0.cells, 2)
+    h1 = refine.Hierarchy(m1.coords, m1.cells, 2)
+    aff = lambda X: 0.3 - 1.7 * X[:, 0] + 0.6 * X[:, 1] + 0.45 * X[:, 2]
+    got = transfer.transfer(h0, aff(h0.levels[2].X), h1.levels[2].X)
+    assert np.all(np.isfinite(got))
+    assert np.abs(got - aff(h1.levels[2].X)).max() < 1e-13
+    u = np.random.default_rng(4).standard_normal(h0.levels[1].n)
+    got = transfer.transfer(h0, u, h0.levels[2].X, level=1)
+    assert np.abs(got - assemble.prolongation(h0, 1) @ u).max() < 1e-13
