@@ -7,6 +7,9 @@ midpoints); a triangle with more than one hanging node is split red as well, rep
 triangles with exactly one hanging node are bisected towards it (green).  Green triangles
 are transient: the state kept between steps holds only red leaves, so greens are reverted
 before the next step, and marking a green triangle refines its red parent instead.
+Coarsening (named as future work in the conclusion, Section 6) merges the four red children
+of a parent back into it when all four are leaves and marked, as long as the parent is left
+with at most one hanging node.
 
 3D red-green (Algorithm 3): red-refine marked cells; repeatedly red-refine every face that
 has more than one hanging node on its boundary; cells with more than three hanging nodes
@@ -40,7 +43,14 @@ class RedGreen2D:
         self.X = [tuple(float(v) for v in p) for p in mesh.coords]
         self.tris = [tuple(int(v) for v in t) for t in mesh.cells]   # red leaves
         self.mid = {}                                                 # edge -> midpoint vertex
+        self.children = {}                                            # red parent -> its 4 children
         self._last_parent = None
+        self._act = None                                              # vertices of the leaves
+
+    def _active(self):
+        if self._act is None:
+            self._act = {v for t in self.tris for v in t}
+        return self._act
 
     def _midpoint(self, a, b):
         e = (min(a, b), max(a, b))
@@ -53,21 +63,28 @@ class RedGreen2D:
     def _red(self, t):
         a, b, c = t
         ab, ac, bc = self._midpoint(a, b), self._midpoint(a, c), self._midpoint(b, c)
-        return [(a, ab, ac), (ab, b, bc), (ac, bc, c), (ab, bc, ac)]
+        ch = [(a, ab, ac), (ab, b, bc), (ac, bc, c), (ab, bc, ac)]
+        self.children[t] = ch
+        return ch
+
+    def _mid_active(self, p, q):
+        """Midpoint of edge (p, q) if it is a vertex of the current leaves (else None)."""
+        m = self.mid.get((min(p, q), max(p, q)))
+        return m if m is not None and m in self._active() else None
 
     def _hanging(self, t):
-        """Edges of leaf t whose midpoint exists (refined from the other side)."""
+        """Edges of leaf t whose midpoint is a vertex of the leaves (refined from the other side)."""
         a, b, c = t
         out = []
         for i, (p, q) in enumerate(((b, c), (a, c), (a, b))):     # edge opposite vertex i
-            e = (min(p, q), max(p, q))
-            if e in self.mid:
-                out.append((i, self.mid[e]))
+            m = self._mid_active(p, q)
+            if m is not None:
+                out.append((i, m))
         return out
 
     def _edge_nodes(self, a, b):
-        """Number of vertices in the open edge (a, b): midpoints, recursively."""
-        m = self.mid.get((min(a, b), max(a, b)))
+        """Number of leaf vertices in the open edge (a, b): midpoints, recursively."""
+        m = self._mid_active(a, b)
         return 0 if m is None else 1 + self._edge_nodes(a, m) + self._edge_nodes(m, b)
 
     def _n_hanging(self, t):
@@ -101,6 +118,7 @@ class RedGreen2D:
         for ti, t in enumerate(self.tris):
             tris.extend(self._red(t) if ti in red else [t])
         self.tris = tris
+        self._act = None
         changed = True
         while changed:                       # red closure: more than one hanging node
             changed = False
@@ -111,7 +129,49 @@ class RedGreen2D:
                 else:
                     nxt.append(t)
             self.tris = nxt
+            self._act = None
         self._last_parent = None
+
+    def coarsen(self, marked_cells) -> int:
+        """Merge red sibling groups back into their parents (cells: indices into the last
+        conforming() output; a marked green cell marks its red parent leaf).  All groups whose
+        four children are marked leaves merge at once; the red closure then splits again every
+        merged parent left with more than one hanging node (merging removes vertices, so no
+        other leaf gains one).  Merged parents count as marked, so coarsening repeats upwards
+        while it makes progress.  Returns the number of merged groups."""
+        if self._last_parent is None:
+            self.conforming()
+        marked = {self.tris[self._last_parent[i]] for i in marked_cells}
+        merged = 0
+        while True:
+            leaves = set(self.tris)
+            groups = [P for P, ch in self.children.items() if all(c in leaves and c in marked for c in ch)]
+            if not groups:
+                break
+            drop = {c for P in groups for c in self.children[P]}
+            self.tris = [t for t in self.tris if t not in drop] + groups
+            self._act = None
+            changed = True
+            while changed:                   # red closure
+                changed = False
+                nxt = []
+                for t in self.tris:
+                    if self._n_hanging(t) > 1:
+                        nxt.extend(self._red(t)); changed = True
+                    else:
+                        nxt.append(t)
+                self.tris = nxt
+                self._act = None
+            leaves = set(self.tris)
+            kept = [P for P in groups if P in leaves]
+            if not kept:
+                break
+            for P in kept:
+                del self.children[P]
+                marked.add(P)
+            merged += len(kept)
+        self._last_parent = None
+        return merged
 
     def mesh(self, name="") -> CoarseMesh:
         cells, _ = self.conforming()

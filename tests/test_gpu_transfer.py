@@ -124,3 +124,28 @@ def test_cycle_solve_matches_oracle_cycles():
     for _ in range(3):
         S.vcycle(L, uo, b[L])
     assert np.abs(to_host(ug) - uo[p]).max() <= 1e-12 * np.abs(uo).max()
+
+
+def test_transfer_to_a_coarsened_mesh():
+    # coarsening (red groups merged back, future work in the conclusion) followed by the
+    # transfer from the finer mesh onto the coarser one, against the oracle
+    from paper_2508_06049_amd import HHG
+    m0, m1 = _two_steps()
+    rg = hostmesh.RedGreen2D(m0)
+    cen = m0.coords[m0.cells].mean(axis=1)
+    rg.refine(hostmesh.mark_fraction(-np.hypot(cen[:, 0], cen[:, 1]), 0.25))
+    fine = rg.mesh("fine")
+    c = fine.coords[fine.cells].mean(axis=1)
+    assert rg.coarsen(np.nonzero((np.hypot(c[:, 0], c[:, 1]) < 0.8) & (c[:, 1] > 0))[0]) == 4   # 48 -> 33
+    coarse = rg.mesh("coarsened")
+    L = 3
+    _note("transfer to coarsened", fine.n_cells, "->", coarse.n_cells, L)
+    hf, pf = oracle_hierarchy(fine, L)
+    hc, pc = oracle_hierarchy(coarse, L)
+    a = HHG(fine.coords, fine.cells, L, smoother="multicolour")
+    b = HHG(coarse.coords, coarse.cells, L, smoother="multicolour")
+    u = np.sin(3 * hf.levels[L].X[:, 0]) * np.cos(2 * hf.levels[L].X[:, 1])
+    ref = transfer.transfer(hf, u, hc.levels[L].X)
+    got = to_host(b.transfer_from(a, to_dev(u[pf[L]])))
+    assert np.all(np.isfinite(got))
+    assert np.abs(got - ref[pc[L]]).max() <= 1e-12

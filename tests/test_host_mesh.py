@@ -155,3 +155,34 @@ def test_error_ratio_and_mean_width():
                               np.zeros(32), None, 0, 0, 0, 0, 0))
     rho = kl.error_ratio(steps)
     assert abs(rho[0] - 1.0) < 1e-12 and abs(rho[1] - 0.5) < 1e-12 and abs(rho[2] - 0.5) < 1e-12
+
+
+def test_coarsening_round_trip_and_conformity():
+    # coarsening (future work in the conclusion): marking every cell after two kl-steps merges
+    # all red groups back to the coarse mesh; a partial marking leaves a conforming mesh of the
+    # same area with fewer cells; nothing marked changes nothing
+    m0 = meshes.lshape_24tri()
+    rg = M.RedGreen2D(m0)
+    cen = m0.coords[m0.cells].mean(axis=1)
+    rg.refine(M.mark_fraction(-np.hypot(cen[:, 0], cen[:, 1]), 0.25))
+    m1 = rg.mesh()
+    rg.refine(list(range(0, m1.n_cells, 3)))
+    m2 = rg.mesh()
+    _check_conforming(m2, 3.0)
+    assert rg.coarsen([]) == 0 and rg.mesh().n_cells == m2.n_cells
+    # partial: the cells away from the re-entrant corner
+    c2 = m2.coords[m2.cells].mean(axis=1)
+    far = np.nonzero(np.hypot(c2[:, 0], c2[:, 1]) > 0.6)[0]
+    n = rg.coarsen(far)
+    m3 = rg.mesh()
+    _check_conforming(m3, 3.0)
+    assert n > 0 and m0.n_cells < m3.n_cells < m2.n_cells
+    # everything: back to the coarse mesh
+    rg.coarsen(list(range(m3.n_cells)))
+    m4 = rg.mesh()
+    key = lambda m: sorted(tuple(sorted(map(tuple, np.round(m.coords[c], 12).tolist()))) for c in m.cells)
+    assert key(m4) == key(m0)
+    # and refining again reproduces the first step
+    c4 = m4.coords[m4.cells].mean(axis=1)
+    rg.refine(M.mark_fraction(-np.hypot(c4[:, 0], c4[:, 1]), 0.25))
+    assert key(rg.mesh()) == key(m1)
