@@ -340,20 +340,23 @@ __global__ void __launch_bounds__(256) k_gs3d_rows(LK lk, Tables tb, T* __restri
 // launch, out of place: reads u, writes the interior of uo.  One workgroup takes a tile of
 // kS3I x kS3J points in (i, j) and streams the planes k0 .. k1-1 of one macro.  Per plane p it
 // loads u on the tile plus a two-point halo into LDS, updates the red points of plane p-1 on the
-// tile plus a one-point halo from the old values (red values at halo points are recomputed
-// here, identically to the tile that owns them, since all inputs are old values), then the
-// black points of plane p-2 on the tile from the new red values, and writes both colours of
-// plane p-2.  Per point this moves u and b once in and u once out (plus the halos, mostly
-// served by L2).  Same updates, in the same order within each point, as the class-by-class
-// sweep: red (parity 0) first, then black; interface points are left to the interface sweep.
+// tile plus a one-point halo (in place in LDS: red points read only black neighbours, and the
+// black update reads only red ones), then the black points of plane p-2 on the tile, and writes
+// both colours of plane p-2.  Red values at halo points are recomputed here, identically to the
+// tile that owns them, since all their inputs are old values.  Per point this moves u and b once
+// in and u once out (plus the halos, mostly served by L2).  Same updates, in the same order
+// within each point, as the class-by-class sweep: red (parity 0) first, then black; interface
+// points are left to the interface sweep.  The parity alternates along i on every macro of a
+// level with streaming tiles, so every lane takes one (red, black) pair of neighbouring points
+// and no lane idles in either colour phase.
 template <typename T, bool FINE>
 __global__ void __launch_bounds__(256) k_gs3d_stream(LK lk, Tables tb, const T* __restrict__ u, T* __restrict__ uo,
                                                      const T* __restrict__ b, const int32_t* __restrict__ tiles,
                                                      int ntiles, double sA) {
-  constexpr int W = 64, H = kS3J + 4, NP = W * H / 256;
+  constexpr int W = 64, H = kS3J + 4, NP = W * H / 256, NS = 5;
+  constexpr int NQ = (H - 2) * (W / 2), RQ = (NQ + 255) / 256;   // point pairs of the halo rows
   static_assert(kS3I + 4 == W, "one wavefront per LDS row");
-  __shared__ T sU[3][H * W];
-  __shared__ T sR[3][H * W];
+  __shared__ T sU[NS][H * W];   // u of five planes; red points updated in place
   const int per_xcd = (int)(gridDim.x >> 3);   // gridDim.x is a multiple of 8
   const int blk = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
   if (blk >= lk.nmacro * ntiles) return;
@@ -371,130 +374,130 @@ __global__ void __launch_bounds__(256) k_gs3d_stream(LK lk, Tables tb, const T* 
   const double ks = sA * tb.kappa[m];
   const T diag = (T)(ks * Wt[0]);
   // all 14 neighbours are read and weighted, vanishing weights included: adding the exact zero
-  // products leaves every sum bitwise as it is, and unconditional LDS reads keep in flight
+  // products leaves every sum bitwise as it is, and unconditional LDS reads stay in flight
   T cq[15];
 #pragma unroll
   for (int q = 1; q < 15; ++q) cq[q] = (T)(ks * Wt[q]);
   const int* rp = tb.rbpar + m * 4;
   const int s1 = rp[1], s2 = rp[2], s3 = rp[3];
-  // a wavefront holds one LDS row (64 points along i) per step s: the row's j, its offset in a
-  // plane and the membership of the row in the halo regions are wave-uniform
-  const int lane = (int)(threadIdx.x & 63), w4 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int i = i0 - 2 + lane;
-  const bool lane1 = lane >= 1 && lane < W - 1, lane2 = lane >= 2 && lane < W - 2;
-  const int ipar = (i * s1) & 1;
+  const int tid = (int)threadIdx.x;
+  const int lane = tid & 63, w4 = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int dn = d_tet(n);
-  // offset of point (i, j, k) in the closure: plane(k) + rowin(j, k) + i
   auto plane = [&](int k) { return dn - d_tet(n - k); };
-  auto rowin = [&](int s, int k) {
-    const int j = j0 - 2 + w4 + 4 * s;
-    return j * (n - k + 1) - (j * (j - 1)) / 2;
+  auto rowin = [&](int j, int k) { return j * (n - k + 1) - (j * (j - 1)) / 2; };
+  auto slot = [](int k) { return (k + NS) % NS; };
+  auto inner = [&](int i, int j, int k) { return i >= 1 && j >= 1 && k >= 1 && i + j + k <= n - 1; };
+  auto col = [&](int i, int j, int k) { return (i * s1 + j * s2 + k * s3) & 1; };   // 0: red
+  auto stencil = [&](const T* Um, const T* U0, const T* Up, int idx) {
+    T nb[15];
+#pragma unroll
+    for (int c = 1; c < 15; ++c) {
+      const T* P = kOff3[c][2] < 0 ? Um : (kOff3[c][2] > 0 ? Up : U0);
+      nb[c] = P[idx + kOff3[c][1] * W + kOff3[c][0]];
+    }
+    T off = (T)0;
+#pragma unroll
+    for (int c = 1; c < 15; ++c) off += cq[c] * nb[c];
+    return off;
   };
-  auto slot = [](int k) { return (k + 3) % 3; };
-  // global loads run one plane ahead: u of plane p + 1 and b of plane p are in flight while
-  // plane p is processed (the barriers wait for LDS only).  Points outside the closure (or
-  // outside the interior, for b) load offset 0 and are then replaced by zero.
-  T ureg[NP], bnext[NP], bcur[NP], bprev[NP];
+  // pair slot t: LDS row jj = 1 + t / 32 (the rows of the one-point halo region) and columns
+  // (2 c, 2 c + 1), c = t % 32; the parity alternates along i, so one point of the pair is red
+  // and the other black.  The red phase takes the pairs' red points in the halo region
+  // (columns 1 .. W - 2), the black phase the pairs of the tile (rows 2 .. H - 3, c = 1 .. 30)
+  auto pair_pts = [&](int t, int q, int& jj, int& ir, int& ib) {
+    jj = 1 + (t >> 5);
+    const int c2 = 2 * (t & 31);
+    const int cl = col(i0 - 2 + c2, j0 - 2 + jj, q);
+    ir = c2 + cl;
+    ib = c2 + 1 - cl;
+  };
+  auto tile_pair = [&](int t) { const int jj = 1 + (t >> 5), c = t & 31; return jj >= 2 && jj < H - 2 && c >= 1 && c < W / 2 - 1; };
+  // global loads run ahead: u of plane p + 1, and b of plane p at both points of every pair,
+  // are in flight while plane p is processed (the barriers wait for LDS only); b of the red
+  // points is used one plane later, b of the black points two.  Points outside the closure (or
+  // outside the interior, for b) load offset 0 and are then replaced by zero
+  T ureg[NP], bR[RQ], bRn[RQ], bB[RQ], bB1[RQ], bBn[RQ];
+  auto ld = [&](const __amdgpu_buffer_rsrc_t& r, bool ok, int i, int j, int k) {
+    T v;
+    d_bload(r, ok ? (uint32_t)(plane(k) + rowin(j, k) + i) * (uint32_t)sizeof(T) : 0u, v);
+    return ok ? v : (T)0;
+  };
   auto load_u = [&](int p) {
-    const int pk = plane(p);
 #pragma unroll
     for (int s = 0; s < NP; ++s) {
-      const int j = j0 - 2 + w4 + 4 * s;
-      const bool ok = p >= 0 && i >= 0 && j >= 0 && i + j + p <= n;
-      T v;
-      d_bload(ru, ok ? (uint32_t)(pk + rowin(s, p) + i) * (uint32_t)sizeof(T) : 0u, v);
-      ureg[s] = ok ? v : (T)0;
+      const int i = i0 - 2 + lane, j = j0 - 2 + w4 + 4 * s;
+      ureg[s] = ld(ru, p >= 0 && i >= 0 && j >= 0 && i + j + p <= n, i, j, p);
     }
   };
-  auto load_b = [&](int q) {   // b at the interior points of the one-point halo region of plane q
-    const int pk = plane(q);
+  auto load_b = [&](int q) {
 #pragma unroll
-    for (int s = 0; s < NP; ++s) {
-      const int jj = w4 + 4 * s, j = j0 - 2 + jj;
-      const bool ok = jj >= 1 && jj < H - 1 && lane1 && i >= 1 && j >= 1 && q >= 1 && i + j + q <= n - 1;
-      T v;
-      d_bload(rb, ok ? (uint32_t)(pk + rowin(s, q) + i) * (uint32_t)sizeof(T) : 0u, v);
-      bnext[s] = ok ? v : (T)0;
+    for (int r = 0; r < RQ; ++r) {
+      const int t = tid + 256 * r;
+      int jj = 1, ir = 1, ib = 2;
+      if (t < NQ) pair_pts(t, q, jj, ir, ib);
+      const int j = j0 - 2 + jj;
+      const bool qr = t < NQ && q >= k0 - 1 && q <= k1 && ir >= 1 && ir < W - 1;
+      const bool qbk = t < NQ && q >= k0 && q < k1 && tile_pair(t);
+      bRn[r] = ld(rb, qr && inner(i0 - 2 + ir, j, q), i0 - 2 + ir, j, q);
+      bBn[r] = ld(rb, qbk && inner(i0 - 2 + ib, j, q), i0 - 2 + ib, j, q);
     }
   };
 #pragma unroll
-  for (int s = 0; s < NP; ++s) bnext[s] = bcur[s] = bprev[s] = (T)0;
+  for (int r = 0; r < RQ; ++r) bR[r] = bRn[r] = bB[r] = bB1[r] = bBn[r] = (T)0;
   load_u(k0 - 2);
   for (int p = k0 - 2; p <= k1 + 1; ++p) {
-    // u of plane p on the tile and its two-point halo
     {
       T* U = sU[slot(p)];
 #pragma unroll
       for (int s = 0; s < NP; ++s) U[(w4 + 4 * s) * W + lane] = ureg[s];
     }
     if (p + 1 <= k1 + 1) load_u(p + 1);
-    if (p >= k0 - 1 && p <= k1) load_b(p);
+    load_b(p);
     __syncthreads();
-    const int q = p - 1;   // red points of plane q on the tile and a one-point halo
+    const int q = p - 1;   // red points of plane q on the tile and the one-point halo, in place
     if (q >= k0 - 1 && q <= k1) {
       const T* Um = sU[slot(q - 1)];
-      const T* U0 = sU[slot(q)];
+      T* U0 = sU[slot(q)];
       const T* Up = sU[slot(q + 1)];
-      T* R = sR[slot(q)];
-      const int qpar = (q * s3) & 1;
 #pragma unroll
-      for (int s = 0; s < NP; ++s) {
-        const int jj = w4 + 4 * s;
-        if (jj < 1 || jj >= H - 1) continue;   // wave-uniform
-        const int j = j0 - 2 + jj;
-        const int idx = jj * W + lane;
-        if (!lane1) continue;
-        T r = U0[idx];
-        if (i >= 1 && j >= 1 && q >= 1 && i + j + q <= n - 1 && (ipar ^ ((j * s2) & 1) ^ qpar) == 0) {
-          T nb[15];
-#pragma unroll
-          for (int c = 1; c < 15; ++c) {
-            const T* P = kOff3[c][2] < 0 ? Um : (kOff3[c][2] > 0 ? Up : U0);
-            nb[c] = P[idx + kOff3[c][1] * W + kOff3[c][0]];
-          }
-          T off = (T)0;
-#pragma unroll
-          for (int c = 1; c < 15; ++c) off += cq[c] * nb[c];
-          r = (bcur[s] - off) / diag;
-        }
-        R[idx] = r;
+      for (int r = 0; r < RQ; ++r) {
+        const int t = tid + 256 * r;
+        if (t >= NQ) continue;
+        int jj, ir, ib;
+        pair_pts(t, q, jj, ir, ib);
+        if (ir < 1 || ir >= W - 1 || !inner(i0 - 2 + ir, j0 - 2 + jj, q)) continue;
+        const int idx = jj * W + ir;
+        const T off = stencil(Um, U0, Up, idx);
+        U0[idx] = (bR[r] - off) / diag;
       }
     }
     __syncthreads();
     const int qb = p - 2;   // black points of plane qb on the tile; both colours written
     if (qb >= k0 && qb < k1) {
-      const T* Rm = sR[slot(qb - 1)];
-      const T* R0 = sR[slot(qb)];
-      const T* Rp = sR[slot(qb + 1)];
+      const T* Rm = sU[slot(qb - 1)];
+      const T* R0 = sU[slot(qb)];
+      const T* Rp = sU[slot(qb + 1)];
       const int pk = plane(qb);
-      const int qpar = (qb * s3) & 1;
 #pragma unroll
-      for (int s = 0; s < NP; ++s) {
-        const int jj = w4 + 4 * s;
-        if (jj < 2 || jj >= H - 2) continue;   // wave-uniform
-        const int j = j0 - 2 + jj;
-        if (!lane2 || i + j + qb > n - 1) continue;   // i, j, qb >= 1 on the tile
-        const int idx = jj * W + lane;
-        T v = R0[idx];
-        if ((ipar ^ ((j * s2) & 1) ^ qpar) != 0) {
-          T nb[15];
-#pragma unroll
-          for (int c = 1; c < 15; ++c) {
-            const T* P = kOff3[c][2] < 0 ? Rm : (kOff3[c][2] > 0 ? Rp : R0);
-            nb[c] = P[idx + kOff3[c][1] * W + kOff3[c][0]];
-          }
-          T off = (T)0;
-#pragma unroll
-          for (int c = 1; c < 15; ++c) off += cq[c] * nb[c];
-          v = (bprev[s] - off) / diag;
+      for (int r = 0; r < RQ; ++r) {
+        const int t = tid + 256 * r;
+        if (t >= NQ || !tile_pair(t)) continue;
+        int jj, ir, ib;
+        pair_pts(t, qb, jj, ir, ib);
+        const int j = j0 - 2 + jj, gi = i0 - 2 + ib, gr = i0 - 2 + ir;
+        const int row = pk + rowin(j, qb);
+        if (inner(gi, j, qb)) {
+          const T off = stencil(Rm, R0, Rp, jj * W + ib);
+          d_bstore(ro, (uint32_t)(row + gi) * (uint32_t)sizeof(T), (bB[r] - off) / diag);
         }
-        d_bstore(ro, (uint32_t)(pk + rowin(s, qb) + i) * (uint32_t)sizeof(T), v);
+        if (inner(gr, j, qb)) d_bstore(ro, (uint32_t)(row + gr) * (uint32_t)sizeof(T), R0[jj * W + ir]);
       }
     }
 #pragma unroll
-    for (int s = 0; s < NP; ++s) {
-      bprev[s] = bcur[s];
-      bcur[s] = bnext[s];
+    for (int r = 0; r < RQ; ++r) {
+      bR[r] = bRn[r];
+      bB[r] = bB1[r];
+      bB1[r] = bBn[r];
     }
   }
 }

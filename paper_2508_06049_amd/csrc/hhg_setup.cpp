@@ -537,8 +537,11 @@ hhg_status build_colouring(hhg_ctx c) {
     // 3D red-black with a per-macro coefficient: plane-streaming tiles (i0, j0, k0 in units of
     // kS3I, kS3J, kS3K) of the levels with n >= kStream3dMinN, or of all levels with n >= 4
     // under HHG_FLAG_STREAM3D
+    // (red-black colour alternating along i on every macro: the kernel pairs neighbouring points)
+    bool alt_i = true;
+    for (int64_t m = 0; m < c->nC && d == 3; ++m) alt_i = alt_i && (c->rbpar[m * 4 + 1] & 1) != 0;
     const bool stream3d = d == 3 && lv.NI > 0 && c->opt.smoother == HHG_GS_REDBLACK &&
-                          c->opt.coefficient == HHG_KAPPA_MACRO &&
+                          c->opt.coefficient == HHG_KAPPA_MACRO && alt_i &&
                           (lv.n >= kStream3dMinN || (c->force_stream3d && lv.n >= 4));
     if (stream3d) {
       for (int tk = 0; 1 + tk * kS3K <= lv.n - 3; ++tk)
