@@ -99,9 +99,9 @@ typedef struct {
                                  interior sweep) on every level, not only from n = 128 on
                                  (same result; for checking them on small levels).
                                  HHG_FLAG_STREAM3D: with the red-black smoother and a per-macro
-                                 coefficient, use the plane-streaming 3D interior sweep (float32
-                                 sweeps) on every level with n >= 4, not only from n = 256 on
-                                 (same result; for checking it on small levels)               */
+                                 coefficient, use the plane-streaming 3D interior sweep on every
+                                 level with n >= 4, not only from n = 256 on (same result; for
+                                 checking it on small levels)                                 */
 } hhg_options;
 
 enum {

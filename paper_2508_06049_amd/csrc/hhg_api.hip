@@ -130,9 +130,7 @@ bool fused_available(hhg_ctx c, int l, size_t tsize) {
   const Level& lv = c->lev[l];
   if (p1(c) || lv.NI <= 0 || c->opt.smoother == HHG_JACOBI || c->no_fused) return false;
   if (c->dim == 2) return !lv.tiles.empty();
-  // the plane-streaming 3D sweep runs in float32; float64 sweeps stay class by class (with
-  // twice the LDS per tile the float64 form holds one workgroup per CU and was measured slower)
-  if (!lv.tiles.empty()) return tsize == 4;
+  if (!lv.tiles.empty()) return true;   // the plane-streaming 3D sweep
   return !lv.itab.empty() && (size_t)lv.Sraw * tsize <= 64 * 1024;
 }
 

@@ -2185,16 +2185,11 @@ bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* 
   }
   if (ntiles > 0) {
     // red-black with per-macro coefficient on a level with the plane-streaming tile table
-    // (float32 only: float64 sweeps of these levels go class by class)
-    if constexpr (sizeof(T) == 4) {
-      if (!rb) return false;
-      const unsigned g = (unsigned)(((int64_t)lk.nmacro * ntiles + 7) / 8 * 8);   // a multiple of 8 blocks (XCDs)
-      if (fine) k_gs3d_stream<T, true><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, sA);
-      else k_gs3d_stream<T, false><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, sA);
-      return true;
-    } else {
-      return false;
-    }
+    if (!rb) return false;
+    const unsigned g = (unsigned)(((int64_t)lk.nmacro * ntiles + 7) / 8 * 8);   // a multiple of 8 blocks (XCDs)
+    if (fine) k_gs3d_stream<T, true><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, sA);
+    else k_gs3d_stream<T, false><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, sA);
+    return true;
   }
   if (!itab || lk.n > kMacroLdsN) return false;
   const size_t shm = (size_t)lk.Sraw * sizeof(T);

@@ -717,8 +717,8 @@ void plan_workspace(hhg_ctx c) {
     lv.off_tseg = take((int64_t)lv.task_seg.size() * 4);
     lv.off_twmax = take((int64_t)lv.task_wmax.size() * 4);
     lv.off_twoff = take((int64_t)lv.task_woff.size() * 4);
-    // second iterate buffers of the out-of-place fused sweeps (2D; 3D streaming tiles: float32)
-    lv.off_x2 = take(d == 2 ? nf * 8 : 0);
+    // second iterate buffers of the out-of-place fused sweeps (2D, and 3D with streaming tiles)
+    lv.off_x2 = take(d == 2 || !lv.tiles.empty() ? nf * 8 : 0);
     lv.off_x2_32 = take(d == 2 || !lv.tiles.empty() ? nf * 4 : 0);
     lv.off_itab = take((int64_t)lv.itab.size() * 4);
     lv.off_itoff = take((int64_t)lv.itab_off.size() * 4);
