@@ -168,11 +168,11 @@ def test_3d_row_sweep_matches(name, smoother):
 
 @pytest.mark.parametrize("name,L", [("kuhn1", 5), ("kuhn2", 4), ("kuhn1", 6)])
 def test_3d_stream_sweep_matches(name, L):
-    # the plane-streaming red-black 3D sweep (both colours in one out-of-place float32 launch,
-    # used from n = 256 on; forced here from n = 4 on with HHG_FLAG_STREAM3D) runs in the
-    # float32 cycles of the float32-refined solve: bit for bit the same iterates as the
-    # class-by-class row sweep, over odd and even smoothing counts (odd counts leave the two
-    # iterate buffers exchanged), and the oracle's solution at convergence
+    # the plane-streaming red-black 3D sweep (both colours in one out-of-place launch, used
+    # from n = 256 on; forced here from n = 4 on with HHG_FLAG_STREAM3D): float64 sweeps and
+    # the float32-refined solve (float64 FMG, float32 cycles) give bit for bit the iterates of
+    # the class-by-class row sweep, over odd and even smoothing counts (odd counts leave the
+    # two iterate buffers exchanged), and the oracle's solution at convergence
     from paper_2508_06049_amd import HHG
     from paper_2508_06049_amd._lib import HHG_FLAG_NO_FUSED, HHG_FLAG_ROWS3D, HHG_FLAG_STREAM3D
     _note("3d stream sweep", name, L)
@@ -187,6 +187,13 @@ def test_3d_stream_sweep_matches(name, L):
     f = problems.fourier3d(X, problems.fourier_amplitudes(0))
     g = 0.1 * X[:, 0] - 0.2 * X[:, 2]
     fd, gd = to_dev(f[p]), to_dev(g[p])
+    rng = np.random.default_rng(14)
+    u0, b0 = to_dev(rng.standard_normal(len(X))[p]), to_dev(rng.standard_normal(len(X))[p])
+    for sweeps in (1, 2, 3):
+        a1, a2 = u0.clone(), u0.clone()
+        hs.smooth(L, a1, b0, sweeps)
+        hr.smooth(L, a2, b0, sweeps)
+        assert np.array_equal(to_host(a1), to_host(a2))
     for pre, post, iters in ((2, 2, 3), (1, 2, 2), (3, 1, 4)):
         us, ss = hs.fmg_solve(fd, gd, nu=1, pre=pre, post=post, precision="fp32_refined", rtol=1e-30, max_iter=iters)
         ur, sr = hr.fmg_solve(fd, gd, nu=1, pre=pre, post=post, precision="fp32_refined", rtol=1e-30, max_iter=iters)
