@@ -37,21 +37,27 @@ def _oracle(mesh, L, f, g, u, nu, smoother):
 
 CASES = {
     # Section 5.1: waves problem on the 32-triangle unit square, refinement by local errors
-    "waves": (meshes.unit_square_grid(4), problems.waves_f, problems.zero, problems.waves_u, "error"),
+    "waves": (meshes.unit_square_grid(4), problems.waves_f, problems.zero, problems.waves_u, "error", 4, 3),
     # Section 5.2: L-shape on 24 triangles, here driven by the estimator
-    "lshape24": (meshes.lshape_24tri(), problems.zero, problems.lshape_u, problems.lshape_u, "estimate"),
+    "lshape24": (meshes.lshape_24tri(), problems.zero, problems.lshape_u, problems.lshape_u, "estimate", 4, 3),
+    # tetrahedra: the corner singularity |x|^(1/4) on the 6-tetrahedron cube, by the estimator
+    # and (warm-started) by local errors
+    "corner3d": (meshes.kuhn_cube(1), problems.corner3d_f, problems.corner3d_u, problems.corner3d_u, "estimate", 3, 2),
+    "corner3d_err": (meshes.kuhn_cube(1), problems.corner3d_f, problems.corner3d_u, problems.corner3d_u, "error", 3, 2),
 }
 
 
-@pytest.mark.parametrize("name,warm", [("waves", False), ("lshape24", False), ("waves", True)])
+@pytest.mark.parametrize("name,warm", [("waves", False), ("lshape24", False), ("waves", True), ("corner3d", False),
+                                       ("corner3d_err", True)])
 def test_kl_loop_matches_oracle(name, warm):
     # warm: steps after the first start from the transferred solution of the previous step
     from paper_2508_06049_amd import kl
-    coarse, f, g, u, crit = CASES[name]
-    L, K, nu = 4, 3, 2
+    coarse, f, g, u, crit, L, K = CASES[name]
+    nu = 2
+    js = tuple(range(1, min(L, 4)))
     _note("kl loop", name, crit, L, K, "warm" if warm else "fmg")
     steps = kl.kl_refine(coarse, L, K, f, g, u, criterion=crit, nu=nu, rtol=1e-13, max_iter=200, tighten=0,
-                         warm=warm, estimate_js=(1, 2, 3))
+                         warm=warm, estimate_js=js)
     assert len(steps) == K + 1
     for s in steps:
         sq, sq0, eta_T, eta, scale = _oracle(s.mesh, L, f, g, u, nu, "multicolour")
@@ -63,8 +69,8 @@ def test_kl_loop_matches_oracle(name, warm):
             assert s.err_level0 is None and s.extra["transfer_s"] > 0 and not s.extra["eta"]
         else:
             assert abs(s.err_level0 - math.sqrt(sq0.sum())) <= tol
-            assert sorted(s.extra["eta"]) == [1, 2, 3]
-            for j in (1, 2, 3):
+            assert sorted(s.extra["eta"]) == list(js)
+            for j in js:
                 assert abs(s.extra["eta"][j] - eta[j]) <= tol
         if s.marked is None:
             continue

@@ -5,7 +5,7 @@ Every function takes an (N, dim) array of points and returns (N,) float64.  Thes
 *inputs*: they are evaluated at node coordinates by whoever needs nodal values.  The 2D
 functions of the convergence studies (sine, L-shape, waves, zero, one) also take a torch tensor
 of points and then evaluate where the tensor lives, so that nodal data of a large level is made
-on the device instead of on the host.
+on the device instead of on the host; so do the 3D corner problem's functions.
 """
 from __future__ import annotations
 
@@ -83,16 +83,16 @@ def fourier3d(x, amplitudes: np.ndarray, chunk: int = 1 << 20):
 
 # --- 3D corner singularity u = |x|^alpha ------------------------------------------------------
 def corner3d_u(x, alpha: float = 0.25):
-    r = np.linalg.norm(x, axis=1)
+    r = (x * x).sum(1) ** 0.5
     return r ** alpha
 
 
 def corner3d_f(x, alpha: float = 0.25):
     """-Laplace(r^alpha) = -alpha (alpha + 1) r^(alpha - 2) in 3D; the singular node gets 0."""
-    r = np.linalg.norm(x, axis=1)
-    with np.errstate(divide="ignore"):
-        v = -alpha * (alpha + 1.0) * np.where(r > 0.0, r, 1.0) ** (alpha - 2.0)
-    return np.where(r > 0.0, v, 0.0)
+    xp = _xp(x)
+    r = (x * x).sum(1) ** 0.5
+    v = -alpha * (alpha + 1.0) * xp.where(r > 0.0, r, 1.0) ** (alpha - 2.0)
+    return xp.where(r > 0.0, v, 0.0)
 
 
 # --- goal weight: Gaussian bump ---------------------------------------------------------------
