@@ -1279,9 +1279,10 @@ __global__ void __launch_bounds__(256) k_apply3d_rows(LK lk, Tables tb, const Ti
 }
 
 // 2D y = alpha b + beta (A_m x) with a per-macro coefficient in two wavefront roles of one
-// launch.  Interior role (wavefronts 0 .. nint-1): a 64-node segment of kApplyRows rows of one
-// macro, lanes along i, the macro's full stencil with weights computed once per wavefront,
-// every load of the rows issued before the arithmetic; nodes on the macro boundary are left
+// launch.  Interior role (wavefronts 0 .. nint-1): a 62-node segment of kApplyRows rows of one
+// macro, lanes along i, the macro's full stencil with weights computed once per wavefront;
+// each lane loads its column of the kApplyRows + 2 rows once, all before the arithmetic, and
+// takes the neighbours along i from the adjacent lanes; nodes on the macro boundary are left
 // to the other role.  Boundary role: one lane per boundary node (3n per macro: row j = 0,
 // column i = 0, the edge i + j = n) with its partial stencil.  x and y are accessed through
 // buffer descriptors bounded to the macro block.
@@ -1321,8 +1322,10 @@ __global__ void __launch_bounds__(256) k_apply2d_rows(LK lk, Tables tb, const Ti
   const int m = wid / (nrb * nseg);
   const int rem = wid - m * nrb * nseg;
   const int jb = rem / nseg, seg = rem - jb * nseg;
-  if (seg * 64 > n - jb * R) return;   // the segment starts beyond the first row's end
-  const int i = seg * 64 + lane;
+  if (seg * 62 > n - jb * R) return;   // the segment starts beyond the first row's end
+  // lanes 1 .. 62 own the points i = seg * 62 + lane - 1; lanes 0 and 63 only load the
+  // neighbours i - 1 and i + 1 of the end lanes, which reach them by full-wave lane shifts
+  const int i = seg * 62 + lane - 1;
   const int64_t base = (int64_t)m * lk.S;
   const __amdgpu_buffer_rsrc_t rx = d_rsrc(x + base, (uint32_t)lk.Sraw * (uint32_t)sizeof(Tin));
   const __amdgpu_buffer_rsrc_t ry = d_rsrc(y + base, (uint32_t)lk.Sraw * (uint32_t)sizeof(Tout));
@@ -1331,30 +1334,32 @@ __global__ void __launch_bounds__(256) k_apply2d_rows(LK lk, Tables tb, const Ti
   Tin w[7];
 #pragma unroll
   for (int d = 0; d < 7; ++d) w[d] = (Tin)(sc * Wt[d]);
-  Tin xv[R][7], bv[R];
-  int ctr[R];
-  bool ok[R];
+  // rows jb R - 1 .. jb R + R of x at column i (zero outside the closure)
+  Tin xr[R + 2];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int j = jb * R + r;
-    const int rowlen = n + 1 - j;
-    ok[r] = j >= 1 && i >= 1 && i + j <= n - 1;
-    const int ro = d_lin2(n, 0, j), rup = ro + rowlen, rdn = ro - rowlen - 1;
-    const int od[7] = {ro + i, ro + i + 1, rup + i, rup + i - 1, ro + i - 1, rdn + i, rdn + i + 1};
-#pragma unroll
-    for (int d = 0; d < 7; ++d) d_bload(rx, ok[r] ? (uint32_t)od[d] * (uint32_t)sizeof(Tin) : 0u, xv[r][d]);
-    ctr[r] = ok[r] ? od[0] : 0;
-    bv[r] = (b && ok[r]) ? b[base + od[0]] : (Tin)0;
+  for (int q = 0; q < R + 2; ++q) {
+    const int j = jb * R - 1 + q;
+    const bool in = j >= 0 && j <= n && i >= 0 && i <= n - j;
+    Tin v;
+    d_bload(rx, in ? (uint32_t)(d_lin2(n, 0, j) + i) * (uint32_t)sizeof(Tin) : 0u, v);
+    xr[q] = in ? v : (Tin)0;
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    if (!ok[r]) continue;
+    const int j = jb * R + r;
+    const Tin xc = xr[r + 1], xu = xr[r + 2], xd = xr[r];
+    // neighbours in the order of the stencil directions (i+1,j) (i,j+1) (i-1,j+1) (i-1,j)
+    // (i,j-1) (i+1,j-1); the shifts run on every lane
+    const Tin nb[7] = {xc, from_next(xc), xu, from_prev(xu), from_prev(xc), xd, from_next(xd)};
+    const bool ok = lane >= 1 && lane <= 62 && j >= 1 && i >= 1 && i + j <= n - 1;
+    if (!ok) continue;
+    const int ctr = d_lin2(n, 0, j) + i;
     Tin off = (Tin)0;
 #pragma unroll
-    for (int d = 1; d < 7; ++d) off += w[d] * xv[r][d];
-    Tin v = (Tin)beta * (off + w[0] * xv[r][0]);
-    if (b) v += (Tin)alpha * bv[r];
-    d_bstore(ry, (uint32_t)ctr[r] * (uint32_t)sizeof(Tout), (Tout)v);
+    for (int d = 1; d < 7; ++d) off += w[d] * nb[d];
+    Tin v = (Tin)beta * (off + w[0] * nb[0]);
+    if (b) v += (Tin)alpha * b[base + ctr];
+    d_bstore(ry, (uint32_t)ctr * (uint32_t)sizeof(Tout), (Tout)v);
   }
 }
 
@@ -2277,7 +2282,7 @@ template <typename Tin, typename Tout>
 void launch_apply(int dim, bool p1, const LK& lk, const Tables& tb, const Tin* x, const Tin* b, Tout* y, int op,
                   double scale, double alpha, double beta, int zero_dir, const double* kn, hipStream_t st) {
   if (dim == 2 && !(p1 && op == 0)) {
-    const int nseg = (lk.n + 1 + 63) / 64, nrb = (lk.n + 1 + kApplyRows - 1) / kApplyRows;
+    const int nseg = (lk.n + 1 + 61) / 62, nrb = (lk.n + 1 + kApplyRows - 1) / kApplyRows;
     const int nint = lk.nmacro * nrb * nseg;
     const int nbnd = (int)(((int64_t)lk.nmacro * 3 * lk.n + 63) / 64);
     const unsigned gw = (unsigned)(((int64_t)nint + nbnd + 3) / 4);
