@@ -1257,7 +1257,31 @@ __global__ void __launch_bounds__(256) k_apply3d_rows(LK lk, Tables tb, const Ti
   const int len = n - j - k;   // points i = 0 .. len
   const uint32_t dirb = tb.dirbits[m];
   const int lane = (int)(threadIdx.x & 63);
-  for (int i = lane; i <= len; i += 64) {
+  // chunks of 62 points: lane l owns i = 62 c + l - 1 (lanes 1 .. 62); the 14 neighbours of an
+  // inner point lie in 7 rows, each loaded once per lane, the i +- 1 ones reached by full-wave
+  // lane shifts (lanes 0 and 63 only load)
+  const int nchunk = (len + 1 + 61) / 62;
+  for (int c = 0; c < nchunk; ++c) {
+    const int i = 62 * c + lane - 1;
+    Tin v0 = (Tin)0, v2 = (Tin)0, v3 = (Tin)0, v6 = (Tin)0, v9 = (Tin)0, v10 = (Tin)0, v13 = (Tin)0;
+    if (inner_row) {
+      // row (j + dj, k + dk) holds i = 0 .. n - j - dj - k - dk
+      auto ld = [&](int q, int dj, int dk) {
+        const int ii = i - kOff3[q][0];
+        return (ii >= 0 && ii <= n - j - dj - k - dk) ? x[ro[q] + i] : (Tin)0;
+      };
+      v0 = ld(0, 0, 0);
+      v2 = ld(2, 1, 0);
+      v3 = ld(3, 0, 1);
+      v6 = ld(6, -1, 1);
+      v9 = ld(9, -1, 0);
+      v10 = ld(10, 0, -1);
+      v13 = ld(13, 1, -1);
+    }
+    // neighbours by direction (kOff3 order): shifts run on every lane
+    const Tin nb[15] = {v0, from_next(v0), v2, v3, from_prev(v2), from_prev(v3), v6, from_next(v6),
+                        from_prev(v0), v9, v10, from_next(v9), from_next(v10), v13, from_prev(v13)};
+    if (lane < 1 || lane > 62 || i > len) continue;
     const int mask = d_mask<3>(n, i, j, k);
     const int64_t ctr = r0 + i;
     if (zero_dir && ((dirb >> mask) & 1)) { y[ctr] = (Tout)0; continue; }
@@ -1265,7 +1289,7 @@ __global__ void __launch_bounds__(256) k_apply3d_rows(LK lk, Tables tb, const Ti
     if (mask == 0) {
       Tin acc = (Tin)0;
 #pragma unroll
-      for (int q = 1; q < 15; ++q) acc += cq[q] * x[ro[q] + i];
+      for (int q = 1; q < 15; ++q) acc += cq[q] * nb[q];
       off = acc;
       diag = cq[0];
     } else {
