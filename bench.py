@@ -16,7 +16,8 @@ roofline entry uses the finest-level interior smoother kernel (float32), timed p
 with HIP events on the library's stream.
 
 cpu_baseline: the CPU oracle (assembled sparse matrices, same FMG, same colouring and
-smoother, same tolerance) on the same mesh at L = 7 (1.18 M DoFs), repeated for >= 10 s.
+smoother) on the same mesh at L = 7, solved to its own fixed error at that level, on one host
+core and on every host core at once (one process each), before the GPU is touched.
 """
 from __future__ import annotations
 
@@ -82,27 +83,129 @@ def timed_steps(hh, f, g, w, precision, rtol, steps, warmup):
     return (t1 - t0) * 1e3 / steps, st, est
 
 
-def cpu_baseline(w, rtol, min_seconds=10.0, L=7):
-    """The oracle, as it stands, on the same macro mesh at a smaller level."""
-    import numpy as np
+def _oracle_solver(w, L):
     from oracle import fmg, refine
     h = refine.Hierarchy(w.mesh.coords, w.mesh.cells, L)
     S = fmg.FMGSolver(h, smoother=w.smoother, nu1=w.pre, nu2=w.post)
     X = h.levels[L].X
-    b = S.rhs_levels(w.f(X))
-    g = w.g(X)
+    return h, S, S.rhs_levels(w.f(X)), w.g(X), X
+
+
+def _oracle_timed(S, b, g, L, nu, rtol, seconds):
     reps, t = 0, 0.0
-    while t < min_seconds:
+    while t < seconds:
         t0 = time.perf_counter()
-        u, _ = S.fmg(b, g, nu=w.nu)
+        u, _ = S.fmg(b, g, nu=nu)
         S.extra_cycles(u, b[L], g, rtol=rtol, max_iter=100)
         t += time.perf_counter() - t0
         reps += 1
+    return reps, t
+
+
+def _oracle_worker(args):
+    """One host core: set up the oracle and time solves for `seconds` (spawned process)."""
+    cfg, L_, rtol, seconds = args
+    from paper_2508_06049_amd import configs
+    w = configs.config(cfg)
+    h, S, b, g, _ = _oracle_solver(w, L_)
+    reps, t = _oracle_timed(S, b, g, L_, w.nu, rtol, seconds)
+    return h.levels[L_].n * reps, t
+
+
+def host_cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    # at most 16 workers: the host share of one GPU on the measurement machines
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(w, cfg, L=7, seconds=8.0):
+    """The oracle, as it stands, on the same macro mesh at L = 7: its own fixed error (the
+    converged float64 discretisation error at that level, against the exact solution when one
+    is known), the loosest residual tolerance of the ladder within 1 % of it, then solves to
+    that tolerance timed on one core (median of 3 runs of `seconds` each) and on every host
+    core at once (one process per core, each solving the same problem).  Assembly excluded.
+    Must run before this process touches the GPU (its workers are spawned processes)."""
+    import multiprocessing as mp
+    import numpy as np
+    t_setup = time.perf_counter()
+    h, S, b, g, X = _oracle_solver(w, L)
+    t_setup = time.perf_counter() - t_setup
+    M = S.sys[L].M
+    ud = S.direct(L, b[L], g)
+    uex = w.u_exact(X) if w.u_exact is not None else ud
+    err = lambda u: float(np.sqrt((uex - u) @ (M @ (uex - u))))
+    e_ref = err(ud)
+    # without an exact solution the reference is the discrete solution itself (e_ref = 0) and
+    # the ladder's last tolerance is taken, as on the GPU
+    rtol = 1e-12
+    for rt in (1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 3e-9, 1e-9, 3e-10, 1e-10, 3e-11, 1e-11, 1e-12):
+        u, _ = S.fmg(b, g, nu=w.nu)
+        S.extra_cycles(u, b[L], g, rtol=rt, max_iter=100)
+        if err(u) <= 1.01 * e_ref:
+            rtol = rt
+            break
     n = h.levels[L].n
-    return dict(value=n * reps / t, unit="DoF/s", cores=1, kind="oracle",
-                sample=f"{w.name} macro mesh at L={L} ({n} DoFs), float64 FMG nu={w.nu} V({w.pre},{w.post}) "
-                       f"{w.smoother} + cycles to rel. residual {rtol:g}, {reps} solves in {t:.1f} s "
-                       f"(assembly excluded; scipy sparse, single thread)")
+    one = []
+    for _ in range(3):
+        reps, t = _oracle_timed(S, b, g, L, w.nu, rtol, seconds / 3)
+        one.append(n * reps / t)
+    v1 = float(np.median(one))
+    del S, h
+    cores = host_cores()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(cfg, L, rtol, seconds)] * cores)
+    vN = sum(d / t for d, t in res)
+    return dict(value=vN, unit="DoF/s", cores=cores, kind="oracle", cpu_model=host_cpu_model(),
+                single_core=dict(value=v1, cores=1, median_of=3),
+                sample=f"{w.name} macro mesh at L={L} ({n} DoFs): float64 FMG nu={w.nu} V({w.pre},{w.post}) "
+                       f"{w.smoother} + cycles to rel. residual {rtol:g}, the loosest whose L2 error is within 1 % of "
+                       f"the converged one at L={L} ({e_ref:.4e}); one core: median of 3; all cores: {cores} "
+                       f"processes, each timing its own solves for {seconds:g} s; assembly ({t_setup:.1f} s) excluded; "
+                       f"scipy sparse, one thread per process")
+
+
+def step_algorithmic_bytes(ndofs, dim, nu, pre, post, fmg_cycles, extra_cycles, precision):
+    """Bytes the method must move per step (one FMG solve with its extra cycles, the right-hand
+    sides and the estimate) with every kernel at its ideal traffic: a smoother sweep moves
+    3 s bytes per DoF (s = 8 float64, 4 float32), a residual fused with the restriction
+    2 s + s/2^d, a prolongation-add 2 s + s/2^d, the FMG prolongation with the w store
+    16 + 8/2^d, the float32-refined fine residual and update 20 each, the estimate
+    16 + 8/2^d, a right-hand side b_l = M_l f_l 16 per DoF of its level, the canonical-order
+    conversion of f, g and u 16 per level-L DoF each.  ndofs[l]: DoFs of level l."""
+    c = 1.0 / 2 ** dim
+
+    def vcyc(l, s):
+        tot = 0.0
+        for k in range(l, 0, -1):
+            tot += ndofs[k] * ((pre + post) * 3 * s + 2 * (2 * s + s * c))
+        return tot
+
+    def cyc(l):
+        if precision == "fp64":
+            return vcyc(l, 8)
+        return ndofs[l] * 40 + vcyc(l, 4)
+
+    L = len(ndofs) - 1
+    b = sum(16.0 * n for n in ndofs) + 3 * 16.0 * ndofs[L]
+    for l in range(1, L + 1):
+        b += ndofs[l] * (16 + 8 * c) + nu * cyc(l)
+    norm = 32.0 if precision == "fp64" else 4.0
+    b += extra_cycles * (cyc(L) + norm * ndofs[L])
+    b += ndofs[L] * (16 + 8 * c)
+    return b
 
 
 # convergence studies of Section 5 (coarse mesh, f, g, u, criterion): the waves problem on the
@@ -240,10 +343,23 @@ def main():
         run_kl_study(args) if args.kl_study else run_kl(args)
         return
 
+    from paper_2508_06049_amd import configs
+    cpu = None
+    if not args.no_cpu_baseline and not args.kernel_only:
+        # the oracle runs first: its worker processes start before this process touches the GPU
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(configs.config(args.config), args.config)
+        log(f"cpu baseline: {cpu['value']:.3e} DoF/s on {cpu['cores']} cores, "
+            f"{cpu['single_core']['value']:.3e} DoF/s on one ({cpu['cpu_model']})")
+
     import numpy as np
     import torch
-    from paper_2508_06049_amd import HHG, configs
+    from paper_2508_06049_amd import HHG
 
+    if args.config == 3:
+        print("bench.py: workload 3 needs the nodal-coefficient path, which is switched off in this build "
+              "(a parity run of it ended in a GPU memory fault whose cause was not found)", file=sys.stderr)
+        sys.exit(2)
     w = configs.config(args.config, args.L)
     log(f"workload {w.name}: {w.mesh.n_cells} macros, L={w.L}, smoother {w.smoother}")
     hh = HHG(w.mesh.coords, w.mesh.cells, w.L, smoother=w.smoother, coefficient=w.coefficient,
@@ -316,6 +432,18 @@ def main():
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=TRAFFIC_BYTES.get((w.name, w.L, kname)),
                 kernel=kname, bytes_per_launch=k["launch_bytes"], avg_launch_us=round(k["launch_ms"] * 1e3, 2))
 
+    # the whole finest-level sweep (interior and interface) and the whole step against the same
+    # peak: algorithmic bytes over measured time
+    roof["sweep_frac"] = round(sm["fp32_refined"]["gbs"] / HBM_PEAK_GBS, 4)
+    nd = [hh.num_dofs(l) for l in range(w.L + 1)]
+    for prec in ("fp64", "fp32_refined"):
+        r = res[prec]
+        extra = r["vcycles"] - w.nu * w.L
+        sb = step_algorithmic_bytes(nd, w.mesh.dim, w.nu, w.pre, w.post, w.nu * w.L, extra, prec)
+        r["step_algorithmic_bytes"] = sb
+        r["step_frac"] = round(sb / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    roof["step_frac"] = res["fp32_refined"]["step_frac"]
+
     ms = res["fp32_refined"]["ms"]
     out = {
         "metric": "FMG DoF/s + smoother HBM GB/s at fixed L2 error; FP32-refined vs FP64",
@@ -339,9 +467,8 @@ def main():
         "smoother_dof_updates_per_s": {p: float(f"{v['dof_updates_per_s']:.4e}") for p, v in sm.items()},
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(w, res["fp64"]["rtol"])
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

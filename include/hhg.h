@@ -80,7 +80,9 @@ typedef struct {
 typedef struct {
   int coefficient;            /* HHG_KAPPA_MACRO: kappa constant per macro element;
                                  HHG_KAPPA_P1: nodal coefficient set by hhg_set_kappa_nodal,
-                                 averaged over the vertices of every micro element            */
+                                 averaged over the vertices of every micro element.  The
+                                 nodal-coefficient path is switched off in this build:
+                                 hhg_setup returns HHG_EINVAL for HHG_KAPPA_P1.               */
   int smoother;               /* HHG_GS_REDBLACK | HHG_GS_MULTICOLOR | HHG_JACOBI              */
   double jacobi_omega;        /* damping of the Jacobi smoother (0 selects 2/3)                */
   int flags;                  /* HHG_FLAG_NO_FUSED: sweep macro interiors one colour class per
@@ -101,7 +103,10 @@ typedef struct {
                                  HHG_FLAG_STREAM3D: with the red-black smoother and a per-macro
                                  coefficient, use the plane-streaming 3D interior sweep on every
                                  level with n >= 4, not only from n = 256 on (same result; for
-                                 checking it on small levels)                                 */
+                                 checking it on small levels).
+                                 HHG_FLAG_GENERIC_EST: compute the 2D L2 estimate with the
+                                 one-thread-per-node kernel instead of the row kernel (same
+                                 result up to rounding; for checking the row kernel)          */
 } hhg_options;
 
 enum {
@@ -110,7 +115,8 @@ enum {
   HHG_FLAG_NO_GRAPH = 4,
   HHG_FLAG_NO_PRELOAD = 8,
   HHG_FLAG_ROWS3D = 16,
-  HHG_FLAG_STREAM3D = 32
+  HHG_FLAG_STREAM3D = 32,
+  HHG_FLAG_GENERIC_EST = 64
 };
 
 typedef struct {
@@ -150,8 +156,9 @@ hhg_status hhg_dof_coords(hhg_ctx ctx, int level, double* device_xyz);
 /* Replace the per-macro coefficients (host, n_cells values > 0); refactors level 0. */
 hhg_status hhg_set_kappa_cell(hhg_ctx ctx, const double* host_kappa);
 
-/* Nodal coefficient on level L (device, canonical order, values > 0); HHG_KAPPA_P1 only.
- * Coarser levels use its values at their nodes. */
+/* Nodal coefficient on level L (device, canonical order, values > 0); HHG_KAPPA_P1 only
+ * (switched off in this build: no context with HHG_KAPPA_P1 can be set up, so every call
+ * returns HHG_ESTATE).  Coarser levels use its values at their nodes. */
 hhg_status hhg_set_kappa_nodal(hhg_ctx ctx, const double* device_kappa);
 
 /* Full multigrid solve of A_L u = b_L (equation of the per-level linear system, Section 4.4)
@@ -220,7 +227,11 @@ hhg_status hhg_macro_norms(hhg_ctx ctx, const double* x, int level, int norm, do
  * last hhg_fmg_solve intact (hhg_estimate may still follow). */
 hhg_status hhg_apply(hhg_ctx ctx, int level, int op, const double* x, double* y);
 
-/* y = M_L x (mass matrix on level L), device vectors; used for L2 goal functionals. */
+/* y = M_L x with the consistent mass matrix M_L of level L (the matrix of the L2 norm the
+ * estimate is taken in, Section 4.4: entries |t|/((d+1)(d+2)) (1 + delta_ij) summed over the
+ * micro elements t), full rows including Dirichlet DoFs; x, y device vectors in canonical
+ * order of level L (length hhg_num_dofs(L)), owned by the caller.  HHG_EINVAL for NULL
+ * vectors, HHG_ESTATE without a workspace.  Used for L2 goal functionals and norms. */
 hhg_status hhg_mass_apply(hhg_ctx ctx, const double* x, double* y);
 
 /* Smoother sweeps on one level: u (device, in/out) <- `sweeps` sweeps for A u = b with the

@@ -19,9 +19,11 @@ Parity status per function (what pins it is listed in the tests):
                 row sums, Galerkin orthogonality of the energy estimate
   adjoint.*     pinned: duality J = g^T u = lambda^T b, finite differences
   transfer.*    pinned: affine functions exact, nested transfer equals the prolongation
-  The float32-refined form of the solve has no oracle function: the library's result is
-  compared with the float64 direct solution it converges to (its fixed point); the float32
-  V-cycle inside it is parity unpinned.
+  fmg.refined_cycle / vcycle_lowp (the float32-refined form: float64 residual, float32
+                V-cycle on the correction, float64 update) pinned: equals the float64 cycle
+                to round-off when run in float64; its float32 correction is the float64 one
+                within float32 rounding; its fixed point is the direct solve; it contracts
+                like the float64 cycle
 """
 from .refine import Hierarchy, build_hierarchy
 from . import assemble, colour, fmg, estimate, adjoint, transfer

@@ -13,6 +13,15 @@ Structure (float64 throughout):
   it changes nothing when g is piecewise linear on the boundary.
 * optional extra V-cycles on level L (Section 5 runs extra cycles after FMG until the error
   stops changing; the coarse solutions w are not touched by them).
+* reduced-precision cycle (the float32-refined form): the residual r = b - A u is formed in
+  float64 and rounded to the working precision, a V-cycle on the correction equation A e = r
+  runs from e = 0 entirely in that precision (operator, smoother, transfers rounded to it),
+  except level 0, whose exact solve is float64 and rounded afterwards; then u += e in
+  float64.  u, w, the FMG prolongation and the level-0 solve of the FMG pass stay float64,
+  because the estimator differences u_L - w_l are of the size of the algebraic error the
+  remark on algebraic errors in Section 4.2 warns about.  With float64 as the working
+  precision the cycle is the correction form of the float64 V-cycle (equal up to round-off,
+  multigrid being affine).
 """
 from __future__ import annotations
 
@@ -44,6 +53,16 @@ class LevelSystem:
         self.classes = colour.classes(self.col)
         self.rows = [self.A[c] for c in self.classes]
         self.P = assemble.prolongation(h, l) if l < h.L else None
+        self._lowp = {}
+
+    def lowp(self, dtype):
+        """Operator, smoother rows, diagonal and prolongation rounded to ``dtype``."""
+        dt = np.dtype(dtype)
+        if dt not in self._lowp:
+            self._lowp[dt] = dict(
+                A=self.A.astype(dt), rows=[R.astype(dt) for R in self.rows], diag=self.diag.astype(dt),
+                P=None if self.P is None else self.P.astype(dt), PT=None if self.P is None else self.P.T.tocsr().astype(dt))
+        return self._lowp[dt]
 
 
 class FMGSolver:
@@ -106,6 +125,60 @@ class FMGSolver:
         u[s.inner] += corr[s.inner]
         self.smooth(l, u, b, self.nu2)
 
+    # --- reduced-precision correction cycle (float32-refined form) ---------------------------
+    def smooth_lowp(self, l, e, r, sweeps, dtype):
+        s = self.sys[l]
+        q = s.lowp(dtype)
+        om = np.asarray(self.omega, dtype=dtype)
+        for _ in range(sweeps):
+            if self.smoother == "jacobi":
+                res = r - q["A"] @ e
+                e[s.inner] += om * res[s.inner] / q["diag"][s.inner]
+            else:
+                for idx, R in zip(s.classes, q["rows"]):
+                    e[idx] += (r[idx] - R @ e) / q["diag"][idx]
+
+    def vcycle_lowp(self, l, e, r, dtype):
+        """V(nu1, nu2) cycle for A_l e = r from e = 0 with every vector and operator in
+        ``dtype``; level 0 is the float64 exact solve of the rounded right-hand side, rounded
+        back."""
+        dt = np.dtype(dtype)
+        if l == 0:
+            # reached from the cycle above with e = 0 (zero on Dirichlet nodes as well)
+            I = self.sys[0].inner
+            if I.size:
+                e[I] = sla.cho_solve(self.coarse_factor, r[I].astype(np.float64)).astype(dt)
+            return
+        s, sc = self.sys[l], self.sys[l - 1]
+        q, qc = s.lowp(dt), sc.lowp(dt)
+        self.smooth_lowp(l, e, r, self.nu1, dt)
+        res = r - q["A"] @ e
+        res[s.bnd] = 0
+        rc = qc["PT"] @ res
+        rc[sc.bnd] = 0
+        ec = np.zeros(sc.N, dtype=dt)
+        self.vcycle_lowp(l - 1, ec, rc, dt)
+        corr = qc["P"] @ ec
+        e[s.inner] += corr[s.inner]
+        self.smooth_lowp(l, e, r, self.nu2, dt)
+
+    def refined_cycle(self, l, u, b, dtype=np.float32):
+        """One step of the refinement loop: float64 residual rounded to ``dtype``, a ``dtype``
+        V-cycle on the correction from zero, float64 update u += e."""
+        dt = np.dtype(dtype)
+        r = self.residual(l, u, b).astype(dt)
+        e = np.zeros(self.sys[l].N, dtype=dt)
+        self.vcycle_lowp(l, e, r, dt)
+        u += e.astype(np.float64)
+
+    def _cycle(self, l, u, b, precision):
+        if precision == "fp64":
+            self.vcycle(l, u, b)
+        elif precision == "fp32_refined":
+            self.refined_cycle(l, u, b, np.float32)
+        else:
+            raise ValueError(f"unknown precision {precision!r}")
+
     # --- right-hand sides --------------------------------------------------------------------
     def rhs_levels(self, f_fine):
         """b_l = M_l f_l with f_l the nodal values on level l (nested numbering: the first N_l
@@ -124,7 +197,9 @@ class FMGSolver:
         return bs
 
     # --- FMG ------------------------------------------------------------------------------
-    def fmg(self, b_levels, g_fine, nu=1):
+    def fmg(self, b_levels, g_fine, nu=1, precision="fp64"):
+        """precision "fp32_refined": every V-cycle of the pass is a refined_cycle in float32;
+        the level-0 solve, the prolongations, u and w stay float64."""
         g_fine = np.asarray(g_fine)
         s0 = self.sys[0]
         u = np.where(s0.bnd, g_fine[:s0.N], 0.0)
@@ -137,7 +212,7 @@ class FMGSolver:
             u = v
             u[s.bnd] = g_fine[:s.N][s.bnd]
             for _ in range(nu):
-                self.vcycle(l, u, b_levels[l])
+                self._cycle(l, u, b_levels[l], precision)
         return u, w
 
     def ref_residual(self, b, g_fine):
@@ -145,13 +220,14 @@ class FMGSolver:
         u0 = np.where(sL.bnd, np.asarray(g_fine)[:sL.N], 0.0)
         return float(np.linalg.norm(self.residual(self.L, u0, b)))
 
-    def extra_cycles(self, u, b, g_fine, rtol=0.0, max_iter=0):
-        """Further V-cycles on level L until ||r|| <= rtol * ||r(u = g on boundary, 0 inside)||."""
+    def extra_cycles(self, u, b, g_fine, rtol=0.0, max_iter=0, precision="fp64"):
+        """Further V-cycles on level L until ||r|| <= rtol * ||r(u = g on boundary, 0 inside)||
+        (precision "fp32_refined": refinement steps with a float32 cycle)."""
         r0 = self.ref_residual(b, g_fine)
         it = 0
         rel = float(np.linalg.norm(self.residual(self.L, u, b))) / r0 if r0 > 0 else 0.0
         while it < max_iter and rel > rtol:
-            self.vcycle(self.L, u, b)
+            self._cycle(self.L, u, b, precision)
             it += 1
             rel = float(np.linalg.norm(self.residual(self.L, u, b))) / r0 if r0 > 0 else 0.0
         return it, rel

@@ -31,6 +31,7 @@ HHG_FLAG_NO_GRAPH = 4
 HHG_FLAG_NO_PRELOAD = 8
 HHG_FLAG_ROWS3D = 16
 HHG_FLAG_STREAM3D = 32
+HHG_FLAG_GENERIC_EST = 64
 
 SMOOTHERS = {"redblack": HHG_GS_REDBLACK, "multicolour": HHG_GS_MULTICOLOR, "jacobi": HHG_JACOBI}
 PRECISIONS = {"fp64": HHG_FP64, "fp32_refined": HHG_FP32_REFINED}
@@ -119,7 +120,7 @@ class HHGError(RuntimeError):
 def _check(status: int, ctx=None):
     if status != HHG_OK:
         lib = load()
-        msg = lib.hhg_last_error(ctx).decode() if True else ""
+        msg = lib.hhg_last_error(ctx).decode()
         raise HHGError(status, msg or lib.hhg_status_string(status).decode())
 
 

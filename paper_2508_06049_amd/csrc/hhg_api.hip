@@ -466,7 +466,7 @@ hhg_status estimate_pair(hhg_ctx c, int norm, const double* a, const double* bc,
   const int L = c->L;
   double* out = c->d_red + (c->red_capacity - 2 * c->nC - 8);
   launch_estimate(c->dim, norm, lk_of(c, L), lk_of(c, L - 1), c->tab, u ? u : c->lev[L].x, a, bc, c->d_red, out,
-                  norm == HHG_NORM_ENERGY ? sA(c, L) : sM(c, L), ST(c));
+                  norm == HHG_NORM_ENERGY ? sA(c, L) : sM(c, L), !c->generic_est, ST(c));
   LAUNCHCHK();
   std::vector<double> h(2 * c->nC);
   HIPCHK(hipMemcpyAsync(h.data(), out, h.size() * 8, hipMemcpyDeviceToHost, ST(c)));
@@ -509,6 +509,12 @@ hhg_status hhg_setup(const hhg_mesh* mesh, int L, const hhg_options* opt, hhg_ct
     g_err = "invalid options";
     return HHG_EINVAL;
   }
+  // The nodal-coefficient path is switched off: a parity run of it ended in a GPU memory
+  // fault whose cause was not found, so it is not offered until one is shown and fixed.
+  if (opt->coefficient == HHG_KAPPA_P1) {
+    g_err = "HHG_KAPPA_P1 (nodal coefficient) is switched off in this build";
+    return HHG_EINVAL;
+  }
   hhg_ctx c = new (std::nothrow) hhg_ctx_s();
   if (!c) { g_err = "out of host memory"; return HHG_ENOMEM; }
   c->dim = mesh->dim;
@@ -520,6 +526,7 @@ hhg_status hhg_setup(const hhg_mesh* mesh, int L, const hhg_options* opt, hhg_ct
   c->no_preload = (opt->flags & HHG_FLAG_NO_PRELOAD) != 0;
   c->force_rows3d = (opt->flags & HHG_FLAG_ROWS3D) != 0;
   c->force_stream3d = (opt->flags & HHG_FLAG_STREAM3D) != 0;
+  c->generic_est = (opt->flags & HHG_FLAG_GENERIC_EST) != 0;
   c->nV = mesh->n_vertices;
   c->nC = mesh->n_cells;
   const int nv = c->dim + 1;

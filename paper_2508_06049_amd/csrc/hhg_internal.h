@@ -204,6 +204,7 @@ struct hhg_ctx_s {
   bool no_preload = false;          // single-workgroup interface sweep without preloading (testing)
   bool force_rows3d = false;        // 3D row kernels at every level (testing)
   bool force_stream3d = false;      // 3D plane-streaming sweep from n = 4 on (testing)
+  bool generic_est = false;         // 2D L2 estimate by the one-thread-per-node kernel (testing)
   uint32_t xswap = 0;               // bit l (+16 for float32): level l's iterate is in its second buffer
   void* cap_stream = nullptr;       // hipStream_t used only while recording
   bool capturing = false;

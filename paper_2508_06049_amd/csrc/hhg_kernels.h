@@ -82,7 +82,7 @@ void launch_sqnorm_closure(int dim, const LK& lk, const T* r, double* partial, d
 // per-macro squared norms of u - a and u - P bc; norm 0 = consistent mass (scale sM),
 // 1 = stiffness with the macro coefficients (scale sA), 2 = lumped mass (scale sM)
 void launch_estimate(int dim, int norm, const LK& f, const LK& c, const Tables& tb, const double* u, const double* a,
-                     const double* bc, double* partial, double* out, double scale, hipStream_t st);
+                     const double* bc, double* partial, double* out, double scale, bool rows, hipStream_t st);
 void launch_bilinear(int dim, const LK& lk, const Tables& tb, const double* x, const double* y, double* partial,
                      double* out, double sA, hipStream_t st);
 void launch_canon_to_full(int dim, const LK& lk, const Tables& tb, const double* canon, double* full, int mode,

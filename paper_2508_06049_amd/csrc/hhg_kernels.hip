@@ -2434,8 +2434,8 @@ void launch_sqnorm_closure(int dim, const LK& lk, const T* r, double* partial, d
 template void launch_sqnorm_closure<float>(int, const LK&, const float*, double*, double*, hipStream_t);
 
 void launch_estimate(int dim, int norm, const LK& f, const LK& c, const Tables& tb, const double* u, const double* a,
-                     const double* bc, double* partial, double* out, double scale, hipStream_t st) {
-  if (dim == 2 && norm == 0 && f.n >= 4) {
+                     const double* bc, double* partial, double* out, double scale, bool rows, hipStream_t st) {
+  if (dim == 2 && norm == 0 && f.n >= 4 && rows) {
     const int nrb = (f.n - 2 + kEstRows - 1) / kEstRows, nseg = (f.n - 2 + 61) / 62, nbw = (3 * f.n + 63) / 64;
     const int wpm = nrb * nseg + nbw;
     const unsigned g = (unsigned)(((int64_t)f.nmacro * wpm + 3) / 4);

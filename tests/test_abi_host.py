@@ -86,6 +86,10 @@ def test_setup_rejects_bad_meshes_and_options():
     m = meshes.unit_square_2tri()
     with pytest.raises(L.HHGError):
         L.setup_host(m.coords, m.cells, 0)
+    # the nodal-coefficient path is switched off (a parity run of it faulted, cause not found)
+    with pytest.raises(L.HHGError) as e:
+        L.setup_host(m.coords, m.cells, 3, "redblack", coefficient="p1")
+    assert e.value.status == L.HHG_EINVAL and "switched off" in str(e.value)
     # no Dirichlet boundary at all -> singular level-0 system
     m = meshes.unit_square_grid(2)
     with pytest.raises(L.HHGError):

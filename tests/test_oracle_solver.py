@@ -91,17 +91,117 @@ def test_lshape_uniform_rate_four_thirds():
 
 def test_fmg_reaches_discretisation_accuracy():
     # textbook FMG property: the FMG error is a level-independent multiple of the
-    # discretisation error (one V(2,2) per level: about 1.3; two: about 1.02)
-    for L in (5, 6):
+    # discretisation error.  With one V(2,2) per level and the interior-first Gauss-Seidel
+    # order the multiple measured here is 1.311, 1.335, 1.345, 1.348 at L = 5..8 (the plain
+    # red-black order over all nodes gives 1.242 .. 1.272); with two cycles per level about
+    # 1.02.  The pin holds the multiple below 1.38 and its spread over four levels below
+    # 0.05, with shrinking increments (convergence to a level-independent constant).
+    ratios = {1: [], 2: []}
+    for L in (5, 6, 7, 8):
         h = _setup(meshes.unit_square_2tri, L)
         X = h.levels[L].X
         S = fmg.FMGSolver(h, smoother="redblack")
         b = S.rhs_levels(problems.sine2d_f(X))
         ud = S.direct(L, b[L], np.zeros(len(X)))
         e_dir = estimate.quadrature_l2(h, ud, problems.sine2d_u)
-        for nu, bound in ((1, 1.4), (2, 1.03)):
+        for nu in (1, 2):
             u, _ = S.fmg(b, np.zeros(len(X)), nu=nu)
-            assert estimate.quadrature_l2(h, u, problems.sine2d_u) <= bound * e_dir
+            ratios[nu].append(estimate.quadrature_l2(h, u, problems.sine2d_u) / e_dir)
+    r1, r2 = np.array(ratios[1]), np.array(ratios[2])
+    assert np.all((r1 > 1.0) & (r1 < 1.38)), r1
+    assert r1.max() - r1.min() < 0.05, r1
+    inc = np.diff(r1)
+    assert np.all(np.abs(inc[1:]) < np.abs(inc[:-1])), r1
+    assert np.all((r2 > 1.0) & (r2 < 1.03)), r2
+
+
+# --- the float32-refined form (reduced-precision correction cycles) ------------------------
+_O8_CASES = [
+    (meshes.unit_square_2tri, 5, "redblack"),
+    (meshes.lshape_6tri, 4, "multicolour"),
+    (meshes.lshape_6tri, 4, "jacobi"),
+    (lambda: meshes.kuhn_cube(2), 3, "multicolour"),
+]
+
+
+def _o8_problem(mk, L, smoother):
+    h = _setup(mk, L)
+    X = h.levels[L].X
+    S = fmg.FMGSolver(h, smoother=smoother)
+    if h.d == 2:
+        f, g = problems.sine2d_f(X), 0.25 + X[:, 0] - 0.5 * X[:, 1]
+    else:
+        f, g = problems.fourier3d(X, problems.fourier_amplitudes(0)), 0.1 * X[:, 0]
+    return h, S, f, g
+
+
+@pytest.mark.parametrize("mk,L,smoother", _O8_CASES)
+def test_refined_cycle_in_float64_is_the_vcycle(mk, L, smoother):
+    # multigrid is affine: a cycle on the correction equation from zero, added to u, is the
+    # cycle on u itself; in float64 the two code paths agree to round-off
+    h, S, f, g = _o8_problem(mk, L, smoother)
+    b = S.rhs_levels(f)[L]
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal(h.levels[L].n)
+    u[h.levels[L].boundary] = g[h.levels[L].boundary]
+    u1, u2 = u.copy(), u.copy()
+    S.vcycle(L, u1, b)
+    S.refined_cycle(L, u2, b, np.float64)
+    assert np.abs(u1 - u2).max() <= 1e-13 * np.abs(u1).max()
+
+
+@pytest.mark.parametrize("mk,L,smoother", _O8_CASES)
+def test_float32_cycle_is_the_float64_cycle_rounded(mk, L, smoother):
+    # the float32 correction of one cycle against the float64 cycle on u (the solution-form
+    # code path): relative difference of float32 rounding size, not of a changed operator
+    h, S, f, g = _o8_problem(mk, L, smoother)
+    b = S.rhs_levels(f)[L]
+    rng = np.random.default_rng(4)
+    u = rng.standard_normal(h.levels[L].n)
+    u[h.levels[L].boundary] = g[h.levels[L].boundary]
+    u1, u2 = u.copy(), u.copy()
+    S.vcycle(L, u1, b)
+    S.refined_cycle(L, u2, b, np.float32)
+    e64, e32 = u1 - u, u2 - u
+    assert np.abs(e32 - e64).max() <= 2e-5 * np.abs(e64).max()
+    assert np.abs(e32 - e64).max() >= 1e-9 * np.abs(e64).max()   # it did run in float32
+
+
+@pytest.mark.parametrize("mk,L,smoother", _O8_CASES)
+def test_float32_refinement_converges_to_the_direct_solve(mk, L, smoother):
+    # the fixed point of the refinement loop is the float64 discrete solution: the float64
+    # residual drives it, the float32 cycle only approximates the inverse
+    h, S, f, g = _o8_problem(mk, L, smoother)
+    b = S.rhs_levels(f)
+    ud = S.direct(L, b[L], g)
+    u64, _ = S.fmg(b, g, nu=1)
+    u32, w32 = S.fmg(b, g, nu=1, precision="fp32_refined")
+    # one float32-refined FMG pass lands as close to the discrete solution as the float64 one
+    e64, e32 = np.abs(u64 - ud).max(), np.abs(u32 - ud).max()
+    assert abs(e32 - e64) <= 0.05 * e64
+    assert all(w.dtype == np.float64 for w in w32)
+    it, rel = S.extra_cycles(u32, b[L], g, rtol=1e-13, max_iter=100, precision="fp32_refined")
+    assert rel <= 1e-13
+    assert np.abs(u32 - ud).max() <= 1e-11 * np.abs(ud).max()
+
+
+def test_float32_refinement_contracts_like_float64():
+    # above the float32 floor a refinement step reduces the residual by the V-cycle's own
+    # factor: a dropped term in the float32 cycle would show here as a slower contraction
+    h, S, f, g = _o8_problem(meshes.lshape_6tri, 5, "multicolour")
+    b = S.rhs_levels(f)[5]
+    rng = np.random.default_rng(5)
+    u0 = rng.standard_normal(h.levels[5].n)
+    u0[h.levels[5].boundary] = g[h.levels[5].boundary]
+    ra, rb = [], []
+    ua, ub = u0.copy(), u0.copy()
+    for _ in range(4):
+        S.vcycle(5, ua, b)
+        S.refined_cycle(5, ub, b, np.float32)
+        ra.append(np.linalg.norm(S.residual(5, ua, b)))
+        rb.append(np.linalg.norm(S.residual(5, ub, b)))
+    qa, qb = ra[-1] / ra[0], rb[-1] / rb[0]
+    assert abs(np.log(qb / qa)) < np.log(1.1), (qa, qb)
 
 
 def test_multigrid_is_affine_in_rhs():
