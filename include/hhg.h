@@ -106,7 +106,11 @@ typedef struct {
                                  checking it on small levels).
                                  HHG_FLAG_GENERIC_EST: compute the 2D L2 estimate with the
                                  one-thread-per-node kernel instead of the row kernel (same
-                                 result up to rounding; for checking the row kernel)          */
+                                 result up to rounding; for checking the row kernel).
+                                 HHG_FLAG_CLASSWISE_IFACE: sweep the 2D interface classes one
+                                 launch per class (or per run of small classes) instead of
+                                 all of a sweep in one launch (identical result; for checking
+                                 the one-launch form)                                          */
 } hhg_options;
 
 enum {
@@ -116,7 +120,8 @@ enum {
   HHG_FLAG_NO_PRELOAD = 8,
   HHG_FLAG_ROWS3D = 16,
   HHG_FLAG_STREAM3D = 32,
-  HHG_FLAG_GENERIC_EST = 64
+  HHG_FLAG_GENERIC_EST = 64,
+  HHG_FLAG_CLASSWISE_IFACE = 128
 };
 
 typedef struct {
@@ -125,14 +130,18 @@ typedef struct {
   int precision;              /* HHG_FP64, or HHG_FP32_REFINED: float32 V-cycles on the
                                  correction inside float64 residual/update steps              */
   double rtol;                /* extra cycles on level L until ||r|| <= rtol * ||r_0||, where
-                                 r_0 is the residual of u = g on the boundary and 0 inside     */
+                                 r_0 is the residual of u = g on the boundary and 0 inside.
+                                 rtol = 0 with max_iter > 0: exactly max_iter extra cycles and
+                                 no residual norm at all (no host synchronisation inside the
+                                 solve; final_rel_residual is then -1)                        */
   int max_iter;               /* cap on those extra cycles (0 = FMG only)                      */
 } hhg_solve_params;
 
 typedef struct {
   int vcycles;                /* V-cycles on all FMG levels plus extra cycles                  */
   int ir_steps;               /* extra cycles on level L                                       */
-  double final_rel_residual;  /* ||r|| / ||r_0|| after the solve (computed only if max_iter>0) */
+  double final_rel_residual;  /* ||r|| / ||r_0|| after the solve (computed only if max_iter > 0
+                                 and rtol > 0; else -1)                                       */
   double ms_total;            /* device time of the solve (HIP events), milliseconds          */
 } hhg_solve_stats;
 

@@ -14,9 +14,18 @@ Colours:
   vanish (right-isosceles triangles, Kuhn tetrahedra); ``is_proper_for`` checks that.
 * interior nodes, multicolour rule: with integer barycentrics (c_0..c_d) in the macro's vertex
   order, (c_1 + 2 c_2) mod 3 in 2D and (c_1 + 2 c_2 + 3 c_3) mod 4 in 3D; classes 0..C-1.
-* interface nodes come after all interior classes: red-black gives C + parity; multicolour
-  colours them greedily, first fit, in canonical DoF order, avoiding already coloured
-  interface neighbours, and numbers those classes from C on.
+* interface nodes come after all interior classes.
+  - 3D: red-black gives C + parity; multicolour colours them greedily, first fit, in
+    canonical DoF order, avoiding already coloured interface neighbours, and numbers those
+    classes from C on.
+  - 2D (both Gauss-Seidel smoothers): a node interior to a macro edge at lattice distance a
+    from the edge's lower-id vertex, with 2 <= a <= n - 2, gets class C + (a mod 2): the
+    points of every edge alternate between two classes, and no point of one edge with
+    2 <= a <= n - 2 touches another edge.  The remaining interface nodes (macro vertices and
+    the edge points next to them, a = 1 and a = n - 1) follow in classes from C + 2 on:
+    red-black C + 2 + parity, multicolour greedy first fit in canonical order among these
+    nodes.  (Ordering the two edge classes before the vertex neighbourhoods lets one
+    wavefront sweep both classes of an edge segment without waiting on any other.)
 Nodes on the Dirichlet boundary are never updated and get colour -1.
 """
 from __future__ import annotations
@@ -37,12 +46,48 @@ def _interior_mask(h, l):
     return (h.levels[l].node_bary > 0).sum(axis=1) == h.d + 1
 
 
+def edge_position_2d(h, l: int) -> np.ndarray:
+    """2D: for every node of level l interior to a macro edge, its lattice distance a from the
+    edge's lower-id vertex (the barycentric weight of the higher-id vertex); -1 elsewhere."""
+    lv = h.levels[l]
+    gv = h.coarse_cells[lv.node_macro]
+    bary = lv.node_bary
+    on_edge = (bary > 0).sum(axis=1) == 2
+    pos = np.full(lv.n, -1, dtype=np.int64)
+    for i in np.nonzero(on_edge)[0]:
+        sup = np.nonzero(bary[i] > 0)[0]
+        vs, cs = gv[i][sup], bary[i][sup]
+        pos[i] = cs[int(np.argmax(vs))]
+    return pos
+
+
+def _edge_classes_2d(h, l: int, C: int):
+    """2D interface split: class C + (a mod 2) for edge points with 2 <= a <= n - 2; returns
+    the colours and the mask of the remaining interface nodes (vertex neighbourhoods)."""
+    lv = h.levels[l]
+    n = 2 ** l
+    inner = _interior_mask(h, l)
+    a = edge_position_2d(h, l)
+    col = np.full(lv.n, -1, dtype=np.int64)
+    edge = (a >= 2) & (a <= n - 2) & ~lv.boundary
+    col[edge] = C + a[edge] % 2
+    rest = ~inner & ~edge & ~lv.boundary
+    return col, rest
+
+
 def red_black(h, l: int) -> np.ndarray:
     lv = h.levels[l]
     p = _dyadic_power(h.coarse_coords)
     ic = np.round(lv.X * (2.0 ** (p + l))).astype(np.int64)
-    col = (ic.sum(axis=1) % 2).astype(np.int64)
-    col[~_interior_mask(h, l)] += 2
+    par = (ic.sum(axis=1) % 2).astype(np.int64)
+    inner = _interior_mask(h, l)
+    if h.d == 2:
+        col, rest = _edge_classes_2d(h, l, 2)
+        col[inner] = par[inner]
+        col[rest] = 4 + par[rest]
+    else:
+        col = par.copy()
+        col[~inner] += 2
     col[lv.boundary] = -1
     return col
 
@@ -72,15 +117,21 @@ def multicolour(h, l: int) -> np.ndarray:
         ci = (bary[:, 1] + 2 * bary[:, 2]) % 3
     else:
         ci = (bary[:, 1] + 2 * bary[:, 2] + 3 * bary[:, 3]) % 4
+    if d == 2:
+        col, rest = _edge_classes_2d(h, l, C)
+        first = C + 2
+    else:
+        rest = ~inner & ~lv.boundary
+        first = C
     col[inner] = ci[inner]
     G = mesh_graph(lv)
     order = h.canonical_order(l)
     for i in order:
-        if inner[i] or lv.boundary[i]:
+        if not rest[i]:
             continue
         nb = G.indices[G.indptr[i]:G.indptr[i + 1]]
-        used = set(int(c) for c, q in zip(col[nb], nb) if c >= 0 and not inner[q])
-        c = C
+        used = set(int(col[q]) for q in nb if rest[q] and col[q] >= 0)
+        c = first
         while c in used:
             c += 1
         col[i] = c

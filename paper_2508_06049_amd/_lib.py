@@ -32,6 +32,7 @@ HHG_FLAG_NO_PRELOAD = 8
 HHG_FLAG_ROWS3D = 16
 HHG_FLAG_STREAM3D = 32
 HHG_FLAG_GENERIC_EST = 64
+HHG_FLAG_CLASSWISE_IFACE = 128
 
 SMOOTHERS = {"redblack": HHG_GS_REDBLACK, "multicolour": HHG_GS_MULTICOLOR, "jacobi": HHG_JACOBI}
 PRECISIONS = {"fp64": HHG_FP64, "fp32_refined": HHG_FP32_REFINED}
@@ -195,10 +196,10 @@ class HHG:
         nb = C.c_size_t()
         _check(self.lib.hhg_workspace_bytes(self.ctx, C.byref(nb)), self.ctx)
         self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
         self.workspace = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
         aligned = (base + 255) // 256 * 256
-        self.stream = torch.cuda.current_stream(self.device)
         _check(self.lib.hhg_bind_workspace(self.ctx, aligned, int(nb.value), C.c_void_p(self.stream.cuda_stream)),
                self.ctx)
         self.workspace_bytes = int(nb.value)

@@ -163,9 +163,22 @@ hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
       for (int col = 0; col < lv.interior_colours; ++col) interior_launch<T>(c, l, k, x, x, b, col, rb, 0);
     T* mir = twobuf ? x : (T*)nullptr;
     if (lv.task_ok && !c->no_tasks) {
-      // a class of more than kTaskOneGroupWaves wavefronts gets a grid of its own; runs of
-      // smaller consecutive classes share one single-workgroup launch
+      // 2D with large edge classes: both edge classes in one launch by edge chunks; then, as
+      // for all classes otherwise, a class of more than kTaskOneGroupWaves wavefronts gets a
+      // grid of its own and runs of smaller consecutive classes share one single-workgroup
+      // launch
       int col = lv.interior_colours;
+      if (lv.fused_iface && !c->classwise_iface) {
+        launch_iface2d_edges<T>(k, (const int32_t*)(c->ws + c->o_erec), (int)c->nE, lv.d_dvcopy, (int)lv.dvcopy.size(),
+                                y, x, y, mir, b, sA(c, l), ST(c));
+        col = lv.c_vr0;
+        if (lv.wheels) {
+          launch_iface2d_wheels<T>(k, c->tab, lv.d_whcopy, lv.d_whinfo, lv.d_whloc, lv.d_whseg, lv.d_whsrc, lv.d_whcw,
+                                   lv.d_whwmax, (int)lv.wh_wmax.size(), lv.ncolours - lv.c_vr0, y, x, y, mir, b,
+                                   sA(c, l), ST(c));
+          col = lv.ncolours;
+        }
+      }
       while (col < lv.ncolours) {
         auto waves = [&](int cc) { return lv.task_woff[cc + 1] - lv.task_woff[cc]; };
         if (waves(col) > kTaskOneGroupWaves) {
@@ -284,7 +297,7 @@ hhg_status residual_norm(hhg_ctx c, int l, const double* x, const double* b, dou
 }
 
 void drop_graphs(hhg_ctx c) {
-  for (auto& kv : c->graphs) (void)hipGraphExecDestroy((hipGraphExec_t)kv.second);
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy((hipGraphExec_t)g.exec);
   c->graphs.clear();
 }
 
@@ -295,11 +308,11 @@ void drop_graphs(hhg_ctx c) {
 // guarantee the latter by using graphs only for even pre- and post-smoothing counts (each
 // out-of-place sweep swaps the two iterate buffers).
 template <class F>
-hhg_status run_recorded(hhg_ctx c, int64_t key, F&& body) {
+hhg_status run_recorded(hhg_ctx c, int64_t key, F&& body, int64_t key2 = 0) {
   if (c->no_graph || c->prof_on || c->capturing) return body();
   hipGraphExec_t ex = nullptr;
-  for (auto& kv : c->graphs)
-    if (kv.first == key) ex = (hipGraphExec_t)kv.second;
+  for (auto& g : c->graphs)
+    if (g.key == key && g.key2 == key2) ex = (hipGraphExec_t)g.exec;
   if (!ex) {
     if (!c->cap_stream) {
       hipStream_t cs;
@@ -320,7 +333,7 @@ hhg_status run_recorded(hhg_ctx c, int64_t key, F&& body) {
     const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (ei != hipSuccess) { c->err = std::string("HIP graph instantiation: ") + hipGetErrorString(ei); return HHG_EHIP; }
-    c->graphs.push_back({key, (void*)ex});
+    c->graphs.push_back({key, key2, (void*)ex});
   }
   HIPCHK(hipGraphLaunch(ex, (hipStream_t)c->stream));
   return HHG_OK;
@@ -351,10 +364,28 @@ hhg_status fmg_core(hhg_ctx c, const hhg_solve_params& p, hhg_solve_stats* stats
     return HHG_OK;
   };
   // warm: the iterate on level L is given; only the cycles below run
-  if (!warm) TRY(rec ? run_recorded(c, graph_key(c, 1, p), body) : body());
   int vcycles = warm ? 0 : p.nu * L;
+  if (p.max_iter > 0 && p.rtol == 0.0) {
+    // a fixed number of extra cycles, no residual norms: the FMG pass and the cycles are one
+    // launch sequence (one recorded graph)
+    Level& lL = c->lev[L];
+    auto all = [&]() -> hhg_status {
+      if (!warm) TRY(body());
+      for (int it = 0; it < p.max_iter; ++it) TRY(cycle(c, L, lL.bf, p));
+      return HHG_OK;
+    };
+    TRY(rec ? run_recorded(c, graph_key(c, 4, p), all, (int64_t)p.max_iter | ((int64_t)warm << 32)) : all());
+    if (stats) {
+      stats->vcycles = vcycles + p.max_iter;
+      stats->ir_steps = p.max_iter;
+      stats->final_rel_residual = -1.0;
+    }
+    c->res_hist.clear();
+    return HHG_OK;
+  }
+  if (!warm) TRY(rec ? run_recorded(c, graph_key(c, 1, p), body) : body());
   int extra = 0;
-  double rel = 0.0;
+  double rel = -1.0;   // not computed without extra cycles
   if (p.max_iter > 0) {
     Level& lL = c->lev[L];
     // reference residual: u = g on the boundary, 0 inside (assembled into rc_L as scratch)
@@ -477,113 +508,51 @@ hhg_status estimate_pair(hhg_ctx c, int norm, const double* a, const double* bc,
   return HHG_OK;
 }
 
-}  // namespace
-
-// =========================================================================================
-extern "C" {
-
-const char* hhg_status_string(hhg_status s) {
-  switch (s) {
-    case HHG_OK: return "HHG_OK";
-    case HHG_EINVAL: return "HHG_EINVAL: invalid argument";
-    case HHG_EMESH: return "HHG_EMESH: invalid mesh";
-    case HHG_ENOMEM: return "HHG_ENOMEM: workspace too small";
-    case HHG_EHIP: return "HHG_EHIP: HIP runtime error";
-    case HHG_ENOTCONV: return "HHG_ENOTCONV: no convergence";
-    case HHG_ESTATE: return "HHG_ESTATE: wrong state";
-  }
-  return "unknown status";
-}
-
-const char* hhg_last_error(hhg_ctx c) { return c ? c->err.c_str() : g_err.c_str(); }
-
-hhg_status hhg_setup(const hhg_mesh* mesh, int L, const hhg_options* opt, hhg_ctx* out) {
-  if (!out) { g_err = "out is NULL"; return HHG_EINVAL; }
-  *out = nullptr;
-  if (!mesh || !opt) { g_err = "mesh or options is NULL"; return HHG_EINVAL; }
-  if (mesh->dim != 2 && mesh->dim != 3) { g_err = "dim must be 2 or 3"; return HHG_EINVAL; }
-  if (L < 1 || L > (mesh->dim == 3 ? 9 : 12)) { g_err = "level L out of range"; return HHG_EINVAL; }
-  if (mesh->n_vertices <= 0 || mesh->n_cells <= 0 || !mesh->coords || !mesh->cells) { g_err = "empty mesh"; return HHG_EMESH; }
-  if (opt->smoother < HHG_GS_REDBLACK || opt->smoother > HHG_JACOBI ||
-      (opt->coefficient != HHG_KAPPA_MACRO && opt->coefficient != HHG_KAPPA_P1)) {
-    g_err = "invalid options";
-    return HHG_EINVAL;
-  }
-  // The nodal-coefficient path is switched off: a parity run of it ended in a GPU memory
-  // fault whose cause was not found, so it is not offered until one is shown and fixed.
-  if (opt->coefficient == HHG_KAPPA_P1) {
-    g_err = "HHG_KAPPA_P1 (nodal coefficient) is switched off in this build";
-    return HHG_EINVAL;
-  }
-  hhg_ctx c = new (std::nothrow) hhg_ctx_s();
-  if (!c) { g_err = "out of host memory"; return HHG_ENOMEM; }
-  c->dim = mesh->dim;
-  c->L = L;
-  c->opt = *opt;
-  c->no_fused = (opt->flags & HHG_FLAG_NO_FUSED) != 0;
-  c->no_tasks = (opt->flags & HHG_FLAG_NO_LANE_IFACE) != 0;
-  c->no_graph = (opt->flags & HHG_FLAG_NO_GRAPH) != 0;
-  c->no_preload = (opt->flags & HHG_FLAG_NO_PRELOAD) != 0;
-  c->force_rows3d = (opt->flags & HHG_FLAG_ROWS3D) != 0;
-  c->force_stream3d = (opt->flags & HHG_FLAG_STREAM3D) != 0;
-  c->generic_est = (opt->flags & HHG_FLAG_GENERIC_EST) != 0;
-  c->nV = mesh->n_vertices;
-  c->nC = mesh->n_cells;
-  const int nv = c->dim + 1;
-  c->coords.assign(mesh->coords, mesh->coords + c->nV * c->dim);
-  c->cells.assign(mesh->cells, mesh->cells + c->nC * nv);
-  c->kappa_cell.assign(c->nC, 1.0);
-  if (mesh->kappa_cell) c->kappa_cell.assign(mesh->kappa_cell, mesh->kappa_cell + c->nC);
-  for (double k : c->kappa_cell)
-    if (!(k > 0) || !std::isfinite(k)) { g_err = "kappa_cell must be positive"; delete c; return HHG_EINVAL; }
-  if (mesh->dirichlet) c->vdir_user.assign(mesh->dirichlet, mesh->dirichlet + c->nV);
-  hhg_status s = build_topology(c);
-  if (s == HHG_OK) s = build_stencils(c);
-  if (s != HHG_OK) { g_err = c->err; delete c; return s; }
-  // levels
-  c->lev.resize(L + 1);
-  for (int l = 0; l <= L; ++l) {
-    Level& lv = c->lev[l];
-    lv.l = l;
-    lv.n = 1 << l;
-    const int n = lv.n;
-    lv.Sraw = c->dim == 3 ? tet_count(n) : tri_count(n);
-    lv.S = (lv.Sraw + 63) / 64 * 64;
-    lv.NI = c->dim == 3 ? tet_count(n - 4) : tri_count(n - 3);
-    lv.nEd = n - 1;
-    lv.nFd = tri_count(n - 3);
-    lv.nIface = c->nV + (int64_t)c->nE * lv.nEd + (c->dim == 3 ? (int64_t)c->nF * lv.nFd : 0);
-    lv.ndof = lv.nIface + c->nC * lv.NI;
-    lv.nfull = c->nC * lv.S;
-  }
-  s = build_colouring(c);
-  if (s == HHG_OK) s = build_coarse(c, nullptr);
-  if (s != HHG_OK) { g_err = c->err; delete c; return s; }
-  plan_workspace(c);
-  *out = c;
+// the pair of timing events of the solve entry points (not created for the static workspace)
+hhg_status ensure_events(hhg_ctx c) {
+  if (c->ev0) return HHG_OK;
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  c->ev0 = a;
+  c->ev1 = b;
   return HHG_OK;
 }
 
-hhg_status hhg_workspace_bytes(hhg_ctx c, size_t* bytes) {
-  if (!c || !bytes) return HHG_EINVAL;
-  *bytes = c->ws_bytes;
+// record a timing event if the context has them
+hipError_t record(hhg_ctx c, void* ev) { return ev ? hipEventRecord((hipEvent_t)ev, ST(c)) : hipSuccess; }
+
+// milliseconds between the two timing events (0 without events)
+hhg_status elapsed(hhg_ctx c, double* ms) {
+  *ms = 0.0;
+  if (!c->ev0) return HHG_OK;
+  HIPCHK(hipEventSynchronize((hipEvent_t)c->ev1));
+  float t = 0;
+  HIPCHK(hipEventElapsedTime(&t, (hipEvent_t)c->ev0, (hipEvent_t)c->ev1));
+  *ms = t;
   return HHG_OK;
 }
 
-hhg_status hhg_bind_workspace(hhg_ctx c, void* ptr, size_t bytes, void* stream) {
-  if (!c) return HHG_EINVAL;
-  if (!ptr || bytes < c->ws_bytes) { c->err = "workspace too small"; return HHG_ENOMEM; }
-  if (((uintptr_t)ptr & 255) != 0) { c->err = "workspace must be 256-byte aligned"; return HHG_EINVAL; }
+// bind a workspace: clear it, upload the tables, point the level arrays into it.  With
+// no_alloc (the static workspace) the clear is a fill kernel and no HIP events are created.
+hhg_status bind_impl(hhg_ctx c, void* ptr, void* stream, bool no_alloc) {
+  // recorded launches of a previous binding may still run on the old stream
+  if (c->bound) HIPCHK(hipStreamSynchronize(ST(c)));
+  drop_graphs(c);
+  c->bound = false;
   c->ws = (char*)ptr;
   c->stream = stream;
   hipStream_t st = ST(c);
   const int d = c->dim, nv = d + 1;
   char* w = c->ws;
-  HIPCHK(hipMemsetAsync(w, 0, c->ws_bytes, st));
+  if (no_alloc) launch_fill<float>((float*)w, (int64_t)(c->ws_bytes / 4), 0.0f, st);
+  else HIPCHK(hipMemsetAsync(w, 0, c->ws_bytes, st));
   auto up = [&](int64_t off, const void* src, size_t n) -> hipError_t {
     if (n == 0) return hipSuccess;
     return hipMemcpyAsync(w + off, src, n, hipMemcpyHostToDevice, st);
   };
+  fill_kappa_tables(c);
+  HIPCHK(up(c->o_erec, c->erec.data(), c->erec.size() * 4));
   HIPCHK(up(c->o_stiff, c->stiff.data(), c->stiff.size() * 8));
   HIPCHK(up(c->o_mass, c->mass.data(), c->mass.size() * 8));
   HIPCHK(up(c->o_elemK, c->elemK.data(), c->elemK.size() * 8));
@@ -656,6 +625,22 @@ hhg_status hhg_bind_workspace(hhg_ctx c, void* ptr, size_t bytes, void* stream) 
     HIPCHK(up(lv.off_twmax, lv.task_wmax.data(), lv.task_wmax.size() * 4));
     lv.d_task_woff = (int32_t*)(w + lv.off_twoff);
     HIPCHK(up(lv.off_twoff, lv.task_woff.data(), lv.task_woff.size() * 4));
+    lv.d_dvcopy = (int32_t*)(w + lv.off_dvcopy);
+    HIPCHK(up(lv.off_dvcopy, lv.dvcopy.data(), lv.dvcopy.size() * 4));
+    lv.d_whcopy = (int32_t*)(w + lv.off_whcopy);
+    HIPCHK(up(lv.off_whcopy, lv.wh_copy.data(), lv.wh_copy.size() * 4));
+    lv.d_whinfo = (int32_t*)(w + lv.off_whinfo);
+    HIPCHK(up(lv.off_whinfo, lv.wh_info.data(), lv.wh_info.size() * 4));
+    lv.d_whloc = (int32_t*)(w + lv.off_whloc);
+    HIPCHK(up(lv.off_whloc, lv.wh_loc.data(), lv.wh_loc.size() * 4));
+    lv.d_whseg = (int32_t*)(w + lv.off_whseg);
+    HIPCHK(up(lv.off_whseg, lv.wh_seg.data(), lv.wh_seg.size() * 4));
+    lv.d_whsrc = (int32_t*)(w + lv.off_whsrc);
+    HIPCHK(up(lv.off_whsrc, lv.wh_src.data(), lv.wh_src.size() * 4));
+    lv.d_whwmax = (int32_t*)(w + lv.off_whwmax);
+    HIPCHK(up(lv.off_whwmax, lv.wh_wmax.data(), lv.wh_wmax.size() * 4));
+    lv.d_whcw = (double*)(w + lv.off_whcw);
+    HIPCHK(up(lv.off_whcw, lv.wh_cw.data(), lv.wh_cw.size() * 8));
     lv.d_colour_off = (int32_t*)(w + lv.off_coff);
     HIPCHK(up(lv.off_coff, lv.colour_off.data(), lv.colour_off.size() * 4));
     lv.d_tiles = (int32_t*)(w + lv.off_tiles);
@@ -665,19 +650,114 @@ hhg_status hhg_bind_workspace(hhg_ctx c, void* ptr, size_t bytes, void* stream) 
     lv.d_itab_off = (int32_t*)(w + lv.off_itoff);
     HIPCHK(up(lv.off_itoff, lv.itab_off.data(), lv.itab_off.size() * 4));
   }
-  if (!c->ev0) {
-    hipEvent_t a, b;
-    HIPCHK(hipEventCreate(&a));
-    HIPCHK(hipEventCreate(&b));
-    c->ev0 = a;
-    c->ev1 = b;
-  }
-  drop_graphs(c);   // recorded launches refer to the previous workspace and stream
+  if (!no_alloc) TRY(ensure_events(c));
   c->bound = true;
   c->solved = false;
   c->have_u = false;
   return upload_coarse(c);
 }
+
+
+}  // namespace
+
+extern "C" {
+
+const char* hhg_status_string(hhg_status s) {
+  switch (s) {
+    case HHG_OK: return "HHG_OK";
+    case HHG_EINVAL: return "HHG_EINVAL: invalid argument";
+    case HHG_EMESH: return "HHG_EMESH: invalid mesh";
+    case HHG_ENOMEM: return "HHG_ENOMEM: workspace too small";
+    case HHG_EHIP: return "HHG_EHIP: HIP runtime error";
+    case HHG_ENOTCONV: return "HHG_ENOTCONV: no convergence";
+    case HHG_ESTATE: return "HHG_ESTATE: wrong state";
+  }
+  return "unknown status";
+}
+
+const char* hhg_last_error(hhg_ctx c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+hhg_status hhg_setup(const hhg_mesh* mesh, int L, const hhg_options* opt, hhg_ctx* out) {
+  if (!out) { g_err = "out is NULL"; return HHG_EINVAL; }
+  *out = nullptr;
+  if (!mesh || !opt) { g_err = "mesh or options is NULL"; return HHG_EINVAL; }
+  if (mesh->dim != 2 && mesh->dim != 3) { g_err = "dim must be 2 or 3"; return HHG_EINVAL; }
+  if (L < 1 || L > (mesh->dim == 3 ? 9 : 12)) { g_err = "level L out of range"; return HHG_EINVAL; }
+  if (mesh->n_vertices <= 0 || mesh->n_cells <= 0 || !mesh->coords || !mesh->cells) { g_err = "empty mesh"; return HHG_EMESH; }
+  if (opt->smoother < HHG_GS_REDBLACK || opt->smoother > HHG_JACOBI ||
+      (opt->coefficient != HHG_KAPPA_MACRO && opt->coefficient != HHG_KAPPA_P1)) {
+    g_err = "invalid options";
+    return HHG_EINVAL;
+  }
+  // The nodal-coefficient path is switched off: a parity run of it ended in a GPU memory
+  // fault whose cause was not found, so it is not offered until one is shown and fixed.
+  if (opt->coefficient == HHG_KAPPA_P1) {
+    g_err = "HHG_KAPPA_P1 (nodal coefficient) is switched off in this build";
+    return HHG_EINVAL;
+  }
+  hhg_ctx c = new (std::nothrow) hhg_ctx_s();
+  if (!c) { g_err = "out of host memory"; return HHG_ENOMEM; }
+  c->dim = mesh->dim;
+  c->L = L;
+  c->opt = *opt;
+  c->no_fused = (opt->flags & HHG_FLAG_NO_FUSED) != 0;
+  c->no_tasks = (opt->flags & HHG_FLAG_NO_LANE_IFACE) != 0;
+  c->classwise_iface = (opt->flags & HHG_FLAG_CLASSWISE_IFACE) != 0;
+  c->no_graph = (opt->flags & HHG_FLAG_NO_GRAPH) != 0;
+  c->no_preload = (opt->flags & HHG_FLAG_NO_PRELOAD) != 0;
+  c->force_rows3d = (opt->flags & HHG_FLAG_ROWS3D) != 0;
+  c->force_stream3d = (opt->flags & HHG_FLAG_STREAM3D) != 0;
+  c->generic_est = (opt->flags & HHG_FLAG_GENERIC_EST) != 0;
+  c->nV = mesh->n_vertices;
+  c->nC = mesh->n_cells;
+  const int nv = c->dim + 1;
+  c->coords.assign(mesh->coords, mesh->coords + c->nV * c->dim);
+  c->cells.assign(mesh->cells, mesh->cells + c->nC * nv);
+  c->kappa_cell.assign(c->nC, 1.0);
+  if (mesh->kappa_cell) c->kappa_cell.assign(mesh->kappa_cell, mesh->kappa_cell + c->nC);
+  for (double k : c->kappa_cell)
+    if (!(k > 0) || !std::isfinite(k)) { g_err = "kappa_cell must be positive"; delete c; return HHG_EINVAL; }
+  if (mesh->dirichlet) c->vdir_user.assign(mesh->dirichlet, mesh->dirichlet + c->nV);
+  hhg_status s = build_topology(c);
+  if (s == HHG_OK) s = build_stencils(c);
+  if (s != HHG_OK) { g_err = c->err; delete c; return s; }
+  // levels
+  c->lev.resize(L + 1);
+  for (int l = 0; l <= L; ++l) {
+    Level& lv = c->lev[l];
+    lv.l = l;
+    lv.n = 1 << l;
+    const int n = lv.n;
+    lv.Sraw = c->dim == 3 ? tet_count(n) : tri_count(n);
+    lv.S = (lv.Sraw + 63) / 64 * 64;
+    lv.NI = c->dim == 3 ? tet_count(n - 4) : tri_count(n - 3);
+    lv.nEd = n - 1;
+    lv.nFd = tri_count(n - 3);
+    lv.nIface = c->nV + (int64_t)c->nE * lv.nEd + (c->dim == 3 ? (int64_t)c->nF * lv.nFd : 0);
+    lv.ndof = lv.nIface + c->nC * lv.NI;
+    lv.nfull = c->nC * lv.S;
+  }
+  s = build_colouring(c);
+  if (s == HHG_OK) s = build_coarse(c, nullptr);
+  if (s != HHG_OK) { g_err = c->err; delete c; return s; }
+  plan_workspace(c);
+  *out = c;
+  return HHG_OK;
+}
+
+hhg_status hhg_workspace_bytes(hhg_ctx c, size_t* bytes) {
+  if (!c || !bytes) return HHG_EINVAL;
+  *bytes = c->ws_bytes;
+  return HHG_OK;
+}
+
+hhg_status hhg_bind_workspace(hhg_ctx c, void* ptr, size_t bytes, void* stream) {
+  if (!c) return HHG_EINVAL;
+  if (!ptr || bytes < c->ws_bytes) { c->err = "workspace too small"; return HHG_ENOMEM; }
+  if (((uintptr_t)ptr & 255) != 0) { c->err = "workspace must be 256-byte aligned"; return HHG_EINVAL; }
+  return bind_impl(c, ptr, stream, false);
+}
+
 
 hhg_status hhg_num_dofs(hhg_ctx c, int level, int64_t* n) {
   if (!c || !n) return HHG_EINVAL;
@@ -701,8 +781,14 @@ hhg_status hhg_set_kappa_cell(hhg_ctx c, const double* kappa) {
     if (!(kappa[m] > 0) || !std::isfinite(kappa[m])) { c->err = "kappa_cell must be positive"; return HHG_EINVAL; }
   c->kappa_cell.assign(kappa, kappa + c->nC);
   TRY(build_coarse(c, nullptr));
+  fill_kappa_tables(c);
   if (c->bound) {
     HIPCHK(hipMemcpyAsync(c->ws + c->o_kappa, c->kappa_cell.data(), c->nC * 8, hipMemcpyHostToDevice, ST(c)));
+    if (!c->erec.empty())
+      HIPCHK(hipMemcpyAsync(c->ws + c->o_erec, c->erec.data(), c->erec.size() * 4, hipMemcpyHostToDevice, ST(c)));
+    for (auto& lv : c->lev)
+      if (!lv.wh_cw.empty())
+        HIPCHK(hipMemcpyAsync(c->ws + lv.off_whcw, lv.wh_cw.data(), lv.wh_cw.size() * 8, hipMemcpyHostToDevice, ST(c)));
     TRY(upload_coarse(c));
   }
   c->solved = false;
@@ -736,19 +822,16 @@ hhg_status hhg_fmg_solve(hhg_ctx c, const double* f, const double* g, double* u_
   TRY(check_ready(c));
   TRY(validate_params(c, p));
   if (!f || !g || !u_out) { c->err = "NULL vector"; return HHG_EINVAL; }
-  HIPCHK(hipEventRecord((hipEvent_t)c->ev0, ST(c)));
+  HIPCHK(record(c, c->ev0));
   TRY(setup_rhs(c, f, g));
   hhg_solve_stats st{};
   hhg_status s = fmg_core(c, *p, &st);
   if (s != HHG_OK && s != HHG_ENOTCONV) return s;
   launch_full_to_canon(c->dim, lk_of(c, c->L), c->tab, c->lev[c->L].x, u_out, 0, ST(c));
   LAUNCHCHK();
-  HIPCHK(hipEventRecord((hipEvent_t)c->ev1, ST(c)));
+  HIPCHK(record(c, c->ev1));
   if (stats) {
-    HIPCHK(hipEventSynchronize((hipEvent_t)c->ev1));
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, (hipEvent_t)c->ev0, (hipEvent_t)c->ev1));
-    st.ms_total = ms;
+    TRY(elapsed(c, &st.ms_total));
     *stats = st;
   }
   c->solved = (s == HHG_OK);
@@ -764,7 +847,7 @@ hhg_status hhg_cycle_solve(hhg_ctx c, const double* f, const double* g, double* 
   if (!f || !g || !u) { c->err = "NULL vector"; return HHG_EINVAL; }
   if (p->max_iter < 1) { c->err = "hhg_cycle_solve needs max_iter >= 1"; return HHG_EINVAL; }
   c->solved = c->have_u = false;
-  HIPCHK(hipEventRecord((hipEvent_t)c->ev0, ST(c)));
+  HIPCHK(record(c, c->ev0));
   TRY(setup_rhs(c, f, g));
   const int L = c->L;
   Level& lL = c->lev[L];
@@ -776,12 +859,9 @@ hhg_status hhg_cycle_solve(hhg_ctx c, const double* f, const double* g, double* 
   if (s != HHG_OK && s != HHG_ENOTCONV) return s;
   launch_full_to_canon(c->dim, lk_of(c, L), c->tab, lL.x, u, 0, ST(c));
   LAUNCHCHK();
-  HIPCHK(hipEventRecord((hipEvent_t)c->ev1, ST(c)));
+  HIPCHK(record(c, c->ev1));
   if (stats) {
-    HIPCHK(hipEventSynchronize((hipEvent_t)c->ev1));
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, (hipEvent_t)c->ev0, (hipEvent_t)c->ev1));
-    st.ms_total = ms;
+    TRY(elapsed(c, &st.ms_total));
     *stats = st;
   }
   c->have_u = (s == HHG_OK);
@@ -1074,6 +1154,7 @@ hhg_status hhg_bench_smoother(hhg_ctx c, int precision, int sweeps, double* ms, 
     HIPCHK(hipEventCreate(&e));
     c->prof_ev.push_back(e);
   }
+  TRY(ensure_events(c));
   c->prof_used = 0;
   c->prof_bytes = 0.0;
   c->prof_on = launch_ms != nullptr || launch_bytes != nullptr;
@@ -1112,6 +1193,8 @@ hhg_status hhg_residual_history(hhg_ctx c, double* out, int capacity, int* count
 
 void hhg_destroy(hhg_ctx c) {
   if (!c) return;
+  // recorded launches may still run: finish them before their executable graphs go
+  if (c->bound) (void)hipStreamSynchronize(ST(c));
   drop_graphs(c);
   if (c->cap_stream) (void)hipStreamDestroy((hipStream_t)c->cap_stream);
   for (void* e : c->prof_ev) (void)hipEventDestroy((hipEvent_t)e);

@@ -45,6 +45,12 @@ constexpr int kIfaceOneGroup = 4096;
 // lane-parallel interface sweeps: levels whose largest class spans at most this many
 // wavefronts sweep all classes in one workgroup of 16 wavefronts
 constexpr int kTaskOneGroupWaves = 32;
+// record of one 2D macro edge for the edge-class sweep (int32 words): [0] copies | Dirichlet
+// << 2; per copy k at 2 + kEdgeCopyWords k: macro, slot of the edge's lower-id vertex | slot
+// of its higher-id vertex << 8 | zero-set mask << 16, then the macro's coefficient and its 7
+// unit stencil weights for that mask (doubles, words 2..17), then the mask's valid directions
+constexpr int kEdgeCopyWords = 20;
+constexpr int kEdgeRecWords = 2 + 2 * kEdgeCopyWords;
 // blocks of the interior part of a squared norm (one partial each)
 constexpr int kNormBlocks = 8192;
 // interior rows per wavefront of the 2D row estimator
@@ -117,6 +123,26 @@ struct Level {
   int32_t *d_task_copy = nullptr, *d_task_info = nullptr, *d_task_loc = nullptr, *d_task_seg = nullptr,
           *d_task_wmax = nullptr, *d_task_woff = nullptr;
   int64_t off_tcopy = 0, off_tinfo = 0, off_tloc = 0, off_tseg = 0, off_twmax = 0, off_twoff = 0;
+  // 2D edge classes in one launch (k_iface2d_edges, from the context's edge records):
+  // dvcopy = level-vector indices of the copies of Dirichlet vertices (which the same launch
+  // copies); the vertex classes c_vr0 .. ncolours - 1 follow (wheels or interface tasks)
+  bool fused_iface = false;
+  int c_vr0 = 0;
+  std::vector<int32_t> dvcopy;
+  int32_t* d_dvcopy = nullptr;
+  int64_t off_dvcopy = 0;
+  // vertex classes by wheels (k_iface2d_wheels): one lane per DoF copy, 64 per wavefront;
+  // wh_info = macro | mask << 24 | (class - c_vr0) << 28, wh_loc = i | j << 11, wh_seg = lead
+  // lane | copies << 8, wh_src = two words per lane with the lane of each direction's
+  // neighbour (8 bits per direction 1..4, then 5..6; 0xff: from memory), wh_wmax per wavefront
+  bool wheels = false;
+  std::vector<int32_t> wh_copy, wh_info, wh_loc, wh_seg, wh_src, wh_wmax;
+  std::vector<double> wh_cw;          // per lane: kappa, then the 7 unit weights (struct of arrays)
+  int32_t *d_whcopy = nullptr, *d_whinfo = nullptr, *d_whloc = nullptr, *d_whseg = nullptr, *d_whsrc = nullptr,
+          *d_whwmax = nullptr;
+  double* d_whcw = nullptr;
+  int64_t off_whcopy = 0, off_whinfo = 0, off_whloc = 0, off_whseg = 0, off_whsrc = 0, off_whwmax = 0,
+          off_whcw = 0;
   std::vector<int32_t> tiles;          // 2D: interior tiles (ti | tj << 16) of the fused sweep
   std::vector<uint32_t> itab;          // 3D, n <= kMacroLdsN: interior points (i | j << 10 | k << 20)
   int32_t* d_tiles = nullptr;
@@ -153,6 +179,7 @@ struct hhg_ctx_s {
   std::vector<uint16_t> dirbits, ownbits;
   std::vector<int32_t> rbpar;       // nC * 4
   std::vector<double> stiff, mass, elemK;
+  std::vector<int32_t> erec;        // 2D edge records of the edge-class sweep (kEdgeRecWords per edge)
   std::vector<uint16_t> validdirs;  // [16] bitmask of valid directions per zero-set mask
   std::vector<uint32_t> incvalid;   // [16] bitmask of valid incident (type, vertex) pairs
 
@@ -177,7 +204,7 @@ struct hhg_ctx_s {
   // workspace offsets of tables
   int64_t o_stiff = 0, o_mass = 0, o_elemK = 0, o_kappa = 0, o_subprim = 0, o_suborder = 0, o_dirbits = 0,
           o_ownbits = 0, o_rbpar = 0, o_incoff = 0, o_inc = 0, o_primdir = 0, o_ccopyoff = 0, o_ccopy = 0,
-          o_ainv = 0, o_red = 0, o_scal = 0, o_mxyz = 0, o_aux0 = 0, o_aux1 = 0;
+          o_ainv = 0, o_red = 0, o_scal = 0, o_mxyz = 0, o_aux0 = 0, o_aux1 = 0, o_erec = 0;
   int64_t red_capacity = 0;         // doubles in the reduction scratch
   double* d_red = nullptr;          // reduction scratch
   double* d_scal = nullptr;         // small scalar scratch
@@ -199,16 +226,22 @@ struct hhg_ctx_s {
   bool no_tasks = false;            // force the per-DoF interface kernels (testing)
   // HIP graphs of the launch-bound sequences (FMG body; one extra cycle with its residual
   // norm), recorded once per parameter set on a private capture stream and replayed on the
-  // caller's stream; key = kind | nu << 4 | pre << 12 | post << 20 | precision << 28
+  // caller's stream; key = kind | nu << 4 | pre << 12 | post << 20 | precision << 28 |
+  // xswap << 32, key2 = the number of fixed extra cycles (kind 4)
   bool no_graph = false;            // run every launch eagerly (testing)
   bool no_preload = false;          // single-workgroup interface sweep without preloading (testing)
   bool force_rows3d = false;        // 3D row kernels at every level (testing)
   bool force_stream3d = false;      // 3D plane-streaming sweep from n = 4 on (testing)
   bool generic_est = false;         // 2D L2 estimate by the one-thread-per-node kernel (testing)
+  bool classwise_iface = false;     // 2D interface classes one launch each (testing)
   uint32_t xswap = 0;               // bit l (+16 for float32): level l's iterate is in its second buffer
   void* cap_stream = nullptr;       // hipStream_t used only while recording
   bool capturing = false;
-  std::vector<std::pair<int64_t, void*>> graphs;   // (key, hipGraphExec_t)
+  struct Recorded {
+    int64_t key, key2;              // launch sequence and parameters (graph_key), extra count
+    void* exec;                     // hipGraphExec_t
+  };
+  std::vector<Recorded> graphs;
   double prof_bytes = 0.0;
 
   std::string err;
@@ -222,6 +255,7 @@ hhg_status build_stencils(hhg_ctx c);
 hhg_status build_colouring(hhg_ctx c);
 hhg_status build_coarse(hhg_ctx c, const double* kappa_vertex /* nullable, per vertex */);
 void plan_workspace(hhg_ctx c);
+void fill_kappa_tables(hhg_ctx c);
 
 // index helpers shared by host code
 int64_t tet_count(int64_t m);

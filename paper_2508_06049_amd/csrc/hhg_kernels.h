@@ -41,6 +41,17 @@ void launch_iface_tasks_1wg(int dim, const LK& lk, const Tables& tb, const int32
                             const int32_t* tco, const int32_t* tseg, const int32_t* wmax, const int32_t* woff, int c0,
                             int c1, const T* xi, const T* xf, T* uout, T* umirror, const T* b, double sA, bool pre,
                             hipStream_t st);
+// 2D: both edge classes of a sweep in one launch (edge chunks; erec: one record of
+// kEdgeRecWords words per macro edge), plus the copies of the Dirichlet vertex values
+template <typename T>
+void launch_iface2d_edges(const LK& lk, const int32_t* erec, int nE, const int32_t* dvcopy, int n_dv, const T* xi,
+                          const T* xf, T* uout, T* umirror, const T* b, double sA, hipStream_t st);
+// 2D: the vertex classes c_vr0 .. c_vr0 + ncls - 1 of a sweep by wheels, one launch
+template <typename T>
+void launch_iface2d_wheels(const LK& lk, const Tables& tb, const int32_t* wcopy, const int32_t* winfo,
+                           const int32_t* wloc, const int32_t* wseg, const int32_t* wsrc, const double* wcw,
+                           const int32_t* wwmax, int nwaves, int ncls, const T* xi, const T* xf, T* uout, T* umirror,
+                           const T* b, double sA, hipStream_t st);
 // classes the preloading single-workgroup interface form holds at once
 int iface_pre_classes(int dim, bool dbl);
 template <typename T>

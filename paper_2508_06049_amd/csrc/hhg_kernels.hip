@@ -844,6 +844,282 @@ __global__ void __launch_bounds__(1024) k_iface_tasks_1wg_pre(LK lk, Tables tb, 
   }
 }
 
+// The two 2D edge classes of one level in one launch.  Wavefront v of workgroup g takes chunk
+// v mod nch (64 consecutive points a = 1 + 64 c .. 64 c + 64) of edge g * epb + v / nch, so
+// an edge's chunks sit in consecutive wavefronts of one workgroup.  Everything the edge needs
+// (incident macros, their vertex slots and zero-set masks, coefficients and stencils) is one
+// record of kEdgeRecWords words read by the scalar unit; the point addresses follow from a.
+// On a Dirichlet edge the wavefront copies the fixed values into the output buffers.
+// Otherwise it updates the class a even (2 <= a <= n - 2) from the loaded old values, hands
+// the new values to the odd class through LDS (a workgroup barrier between the two), and
+// updates the odd class; the points next to the vertices (a = 1, n - 1) keep their old
+// values, they belong to the vertex classes that follow.  A point's row is the sum of the
+// partial rows of its (at most two) incident macros, summed in the order of the lane-parallel
+// class kernels (identical results).  The copies of the Dirichlet vertices (dvcopy) are
+// copied into the output buffers on the side.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_iface2d_edges(LK lk, const int32_t* __restrict__ erec, int nE, int nch,
+                                                         int epb, const int32_t* __restrict__ dvcopy, int n_dv,
+                                                         const T* xi, const T* xf, T* uout, T* umirror,
+                                                         const T* __restrict__ b, double sA) {
+  __shared__ T s_e0[1024 + 2];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = (int)(threadIdx.x & 63);
+  const int n = lk.n;
+  const int e = (int)blockIdx.x * epb + wave / nch, chunk = wave - (wave / nch) * nch;
+  const bool has = wave < epb * nch && e < nE;
+  const bool same = xi == xf;
+  // per lane: position a on the edge, its copies k < ncp (closure index cp[k]); per copy the
+  // partial row: right-hand side, diagonal, and per direction the weight, the neighbour value
+  // and whether the neighbour is the edge point a - 1 or a + 1 (side -1 / +1)
+  int a = 0, ncp = 0;
+  bool dir = false, isE = false;
+  int64_t cp[2] = {0, 0};
+  T rhs[2] = {(T)0, (T)0}, dg[2] = {(T)0, (T)0};
+  T coef[2][kNDir2 - 1], val[2][kNDir2 - 1];
+  int side[2][kNDir2 - 1];
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int dd = 0; dd < kNDir2 - 1; ++dd) { coef[k][dd] = (T)0; val[k][dd] = (T)0; side[k][dd] = 0; }
+  uint32_t vmask[2] = {0u, 0u};
+  if (has) {
+    const int32_t* R = erec + (size_t)e * kEdgeRecWords;
+    const int hdr = R[0];
+    ncp = min(hdr & 3, 2);   // 1 or 2 (checked by the host)
+    dir = (hdr >> 2) & 1;
+    a = 1 + 64 * chunk + lane;
+    if (a <= n - 1) {
+      isE = !dir && a >= 2 && a <= n - 2;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        if (k >= ncp) break;
+        const int32_t* C = R + 2 + kEdgeCopyWords * k;
+        const int macro = C[0], sl = C[1];
+        const int s0 = sl & 3, s1 = (sl >> 8) & 3, mask = (sl >> 16) & 15;
+        int lc[3] = {0, 0, 0};
+        lc[s0] = n - a;
+        lc[s1] = a;
+        const int i = lc[1], j = lc[2];
+        const int64_t base = (int64_t)macro * lk.S;
+        cp[k] = base + d_lin2(n, i, j);
+        if (!isE) continue;
+        rhs[k] = b[cp[k]];
+        const double* KW = reinterpret_cast<const double*>(C + 2);   // kappa, then the 7 weights
+        const uint32_t valid = (uint32_t)C[18];
+        vmask[k] = valid;
+        const double scale = sA * KW[0];
+#pragma unroll
+        for (int dd = 1; dd < kNDir2; ++dd) {
+          if (!((valid >> dd) & 1)) continue;
+          int o0, o1, o2;
+          d_off<2>(dd, o0, o1, o2);
+          const int i2 = i + o0, j2 = j + o1;
+          const int m2 = d_mask<2>(n, i2, j2, 0);
+          const int64_t ix = base + d_lin2(n, i2, j2);
+          coef[k][dd - 1] = (T)(scale * KW[1 + dd]);
+          val[k][dd - 1] = same ? xf[ix] : (m2 ? xf : xi)[ix];
+          if (m2) {
+            // a neighbour on the macro boundary lies on this edge (or is one of its vertices)
+            const int cc[3] = {n - i2 - j2, i2, j2};
+            const int a2 = cc[s1];
+            side[k][dd - 1] = (a2 >= 1 && a2 <= n - 1) ? a2 - a : 0;
+          }
+        }
+        dg[k] = (T)(scale * KW[1]);
+      }
+    }
+  }
+  auto update = [&]() -> T {
+    T snum = (T)0, sdiag = (T)0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (k >= ncp) break;
+      T off = (T)0;
+#pragma unroll
+      for (int dd = 1; dd < kNDir2; ++dd) {
+        if (!((vmask[k] >> dd) & 1)) continue;
+        off += coef[k][dd - 1] * val[k][dd - 1];
+      }
+      snum += rhs[k] - off;
+      sdiag += dg[k];
+    }
+    return snum / sdiag;
+  };
+  auto store = [&](T v) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (k >= ncp) break;
+      uout[cp[k]] = v;
+      if (umirror) umirror[cp[k]] = v;
+    }
+  };
+  const bool even = isE && (a & 1) == 0, odd = isE && (a & 1) == 1;
+  T u = (T)0;
+  if (even) {
+    u = update();
+    store(u);
+  }
+  s_e0[threadIdx.x + 1] = u;
+  __syncthreads();
+  if (odd) {
+    // both edge neighbours are in the even class: their new values come from LDS (the
+    // previous or next chunk of the edge sits in the neighbouring wavefront)
+    const T um = s_e0[threadIdx.x], up = s_e0[threadIdx.x + 2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int dd = 0; dd < kNDir2 - 1; ++dd) {
+        if (side[k][dd] == -1) val[k][dd] = um;
+        if (side[k][dd] == 1) val[k][dd] = up;
+      }
+    store(update());
+  }
+  if (dir && has && a <= n - 1) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (k >= ncp) break;
+      const T v = xf[cp[k]];
+      uout[cp[k]] = v;
+      if (umirror) umirror[cp[k]] = v;
+    }
+  }
+  for (int q = (int)(blockIdx.x * 1024 + threadIdx.x); q < n_dv; q += (int)(gridDim.x * 1024)) {
+    const int c = dvcopy[q];
+    const T v = xf[c];
+    uout[c] = v;
+    if (umirror) umirror[c] = v;
+  }
+}
+
+template <typename T>
+void launch_iface2d_edges(const LK& lk, const int32_t* erec, int nE, const int32_t* dvcopy, int n_dv, const T* xi,
+                          const T* xf, T* uout, T* umirror, const T* b, double sA, hipStream_t st) {
+  if (nE <= 0 && n_dv <= 0) return;
+  const int nch = (lk.n - 1 + 63) / 64, epb = 16 / nch;
+  const unsigned g = (unsigned)std::max(1, (nE + epb - 1) / epb);
+  k_iface2d_edges<T><<<g, 1024, 0, st>>>(lk, erec, nE, nch, epb, dvcopy, n_dv, xi, xf, uout, umirror, b, sA);
+}
+template void launch_iface2d_edges<double>(const LK&, const int32_t*, int, const int32_t*, int, const double*,
+                                           const double*, double*, double*, const double*, double, hipStream_t);
+template void launch_iface2d_edges<float>(const LK&, const int32_t*, int, const int32_t*, int, const float*,
+                                          const float*, float*, float*, const float*, double, hipStream_t);
+
+// The 2D vertex classes of one level by wheels: a wheel is a macro vertex with the edge points
+// next to it, and no point of one wheel touches another when n >= 4.  One lane per copy of
+// each DoF of a wheel, the wheel's lanes inside one wavefront, its DoFs in class order.  Every
+// lane loads its partial row once; then for each class in turn the lanes take the current
+// values of same-wheel neighbours from the lanes holding them (new after their class, old
+// before), the lanes of the class sum their partial rows over the copies of their DoF as the
+// lane-parallel class kernel does (identical results), and keep the new value.  Neighbours
+// outside the wheel (interior and edge-class points, already swept, and Dirichlet points)
+// come from memory.
+template <typename T>
+__global__ void __launch_bounds__(256) k_iface2d_wheels(LK lk, Tables tb, const int32_t* __restrict__ wcopy,
+                                                         const int32_t* __restrict__ winfo,
+                                                         const int32_t* __restrict__ wloc,
+                                                         const int32_t* __restrict__ wseg,
+                                                         const int32_t* __restrict__ wsrc,
+                                                         const double* __restrict__ wcw,
+                                                         const int32_t* __restrict__ wwmax, int nwaves, int ncls,
+                                                         const T* xi, const T* xf, T* uout, T* umirror,
+                                                         const T* __restrict__ b, double sA) {
+  const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+  if (w >= nwaves) return;
+  const int n = lk.n;
+  const int lane = (int)(threadIdx.x & 63);
+  const int idx = w * 64 + lane;
+  const int cp = wcopy[idx], info = winfo[idx], loc = wloc[idx], seg = wseg[idx];
+  const uint32_t sa = (uint32_t)wsrc[2 * idx], sb = (uint32_t)wsrc[2 * idx + 1];
+  const int wm = wwmax[w];
+  const bool live = cp >= 0;
+  const bool same = xi == xf;
+  T rhs = (T)0, dg = (T)0, u = (T)0;
+  T coef[kNDir2 - 1], val[kNDir2 - 1];
+#pragma unroll
+  for (int dd = 0; dd < kNDir2 - 1; ++dd) { coef[dd] = (T)0; val[dd] = (T)0; }
+  uint32_t valid = 0;
+  int cls = -1;
+  if (live) {
+    const int m = info & 0xffffff, mask = (info >> 24) & 15;
+    cls = (info >> 28) & 15;
+    const int i = loc & 2047, j = loc >> 11;
+    const int64_t base = (int64_t)m * lk.S;
+    u = xf[cp];
+    rhs = b[cp];
+    // the lane's coefficient and unit stencil for its mask, one table entry per lane (struct
+    // of arrays: kappa, then the 7 weights)
+    const int nl = nwaves * 64;
+    double W[kNDir2];
+#pragma unroll
+    for (int dd = 0; dd < kNDir2; ++dd) W[dd] = wcw[(size_t)(1 + dd) * nl + idx];
+    valid = tb.validdirs[mask];
+    const double scale = sA * wcw[idx];
+#pragma unroll
+    for (int dd = 1; dd < kNDir2; ++dd) {
+      if (!((valid >> dd) & 1)) continue;
+      int o0, o1, o2;
+      d_off<2>(dd, o0, o1, o2);
+      const int i2 = i + o0, j2 = j + o1;
+      const int64_t ix = base + d_lin2(n, i2, j2);
+      coef[dd - 1] = (T)(scale * W[dd]);
+      val[dd - 1] = same ? xf[ix] : (d_mask<2>(n, i2, j2, 0) ? xf : xi)[ix];
+    }
+    dg = (T)(scale * W[0]);
+  }
+  const int lead = seg & 63, len = seg >> 8;
+  for (int c = 0; c < ncls; ++c) {
+#pragma unroll
+    for (int dd = 1; dd < kNDir2; ++dd) {
+      const int s = (int)(((dd <= 4 ? sa >> (8 * (dd - 1)) : sb >> (8 * (dd - 5)))) & 0xffu);
+      const T v = __shfl(u, s == 0xff ? lane : s, 64);
+      if (s != 0xff) val[dd - 1] = v;
+    }
+    const bool mine = live && cls == c;
+    T num = (T)0, diag = (T)0;
+    if (mine) {
+      T off = (T)0;
+#pragma unroll
+      for (int dd = 1; dd < kNDir2; ++dd) {
+        if (!((valid >> dd) & 1)) continue;
+        off += coef[dd - 1] * val[dd - 1];
+      }
+      num = rhs - off;
+      diag = dg;
+    }
+    T snum = (T)0, sdiag = (T)0;
+    for (int kq = 0; kq < wm; ++kq) {
+      const int src = min(lead + kq, 63);
+      const T a = __shfl(num, src, 64), d = __shfl(diag, src, 64);
+      if (kq < len) { snum += a; sdiag += d; }
+    }
+    if (mine) u = snum / sdiag;
+  }
+  if (live) {
+    uout[cp] = u;
+    if (umirror) umirror[cp] = u;
+  }
+}
+
+template <typename T>
+void launch_iface2d_wheels(const LK& lk, const Tables& tb, const int32_t* wcopy, const int32_t* winfo,
+                           const int32_t* wloc, const int32_t* wseg, const int32_t* wsrc, const double* wcw,
+                           const int32_t* wwmax, int nwaves, int ncls, const T* xi, const T* xf, T* uout, T* umirror,
+                           const T* b, double sA, hipStream_t st) {
+  if (nwaves <= 0 || ncls <= 0) return;
+  const unsigned g = (unsigned)((nwaves + 3) / 4);
+  k_iface2d_wheels<T><<<g, 256, 0, st>>>(lk, tb, wcopy, winfo, wloc, wseg, wsrc, wcw, wwmax, nwaves, ncls, xi, xf,
+                                          uout, umirror, b, sA);
+}
+template void launch_iface2d_wheels<double>(const LK&, const Tables&, const int32_t*, const int32_t*, const int32_t*,
+                                            const int32_t*, const int32_t*, const double*, const int32_t*, int, int,
+                                            const double*, const double*, double*, double*, const double*, double,
+                                            hipStream_t);
+template void launch_iface2d_wheels<float>(const LK&, const Tables&, const int32_t*, const int32_t*, const int32_t*,
+                                           const int32_t*, const int32_t*, const double*, const int32_t*, int, int,
+                                           const float*, const float*, float*, float*, const float*, double,
+                                           hipStream_t);
+
 // The same assembled residual rows from the interface tasks: one lane per (DoF, incident
 // macro) pair forms its macro's term b_m - A_m x, the lanes of a DoF sum the terms in
 // incidence order through shuffles, and the first lane (the lowest-id copy) stores the sum;

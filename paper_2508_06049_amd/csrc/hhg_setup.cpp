@@ -397,11 +397,49 @@ static int interior_colour(hhg_ctx c, int l, int m, int i, int j, int k) {
   return c->dim == 2 ? (i + 2 * j) % 3 : (i + 2 * j + 3 * k) % 4;
 }
 
+// 2D Gauss-Seidel: an edge point at distance a (2 <= a <= n - 2) from the edge's lower-id
+// vertex sweeps in class Cint + (a mod 2); it touches only interior points, its own edge and
+// the vertex neighbourhoods (a = 1, a = n - 1, macro vertices), which follow from Cint + 2
+static bool edge_class_2d(hhg_ctx c, const Level& lv, int p, const int co[3]) {
+  return c->dim == 2 && c->opt.smoother != HHG_JACOBI && p >= c->nV && p < c->nV + c->nE && co[1] >= 2 &&
+         co[1] <= lv.n - 2;
+}
+
 hhg_status build_colouring(hhg_ctx c) {
   // Sweep order: macro-interior colour classes 0..Cint-1, then interface classes Cint, ...
+  // (2D: the two edge classes Cint, Cint + 1, then the vertex neighbourhoods from Cint + 2)
   const int d = c->dim;
   const int ND = d == 3 ? kNDir3 : kNDir2;
   const int Cint = c->opt.smoother == HHG_JACOBI ? 1 : (c->opt.smoother == HHG_GS_REDBLACK ? 2 : (d == 2 ? 3 : 4));
+  const int Cvr = d == 2 && c->opt.smoother != HHG_JACOBI ? Cint + 2 : Cint;
+  // 2D edge records of the edge-class sweep (kEdgeRecWords words per macro edge; the
+  // coefficients are filled in at upload, fill_kappa_tables)
+  c->erec.clear();
+  bool erec_ok = d == 2 && c->opt.smoother != HHG_JACOBI && c->opt.coefficient == HHG_KAPPA_MACRO;
+  if (erec_ok) {
+    c->erec.assign((size_t)c->nE * kEdgeRecWords, 0);
+    for (int64_t e = 0; e < c->nE && erec_ok; ++e) {
+      const int p = (int)(c->nV + e);
+      const int cnt = c->inc_off[p + 1] - c->inc_off[p];
+      if (cnt < 1 || cnt > 2) { erec_ok = false; break; }
+      int32_t* Rr = &c->erec[(size_t)e * kEdgeRecWords];
+      Rr[0] = cnt | (c->primdir[p] ? 4 : 0);
+      for (int k = 0; k < cnt; ++k) {
+        const Inc& in = c->inc[c->inc_off[p] + k];
+        if (in.macro < 0 || in.macro >= c->nC || in.slot[0] > 2 || in.slot[1] > 2 || in.mask >= kMaxMask) {
+          erec_ok = false;
+          break;
+        }
+        int32_t* Cc = Rr + 2 + kEdgeCopyWords * k;
+        Cc[0] = in.macro;
+        Cc[1] = in.slot[0] | (in.slot[1] << 8) | (in.mask << 16);
+        double* KW = reinterpret_cast<double*>(Cc + 2);
+        for (int dd = 0; dd < kNDir2; ++dd) KW[1 + dd] = c->stiff[((size_t)in.macro * kMaxMask + in.mask) * kNDir2 + dd];
+        Cc[18] = (int32_t)c->validdirs[in.mask];
+      }
+    }
+    if (!erec_ok) c->erec.clear();
+  }
   for (auto& lv : c->lev) {
     std::vector<int> col(lv.nIface, -1);
     for (int64_t t = 0; t < lv.nIface; ++t) {
@@ -413,11 +451,13 @@ hhg_status build_colouring(hhg_ctx c) {
       int np = p < c->nV ? 1 : (p < c->nV + c->nE ? 2 : 3);
       for (int r = 0; r < np; ++r) cc[in0.slot[r]] = co[r];
       if (c->opt.smoother == HHG_JACOBI) { col[t] = Cint; continue; }
+      if (edge_class_2d(c, lv, p, co)) { col[t] = Cint + (co[1] & 1); continue; }
       if (c->opt.smoother == HHG_GS_REDBLACK) {
-        col[t] = Cint + interior_colour(c, lv.l, in0.macro, cc[1], cc[2], cc[3]);
+        col[t] = Cvr + interior_colour(c, lv.l, in0.macro, cc[1], cc[2], cc[3]);
         continue;
       }
-      // greedy first fit against the interface neighbours coloured so far
+      // greedy first fit against the neighbours of the same kind coloured so far (2D: vertex
+      // neighbourhoods only; the edge classes lie below Cvr)
       uint64_t used = 0;
       for (int q = c->inc_off[p]; q < c->inc_off[p + 1]; ++q) {
         const Inc& in = c->inc[q];
@@ -433,7 +473,7 @@ hhg_status build_colouring(hhg_ctx c) {
           if (cn >= 0 && cn < 64) used |= (1ull << cn);
         }
       }
-      int cnew = Cint;
+      int cnew = Cvr;
       while ((used >> cnew) & 1) ++cnew;
       col[t] = cnew;
     }
@@ -523,6 +563,147 @@ hhg_status build_colouring(hhg_ctx c) {
       } else {
         lv.task_copy.clear(); lv.task_info.clear(); lv.task_loc.clear(); lv.task_seg.clear();
         lv.task_woff.assign(lv.ncolours + 1, 0);
+      }
+    }
+    // 2D levels whose edge classes are too large for the single-workgroup interface sweep:
+    // both edge classes in one launch by edge chunks (at most two incident macros per edge, at
+    // most 16 chunks), which also copies the Dirichlet vertex values; indices checked here
+    lv.fused_iface = false;
+    lv.dvcopy.clear();
+    lv.c_vr0 = Cint + 2;
+    if (d == 2 && lv.task_ok && erec_ok && lv.n >= 4 && lv.n <= 1024 && lv.ncolours >= Cint + 2) {
+      bool ok = true;
+      for (int64_t v = 0; v < c->nV && ok; ++v) {
+        if (!c->primdir[v]) continue;
+        for (int q = c->inc_off[v]; q < c->inc_off[v + 1]; ++q) {
+          const Inc& in = c->inc[q];
+          int lc[3] = {0, 0, 0};
+          lc[in.slot[0]] = lv.n;
+          const int64_t loc = lin_closure(2, lv.n, lc[1], lc[2], 0);
+          if (in.macro < 0 || in.macro >= c->nC || loc < 0 || loc >= lv.Sraw) { ok = false; break; }
+          lv.dvcopy.push_back((int32_t)(in.macro * lv.S + loc));
+        }
+      }
+      lv.fused_iface = ok;
+      if (!ok) lv.dvcopy.clear();
+    }
+    // the vertex classes of such a level by vertex neighbourhoods ("wheels"): a macro vertex
+    // and the edge points next to it (a = 1 from it) touch no other vertex neighbourhood when
+    // n >= 4, so one wavefront sweeps all vertex classes of a wheel in order, passing new
+    // values between lanes; a wheel's lanes (one per copy of each DoF, DoFs in class order)
+    // never split across wavefronts
+    lv.wheels = false;
+    lv.wh_copy.clear(); lv.wh_info.clear(); lv.wh_loc.clear(); lv.wh_seg.clear(); lv.wh_src.clear();
+    lv.wh_wmax.clear(); lv.wh_cw.clear();
+    if (lv.fused_iface && lv.ncolours - lv.c_vr0 <= 15) {
+      bool ok = true;
+      const int n = lv.n;
+      std::vector<int> ev0(c->nE), ev1(c->nE);
+      std::vector<std::vector<int>> vedges(c->nV);
+      for (int64_t e = 0; e < c->nE; ++e) {
+        const Inc& in = c->inc[c->inc_off[c->nV + e]];
+        ev0[e] = c->cells[in.macro * 3 + in.slot[0]];
+        ev1[e] = c->cells[in.macro * 3 + in.slot[1]];
+        vedges[ev0[e]].push_back((int)e);
+        vedges[ev1[e]].push_back((int)e);
+      }
+      // lead lane (within its wavefront) of every interface DoF placed so far, -1 otherwise
+      std::vector<int> lead_of(lv.nIface, -1), wheel_of(lv.nIface, -1);
+      int64_t placed = 0;
+      for (int v = 0; v < c->nV && ok; ++v) {
+        std::vector<int64_t> dofs;
+        if (!c->primdir[v]) dofs.push_back(v);
+        for (int e : vedges[v]) {
+          if (c->primdir[c->nV + e]) continue;
+          const int a = v == ev0[e] ? 1 : n - 1;
+          dofs.push_back(c->nV + (int64_t)e * lv.nEd + (a - 1));
+        }
+        for (int64_t t : dofs)
+          if (col[t] < lv.c_vr0) ok = false;
+        if (!ok || dofs.empty()) continue;
+        std::sort(dofs.begin(), dofs.end(), [&](int64_t x, int64_t y) { return col[x] != col[y] ? col[x] < col[y] : x < y; });
+        int lanes = 0;
+        for (int64_t t : dofs) {
+          int p, co[3];
+          iface_decode(c, lv, t, p, co);
+          lanes += c->inc_off[p + 1] - c->inc_off[p];
+        }
+        if (lanes > 64) { ok = false; break; }
+        if ((int)(lv.wh_copy.size() % 64) + lanes > 64)
+          while (lv.wh_copy.size() % 64) {
+            lv.wh_copy.push_back(-1); lv.wh_info.push_back(0); lv.wh_loc.push_back(0); lv.wh_seg.push_back(0);
+          }
+        for (int64_t t : dofs) {
+          int p, co[3];
+          iface_decode(c, lv, t, p, co);
+          const int lead = (int)(lv.wh_copy.size() % 64), cnt = c->inc_off[p + 1] - c->inc_off[p];
+          lead_of[t] = lead;
+          wheel_of[t] = v;
+          const int np = p < c->nV ? 1 : 2;
+          for (int q = c->inc_off[p]; q < c->inc_off[p + 1]; ++q) {
+            const Inc& in = c->inc[q];
+            int lc[4] = {0, 0, 0, 0};
+            for (int r = 0; r < np; ++r) lc[in.slot[r]] = co[r];
+            const int64_t loc = lin_closure(2, n, lc[1], lc[2], 0);
+            if (loc < 0 || loc >= lv.Sraw || zero_mask(2, n, lc[1], lc[2], 0) != in.mask) { ok = false; break; }
+            lv.wh_copy.push_back((int32_t)(in.macro * lv.S + loc));
+            lv.wh_info.push_back(in.macro | (in.mask << 24) | ((col[t] - lv.c_vr0) << 28));
+            lv.wh_loc.push_back(lc[1] | (lc[2] << 11));
+            lv.wh_seg.push_back(lead | (cnt << 8));
+          }
+        }
+        placed += (int64_t)dofs.size();
+      }
+      // every vertex-class DoF sits in exactly one wheel
+      int64_t nvr = 0;
+      for (int64_t t = 0; t < lv.nIface; ++t)
+        if (col[t] >= lv.c_vr0) ++nvr;
+      if (placed != nvr) ok = false;
+      while (lv.wh_copy.size() % 64) {
+        lv.wh_copy.push_back(-1); lv.wh_info.push_back(0); lv.wh_loc.push_back(0); lv.wh_seg.push_back(0);
+      }
+      // per lane and direction: the lane holding that neighbour if it is a DoF of the same
+      // wheel (0xff otherwise: read from memory); no vertex-class neighbour may lie outside
+      for (size_t idx = 0; idx < lv.wh_copy.size() && ok; ++idx) {
+        uint32_t sa = 0xffffffffu, sb = 0xffffffffu;
+        if (lv.wh_copy[idx] >= 0) {
+          const int m = lv.wh_info[idx] & 0xffffff, mask = (lv.wh_info[idx] >> 24) & 15;
+          const int i = lv.wh_loc[idx] & 2047, j = lv.wh_loc[idx] >> 11;
+          // the DoF of this lane
+          const int64_t tself = canonical_index(c, lv, m, i, j, 0);
+          for (int dd = 1; dd < kNDir2; ++dd) {
+            if (!((c->validdirs[mask] >> dd) & 1)) continue;
+            const int i2 = i + kOff2[dd][0], j2 = j + kOff2[dd][1];
+            if (zero_mask(2, n, i2, j2, 0) == 0) continue;
+            const int64_t tn = canonical_index(c, lv, m, i2, j2, 0);
+            if (tn < 0 || tn >= lv.nIface) { ok = false; break; }
+            if (col[tn] < lv.c_vr0) continue;   // edge class or Dirichlet: from memory
+            if (wheel_of[tn] != wheel_of[tself] || lead_of[tn] < 0) { ok = false; break; }
+            const uint32_t sl = (uint32_t)lead_of[tn];
+            if (dd <= 4) sa = (sa & ~(0xffu << (8 * (dd - 1)))) | (sl << (8 * (dd - 1)));
+            else sb = (sb & ~(0xffu << (8 * (dd - 5)))) | (sl << (8 * (dd - 5)));
+          }
+        }
+        lv.wh_src.push_back((int32_t)sa);
+        lv.wh_src.push_back((int32_t)sb);
+      }
+      // per lane: the macro's coefficient (filled in at upload) and its unit stencil weights
+      // for the lane's mask, as a struct of arrays
+      const size_t nl = lv.wh_copy.size();
+      lv.wh_cw.assign(nl * (kNDir2 + 1), 0.0);
+      for (size_t idx = 0; idx < nl; ++idx) {
+        if (lv.wh_copy[idx] < 0) continue;
+        const int m = lv.wh_info[idx] & 0xffffff, mask = (lv.wh_info[idx] >> 24) & 15;
+        for (int dd = 0; dd < kNDir2; ++dd) lv.wh_cw[(1 + dd) * nl + idx] = c->stiff[((size_t)m * kMaxMask + mask) * kNDir2 + dd];
+      }
+      const int nw = (int)(lv.wh_copy.size() / 64);
+      lv.wh_wmax.assign(nw, 0);
+      for (int w = 0; w < nw; ++w)
+        for (int q = 0; q < 64; ++q) lv.wh_wmax[w] = std::max(lv.wh_wmax[w], lv.wh_seg[w * 64 + q] >> 8);
+      lv.wheels = ok;
+      if (!ok) {
+        lv.wh_copy.clear(); lv.wh_info.clear(); lv.wh_loc.clear(); lv.wh_seg.clear(); lv.wh_src.clear();
+        lv.wh_wmax.clear(); lv.wh_cw.clear();
       }
     }
     // tables of the fused interior sweeps
@@ -654,6 +835,20 @@ hhg_status build_coarse(hhg_ctx c, const double* kappa_vertex) {
   return HHG_OK;
 }
 
+// the per-macro coefficients inside the edge records and the wheel lane tables
+void fill_kappa_tables(hhg_ctx c) {
+  for (int64_t e = 0; e < (int64_t)(c->erec.size() / kEdgeRecWords); ++e) {
+    int32_t* Rr = &c->erec[(size_t)e * kEdgeRecWords];
+    for (int k = 0; k < (Rr[0] & 3); ++k) {
+      int32_t* Cc = Rr + 2 + kEdgeCopyWords * k;
+      reinterpret_cast<double*>(Cc + 2)[0] = c->kappa_cell[Cc[0]];
+    }
+  }
+  for (auto& lv : c->lev)
+    for (size_t idx = 0; idx < lv.wh_copy.size(); ++idx)
+      if (lv.wh_copy[idx] >= 0) lv.wh_cw[idx] = c->kappa_cell[lv.wh_info[idx] & 0xffffff];
+}
+
 // ---------------------------------------------------------------------------------------
 // workspace plan
 static int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
@@ -693,6 +888,7 @@ void plan_workspace(hhg_ctx c) {
   }
   c->o_red = take(c->red_capacity * 8);
   c->o_scal = take(64 * 8);
+  c->o_erec = take((int64_t)c->erec.size() * 4);
   c->o_mxyz = take(nC * nv * d * 8);
   c->o_aux0 = take(lt.nfull * 8);
   c->o_aux1 = take(lt.nfull * 8);
@@ -717,6 +913,14 @@ void plan_workspace(hhg_ctx c) {
     lv.off_tseg = take((int64_t)lv.task_seg.size() * 4);
     lv.off_twmax = take((int64_t)lv.task_wmax.size() * 4);
     lv.off_twoff = take((int64_t)lv.task_woff.size() * 4);
+    lv.off_dvcopy = take((int64_t)lv.dvcopy.size() * 4);
+    lv.off_whcw = take((int64_t)lv.wh_cw.size() * 8);
+    lv.off_whcopy = take((int64_t)lv.wh_copy.size() * 4);
+    lv.off_whinfo = take((int64_t)lv.wh_info.size() * 4);
+    lv.off_whloc = take((int64_t)lv.wh_loc.size() * 4);
+    lv.off_whseg = take((int64_t)lv.wh_seg.size() * 4);
+    lv.off_whsrc = take((int64_t)lv.wh_src.size() * 4);
+    lv.off_whwmax = take((int64_t)lv.wh_wmax.size() * 4);
     // second iterate buffers of the out-of-place fused sweeps (2D, and 3D with streaming tiles)
     lv.off_x2 = take(d == 2 || !lv.tiles.empty() ? nf * 8 : 0);
     lv.off_x2_32 = take(d == 2 || !lv.tiles.empty() ? nf * 4 : 0);

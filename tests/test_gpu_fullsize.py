@@ -342,3 +342,29 @@ def test_largest_3d_level():
     assert np.all(np.isfinite(est["eta_T"])) and est["norm_e"] > 0
     u64, s64 = hh.fmg_solve(f, g, nu=1, rtol=1e-8, max_iter=60)
     assert rel_err(to_host(u32), to_host(u64)) < 1e-6
+
+
+@pytest.mark.parametrize("L,precision", [(4, "fp64"), (6, "fp32_refined"), (9, "fp64"), (9, "fp32_refined")])
+def test_one_launch_interface_equals_classwise(lshape, L, precision):
+    # all interface classes of a 2D sweep in one launch (the edge classes by edge chunks, the
+    # vertex classes in the last workgroup to finish) against one launch per class (or per run
+    # of small classes): three sweeps from a random iterate, then a solve, bitwise identical
+    import torch
+    from paper_2508_06049_amd import HHG
+    from paper_2508_06049_amd._lib import HHG_FLAG_CLASSWISE_IFACE
+    w = lshape
+    _note("one-launch vs classwise interface", w.name, L, precision)
+    out = []
+    for flags in (0, HHG_FLAG_CLASSWISE_IFACE):
+        hh = HHG(w.mesh.coords, w.mesh.cells, L, smoother=w.smoother, flags=flags)
+        X = hh.dof_coords().cpu().numpy()
+        rng = np.random.default_rng(7)
+        ua = to_dev(rng.standard_normal(len(X)))
+        hh.smooth(L, ua, to_dev(rng.standard_normal(len(X))), 3)
+        u, st = hh.fmg_solve(to_dev(w.f(X)), to_dev(w.g(X)), nu=1, precision=precision, rtol=0.0, max_iter=2)
+        out.append((to_host(ua), to_host(u)))
+        hh.close()
+        del hh
+        torch.cuda.synchronize()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])

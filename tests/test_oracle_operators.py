@@ -138,3 +138,35 @@ def test_colour_sweep_equals_pointwise_gauss_seidel():
         for i in np.nonzero(s.col == c)[0]:
             u2[i] = (b[i] - A[i] @ u2 + A[i, i] * u2[i]) / A[i, i]
     assert np.abs(u1 - u2).max() < 1e-12
+
+
+@pytest.mark.parametrize("mk,L,rule", [(meshes.unit_square_2tri, 5, "redblack"), (meshes.lshape_6tri, 5, "multicolour"),
+                                       (lambda: meshes.unit_square_grid(4), 4, "multicolour"),
+                                       (lambda: meshes.unit_square_grid(4), 3, "redblack")])
+def test_2d_edge_classes_touch_only_their_own_edge(mk, L, rule):
+    # the reading that lets one wavefront sweep both edge classes of an edge segment: a node of
+    # the two edge classes (C, C + 1) lies on a macro edge at distance 2 <= a <= n - 2 from its
+    # lower-id vertex, its class is C + (a mod 2), and each of its mesh neighbours is interior,
+    # on the same macro edge, or in a later (vertex) class
+    h = _h(mk, L)
+    C = 2 if rule == "redblack" else 3
+    for l in range(L + 1):
+        lv = h.levels[l]
+        n = 2 ** l
+        col = colour.red_black(h, l) if rule == "redblack" else colour.multicolour(h, l)
+        a = colour.edge_position_2d(h, l)
+        gv = h.coarse_cells[lv.node_macro]
+        sup = lv.node_bary > 0
+        def edge_of(i):
+            return tuple(sorted(int(v) for v in gv[i][sup[i]])) if sup[i].sum() == 2 else None
+        G = colour.mesh_graph(lv)
+        inner = sup.sum(axis=1) == 3
+        E = np.nonzero((col == C) | (col == C + 1))[0]
+        assert np.all((a[E] >= 2) & (a[E] <= n - 2))
+        assert np.all(col[E] == C + a[E] % 2)
+        for i in E:
+            for q in G.indices[G.indptr[i]:G.indptr[i + 1]]:
+                assert inner[q] or edge_of(q) == edge_of(i) or col[q] >= C + 2 or col[q] == -1
+        # every edge point with 2 <= a <= n - 2 off the Dirichlet boundary is in them
+        want = (a >= 2) & (a <= n - 2) & ~lv.boundary
+        assert np.array_equal(np.sort(E), np.nonzero(want)[0])
