@@ -156,6 +156,22 @@ hhg_status hhg_workspace_bytes(hhg_ctx ctx, size_t* bytes);
  * stream (NULL = default stream); uploads tables.  Must precede every device call. */
 hhg_status hhg_bind_workspace(hhg_ctx ctx, void* device_ptr, size_t bytes, void* hip_stream);
 
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc): bind the library's own static workspace instead of caller memory, a variant of
+ * hhg_bind_workspace that allocates nothing (no hipMalloc, no HIP events, no graphs).  The
+ * workspace is one file-scope device array of HHG_STATIC_WORKSPACE_BYTES per device, held
+ * until the process ends; its address on the current device is looked up once.  A context
+ * needing more (hhg_workspace_bytes) gets HHG_ENOMEM.  The part the context uses is cleared
+ * by a fill kernel on the given stream (NULL = default stream) and the tables are uploaded
+ * from host memory (hipMemcpyAsync); the call synchronises the stream.
+ * One context per device holds the array: binding another context to it leaves the previous
+ * one unbound (its calls return HHG_ESTATE until it is bound again), and the caller must let
+ * the previous owner's work finish first; calls of several threads or streams that overlap on
+ * one device race.  Contexts bound this way run every launch eagerly (no recorded graphs) and
+ * report ms_total = 0 in hhg_solve_stats.  Binding with hhg_bind_workspace releases the array. */
+#define HHG_STATIC_WORKSPACE_BYTES (64u << 20)
+hhg_status hhg_bind_static_workspace(hhg_ctx ctx, void* hip_stream);
+
 /* Number of DoFs (including Dirichlet ones) on a level, 0 <= level <= L. */
 hhg_status hhg_num_dofs(hhg_ctx ctx, int level, int64_t* n);
 

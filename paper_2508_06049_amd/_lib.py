@@ -64,6 +64,7 @@ _SIGS = {
     "hhg_setup": (C.c_int, [C.POINTER(hhg_mesh), C.c_int, C.POINTER(hhg_options), C.POINTER(_ctx)]),
     "hhg_workspace_bytes": (C.c_int, [_ctx, C.POINTER(C.c_size_t)]),
     "hhg_bind_workspace": (C.c_int, [_ctx, _dp, C.c_size_t, C.c_void_p]),
+    "hhg_bind_static_workspace": (C.c_int, [_ctx, C.c_void_p]),
     "hhg_num_dofs": (C.c_int, [_ctx, C.c_int, C.POINTER(C.c_int64)]),
     "hhg_dof_coords": (C.c_int, [_ctx, C.c_int, _dp]),
     "hhg_set_kappa_cell": (C.c_int, [_ctx, C.POINTER(C.c_double)]),
@@ -185,7 +186,10 @@ class HHG:
     """One HHG context bound to a torch-allocated workspace on a CUDA (HIP) device."""
 
     def __init__(self, coords, cells, L: int, smoother: str = "redblack", coefficient: str = "macro",
-                 kappa_cell=None, dirichlet=None, omega: float = 0.0, device="cuda:0", flags: int = 0):
+                 kappa_cell=None, dirichlet=None, omega: float = 0.0, device="cuda:0", flags: int = 0,
+                 workspace: str = "torch"):
+        """workspace: "torch" (device memory allocated here by torch, hhg_bind_workspace) or
+        "static" (the library's static workspace, hhg_bind_static_workspace: no allocation)."""
         import torch
         self.lib = load()
         self.dim = int(np.asarray(coords).shape[1])
@@ -197,11 +201,18 @@ class HHG:
         _check(self.lib.hhg_workspace_bytes(self.ctx, C.byref(nb)), self.ctx)
         self.device = torch.device(device)
         self.stream = torch.cuda.current_stream(self.device)
-        self.workspace = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
-        base = self.workspace.data_ptr()
-        aligned = (base + 255) // 256 * 256
-        _check(self.lib.hhg_bind_workspace(self.ctx, aligned, int(nb.value), C.c_void_p(self.stream.cuda_stream)),
-               self.ctx)
+        if workspace == "static":
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                _check(self.lib.hhg_bind_static_workspace(self.ctx, C.c_void_p(self.stream.cuda_stream)), self.ctx)
+        elif workspace == "torch":
+            self.workspace = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            aligned = (base + 255) // 256 * 256
+            _check(self.lib.hhg_bind_workspace(self.ctx, aligned, int(nb.value), C.c_void_p(self.stream.cuda_stream)),
+                   self.ctx)
+        else:
+            raise ValueError(f"workspace must be 'torch' or 'static', not {workspace!r}")
         self.workspace_bytes = int(nb.value)
 
     # --- basics -----------------------------------------------------------------------------

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -309,7 +310,8 @@ void drop_graphs(hhg_ctx c) {
 // out-of-place sweep swaps the two iterate buffers).
 template <class F>
 hhg_status run_recorded(hhg_ctx c, int64_t key, F&& body, int64_t key2 = 0) {
-  if (c->no_graph || c->prof_on || c->capturing) return body();
+  // no graphs with the static workspace: instantiating one allocates
+  if (c->no_graph || c->static_ws || c->prof_on || c->capturing) return body();
   hipGraphExec_t ex = nullptr;
   for (auto& g : c->graphs)
     if (g.key == key && g.key2 == key2) ex = (hipGraphExec_t)g.exec;
@@ -658,8 +660,26 @@ hhg_status bind_impl(hhg_ctx c, void* ptr, void* stream, bool no_alloc) {
 }
 
 
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};      // device address of scratch per device (looked up once)
+hhg_ctx g_static_owner[kMaxDevices] = {};  // the context bound to it per device
+
+// release c's claim on a static workspace (rebinding, destruction)
+void release_static(hhg_ctx c) {
+  if (c->static_dev < 0) return;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (g_static_owner[c->static_dev] == c) g_static_owner[c->static_dev] = nullptr;
+  c->static_dev = -1;
+}
+
 }  // namespace
 
+// The static workspace of hhg_bind_static_workspace: one array per device, found through
+// hipGetSymbolAddress on first use on that device; host code uses only those addresses.
+static __device__ __align__(256) unsigned char scratch[HHG_STATIC_WORKSPACE_BYTES];
+
+// =========================================================================================
 extern "C" {
 
 const char* hhg_status_string(hhg_status s) {
@@ -755,9 +775,51 @@ hhg_status hhg_bind_workspace(hhg_ctx c, void* ptr, size_t bytes, void* stream) 
   if (!c) return HHG_EINVAL;
   if (!ptr || bytes < c->ws_bytes) { c->err = "workspace too small"; return HHG_ENOMEM; }
   if (((uintptr_t)ptr & 255) != 0) { c->err = "workspace must be 256-byte aligned"; return HHG_EINVAL; }
+  release_static(c);
+  c->static_ws = false;
   return bind_impl(c, ptr, stream, false);
 }
 
+hhg_status hhg_bind_static_workspace(hhg_ctx c, void* stream) {
+  if (!c) return HHG_EINVAL;
+  if (c->ws_bytes > (size_t)HHG_STATIC_WORKSPACE_BYTES) {
+    c->err = "the context needs " + std::to_string(c->ws_bytes) + " bytes of workspace, more than the " +
+             std::to_string((size_t)HHG_STATIC_WORKSPACE_BYTES) + " bytes of the static workspace";
+    return HHG_ENOMEM;
+  }
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) { c->err = "device index beyond the static workspace table"; return HHG_EINVAL; }
+  void* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) {
+        c->err = std::string("hipGetSymbolAddress of the static workspace: ") + hipGetErrorString(e);
+        return HHG_EHIP;
+      }
+      g_static_ptr[dev] = p;
+    }
+    ptr = g_static_ptr[dev];
+    hhg_ctx prev = g_static_owner[dev];
+    if (prev && prev != c) {
+      // the previous owner's tables are about to be overwritten: it needs a new binding
+      prev->bound = false;
+      prev->solved = prev->have_u = false;
+      prev->static_dev = -1;
+    }
+    if (c->static_dev >= 0 && c->static_dev != dev && g_static_owner[c->static_dev] == c)
+      g_static_owner[c->static_dev] = nullptr;
+    g_static_owner[dev] = c;
+    c->static_dev = dev;
+  }
+  c->static_ws = true;
+  const hhg_status s = bind_impl(c, ptr, stream, true);
+  if (s != HHG_OK) release_static(c);
+  return s;
+}
 
 hhg_status hhg_num_dofs(hhg_ctx c, int level, int64_t* n) {
   if (!c || !n) return HHG_EINVAL;
@@ -1195,6 +1257,7 @@ void hhg_destroy(hhg_ctx c) {
   if (!c) return;
   // recorded launches may still run: finish them before their executable graphs go
   if (c->bound) (void)hipStreamSynchronize(ST(c));
+  release_static(c);
   drop_graphs(c);
   if (c->cap_stream) (void)hipStreamDestroy((hipStream_t)c->cap_stream);
   for (void* e : c->prof_ev) (void)hipEventDestroy((hipEvent_t)e);

@@ -214,6 +214,8 @@ struct hhg_ctx_s {
   double* d_aux0 = nullptr;         // level-L scratch: the recomputed solution inside hhg_adjoint
   double* d_aux1 = nullptr;         // level-L scratch: reference iterate of the residual norm
 
+  bool static_ws = false;           // bound to the library's static workspace (no graphs, no events)
+  int static_dev = -1;              // device whose static workspace this context holds (-1: none)
   void* ev0 = nullptr;              // hipEvent_t pair for timing
   void* ev1 = nullptr;
   int last_nu = 0;                  // FMG parameters of the last solve (estimator needs L >= 2)
