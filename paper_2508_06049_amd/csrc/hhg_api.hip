@@ -223,12 +223,18 @@ template <typename T>
 hhg_status coarse_step(hhg_ctx c, const T* b, bool x_is_zero) {
   Level& l0 = c->lev[0];
   T* x = Arr<T>::x(l0);
+  auto solve = [&](const T* rhs, int acc) {
+    if (c->coarse_factored)
+      launch_coarse_factored<T>(c->n0, c->d_ccopy_off, c->d_ccopy, c->d_cperm, c->d_ainv, c->d_cscr, rhs, x, acc, ST(c));
+    else
+      launch_coarse<T>(c->n0, c->d_ccopy_off, c->d_ccopy, c->d_ainv, rhs, x, acc, ST(c));
+  };
   if (x_is_zero) {
-    launch_coarse<T>(c->n0, c->d_ccopy_off, c->d_ccopy, c->d_ainv, b, x, 0, ST(c));
+    solve(b, 0);
   } else {
     T* r = Arr<T>::t(l0);
     launch_apply<T, T>(c->dim, p1(c), lk_of(c, 0), c->tab, x, b, r, 0, sA(c, 0), 1.0, -1.0, 1, l0.kn, ST(c));
-    launch_coarse<T>(c->n0, c->d_ccopy_off, c->d_ccopy, c->d_ainv, r, x, 1, ST(c));
+    solve(r, 1);
   }
   LAUNCHCHK();
   return HHG_OK;
@@ -475,8 +481,11 @@ hhg_status validate_params(hhg_ctx c, const hhg_solve_params* p) {
 }
 
 hhg_status upload_coarse(hhg_ctx c) {
-  if (c->n0 > 0)
+  if (c->n0 > 0) {
     HIPCHK(hipMemcpyAsync(c->d_ainv, c->Ainv.data(), c->Ainv.size() * 8, hipMemcpyHostToDevice, ST(c)));
+    HIPCHK(hipMemcpyAsync(c->d_cperm, c->coarse_perm.data(), c->coarse_perm.size() * 4, hipMemcpyHostToDevice,
+                          ST(c)));
+  }
   HIPCHK(hipStreamSynchronize(ST(c)));
   return HHG_OK;
 }
@@ -598,6 +607,8 @@ hhg_status bind_impl(hhg_ctx c, void* ptr, void* stream, bool no_alloc) {
   c->d_ccopy_off = (int32_t*)(w + c->o_ccopyoff);
   c->d_ccopy = (int64_t*)(w + c->o_ccopy);
   c->d_ainv = (double*)(w + c->o_ainv);
+  c->d_cperm = (int32_t*)(w + c->o_cperm);
+  c->d_cscr = (double*)(w + c->o_cscr);
   c->d_aux0 = (double*)(w + c->o_aux0);
   c->d_aux1 = (double*)(w + c->o_aux1);
   for (auto& lv : c->lev) {

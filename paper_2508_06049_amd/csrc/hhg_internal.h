@@ -51,6 +51,9 @@ constexpr int kTaskOneGroupWaves = 32;
 // unit stencil weights for that mask (doubles, words 2..17), then the mask's valid directions
 constexpr int kEdgeCopyWords = 20;
 constexpr int kEdgeRecWords = 2 + 2 * kEdgeCopyWords;
+// level 0 is solved by its explicit inverse up to this many inner vertices, above it by the
+// factored form (envelope Cholesky after reverse Cuthill-McKee)
+constexpr int kCoarseDenseMax = 2048;
 // blocks of the interior part of a squared norm (one partial each)
 constexpr int kNormBlocks = 8192;
 // interior rows per wavefront of the 2D row estimator
@@ -188,7 +191,9 @@ struct hhg_ctx_s {
   std::vector<int32_t> coarse_vertex;      // inner vertex ids
   std::vector<int32_t> coarse_copy_off;    // CSR into coarse_copy
   std::vector<int64_t> coarse_copy;        // full-layout indices at level 0
-  std::vector<double> Ainv;                // n0 * n0
+  std::vector<double> Ainv;                // n0 * n0: the inverse, or X = L^{-1} (factored form)
+  bool coarse_factored = false;            // n0 > kCoarseDenseMax: x = P^T X^T X P r
+  std::vector<int32_t> coarse_perm;        // position -> inner vertex (reverse Cuthill-McKee)
 
   std::vector<hhg::Level> lev;
   hhg::Tables tab;
@@ -204,13 +209,15 @@ struct hhg_ctx_s {
   // workspace offsets of tables
   int64_t o_stiff = 0, o_mass = 0, o_elemK = 0, o_kappa = 0, o_subprim = 0, o_suborder = 0, o_dirbits = 0,
           o_ownbits = 0, o_rbpar = 0, o_incoff = 0, o_inc = 0, o_primdir = 0, o_ccopyoff = 0, o_ccopy = 0,
-          o_ainv = 0, o_red = 0, o_scal = 0, o_mxyz = 0, o_aux0 = 0, o_aux1 = 0, o_erec = 0;
+          o_ainv = 0, o_red = 0, o_scal = 0, o_mxyz = 0, o_aux0 = 0, o_aux1 = 0, o_erec = 0, o_cperm = 0, o_cscr = 0;
   int64_t red_capacity = 0;         // doubles in the reduction scratch
   double* d_red = nullptr;          // reduction scratch
   double* d_scal = nullptr;         // small scalar scratch
   int32_t* d_ccopy_off = nullptr;
   int64_t* d_ccopy = nullptr;
   double* d_ainv = nullptr;
+  int32_t* d_cperm = nullptr;       // factored level 0: permutation, and two n0 scratch vectors
+  double* d_cscr = nullptr;
   double* d_aux0 = nullptr;         // level-L scratch: the recomputed solution inside hhg_adjoint
   double* d_aux1 = nullptr;         // level-L scratch: reference iterate of the residual norm
 

@@ -86,6 +86,10 @@ void launch_init_dirichlet(int dim, const LK& lk, const Tables& tb, const double
 template <typename T>
 void launch_coarse(int n0, const int32_t* coff, const int64_t* copy, const double* Ainv, const T* rhs, T* x, int accumulate,
                    hipStream_t st);
+// level 0 in factored form: x (+)= P^T X^T X P rhs (scr: 2 n0 doubles of scratch)
+template <typename T>
+void launch_coarse_factored(int n0, const int32_t* coff, const int64_t* copy, const int32_t* perm, const double* X,
+                            double* scr, const T* rhs, T* x, int accumulate, hipStream_t st);
 void launch_sqnorm(int dim, const LK& lk, const Tables& tb, const double* r, double* partial, double* out, hipStream_t st);
 // sum of squares of every closure entry (interface rows assembled in one copy)
 template <typename T>

@@ -2032,6 +2032,54 @@ __global__ void __launch_bounds__(256) k_coarse(int n0, const int32_t* __restric
   }
 }
 
+// factored level-0 solve, x (+)= P^T X^T X P r with X = L^{-1} (column-major lower triangle,
+// zeros above the diagonal) and perm[p] the inner vertex at position p.  Three launches:
+// s = P r (summing each inner vertex's copies of the dual right-hand side), y = X s (one thread
+// per row, columns in ascending order), x_p = (X^T y)_p (one workgroup per column p, a
+// fixed-order block reduction) written to every copy of vertex perm[p]
+template <typename T>
+__global__ void __launch_bounds__(256) k_coarse_gather(int n0, const int32_t* __restrict__ coff,
+                                                        const int64_t* __restrict__ copy,
+                                                        const int32_t* __restrict__ perm, const T* __restrict__ rhs,
+                                                        double* __restrict__ s) {
+  const int p = (int)(blockIdx.x * 256 + threadIdx.x);
+  if (p >= n0) return;
+  const int r = perm[p];
+  double t = 0.0;
+  for (int q = coff[r]; q < coff[r + 1]; ++q) t += (double)rhs[copy[q]];
+  s[p] = t;
+}
+
+__global__ void __launch_bounds__(256) k_coarse_fwd(int n0, const double* __restrict__ X, const double* __restrict__ s,
+                                                     double* __restrict__ y) {
+  const int i = (int)(blockIdx.x * 256 + threadIdx.x);
+  // the wavefront's rows end at iw; X is zero above the diagonal, so the row sums need no
+  // per-lane bounds inside the loop
+  const int iw = min(n0 - 1, (int)(blockIdx.x * 256 + (threadIdx.x & ~63u)) + 63);
+  const int ii = min(i, n0 - 1);
+  double acc = 0.0;
+  for (int j = 0; j <= iw; ++j) acc += X[(size_t)j * n0 + ii] * s[j];
+  if (i < n0) y[i] = acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_coarse_bwd(int n0, const double* __restrict__ X, const double* __restrict__ y,
+                                                     const int32_t* __restrict__ coff, const int64_t* __restrict__ copy,
+                                                     const int32_t* __restrict__ perm, T* __restrict__ x,
+                                                     int accumulate) {
+  __shared__ double sh[4];
+  const int p = (int)blockIdx.x;
+  double acc = 0.0;
+  for (int i = p + (int)threadIdx.x; i < n0; i += 256) acc += X[(size_t)p * n0 + i] * y[i];
+  const double e = block_sum(acc, sh);
+  if (threadIdx.x != 0) return;
+  const int r = perm[p];
+  for (int q = coff[r]; q < coff[r + 1]; ++q) {
+    const int64_t ix = copy[q];
+    x[ix] = accumulate ? (T)((double)x[ix] + e) : (T)e;
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // reductions
 // sum over macro-interior nodes of r^2 (per block partials)
@@ -2680,8 +2728,22 @@ template <typename T>
 void launch_coarse(int n0, const int32_t* coff, const int64_t* copy, const double* Ainv, const T* rhs, T* x, int accumulate,
                    hipStream_t st) {
   if (n0 <= 0) return;
+  // the explicit inverse serves n0 <= kCoarseDenseMax (16 KiB of LDS at most)
   k_coarse<T><<<nblk(n0), 256, (size_t)n0 * sizeof(double), st>>>(n0, coff, copy, Ainv, rhs, x, accumulate);
 }
+
+template <typename T>
+void launch_coarse_factored(int n0, const int32_t* coff, const int64_t* copy, const int32_t* perm, const double* X,
+                            double* scr, const T* rhs, T* x, int accumulate, hipStream_t st) {
+  if (n0 <= 0) return;
+  k_coarse_gather<T><<<nblk(n0), 256, 0, st>>>(n0, coff, copy, perm, rhs, scr);
+  k_coarse_fwd<<<nblk(n0), 256, 0, st>>>(n0, X, scr, scr + n0);
+  k_coarse_bwd<T><<<(unsigned)n0, 256, 0, st>>>(n0, X, scr + n0, coff, copy, perm, x, accumulate);
+}
+template void launch_coarse_factored<double>(int, const int32_t*, const int64_t*, const int32_t*, const double*,
+                                             double*, const double*, double*, int, hipStream_t);
+template void launch_coarse_factored<float>(int, const int32_t*, const int64_t*, const int32_t*, const double*,
+                                            double*, const float*, float*, int, hipStream_t);
 
 void launch_sqnorm(int dim, const LK& lk, const Tables& tb, const double* r, double* partial, double* out, hipStream_t st) {
   // 2D: one wavefront per row; 3D: one block per 256-entry chunk of a macro block

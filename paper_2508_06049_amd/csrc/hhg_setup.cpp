@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <numeric>
+#include <thread>
 
 #include "hhg_internal.h"
 #include "hhg_lattice.h"
@@ -760,7 +761,12 @@ hhg_status build_colouring(hhg_ctx c) {
 }
 
 // ---------------------------------------------------------------------------------------
-// level 0: dense inverse of the inner block of A_0
+// level 0: exact solve on the inner coarse vertices.  Up to kCoarseDenseMax of them: the
+// explicit inverse of the inner block (one matrix-vector product per solve).  More (the
+// coarse mesh of a kl loop grows with every k-step): the inner block is renumbered by reverse
+// Cuthill-McKee, factored P A P^T = L L^T by an envelope Cholesky (the fill stays inside the
+// profile of the renumbered matrix), and the solve applies x = P^T X^T X P r with X = L^{-1},
+// a dense lower triangle computed column by column on the host threads.
 hhg_status build_coarse(hhg_ctx c, const double* kappa_vertex) {
   const int d = c->dim, nv = d + 1;
   std::vector<int> idx(c->nV, -1);
@@ -781,9 +787,13 @@ hhg_status build_coarse(hhg_ctx c, const double* kappa_vertex) {
     }
   }
   c->coarse_copy_off[n0] = (int32_t)c->coarse_copy.size();
+  c->coarse_factored = n0 > kCoarseDenseMax;
+  c->coarse_perm.assign(n0, 0);
+  std::iota(c->coarse_perm.begin(), c->coarse_perm.end(), 0);
   c->Ainv.assign((size_t)n0 * n0, 0.0);
   if (n0 == 0) return HHG_OK;
-  std::vector<double> A((size_t)n0 * n0, 0.0);
+  // inner block of A_0, row by row (sparse)
+  std::vector<std::map<int, double>> rows(n0);
   for (int64_t m = 0; m < c->nC; ++m) {
     const int* cv = &c->cells[m * nv];
     double y[4][3] = {{0}};
@@ -799,39 +809,126 @@ hhg_status build_coarse(hhg_ctx c, const double* kappa_vertex) {
     for (int a = 0; a < nv; ++a)
       for (int b = 0; b < nv; ++b) {
         int ra = idx[cv[a]], rb = idx[cv[b]];
-        if (ra >= 0 && rb >= 0) A[(size_t)ra * n0 + rb] += kap * K[a][b];
+        if (ra >= 0 && rb >= 0) rows[ra][rb] += kap * K[a][b];
       }
   }
-  // Cholesky A = R^T R (upper R stored in A), then inverse column by column
-  for (int k = 0; k < n0; ++k) {
-    const double akk = A[(size_t)k * n0 + k];
-    double s = akk;
-    for (int q = 0; q < k; ++q) s -= A[(size_t)q * n0 + k] * A[(size_t)q * n0 + k];
-    if (!(s > 1e-10 * akk)) { c->err = "level-0 matrix is not positive definite (no Dirichlet boundary?)"; return HHG_EINVAL; }
-    double rkk = std::sqrt(s);
-    A[(size_t)k * n0 + k] = rkk;
-    for (int j = k + 1; j < n0; ++j) {
-      double t = A[(size_t)k * n0 + j];
-      for (int q = 0; q < k; ++q) t -= A[(size_t)q * n0 + k] * A[(size_t)q * n0 + j];
-      A[(size_t)k * n0 + j] = t / rkk;
+  const char* spd = "level-0 matrix is not positive definite (no Dirichlet boundary?)";
+  if (!c->coarse_factored) {
+    std::vector<double> A((size_t)n0 * n0, 0.0);
+    for (int r = 0; r < n0; ++r)
+      for (const auto& kv : rows[r]) A[(size_t)r * n0 + kv.first] = kv.second;
+    // Cholesky A = R^T R (upper R stored in A), then inverse column by column
+    for (int k = 0; k < n0; ++k) {
+      const double akk = A[(size_t)k * n0 + k];
+      double s = akk;
+      for (int q = 0; q < k; ++q) s -= A[(size_t)q * n0 + k] * A[(size_t)q * n0 + k];
+      if (!(s > 1e-10 * akk)) { c->err = spd; return HHG_EINVAL; }
+      double rkk = std::sqrt(s);
+      A[(size_t)k * n0 + k] = rkk;
+      for (int j = k + 1; j < n0; ++j) {
+        double t = A[(size_t)k * n0 + j];
+        for (int q = 0; q < k; ++q) t -= A[(size_t)q * n0 + k] * A[(size_t)q * n0 + j];
+        A[(size_t)k * n0 + j] = t / rkk;
+      }
+    }
+    std::vector<double> y(n0), x(n0);
+    for (int col = 0; col < n0; ++col) {
+      // R^T y = e_col
+      for (int i = 0; i < n0; ++i) {
+        double t = (i == col) ? 1.0 : 0.0;
+        for (int q = 0; q < i; ++q) t -= A[(size_t)q * n0 + i] * y[q];
+        y[i] = t / A[(size_t)i * n0 + i];
+      }
+      // R x = y
+      for (int i = n0 - 1; i >= 0; --i) {
+        double t = y[i];
+        for (int q = i + 1; q < n0; ++q) t -= A[(size_t)i * n0 + q] * x[q];
+        x[i] = t / A[(size_t)i * n0 + i];
+      }
+      for (int i = 0; i < n0; ++i) c->Ainv[(size_t)i * n0 + col] = x[i];
+    }
+    return HHG_OK;
+  }
+  // reverse Cuthill-McKee: breadth-first from a low-degree start vertex of every component,
+  // neighbours by increasing degree, order reversed; perm[p] = inner vertex at position p
+  std::vector<int> deg(n0), order;
+  order.reserve(n0);
+  for (int r = 0; r < n0; ++r) deg[r] = (int)rows[r].size();
+  std::vector<char> seen(n0, 0);
+  std::vector<int> byDeg(n0);
+  std::iota(byDeg.begin(), byDeg.end(), 0);
+  std::stable_sort(byDeg.begin(), byDeg.end(), [&](int x, int y) { return deg[x] < deg[y]; });
+  for (int start : byDeg) {
+    if (seen[start]) continue;
+    size_t head = order.size();
+    order.push_back(start);
+    seen[start] = 1;
+    while (head < order.size()) {
+      const int r = order[head++];
+      std::vector<int> nb;
+      for (const auto& kv : rows[r])
+        if (!seen[kv.first]) { nb.push_back(kv.first); seen[kv.first] = 1; }
+      std::stable_sort(nb.begin(), nb.end(), [&](int x, int y) { return deg[x] < deg[y]; });
+      order.insert(order.end(), nb.begin(), nb.end());
     }
   }
-  std::vector<double> y(n0), x(n0);
-  for (int col = 0; col < n0; ++col) {
-    // R^T y = e_col
-    for (int i = 0; i < n0; ++i) {
-      double t = (i == col) ? 1.0 : 0.0;
-      for (int q = 0; q < i; ++q) t -= A[(size_t)q * n0 + i] * y[q];
-      y[i] = t / A[(size_t)i * n0 + i];
-    }
-    // R x = y
-    for (int i = n0 - 1; i >= 0; --i) {
-      double t = y[i];
-      for (int q = i + 1; q < n0; ++q) t -= A[(size_t)i * n0 + q] * x[q];
-      x[i] = t / A[(size_t)i * n0 + i];
-    }
-    for (int i = 0; i < n0; ++i) c->Ainv[(size_t)i * n0 + col] = x[i];
+  std::reverse(order.begin(), order.end());
+  std::vector<int> pos(n0);
+  for (int p = 0; p < n0; ++p) { c->coarse_perm[p] = order[p]; pos[order[p]] = p; }
+  // envelope of the renumbered matrix: row i holds columns f[i] .. i of L
+  std::vector<int> f(n0);
+  std::vector<int64_t> rs(n0 + 1, 0);
+  for (int i = 0; i < n0; ++i) {
+    int fi = i;
+    for (const auto& kv : rows[order[i]]) fi = std::min(fi, pos[kv.first]);
+    f[i] = fi;
+    rs[i + 1] = rs[i] + (i - fi + 1);
   }
+  std::vector<double> Lv(rs[n0], 0.0);
+  auto L = [&](int i, int j) -> double& { return Lv[rs[i] + (j - f[i])]; };
+  for (int i = 0; i < n0; ++i)
+    for (const auto& kv : rows[order[i]]) {
+      const int j = pos[kv.first];
+      if (j <= i) L(i, j) = kv.second;
+    }
+  // up-looking envelope Cholesky
+  for (int i = 0; i < n0; ++i) {
+    for (int j = f[i]; j < i; ++j) {
+      double t = L(i, j);
+      for (int k = std::max(f[i], f[j]); k < j; ++k) t -= L(i, k) * L(j, k);
+      L(i, j) = t / L(j, j);
+    }
+    const double aii = L(i, i);
+    double t = aii;
+    for (int k = f[i]; k < i; ++k) t -= L(i, k) * L(i, k);
+    if (!(t > 1e-10 * aii)) { c->err = spd; return HHG_EINVAL; }
+    L(i, i) = std::sqrt(t);
+  }
+  // X = L^{-1}, column-major (X[col * n0 + row], zero above the diagonal): column c solves
+  // L x = e_c; the columns are independent and split over the host threads
+  double* X = c->Ainv.data();
+  auto columns = [&](int c0, int c1) {
+    for (int col = c0; col < c1; ++col) {
+      double* x = X + (size_t)col * n0;
+      x[col] = 1.0 / L(col, col);
+      for (int i = col + 1; i < n0; ++i) {
+        double t = 0.0;
+        for (int k = std::max(f[i], col); k < i; ++k) t += L(i, k) * x[k];
+        x[i] = -t / L(i, i);
+      }
+    }
+  };
+  const int nt = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  // columns near the start cost the most (longest solves): deal them out round-robin in blocks
+  std::vector<std::vector<std::pair<int, int>>> work(nt);
+  const int blk = 16;
+  for (int c0 = 0, t = 0; c0 < n0; c0 += blk, t = (t + 1) % nt) work[t].push_back({c0, std::min(n0, c0 + blk)});
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&, t]() {
+      for (auto& r : work[t]) columns(r.first, r.second);
+    });
+  for (auto& th : pool) th.join();
   return HHG_OK;
 }
 
@@ -874,6 +971,8 @@ void plan_workspace(hhg_ctx c) {
   c->o_ccopyoff = take((int64_t)(c->n0 + 1) * 4);
   c->o_ccopy = take((int64_t)c->coarse_copy.size() * 8 + 8);
   c->o_ainv = take((int64_t)c->n0 * c->n0 * 8 + 8);
+  c->o_cperm = take((int64_t)c->n0 * 4 + 4);
+  c->o_cscr = take((int64_t)c->n0 * 2 * 8 + 16);
   // reduction scratch: per macro per block (4 values) on the finest level, and per block norms
   const Level& lt = c->lev[c->L];
   int64_t bpm = (lt.Sraw + 255) / 256;

@@ -14,7 +14,9 @@ with at most one hanging node.
 3D red-green (Algorithm 3): red-refine marked cells; repeatedly red-refine every face that
 has more than one hanging node on its boundary; cells with more than three hanging nodes
 become red; finally every cell with hanging nodes is closed by one of three green types
-(one, two or three new vertices on its faces, each face following the 2D rule).
+(one, two or three new vertices on its faces, each face following the 2D rule).  Coarsening
+merges the eight red children of a parent back when all are marked leaves, drops the
+midpoints no leaf uses any more, and runs the same closure again.
 """
 from __future__ import annotations
 
@@ -215,7 +217,9 @@ class RedGreen3D:
             raise ValueError("RedGreen3D needs a tetrahedral mesh")
         self.X = [tuple(float(v) for v in p) for p in mesh.coords]
         self.tets = [tuple(int(v) for v in t) for t in mesh.cells]
-        self.mid = {}
+        self.mid = {}          # edge -> midpoint vertex, for the midpoints that currently exist
+        self._mid_all = {}     # edge -> midpoint vertex ever created (reused after coarsening)
+        self.children = {}     # red parent -> its 8 children
         self._last_parent = None
 
     def _midpoint(self, a, b, create=True):
@@ -223,14 +227,18 @@ class RedGreen3D:
         if e not in self.mid:
             if not create:
                 return None
-            pa, pb = self.X[a], self.X[b]
-            self.X.append(tuple(0.5 * (x + y) for x, y in zip(pa, pb)))
-            self.mid[e] = len(self.X) - 1
+            if e not in self._mid_all:
+                pa, pb = self.X[a], self.X[b]
+                self.X.append(tuple(0.5 * (x + y) for x, y in zip(pa, pb)))
+                self._mid_all[e] = len(self.X) - 1
+            self.mid[e] = self._mid_all[e]
         return self.mid[e]
 
     def _red(self, t):
         loc = list(t) + [self._midpoint(t[a], t[b]) for a, b in _TET_EDGES]
-        return [tuple(loc[i] for i in c) for c in _BEY]
+        ch = [tuple(loc[i] for i in c) for c in _BEY]
+        self.children[t] = ch
+        return ch
 
     def _hanging_edges(self, t):
         return [k for k, (a, b) in enumerate(_TET_EDGES) if (min(t[a], t[b]), max(t[a], t[b])) in self.mid]
@@ -272,7 +280,13 @@ class RedGreen3D:
     def refine(self, marked_cells) -> None:
         if self._last_parent is None:
             self.conforming()
-        red = {self._last_parent[i] for i in marked_cells}
+        self._closure({self._last_parent[i] for i in marked_cells})
+        self._last_parent = None
+
+    def _closure(self, red):
+        """Red-refine the leaves `red` (indices into self.tets), then close: faces with more
+        than one hanging node on their boundary get all three edge midpoints, and cells with
+        more than three hanging nodes are refined red, until nothing changes."""
         while True:
             tets = []
             for ti, t in enumerate(self.tets):
@@ -293,7 +307,40 @@ class RedGreen3D:
             red = {ti for ti, t in enumerate(self.tets) if self._n_hanging(t) > 3}
             if not red:
                 break
+
+    def coarsen(self, marked_cells) -> int:
+        """Merge red sibling groups back into their parents, the inverse of red refinement
+        (cells: indices into the last conforming() output; a marked green cell marks its red
+        parent leaf).  All groups whose eight children are marked leaves merge at once; the
+        midpoints that no remaining leaf has as a vertex are dropped, and the closure of
+        Algorithm 3 (face rule, red for more than three hanging nodes) runs again, which
+        re-splits a merged parent that the surrounding refinement does not allow.  Merged
+        parents count as marked, so coarsening repeats upwards while it makes progress.
+        Returns the number of merged groups."""
+        if self._last_parent is None:
+            self.conforming()
+        marked = {self.tets[self._last_parent[i]] for i in marked_cells}
+        merged = 0
+        while True:
+            leaves = set(self.tets)
+            groups = [P for P, ch in self.children.items() if all(c in leaves and c in marked for c in ch)]
+            if not groups:
+                break
+            drop = {c for P in groups for c in self.children[P]}
+            self.tets = [t for t in self.tets if t not in drop] + groups
+            used = {v for t in self.tets for v in t}
+            self.mid = {e: m for e, m in self.mid.items() if m in used}
+            self._closure(set())
+            leaves = set(self.tets)
+            kept = [P for P in groups if P in leaves]
+            if not kept:
+                break
+            for P in kept:
+                del self.children[P]
+                marked.add(P)
+            merged += len(kept)
         self._last_parent = None
+        return merged
 
     def _green(self, t):
         he = self._hanging_edges(t)

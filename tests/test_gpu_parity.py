@@ -275,6 +275,39 @@ def test_fmg_matches(name, smoother, nu, extra):
         assert st.vcycles == nu * L
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_factored_level0_matches(precision):
+    # a coarse mesh with more than 5000 inner vertices ((0,2) x (0,1) in 128 x 64 squares of
+    # side 1/64, 16,384 triangles, 8,001 inner vertices): level 0 is solved in factored form
+    # (reverse Cuthill-McKee, envelope Cholesky, X = L^-1 and X^T applied on the device)
+    # instead of by an explicit inverse; FMG and two extra cycles against the oracle's (dense
+    # Cholesky at level 0).  The coordinates are dyadic, so both codes discretise the same
+    # problem exactly (with a grid of side 1/72 the rounded vertex coordinates alone move the
+    # discrete solution by about cond(A) eps ~ 1e-12)
+    m = meshes.rect_grid(128, 64, 1.0 / 64)
+    L = 2
+    _note("factored level 0", m.n_cells, L, precision)
+    h, perms = oracle_hierarchy(m, L)
+    hh = hip_context(m, L, "multicolour")
+    X = h.levels[L].X
+    f, g = problems.sine2d_f(X), 0.25 + X[:, 0] - 0.5 * X[:, 1]
+    S = fmg.FMGSolver(h, smoother="multicolour")
+    b = S.rhs_levels(f)
+    p = perms[L]
+    assert len(S.sys[0].inner) > 5000
+    if precision == "fp64":
+        uo, _ = S.fmg(b, g, nu=1)
+        S.extra_cycles(uo, b[L], g, rtol=1e-300, max_iter=2)
+        ug, _ = hh.fmg_solve(to_dev(f[p]), to_dev(g[p]), nu=1, rtol=0.0, max_iter=2)
+        assert np.abs(to_host(ug) - uo[p]).max() <= 1e-12 * np.abs(uo).max()
+    else:
+        # the refinement loop converges to the float64 discrete solution
+        ud = S.direct(L, b[L], g)
+        ug, st = hh.fmg_solve(to_dev(f[p]), to_dev(g[p]), nu=1, precision=precision, rtol=1e-12, max_iter=60)
+        assert st.final_rel_residual <= 1e-12
+        assert np.abs(to_host(ug) - ud[p]).max() <= 1e-9 * np.abs(ud).max()
+
+
 @pytest.mark.parametrize("name,precision", [("lshape", "fp64"), ("lshape", "fp32_refined"), ("kuhn1", "fp64"),
                                             ("square8", "fp32_refined")])
 def test_fixed_extra_cycles(name, precision):

@@ -149,3 +149,33 @@ def test_transfer_to_a_coarsened_mesh():
     got = to_host(b.transfer_from(a, to_dev(u[pf[L]])))
     assert np.all(np.isfinite(got))
     assert np.abs(got - ref[pc[L]]).max() <= 1e-12
+
+
+def test_transfer_to_a_coarsened_mesh_3d():
+    # 3D coarsening (red groups of eight merged back, closed again by Algorithm 3) followed by
+    # the transfer from the finer mesh onto the coarser one, against the oracle
+    from paper_2508_06049_amd import HHG
+    m0 = meshes.kuhn_cube(1)
+    rg = hostmesh.RedGreen3D(m0)
+    rg.refine([0, 3])
+    fine = rg.mesh("fine")
+    # mark the cells inside coarse tetrahedron 3: its eight red children merge back
+    T = m0.coords[m0.cells[3]]
+    c = fine.coords[fine.cells].mean(axis=1)
+    lam = np.linalg.solve((T[1:] - T[0]).T, (c - T[0]).T).T
+    inside = np.all(lam > 0, axis=1) & (lam.sum(axis=1) < 1)
+    assert rg.coarsen(np.nonzero(inside)[0]) == 1
+    coarse = rg.mesh("coarsened")
+    assert coarse.n_cells < fine.n_cells
+    L = 3
+    _note("transfer to coarsened 3d", fine.n_cells, "->", coarse.n_cells, L)
+    hf, pf = oracle_hierarchy(fine, L)
+    hc, pc = oracle_hierarchy(coarse, L)
+    a = HHG(fine.coords, fine.cells, L, smoother="multicolour")
+    b = HHG(coarse.coords, coarse.cells, L, smoother="multicolour")
+    X = hf.levels[L].X
+    u = np.sin(3 * X[:, 0]) * np.cos(2 * X[:, 1]) + X[:, 2] ** 2
+    ref = transfer.transfer(hf, u, hc.levels[L].X)
+    got = to_host(b.transfer_from(a, to_dev(u[pf[L]])))
+    assert np.all(np.isfinite(got))
+    assert np.abs(got - ref[pc[L]]).max() <= 1e-12 * np.abs(u).max()

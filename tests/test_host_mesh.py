@@ -186,3 +186,35 @@ def test_coarsening_round_trip_and_conformity():
     c4 = m4.coords[m4.cells].mean(axis=1)
     rg.refine(M.mark_fraction(-np.hypot(c4[:, 0], c4[:, 1]), 0.25))
     assert key(rg.mesh()) == key(m1)
+
+
+def test_coarsening_3d_round_trip_and_conformity():
+    # 3D coarsening (the inverse of red refinement, closed again by Algorithm 3): marking
+    # every cell after two steps merges all red groups back to the coarse mesh; a partial
+    # marking leaves a conforming mesh of the same volume with fewer cells; nothing marked
+    # changes nothing; refining the coarsened mesh again reproduces the first step
+    m0 = meshes.kuhn_cube(2)
+    rg = M.RedGreen3D(m0)
+    cen = m0.coords[m0.cells].mean(axis=1)
+    rg.refine(M.mark_fraction(-np.linalg.norm(cen, axis=1), 0.125))
+    m1 = rg.mesh()
+    c1 = m1.coords[m1.cells].mean(axis=1)
+    rg.refine(M.mark_fraction(-np.linalg.norm(c1, axis=1), 0.125))
+    m2 = rg.mesh()
+    _check_conforming(m2, 1.0)
+    assert rg.coarsen([]) == 0 and rg.mesh().n_cells == m2.n_cells
+    # partial: cells away from the refined corner
+    c2 = m2.coords[m2.cells].mean(axis=1)
+    far = np.nonzero(np.linalg.norm(c2, axis=1) > 0.3)[0]
+    n = rg.coarsen(far)
+    m3 = rg.mesh()
+    _check_conforming(m3, 1.0)
+    assert n > 0 and m3.n_cells < m2.n_cells
+    # everything: back to the coarse mesh
+    rg.coarsen(list(range(m3.n_cells)))
+    m4 = rg.mesh()
+    key = lambda m: sorted(tuple(sorted(map(tuple, np.round(m.coords[c], 12).tolist()))) for c in m.cells)
+    assert key(m4) == key(m0)
+    c4 = m4.coords[m4.cells].mean(axis=1)
+    rg.refine(M.mark_fraction(-np.linalg.norm(c4, axis=1), 0.125))
+    assert key(rg.mesh()) == key(m1)

@@ -62,6 +62,21 @@ def unit_square_grid(m: int) -> CoarseMesh:
     return CoarseMesh(coords, np.array(cells, dtype=np.int32), f"unit_square_grid{m}")
 
 
+def rect_grid(mx: int, my: int, h: float) -> CoarseMesh:
+    """(0, mx h) x (0, my h) as an mx x my grid of squares of side h, each split by its (1,1)
+    diagonal: 2 mx my triangles.  With h a power of two every coordinate, and every midpoint of
+    the refined levels, is exact in float64."""
+    coords = np.array([[i * h, j * h] for i in range(mx + 1) for j in range(my + 1)], dtype=np.float64)
+    vid = lambda i, j: i * (my + 1) + j
+    cells = []
+    for i in range(mx):
+        for j in range(my):
+            a, b, c, d = vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)
+            cells.append([a, b, c])
+            cells.append([a, d, c])
+    return CoarseMesh(coords, np.array(cells, dtype=np.int32), f"rect_grid{mx}x{my}")
+
+
 def lshape_6tri() -> CoarseMesh:
     """L-shaped domain (-1,1)^2 without the quadrant x>0, y<0 (polar angle in (0, 3pi/2)).
 
