@@ -110,7 +110,14 @@ typedef struct {
                                  HHG_FLAG_CLASSWISE_IFACE: sweep the 2D interface classes one
                                  launch per class (or per run of small classes) instead of
                                  all of a sweep in one launch (identical result; for checking
-                                 the one-launch form)                                          */
+                                 the one-launch form).
+                                 HHG_FLAG_NO_PLANES3D: with the red-black smoother and a
+                                 per-macro coefficient, sweep the 3D levels with n = 64 with
+                                 the kernels used without the whole-plane sweep (same result;
+                                 for checking and timing it).
+                                 HHG_FLAG_PLANES3D: use the whole-plane 3D sweep on every
+                                 level with 16 <= n <= 64, not only on n = 64 (same result;
+                                 for checking it on small levels)                              */
 } hhg_options;
 
 enum {
@@ -121,7 +128,9 @@ enum {
   HHG_FLAG_ROWS3D = 16,
   HHG_FLAG_STREAM3D = 32,
   HHG_FLAG_GENERIC_EST = 64,
-  HHG_FLAG_CLASSWISE_IFACE = 128
+  HHG_FLAG_CLASSWISE_IFACE = 128,
+  HHG_FLAG_NO_PLANES3D = 256,
+  HHG_FLAG_PLANES3D = 512
 };
 
 typedef struct {

@@ -33,6 +33,8 @@ HHG_FLAG_ROWS3D = 16
 HHG_FLAG_STREAM3D = 32
 HHG_FLAG_GENERIC_EST = 64
 HHG_FLAG_CLASSWISE_IFACE = 128
+HHG_FLAG_NO_PLANES3D = 256
+HHG_FLAG_PLANES3D = 512
 
 SMOOTHERS = {"redblack": HHG_GS_REDBLACK, "multicolour": HHG_GS_MULTICOLOR, "jacobi": HHG_JACOBI}
 PRECISIONS = {"fp64": HHG_FP64, "fp32_refined": HHG_FP32_REFINED}

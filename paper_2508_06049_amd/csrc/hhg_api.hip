@@ -70,6 +70,7 @@ LK lk_of(hhg_ctx c, int l) {
   // one wavefront per 3D lattice row pays off once rows are long (below n = 128 most lanes of
   // a wavefront would idle and the one-thread-per-point kernels are used)
   k.rows3d_min = c->force_rows3d ? 1 : 128;
+  k.planes3d = lv.planes3d ? 1 : 0;
   return k;
 }
 
@@ -131,7 +132,7 @@ bool fused_available(hhg_ctx c, int l, size_t tsize) {
   const Level& lv = c->lev[l];
   if (p1(c) || lv.NI <= 0 || c->opt.smoother == HHG_JACOBI || c->no_fused) return false;
   if (c->dim == 2) return !lv.tiles.empty();
-  if (!lv.tiles.empty()) return true;   // the plane-streaming 3D sweep
+  if (!lv.tiles.empty()) return true;   // the whole-plane or plane-streaming 3D sweep
   return !lv.itab.empty() && (size_t)lv.Sraw * tsize <= 64 * 1024;
 }
 
@@ -142,7 +143,7 @@ hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
   const bool jac = c->opt.smoother == HHG_JACOBI;
   const int rb = c->opt.smoother == HHG_GS_REDBLACK ? 1 : 0;
   const bool fused = fused_available(c, l, sizeof(T));
-  // out-of-place interior sweep (k_gs2d_fused, k_gs3d_stream)
+  // out-of-place interior sweep (k_gs2d_fused, k_gs3d_planes, k_gs3d_stream)
   const bool twobuf = fused && (c->dim == 2 || !lv.tiles.empty());
   for (int s = 0; s < sweeps; ++s) {
     T* x = Arr<T>::x(lv);
@@ -738,6 +739,8 @@ hhg_status hhg_setup(const hhg_mesh* mesh, int L, const hhg_options* opt, hhg_ct
   c->no_preload = (opt->flags & HHG_FLAG_NO_PRELOAD) != 0;
   c->force_rows3d = (opt->flags & HHG_FLAG_ROWS3D) != 0;
   c->force_stream3d = (opt->flags & HHG_FLAG_STREAM3D) != 0;
+  c->no_planes3d = (opt->flags & HHG_FLAG_NO_PLANES3D) != 0;
+  c->force_planes3d = (opt->flags & HHG_FLAG_PLANES3D) != 0;
   c->generic_est = (opt->flags & HHG_FLAG_GENERIC_EST) != 0;
   c->nV = mesh->n_vertices;
   c->nC = mesh->n_cells;

@@ -39,6 +39,11 @@ constexpr int kMacroLdsN = 32;
 // streams kS3K planes; LDS planes are 64 x (kS3J + 4) points (two-point halo in i and j)
 constexpr int kS3I = 60, kS3J = 28, kS3K = 32;
 constexpr int kStream3dMinN = 256;  // levels with n >= this use it (red-black, per-macro coefficient)
+// whole-plane 3D red-black sweep: levels with kPlane3dMinN <= n <= kPlane3dMaxN (a plane of the
+// closure fits one LDS slot and a pair of interior rows one wavefront; below n = 64 the LDS
+// macro sweep measured faster); the interior planes of a macro are cut into chunks so that a
+// level has about kPlane3dBlocks workgroups
+constexpr int kPlane3dMinN = 64, kPlane3dMaxN = 64, kPlane3dBlocks = 2048;
 // levels whose largest interface colour class has at most this many DoFs sweep all interface
 // classes in one single-workgroup launch
 constexpr int kIfaceOneGroup = 4096;
@@ -147,6 +152,7 @@ struct Level {
   int64_t off_whcopy = 0, off_whinfo = 0, off_whloc = 0, off_whseg = 0, off_whsrc = 0, off_whwmax = 0,
           off_whcw = 0;
   std::vector<int32_t> tiles;          // 2D: interior tiles (ti | tj << 16) of the fused sweep
+  bool planes3d = false;               // 3D: tiles are plane chunks (k0 | k1 << 16) of k_gs3d_planes
   std::vector<uint32_t> itab;          // 3D, n <= kMacroLdsN: interior points (i | j << 10 | k << 20)
   int32_t* d_tiles = nullptr;
   uint32_t* d_itab = nullptr;
@@ -241,6 +247,8 @@ struct hhg_ctx_s {
   bool no_preload = false;          // single-workgroup interface sweep without preloading (testing)
   bool force_rows3d = false;        // 3D row kernels at every level (testing)
   bool force_stream3d = false;      // 3D plane-streaming sweep from n = 4 on (testing)
+  bool no_planes3d = false;         // no whole-plane 3D sweep (testing, timing)
+  bool force_planes3d = false;      // whole-plane 3D sweep from n = 16 on (testing)
   bool generic_est = false;         // 2D L2 estimate by the one-thread-per-node kernel (testing)
   bool classwise_iface = false;     // 2D interface classes one launch each (testing)
   uint32_t xswap = 0;               // bit l (+16 for float32): level l's iterate is in its second buffer

@@ -16,6 +16,7 @@ struct LK {
   int64_t nIface = 0, ndof = 0;
   int nmacro = 0;
   int rows3d_min = 128;   // 3D levels with n >= this use the row kernels
+  int planes3d = 0;       // 3D: the level's tiles are chunks of the whole-plane sweep
 };
 
 template <typename T>

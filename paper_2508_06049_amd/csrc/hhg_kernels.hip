@@ -502,6 +502,162 @@ __global__ void __launch_bounds__(256) k_gs3d_stream(LK lk, Tables tb, const T* 
   }
 }
 
+// Red-black Gauss-Seidel sweep of all macro interiors of a 3D level with n <= NMAX (NMAX <= 65),
+// both colours in one launch, out of place: reads u, writes the interior of uo.  One workgroup
+// streams the planes k0 .. k1-1 of one macro.  A plane of the closure (the points of height k,
+// a triangle of side n - k stored contiguously) is copied whole into LDS, so in-plane
+// neighbours need no halo and the copy is one contiguous run.  Per plane p: copy plane p, update
+// the red points of plane p-1 in place in LDS (red points read only black neighbours), then the
+// black points of plane p-2, and write both colours of plane p-2.  The red points of the planes
+// k0-1 and k1 are recomputed from old values, identically to the workgroup that owns them.
+// A wavefront takes a pair of interior rows j and R+1-j of a plane (R rows): their lengths add
+// up to n-1-k, so the pair fills the lanes of one wavefront about evenly over the triangle.
+// Loads run two planes ahead: u of plane p+2 and b of plane p+1 are in flight while plane p is
+// processed (the step loop is unrolled by four so that every register set is fixed).  Same
+// updates, in the same order within each point, as the class-by-class sweep: red (parity 0)
+// first, then black; interface points are left to the interface sweep.
+template <typename T, int NMAX, bool FINE>
+__global__ void __launch_bounds__(512) k_gs3d_planes(LK lk, Tables tb, const T* __restrict__ u, T* __restrict__ uo,
+                                                     const T* __restrict__ b, const int32_t* __restrict__ chunks,
+                                                     int nchunks, double sA) {
+  constexpr int NW = 8, NS = 5;
+  constexpr int PS = (NMAX + 1) * (NMAX + 2) / 2;   // the largest plane (k = 0)
+  constexpr int NL = (PS + 511) / 512;
+  constexpr int RU = ((NMAX - 2) / 2 + NW - 1) / NW;   // row pairs per wavefront
+  static_assert(NMAX <= 65, "a row pair must fit one wavefront");
+  __shared__ T sU[NS * PS];
+  const int per_xcd = (int)(gridDim.x >> 3);   // gridDim.x is a multiple of 8
+  const int blk = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (blk >= lk.nmacro * nchunks) return;
+  const int m = blk / nchunks;
+  const int ch = chunks[blk - m * nchunks];
+  const int k0 = ch & 0xffff, k1 = ch >> 16;   // interior planes k0 .. k1-1 (1 <= k0 < k1 <= n - 2)
+  const int n = lk.n;
+  const int64_t base = (int64_t)m * lk.S;
+  const uint32_t mbytes = (uint32_t)(lk.S * (int64_t)sizeof(T));
+  const __amdgpu_buffer_rsrc_t ru = d_rsrc(u + base, mbytes), rbr = d_rsrc(b + base, mbytes),
+                               ro = d_rsrc(uo + base, mbytes);
+  const double* Wt = tb.stiff + (size_t)m * kMaxMask * 15;
+  const double ks = sA * tb.kappa[m];
+  const T diag = (T)(ks * Wt[0]);
+  T cq[15];
+#pragma unroll
+  for (int q = 1; q < 15; ++q) cq[q] = (T)(ks * Wt[q]);
+  const int* rp = tb.rbpar + m * 4;
+  const int s1 = rp[1], s2 = rp[2], s3 = rp[3];
+  const int tid = (int)threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int dn = d_tet(n);
+  auto plane = [&](int k) { return dn - d_tet(n - k); };                       // first point of plane k
+  auto psize = [&](int k) { return ((n - k + 1) * (n - k + 2)) >> 1; };
+  auto rowin = [&](int j, int k) { return j * (n - k + 1) - ((j * (j - 1)) >> 1); };   // row j within plane k
+  auto slot = [](int k) { return ((k + NS) % NS) * PS; };
+  // interior point (i, row) of this lane in row pair r of plane q; false if the lane idles
+  auto lanept = [&](int q, int r, int& row, int& i) {
+    const int pr = w + NW * r;
+    const int j = 1 + pr, j2 = n - 2 - q - pr;   // rows j and R + 1 - j, R = n - 2 - q
+    const int len1 = n - 1 - q - j, len2 = j2 > j ? j : 0;
+    const bool first = lane < len1;
+    row = first ? j : j2;
+    i = first ? lane + 1 : lane - len1 + 1;
+    return j <= j2 && lane < len1 + len2;
+  };
+  T U[2][NL], B[4][RU];
+  // loads past the end of a plane (or of the needed rows) take distinct offsets outside the
+  // buffer and return zero: no select on (or copy of) a loaded value, which would wait for it
+  constexpr uint32_t kOut = 0xFFFFFFF0u;
+  auto load_u = [&](T (&reg)[NL], int p) {
+    const int sz = p >= 0 && p <= n ? psize(p) : 0;
+    const uint32_t o0 = p >= 0 ? (uint32_t)plane(p) : 0u;
+#pragma unroll
+    for (int s = 0; s < NL; ++s) {
+      const int t = tid + 512 * s;
+      d_bload(ru, t < sz ? (o0 + (uint32_t)t) * (uint32_t)sizeof(T) : kOut - 64u * s, reg[s]);
+    }
+  };
+  // b at this lane's interior points of plane p (loaded one step ahead: used by the red update
+  // two steps later, by the black update three steps later)
+  auto load_b = [&](T (&reg)[RU], int p) {
+    const bool need = p >= k0 - 1 && p <= k1 && p >= 1;
+#pragma unroll
+    for (int r = 0; r < RU; ++r) {
+      int row, i;
+      const bool ok = need && lanept(p, r, row, i);
+      d_bload(rbr, ok ? (uint32_t)(plane(p) + rowin(row, p) + i) * (uint32_t)sizeof(T) : kOut - 64u * r, reg[r]);
+    }
+  };
+  // off-diagonal part of the row of interior point (i, row, q) from the LDS planes q-1, q, q+1,
+  // r00 = rowin(row, q).  The 14 neighbours lie on 7 rows (row + b of plane q + c); their
+  // offsets follow from r00 by additions: rowin(r + 1, k) = rowin(r, k) + (n - k + 1) - r and
+  // rowin(r, k + 1) = rowin(r, k) - r
+  auto stencil = [&](int row, int i, int q, int r00) {
+    const int n1 = n - q + 1, s0 = slot(q), sp = slot(q + 1), sm = slot(q - 1);
+    const int c00 = s0 + r00 + i, cp0 = c00 + n1 - row, cm0 = c00 - n1 + row - 1;
+    const int c0p = sp + r00 + i - row, c0m = sm + r00 + i + row;
+    const int cmp = sp + r00 + i - n1, cpm = sm + r00 + i + n1 + 1;
+    T off = (T)0;
+#pragma unroll
+    for (int c = 1; c < 15; ++c) {
+      const int bb = kOff3[c][1], kc = kOff3[c][2];
+      const int at = kc == 0 ? (bb == 0 ? c00 : (bb > 0 ? cp0 : cm0))
+                             : (kc > 0 ? (bb == 0 ? c0p : cmp) : (bb == 0 ? c0m : cpm));
+      off += cq[c] * sU[at + kOff3[c][0]];
+    }
+    return off;
+  };
+  const int p0 = k0 - 2;
+  load_u(U[0], p0);
+  load_u(U[1], p0 + 1);
+  load_b(B[0], p0);
+  for (int pb = p0; pb <= k1 + 1; pb += 4) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int p = pb + s;
+      if (p > k1 + 1) break;
+      if (p >= 0) {
+        const int sz = psize(p);
+        T* Sl = sU + slot(p);
+#pragma unroll
+        for (int e = 0; e < NL; ++e) {
+          const int t = tid + 512 * e;
+          if (t < sz) Sl[t] = U[s & 1][e];
+        }
+      }
+      if (p + 2 <= k1 + 1) load_u(U[s & 1], p + 2);
+      if (p + 1 <= k1) load_b(B[(s + 1) & 3], p + 1);   // the set of plane p - 3, no longer read
+      __syncthreads();
+      const int q = p - 1;   // red points of plane q, in place (b of plane q: set s + 3)
+      if (q >= k0 - 1 && q <= k1 && q >= 1) {
+#pragma unroll
+        for (int r = 0; r < RU; ++r) {
+          int row, i;
+          if (lanept(q, r, row, i) && ((i * s1 + row * s2 + q * s3) & 1) == 0) {
+            const int r00 = rowin(row, q);
+            const T off = stencil(row, i, q, r00);
+            sU[slot(q) + r00 + i] = (B[(s + 3) & 3][r] - off) / diag;
+          }
+        }
+      }
+      __syncthreads();
+      const int qb = p - 2;   // black points of plane qb (b: set s + 2); both colours written
+      if (qb >= k0 && qb < k1) {
+        const int pk = plane(qb);
+#pragma unroll
+        for (int r = 0; r < RU; ++r) {
+          int row, i;
+          if (lanept(qb, r, row, i)) {
+            const int r00 = rowin(row, qb), li = r00 + i;
+            T v;
+            if ((i * s1 + row * s2 + qb * s3) & 1) v = (B[(s + 2) & 3][r] - stencil(row, i, qb, r00)) / diag;
+            else v = sU[slot(qb) + li];
+            d_bstore(ro, (uint32_t)(pk + li) * (uint32_t)sizeof(T), v);
+          }
+        }
+      }
+    }
+  }
+}
+
 // Gauss-Seidel (or Jacobi) update of one interface DoF t: the assembled row is the sum of the
 // partial rows of all macros containing it.  Interior neighbours are read from xi, interface
 // neighbours (and the DoF's own old value) from xf; the new value goes to every copy in uout
@@ -1462,13 +1618,10 @@ __global__ void __launch_bounds__(1024) k_gs3d_macro(LK lk, Tables tb, T* __rest
 // y = alpha * b + beta * (A_m x) per macro over the closure (dual output); zero on Dirichlet
 // nodes when zero_dir.  op 0: stiffness (scaled by kappa), 1: mass.
 template <int D, typename Tin, typename Tout, bool P1>
-__global__ void __launch_bounds__(256) k_apply(LK lk, Tables tb, const Tin* __restrict__ x, const Tin* __restrict__ b,
-                                                Tout* __restrict__ y, int op, double scale, double alpha, double beta,
-                                                int zero_dir, const double* __restrict__ kn) {
-  const int nchunk = (lk.Sraw + 255) >> 8;
-  const int m = blockIdx.x / nchunk;
-  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
-  if (s >= lk.Sraw) return;
+__device__ __forceinline__ void apply_point(const LK& lk, const Tables& tb, const Tin* __restrict__ x,
+                                            const Tin* __restrict__ b, Tout* __restrict__ y, int op, double scale,
+                                            double alpha, double beta, int zero_dir, const double* __restrict__ kn, int m,
+                                            int s) {
   int i, j, k;
   d_dec<D>(lk.n, s, i, j, k);
   const int mask = d_mask<D>(lk.n, i, j, k);
@@ -1491,6 +1644,17 @@ __global__ void __launch_bounds__(256) k_apply(LK lk, Tables tb, const Tin* __re
   Tin v = (Tin)beta * ax;
   if (b) v += (Tin)alpha * b[base + s];
   y[base + s] = (Tout)v;
+}
+
+template <int D, typename Tin, typename Tout, bool P1>
+__global__ void __launch_bounds__(256) k_apply(LK lk, Tables tb, const Tin* __restrict__ x, const Tin* __restrict__ b,
+                                                Tout* __restrict__ y, int op, double scale, double alpha, double beta,
+                                                int zero_dir, const double* __restrict__ kn) {
+  const int nchunk = (lk.Sraw + 255) >> 8;
+  const int m = blockIdx.x / nchunk;
+  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
+  if (s >= lk.Sraw) return;
+  apply_point<D, Tin, Tout, P1>(lk, tb, x, b, y, op, scale, alpha, beta, zero_dir, kn, m, s);
 }
 
 // 3D y = alpha b + beta (A_m x) per macro by rows: one wavefront per closure row (j, k) of one
@@ -1663,18 +1827,12 @@ __global__ void __launch_bounds__(256) k_apply2d_rows(LK lk, Tables tb, const Ti
   }
 }
 
-// r_c = P^T r_f per macro (dual in, dual out); zero on coarse Dirichlet nodes
+// r_c = P^T r_f per macro (dual in, dual out); zero on coarse Dirichlet nodes.  Coarse closure
+// point s of macro m (s < c.Sraw)
 template <int D, typename T>
-__global__ void __launch_bounds__(256) k_restrict(LK f, LK c, Tables tb, const T* __restrict__ rf, T* __restrict__ bc,
-                                                   T* __restrict__ zc) {
-  // grid over the padded coarse block; zc (if given) is cleared over the whole block: the
-  // coarse correction of the next cycle starts from zero without a separate fill launch
-  const int nchunk = (int)((c.S + 255) >> 8);
-  const int m = blockIdx.x / nchunk;
-  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
+__device__ __forceinline__ void restrict_point(const LK& f, const LK& c, const Tables& tb, const T* __restrict__ rf,
+                                               T* __restrict__ bc, int m, int s) {
   const int64_t cb = (int64_t)m * c.S, fb = (int64_t)m * f.S;
-  if (zc && s < c.S) zc[cb + s] = (T)0;
-  if (s >= c.Sraw) return;
   int i, j, k;
   d_dec<D>(c.n, s, i, j, k);
   const int mask = d_mask<D>(c.n, i, j, k);
@@ -1692,15 +1850,26 @@ __global__ void __launch_bounds__(256) k_restrict(LK f, LK c, Tables tb, const T
   bc[cb + s] = rf[fb + d_lin<D>(f.n, fi, fj, fk)] + (T)0.5 * acc;
 }
 
-// prolongation over the fine closure.  mode 0: uf += P ec on non-Dirichlet nodes;
-// mode 1: uf = P ec everywhere; mode 2 (FMG): w = P ec, uf = P ec (g on Dirichlet nodes).
 template <int D, typename T>
-__global__ void __launch_bounds__(256) k_prolong(LK f, LK c, Tables tb, const T* __restrict__ ec, T* __restrict__ uf,
-                                                  T* __restrict__ w, const T* __restrict__ g, int mode) {
-  const int nchunk = (f.Sraw + 255) >> 8;
+__global__ void __launch_bounds__(256) k_restrict(LK f, LK c, Tables tb, const T* __restrict__ rf, T* __restrict__ bc,
+                                                   T* __restrict__ zc) {
+  // grid over the padded coarse block; zc (if given) is cleared over the whole block: the
+  // coarse correction of the next cycle starts from zero without a separate fill launch
+  const int nchunk = (int)((c.S + 255) >> 8);
   const int m = blockIdx.x / nchunk;
   const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
-  if (s >= f.Sraw) return;
+  if (zc && s < c.S) zc[(int64_t)m * c.S + s] = (T)0;
+  if (s >= c.Sraw) return;
+  restrict_point<D, T>(f, c, tb, rf, bc, m, s);
+}
+
+// prolongation over the fine closure.  mode 0: uf += P ec on non-Dirichlet nodes;
+// mode 1: uf = P ec everywhere; mode 2 (FMG): w = P ec, uf = P ec (g on Dirichlet nodes).
+// Fine closure point s of macro m (s < f.Sraw)
+template <int D, typename T>
+__device__ __forceinline__ void prolong_point(const LK& f, const LK& c, const Tables& tb, const T* __restrict__ ec,
+                                              T* __restrict__ uf, T* __restrict__ w, const T* __restrict__ g, int mode,
+                                              int m, int s) {
   int i, j, k;
   d_dec<D>(f.n, s, i, j, k);
   const int64_t fb = (int64_t)m * f.S;
@@ -1713,6 +1882,16 @@ __global__ void __launch_bounds__(256) k_prolong(LK f, LK c, Tables tb, const T*
     w[fb + s] = v;
     uf[fb + s] = dir ? g[fb + s] : v;
   }
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_prolong(LK f, LK c, Tables tb, const T* __restrict__ ec, T* __restrict__ uf,
+                                                  T* __restrict__ w, const T* __restrict__ g, int mode) {
+  const int nchunk = (f.Sraw + 255) >> 8;
+  const int m = blockIdx.x / nchunk;
+  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
+  if (s >= f.Sraw) return;
+  prolong_point<D, T>(f, c, tb, ec, uf, w, g, mode, m, s);
 }
 
 // 2D prolongation by rows (modes as k_prolong): each wavefront takes a 64-node segment of
@@ -2534,6 +2713,17 @@ bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* 
     else { if (fine) HHG_F2N(3, true); else HHG_F2N(3, false); }
 #undef HHG_F2N
 #undef HHG_F2
+    return true;
+  }
+  if (ntiles > 0 && lk.planes3d) {
+    // red-black with per-macro coefficient, 16 <= n <= 64: whole planes in LDS, chunks of planes
+    if (!rb || lk.n > kPlane3dMaxN) return false;
+    const unsigned g = (unsigned)(((int64_t)lk.nmacro * ntiles + 7) / 8 * 8);   // a multiple of 8 blocks (XCDs)
+#define HHG_P3(N, F) k_gs3d_planes<T, N, F><<<g, 512, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, sA)
+    if (lk.n <= 16) { if (fine) HHG_P3(16, true); else HHG_P3(16, false); }
+    else if (lk.n <= 32) { if (fine) HHG_P3(32, true); else HHG_P3(32, false); }
+    else { if (fine) HHG_P3(64, true); else HHG_P3(64, false); }
+#undef HHG_P3
     return true;
   }
   if (ntiles > 0) {

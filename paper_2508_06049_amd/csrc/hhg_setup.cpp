@@ -722,9 +722,32 @@ hhg_status build_colouring(hhg_ctx c) {
     // (red-black colour alternating along i on every macro: the kernel pairs neighbouring points)
     bool alt_i = true;
     for (int64_t m = 0; m < c->nC && d == 3; ++m) alt_i = alt_i && (c->rbpar[m * 4 + 1] & 1) != 0;
-    const bool stream3d = d == 3 && lv.NI > 0 && c->opt.smoother == HHG_GS_REDBLACK &&
-                          c->opt.coefficient == HHG_KAPPA_MACRO && alt_i &&
-                          (lv.n >= kStream3dMinN || (c->force_stream3d && lv.n >= 4));
+    const bool rbmacro = d == 3 && lv.NI > 0 && c->opt.smoother == HHG_GS_REDBLACK &&
+                         c->opt.coefficient == HHG_KAPPA_MACRO;
+    const bool stream3d = rbmacro && alt_i && (lv.n >= kStream3dMinN || (c->force_stream3d && lv.n >= 4));
+    // whole-plane sweep: the interior planes 1 .. n-3 of every macro in chunks [k0, k1) of about
+    // equal cost (points of the chunk's planes plus the four planes read around it), as many
+    // chunks per macro as make about kPlane3dBlocks workgroups, each at least 8 planes high
+    lv.planes3d = rbmacro && !stream3d && !c->no_planes3d && lv.n <= kPlane3dMaxN &&
+                  (lv.n >= kPlane3dMinN || (c->force_planes3d && lv.n >= 16));
+    if (lv.planes3d) {
+      const int n = lv.n, np = n - 3;
+      auto psz = [&](int k) { return (double)(n - k + 1) * (n - k + 2) / 2.0; };
+      const int nch = (int)std::max<int64_t>(1, std::min<int64_t>((kPlane3dBlocks + c->nC - 1) / c->nC, np / 8));
+      double total = 0.0;
+      for (int k = 1; k <= np; ++k) total += psz(k);
+      int k0 = 1;
+      double acc = 0.0;
+      for (int k = 1; k <= np; ++k) {
+        acc += psz(k);
+        const int left = nch - (int)lv.tiles.size() - 1;   // chunks still to cut after this one
+        if (k == np || (left > 0 && acc + 4.0 * psz(k0) >= total / nch && k - k0 + 1 >= 8 && np - k >= 8)) {
+          lv.tiles.push_back(k0 | ((k + 1) << 16));
+          k0 = k + 1;
+          acc = 0.0;
+        }
+      }
+    }
     if (stream3d) {
       for (int tk = 0; 1 + tk * kS3K <= lv.n - 3; ++tk)
         for (int tj = 0; 1 + tj * kS3J + 1 + tk * kS3K <= lv.n - 2; ++tj)
@@ -732,7 +755,7 @@ hhg_status build_colouring(hhg_ctx c) {
             lv.tiles.push_back(ti | (tj << 10) | (tk << 20));
     }
     lv.itab_off.clear();
-    if (d == 3 && lv.NI > 0 && lv.n <= kMacroLdsN && !stream3d) {
+    if (d == 3 && lv.NI > 0 && lv.n <= kMacroLdsN && !stream3d && !lv.planes3d) {
       // interior points sorted by colour, one list per red-black parity pattern (s1, s2, s3)
       // of a macro (multicolour: one list); itab_off[p * (Cint + 1) + c] starts colour c
       const int n = lv.n;

@@ -212,6 +212,49 @@ def test_3d_stream_sweep_matches(name, L):
         assert np.abs(to_host(us) - ref[p]).max() <= 1e-9 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("name,L", [("kuhn1", 4), ("kuhn2", 5), ("kuhn1", 6)])
+def test_3d_plane_sweep_matches(name, L):
+    # the whole-plane red-black 3D sweep (both colours in one out-of-place launch, chunks of
+    # whole closure planes in LDS; used at n = 64, forced here from n = 16 on with
+    # HHG_FLAG_PLANES3D) gives bit for bit the iterates
+    # of the class-by-class row sweep in float64 sweeps and in the float32-refined solve, over
+    # odd and even smoothing counts, and the oracle's smoother on the same input
+    from paper_2508_06049_amd import HHG
+    from paper_2508_06049_amd._lib import HHG_FLAG_NO_FUSED, HHG_FLAG_PLANES3D, HHG_FLAG_ROWS3D
+    _note("3d plane sweep", name, L)
+    m = meshes.kuhn_cube(1 if name == "kuhn1" else 2)
+    h, perms = oracle_hierarchy(m, L)
+    kc = problems.kappa_cells_uniform(8, m.n_cells)
+    hp = HHG(m.coords, m.cells, L, smoother="redblack", kappa_cell=kc, flags=HHG_FLAG_PLANES3D)
+    hr = HHG(m.coords, m.cells, L, smoother="redblack", kappa_cell=kc, flags=HHG_FLAG_NO_FUSED | HHG_FLAG_ROWS3D)
+    S = fmg.FMGSolver(h, kappa_cell=kc, smoother="redblack")
+    p = perms[L]
+    X = h.levels[L].X
+    f = problems.fourier3d(X, problems.fourier_amplitudes(1))
+    g = 0.1 * X[:, 1] - 0.3 * X[:, 0]
+    fd, gd = to_dev(f[p]), to_dev(g[p])
+    rng = np.random.default_rng(15)
+    u, b = rng.standard_normal(len(X)), rng.standard_normal(len(X))
+    u0, b0 = to_dev(u[p]), to_dev(b[p])
+    for sweeps in (1, 2, 3):
+        a1, a2 = u0.clone(), u0.clone()
+        hp.smooth(L, a1, b0, sweeps)
+        hr.smooth(L, a2, b0, sweeps)
+        assert np.array_equal(to_host(a1), to_host(a2))
+        if sweeps == 2:
+            uo = u.copy()
+            S.smooth(L, uo, b, 2)
+            assert rel_err(to_host(a1), uo[p]) < 1e-12
+    for pre, post, iters in ((2, 2, 3), (1, 2, 2)):
+        up, sp = hp.fmg_solve(fd, gd, nu=1, pre=pre, post=post, precision="fp32_refined", rtol=1e-30, max_iter=iters)
+        ur, sr = hr.fmg_solve(fd, gd, nu=1, pre=pre, post=post, precision="fp32_refined", rtol=1e-30, max_iter=iters)
+        assert sp.vcycles == sr.vcycles == L + iters
+        assert np.array_equal(to_host(up), to_host(ur))
+    uf, _ = S.fmg(S.rhs_levels(f), g, nu=1)
+    ugf, _ = hp.fmg_solve(fd, gd, nu=1)
+    assert np.abs(to_host(ugf) - uf[p]).max() <= 1e-12 * np.abs(uf).max()
+
+
 def test_graph_replay_after_odd_smoothing():
     # an odd number of out-of-place sweeps through hhg_smooth leaves a level's two iterate
     # buffers exchanged; solves recorded as HIP graphs before must not replay stale addresses
