@@ -117,7 +117,12 @@ typedef struct {
                                  for checking and timing it).
                                  HHG_FLAG_PLANES3D: use the whole-plane 3D sweep on every
                                  level with 16 <= n <= 64, not only on n = 64 (same result;
-                                 for checking it on small levels)                              */
+                                 for checking it on small levels).
+                                 HHG_FLAG_TWO_LAUNCH_IFACE: sweep the 2D edge classes and the
+                                 vertex classes in two launches (the vertex classes reading the
+                                 new edge values from memory) instead of one launch in which
+                                 they recompute them (identical result; for checking and
+                                 timing the one-launch form)                                   */
 } hhg_options;
 
 enum {
@@ -130,7 +135,8 @@ enum {
   HHG_FLAG_GENERIC_EST = 64,
   HHG_FLAG_CLASSWISE_IFACE = 128,
   HHG_FLAG_NO_PLANES3D = 256,
-  HHG_FLAG_PLANES3D = 512
+  HHG_FLAG_PLANES3D = 512,
+  HHG_FLAG_TWO_LAUNCH_IFACE = 1024
 };
 
 typedef struct {

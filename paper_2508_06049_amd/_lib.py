@@ -35,6 +35,7 @@ HHG_FLAG_GENERIC_EST = 64
 HHG_FLAG_CLASSWISE_IFACE = 128
 HHG_FLAG_NO_PLANES3D = 256
 HHG_FLAG_PLANES3D = 512
+HHG_FLAG_TWO_LAUNCH_IFACE = 1024
 
 SMOOTHERS = {"redblack": HHG_GS_REDBLACK, "multicolour": HHG_GS_MULTICOLOR, "jacobi": HHG_JACOBI}
 PRECISIONS = {"fp64": HHG_FP64, "fp32_refined": HHG_FP32_REFINED}

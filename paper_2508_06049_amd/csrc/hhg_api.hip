@@ -170,7 +170,15 @@ hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
       // grid of its own and runs of smaller consecutive classes share one single-workgroup
       // launch
       int col = lv.interior_colours;
-      if (lv.fused_iface && !c->classwise_iface) {
+      if (lv.fused_iface && !c->classwise_iface && lv.wheels && lv.wh_merge && twobuf && !c->two_launch_iface) {
+        // edge and vertex classes in one launch (the wheels recompute their edge-class
+        // neighbours); x is only read, so the interface needs no mirror writes
+        launch_iface2d_sweep<T>(k, c->tab, (const int32_t*)(c->ws + c->o_erec), (int)c->nE, lv.d_dvcopy,
+                                (int)lv.dvcopy.size(), lv.d_whcopy, lv.d_whinfo, lv.d_whloc, lv.d_whseg, lv.d_whsrc,
+                                lv.d_whcw, lv.d_whwmax, (int)lv.wh_wmax.size(), lv.ncolours - lv.c_vr0, lv.d_whe2,
+                                lv.d_wha2i, lv.d_wha2w, y, x, y, b, sA(c, l), ST(c));
+        col = lv.ncolours;
+      } else if (lv.fused_iface && !c->classwise_iface) {
         launch_iface2d_edges<T>(k, (const int32_t*)(c->ws + c->o_erec), (int)c->nE, lv.d_dvcopy, (int)lv.dvcopy.size(),
                                 y, x, y, mir, b, sA(c, l), ST(c));
         col = lv.c_vr0;
@@ -655,6 +663,12 @@ hhg_status bind_impl(hhg_ctx c, void* ptr, void* stream, bool no_alloc) {
     HIPCHK(up(lv.off_whwmax, lv.wh_wmax.data(), lv.wh_wmax.size() * 4));
     lv.d_whcw = (double*)(w + lv.off_whcw);
     HIPCHK(up(lv.off_whcw, lv.wh_cw.data(), lv.wh_cw.size() * 8));
+    lv.d_whe2 = (int32_t*)(w + lv.off_whe2);
+    HIPCHK(up(lv.off_whe2, lv.wh_e2.data(), lv.wh_e2.size() * 4));
+    lv.d_wha2i = (int32_t*)(w + lv.off_wha2i);
+    HIPCHK(up(lv.off_wha2i, lv.wh_a2i.data(), lv.wh_a2i.size() * 4));
+    lv.d_wha2w = (double*)(w + lv.off_wha2w);
+    HIPCHK(up(lv.off_wha2w, lv.wh_a2w.data(), lv.wh_a2w.size() * 8));
     lv.d_colour_off = (int32_t*)(w + lv.off_coff);
     HIPCHK(up(lv.off_coff, lv.colour_off.data(), lv.colour_off.size() * 4));
     lv.d_tiles = (int32_t*)(w + lv.off_tiles);
@@ -741,6 +755,7 @@ hhg_status hhg_setup(const hhg_mesh* mesh, int L, const hhg_options* opt, hhg_ct
   c->force_stream3d = (opt->flags & HHG_FLAG_STREAM3D) != 0;
   c->no_planes3d = (opt->flags & HHG_FLAG_NO_PLANES3D) != 0;
   c->force_planes3d = (opt->flags & HHG_FLAG_PLANES3D) != 0;
+  c->two_launch_iface = (opt->flags & HHG_FLAG_TWO_LAUNCH_IFACE) != 0;
   c->generic_est = (opt->flags & HHG_FLAG_GENERIC_EST) != 0;
   c->nV = mesh->n_vertices;
   c->nC = mesh->n_cells;
@@ -862,9 +877,13 @@ hhg_status hhg_set_kappa_cell(hhg_ctx c, const double* kappa) {
     HIPCHK(hipMemcpyAsync(c->ws + c->o_kappa, c->kappa_cell.data(), c->nC * 8, hipMemcpyHostToDevice, ST(c)));
     if (!c->erec.empty())
       HIPCHK(hipMemcpyAsync(c->ws + c->o_erec, c->erec.data(), c->erec.size() * 4, hipMemcpyHostToDevice, ST(c)));
-    for (auto& lv : c->lev)
+    for (auto& lv : c->lev) {
       if (!lv.wh_cw.empty())
         HIPCHK(hipMemcpyAsync(c->ws + lv.off_whcw, lv.wh_cw.data(), lv.wh_cw.size() * 8, hipMemcpyHostToDevice, ST(c)));
+      if (!lv.wh_a2w.empty())
+        HIPCHK(hipMemcpyAsync(c->ws + lv.off_wha2w, lv.wh_a2w.data(), lv.wh_a2w.size() * 8, hipMemcpyHostToDevice,
+                              ST(c)));
+    }
     TRY(upload_coarse(c));
   }
   c->solved = false;

@@ -149,6 +149,21 @@ struct Level {
   int32_t *d_whcopy = nullptr, *d_whinfo = nullptr, *d_whloc = nullptr, *d_whseg = nullptr, *d_whsrc = nullptr,
           *d_whwmax = nullptr;
   double* d_whcw = nullptr;
+  // wheels in the launch of the edge classes: per lane the edge-class neighbour to recompute,
+  // e | side << 24 | direction << 25 (side 1: a = n - 2 on the edge, else a = 2), or -1
+  bool wh_merge = false;
+  std::vector<int32_t> wh_e2;
+  int32_t* d_whe2 = nullptr;
+  int64_t off_whe2 = 0;
+  // and that neighbour's rows, 16 entries per lane (struct of arrays): per copy k of it,
+  // wh_a2i[8k] its closure index (-1: none), [8k + dd] the neighbour in direction dd (-1:
+  // none), [8k + 7] bit dd - 1 set for an interface neighbour; wh_a2w[8k] the coefficient
+  // (filled in at upload), [8k + 1 + d] the unit stencil weight d
+  std::vector<int32_t> wh_a2i;
+  std::vector<double> wh_a2w;
+  int32_t* d_wha2i = nullptr;
+  double* d_wha2w = nullptr;
+  int64_t off_wha2i = 0, off_wha2w = 0;
   int64_t off_whcopy = 0, off_whinfo = 0, off_whloc = 0, off_whseg = 0, off_whsrc = 0, off_whwmax = 0,
           off_whcw = 0;
   std::vector<int32_t> tiles;          // 2D: interior tiles (ti | tj << 16) of the fused sweep
@@ -249,6 +264,7 @@ struct hhg_ctx_s {
   bool force_stream3d = false;      // 3D plane-streaming sweep from n = 4 on (testing)
   bool no_planes3d = false;         // no whole-plane 3D sweep (testing, timing)
   bool force_planes3d = false;      // whole-plane 3D sweep from n = 16 on (testing)
+  bool two_launch_iface = false;    // 2D edge and vertex classes in two launches (testing, timing)
   bool generic_est = false;         // 2D L2 estimate by the one-thread-per-node kernel (testing)
   bool classwise_iface = false;     // 2D interface classes one launch each (testing)
   uint32_t xswap = 0;               // bit l (+16 for float32): level l's iterate is in its second buffer

@@ -53,6 +53,16 @@ void launch_iface2d_wheels(const LK& lk, const Tables& tb, const int32_t* wcopy,
                            const int32_t* wloc, const int32_t* wseg, const int32_t* wsrc, const double* wcw,
                            const int32_t* wwmax, int nwaves, int ncls, const T* xi, const T* xf, T* uout, T* umirror,
                            const T* b, double sA, hipStream_t st);
+// 2D, out of place: both edge classes and all vertex classes of a sweep in one launch (the
+// wheels recompute their edge-class neighbours; we2: per wheel lane the edge, side and
+// direction of that neighbour, or -1; a2i, a2w: that neighbour's rows, 16 entries per lane as a
+// struct of arrays); no mirror writes
+template <typename T>
+void launch_iface2d_sweep(const LK& lk, const Tables& tb, const int32_t* erec, int nE, const int32_t* dvcopy, int n_dv,
+                          const int32_t* wcopy, const int32_t* winfo, const int32_t* wloc, const int32_t* wseg,
+                          const int32_t* wsrc, const double* wcw, const int32_t* wwmax, int nwaves, int ncls,
+                          const int32_t* we2, const int32_t* a2i, const double* a2w, const T* xi, const T* xf,
+                          T* uout, const T* b, double sA, hipStream_t st);
 // classes the preloading single-workgroup interface form holds at once
 int iface_pre_classes(int dim, bool dbl);
 template <typename T>

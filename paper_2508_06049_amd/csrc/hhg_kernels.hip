@@ -123,6 +123,15 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
+// Logical block of this workgroup for kernels whose consecutive logical blocks touch the same
+// data (one macro's chunks, one class's wavefronts): block b runs on XCD b mod 8, so XCD x takes
+// the logical blocks x * per .. (x + 1) * per - 1 and their shared lines stay in one L2.  The
+// grid is padded to a multiple of 8 (grid8); logical blocks past the end return.
+__device__ __forceinline__ int d_xcd_block() {
+  const int per = (int)(gridDim.x >> 3);
+  return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+}
+
 // interface DoF t -> primitive p and coordinates along its sorted vertices
 __device__ __forceinline__ void d_iface_decode(const LK& lk, const Tables& tb, int64_t t, int& p, int co[3], int& np) {
   const int n = lk.n;
@@ -232,9 +241,10 @@ __global__ void __launch_bounds__(256) k_smooth_interior(LK lk, Tables tb, const
                                                           const T* __restrict__ b, int colour, int rb, int jacobi,
                                                           double omega, double sA, const double* __restrict__ kn) {
   const int nchunk = (lk.NI + 255) >> 8;
-  const int m = blockIdx.x / nchunk;
-  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
-  if (s >= lk.NI) return;
+  const int blk = d_xcd_block();
+  const int m = blk / nchunk;
+  const int s = (blk - m * nchunk) * 256 + threadIdx.x;
+  if (m >= lk.nmacro || s >= lk.NI) return;
   int i, j, k;
   d_dec<D>(lk.n - D - 1, s, i, j, k);
   ++i; ++j;
@@ -846,7 +856,7 @@ __global__ void __launch_bounds__(256) k_iface_tasks(LK lk, Tables tb, const int
                                                       const int32_t* __restrict__ tseg, const int32_t* __restrict__ wmax,
                                                       int w0, int w1, const T* xi, const T* xf, T* uout, T* umirror,
                                                       const T* __restrict__ b, int jacobi, double omega, double sA) {
-  const int w = __builtin_amdgcn_readfirstlane(w0 + (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+  const int w = __builtin_amdgcn_readfirstlane(w0 + d_xcd_block() * 4 + (int)(threadIdx.x >> 6));
   if (w >= w1) return;
   iface_task_wave<D, T>(lk, tb, tcopy, tinfo, tloc, tseg, wmax[w], w, xi, xf, uout, umirror, b, jacobi, omega, sA);
 }
@@ -1014,15 +1024,15 @@ __global__ void __launch_bounds__(1024) k_iface_tasks_1wg_pre(LK lk, Tables tb, 
 // class kernels (identical results).  The copies of the Dirichlet vertices (dvcopy) are
 // copied into the output buffers on the side.
 template <typename T>
-__global__ void __launch_bounds__(1024) k_iface2d_edges(LK lk, const int32_t* __restrict__ erec, int nE, int nch,
-                                                         int epb, const int32_t* __restrict__ dvcopy, int n_dv,
-                                                         const T* xi, const T* xf, T* uout, T* umirror,
-                                                         const T* __restrict__ b, double sA) {
-  __shared__ T s_e0[1024 + 2];
+__device__ __forceinline__ void iface2d_edges_body(int vblk, int nvblk, T* s_e0, const LK& lk,
+                                                   const int32_t* __restrict__ erec, int nE, int nch, int epb,
+                                                   const int32_t* __restrict__ dvcopy, int n_dv, const T* xi,
+                                                   const T* xf, T* uout, T* umirror, const T* __restrict__ b,
+                                                   double sA) {
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = (int)(threadIdx.x & 63);
   const int n = lk.n;
-  const int e = (int)blockIdx.x * epb + wave / nch, chunk = wave - (wave / nch) * nch;
+  const int e = vblk * epb + wave / nch, chunk = wave - (wave / nch) * nch;
   const bool has = wave < epb * nch && e < nE;
   const bool same = xi == xf;
   // per lane: position a on the edge, its copies k < ncp (closure index cp[k]); per copy the
@@ -1140,12 +1150,22 @@ __global__ void __launch_bounds__(1024) k_iface2d_edges(LK lk, const int32_t* __
       if (umirror) umirror[cp[k]] = v;
     }
   }
-  for (int q = (int)(blockIdx.x * 1024 + threadIdx.x); q < n_dv; q += (int)(gridDim.x * 1024)) {
+  for (int q = vblk * 1024 + (int)threadIdx.x; q < n_dv; q += nvblk * 1024) {
     const int c = dvcopy[q];
     const T v = xf[c];
     uout[c] = v;
     if (umirror) umirror[c] = v;
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_iface2d_edges(LK lk, const int32_t* __restrict__ erec, int nE, int nch,
+                                                         int epb, const int32_t* __restrict__ dvcopy, int n_dv,
+                                                         const T* xi, const T* xf, T* uout, T* umirror,
+                                                         const T* __restrict__ b, double sA) {
+  __shared__ T s_e0[1024 + 2];
+  iface2d_edges_body<T>((int)blockIdx.x, (int)gridDim.x, s_e0, lk, erec, nE, nch, epb, dvcopy, n_dv, xi, xf, uout,
+                        umirror, b, sA);
 }
 
 template <typename T>
@@ -1171,16 +1191,18 @@ template void launch_iface2d_edges<float>(const LK&, const int32_t*, int, const 
 // outside the wheel (interior and edge-class points, already swept, and Dirichlet points)
 // come from memory.
 template <typename T>
-__global__ void __launch_bounds__(256) k_iface2d_wheels(LK lk, Tables tb, const int32_t* __restrict__ wcopy,
-                                                         const int32_t* __restrict__ winfo,
-                                                         const int32_t* __restrict__ wloc,
-                                                         const int32_t* __restrict__ wseg,
-                                                         const int32_t* __restrict__ wsrc,
-                                                         const double* __restrict__ wcw,
-                                                         const int32_t* __restrict__ wwmax, int nwaves, int ncls,
-                                                         const T* xi, const T* xf, T* uout, T* umirror,
-                                                         const T* __restrict__ b, double sA) {
-  const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+__device__ __forceinline__ void iface2d_wheels_body(int w, const LK& lk, const Tables& tb,
+                                                    const int32_t* __restrict__ wcopy,
+                                                    const int32_t* __restrict__ winfo,
+                                                    const int32_t* __restrict__ wloc,
+                                                    const int32_t* __restrict__ wseg,
+                                                    const int32_t* __restrict__ wsrc,
+                                                    const double* __restrict__ wcw,
+                                                    const int32_t* __restrict__ wwmax, int nwaves, int ncls,
+                                                    const int32_t* __restrict__ we2, const int32_t* __restrict__ a2i,
+                                                    const double* __restrict__ a2w, const T* xi, const T* xf, T* uout,
+                                                    T* umirror,
+                                                    const T* __restrict__ b, double sA) {
   if (w >= nwaves) return;
   const int n = lk.n;
   const int lane = (int)(threadIdx.x & 63);
@@ -1190,6 +1212,18 @@ __global__ void __launch_bounds__(256) k_iface2d_wheels(LK lk, Tables tb, const 
   const int wm = wwmax[w];
   const bool live = cp >= 0;
   const bool same = xi == xf;
+  // the recompute tables of the one-launch form, loaded with the others (no dependence)
+  int e2 = -1, ai[16];
+  double aw[16];
+  if (we2) {
+    const int nl = nwaves * 64;
+    e2 = we2[idx];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      ai[q] = a2i[(size_t)q * nl + idx];
+      aw[q] = a2w[(size_t)q * nl + idx];
+    }
+  }
   T rhs = (T)0, dg = (T)0, u = (T)0;
   T coef[kNDir2 - 1], val[kNDir2 - 1];
 #pragma unroll
@@ -1222,6 +1256,41 @@ __global__ void __launch_bounds__(256) k_iface2d_wheels(LK lk, Tables tb, const 
       val[dd - 1] = same ? xf[ix] : (d_mask<2>(n, i2, j2, 0) ? xf : xi)[ix];
     }
     dg = (T)(scale * W[0]);
+    if (we2) {
+      // the edge-class neighbour (a = 2 from the wheel's vertex) is swept in the same launch:
+      // its new value is recomputed here from old values, with the same terms in the same order
+      // as the edge classes compute it (bitwise the same).  Per lane and copy k of that point
+      // (struct of arrays): a2i[8k] its closure index (-1: no such copy), a2i[8k + dd] the
+      // neighbour in direction dd (-1: none), a2i[8k + 7] bit dd - 1 set if that neighbour is
+      // an interface point (read from xf); a2w[8k] the macro's coefficient, a2w[8k + 1 + d] the
+      // unit stencil weight d
+      if (e2 >= 0) {
+        const int dd2 = (e2 >> 25) & 7;
+        T snum = (T)0, sdiag = (T)0;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int c2 = ai[8 * k];
+          if (c2 < 0) break;
+          const int fl = ai[8 * k + 7];
+          const double sc = sA * aw[8 * k];
+          const T r2 = b[c2];
+          T off2 = (T)0;
+#pragma unroll
+          for (int dd = 1; dd < kNDir2; ++dd) {
+            const int ix = ai[8 * k + dd];
+            if (ix < 0) continue;
+            const T v = ((fl >> (dd - 1)) & 1 ? xf : xi)[ix];
+            off2 += (T)(sc * aw[8 * k + 1 + dd]) * v;
+          }
+          snum += r2 - off2;
+          sdiag += (T)(sc * aw[8 * k + 1]);
+        }
+        const T v2 = snum / sdiag;
+#pragma unroll
+        for (int dd = 1; dd < kNDir2; ++dd)
+          if (dd == dd2) val[dd - 1] = v2;
+      }
+    }
   }
   const int lead = seg & 63, len = seg >> 8;
   for (int c = 0; c < ncls; ++c) {
@@ -1258,6 +1327,79 @@ __global__ void __launch_bounds__(256) k_iface2d_wheels(LK lk, Tables tb, const 
 }
 
 template <typename T>
+__global__ void __launch_bounds__(256) k_iface2d_wheels(LK lk, Tables tb, const int32_t* __restrict__ wcopy,
+                                                         const int32_t* __restrict__ winfo,
+                                                         const int32_t* __restrict__ wloc,
+                                                         const int32_t* __restrict__ wseg,
+                                                         const int32_t* __restrict__ wsrc,
+                                                         const double* __restrict__ wcw,
+                                                         const int32_t* __restrict__ wwmax, int nwaves, int ncls,
+                                                         const T* xi, const T* xf, T* uout, T* umirror,
+                                                         const T* __restrict__ b, double sA) {
+  const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+  iface2d_wheels_body<T>(w, lk, tb, wcopy, winfo, wloc, wseg, wsrc, wcw, wwmax, nwaves, ncls, nullptr, nullptr, nullptr,
+                         xi, xf, uout, umirror, b, sA);
+}
+
+// Both edge classes and all vertex classes of a 2D sweep in one launch (out of place, no
+// mirror writes): workgroups 0 .. ge-1 sweep the edge classes as k_iface2d_edges does, the
+// others the wheels (4 wavefronts each), which recompute their edge-class neighbours from
+// per-lane tables instead of waiting for them.  Every value read is final before the launch
+// (interior points in xi) or unchanged during it (xf), so the workgroups need no ordering; the
+// result is bitwise that of the two launches.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_iface2d_sweep(LK lk, Tables tb, const int32_t* __restrict__ erec, int nE,
+                                                         int nch, int epb, int ge, const int32_t* __restrict__ dvcopy,
+                                                         int n_dv, const int32_t* __restrict__ wcopy,
+                                                         const int32_t* __restrict__ winfo,
+                                                         const int32_t* __restrict__ wloc,
+                                                         const int32_t* __restrict__ wseg,
+                                                         const int32_t* __restrict__ wsrc,
+                                                         const double* __restrict__ wcw,
+                                                         const int32_t* __restrict__ wwmax, int nwaves, int ncls,
+                                                         const int32_t* __restrict__ we2,
+                                                         const int32_t* __restrict__ a2i,
+                                                         const double* __restrict__ a2w, const T* xi, const T* xf,
+                                                         T* uout, const T* __restrict__ b, double sA) {
+  __shared__ T s_e0[1024 + 2];
+  if ((int)blockIdx.x < ge) {
+    iface2d_edges_body<T>((int)blockIdx.x, ge, s_e0, lk, erec, nE, nch, epb, dvcopy, n_dv, xi, xf, uout, nullptr, b,
+                          sA);
+    return;
+  }
+  // four wheel wavefronts per workgroup (the others idle): a wheel wavefront is a long chain of
+  // shuffles and class steps, and more of them per compute unit only queue on its SIMDs
+  const int wv = (int)(threadIdx.x >> 6);
+  if (wv >= 4) return;
+  const int w = __builtin_amdgcn_readfirstlane(((int)blockIdx.x - ge) * 4 + wv);
+  iface2d_wheels_body<T>(w, lk, tb, wcopy, winfo, wloc, wseg, wsrc, wcw, wwmax, nwaves, ncls, we2, a2i, a2w, xi, xf,
+                         uout, nullptr, b, sA);
+}
+
+template <typename T>
+void launch_iface2d_sweep(const LK& lk, const Tables& tb, const int32_t* erec, int nE, const int32_t* dvcopy, int n_dv,
+                          const int32_t* wcopy, const int32_t* winfo, const int32_t* wloc, const int32_t* wseg,
+                          const int32_t* wsrc, const double* wcw, const int32_t* wwmax, int nwaves, int ncls,
+                          const int32_t* we2, const int32_t* a2i, const double* a2w, const T* xi, const T* xf, T* uout,
+                          const T* b, double sA, hipStream_t st) {
+  const int nch = (lk.n - 1 + 63) / 64, epb = 16 / nch;
+  const int ge = std::max(1, (nE + epb - 1) / epb), gw = (nwaves + 3) / 4;
+  k_iface2d_sweep<T><<<(unsigned)(ge + gw), 1024, 0, st>>>(lk, tb, erec, nE, nch, epb, ge, dvcopy, n_dv, wcopy, winfo,
+                                                           wloc, wseg, wsrc, wcw, wwmax, nwaves, ncls, we2, a2i, a2w,
+                                                           xi, xf, uout, b, sA);
+}
+template void launch_iface2d_sweep<double>(const LK&, const Tables&, const int32_t*, int, const int32_t*, int,
+                                           const int32_t*, const int32_t*, const int32_t*, const int32_t*,
+                                           const int32_t*, const double*, const int32_t*, int, int, const int32_t*,
+                                           const int32_t*, const double*, const double*, const double*, double*,
+                                           const double*, double, hipStream_t);
+template void launch_iface2d_sweep<float>(const LK&, const Tables&, const int32_t*, int, const int32_t*, int,
+                                          const int32_t*, const int32_t*, const int32_t*, const int32_t*,
+                                          const int32_t*, const double*, const int32_t*, int, int, const int32_t*,
+                                          const int32_t*, const double*, const float*, const float*, float*,
+                                          const float*, double, hipStream_t);
+
+template <typename T>
 void launch_iface2d_wheels(const LK& lk, const Tables& tb, const int32_t* wcopy, const int32_t* winfo,
                            const int32_t* wloc, const int32_t* wseg, const int32_t* wsrc, const double* wcw,
                            const int32_t* wwmax, int nwaves, int ncls, const T* xi, const T* xf, T* uout, T* umirror,
@@ -1288,7 +1430,7 @@ __global__ void __launch_bounds__(256) k_iface_residual_tasks(LK lk, Tables tb, 
                                                                const int32_t* __restrict__ wmax, int w0, int w1,
                                                                const Tin* __restrict__ x, const Tin* __restrict__ b,
                                                                Tout* __restrict__ y, double sA) {
-  const int w = __builtin_amdgcn_readfirstlane(w0 + (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+  const int w = __builtin_amdgcn_readfirstlane(w0 + d_xcd_block() * 4 + (int)(threadIdx.x >> 6));
   if (w >= w1) return;
   const int lane = (int)(threadIdx.x & 63);
   const int idx = w * 64 + lane;
@@ -1324,7 +1466,7 @@ template <int D, typename Tin, typename Tout, bool P1>
 __global__ void __launch_bounds__(256) k_iface_residual(LK lk, Tables tb, const Tin* __restrict__ x,
                                                          const Tin* __restrict__ b, Tout* __restrict__ y, double sA,
                                                          const double* __restrict__ kn) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t t = (int64_t)d_xcd_block() * 256 + threadIdx.x;
   if (t >= lk.nIface) return;
   int p, co[3], np;
   d_iface_decode(lk, tb, t, p, co, np);
@@ -1651,9 +1793,10 @@ __global__ void __launch_bounds__(256) k_apply(LK lk, Tables tb, const Tin* __re
                                                 Tout* __restrict__ y, int op, double scale, double alpha, double beta,
                                                 int zero_dir, const double* __restrict__ kn) {
   const int nchunk = (lk.Sraw + 255) >> 8;
-  const int m = blockIdx.x / nchunk;
-  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
-  if (s >= lk.Sraw) return;
+  const int blk = d_xcd_block();
+  const int m = blk / nchunk;
+  const int s = (blk - m * nchunk) * 256 + threadIdx.x;
+  if (m >= lk.nmacro || s >= lk.Sraw) return;
   apply_point<D, Tin, Tout, P1>(lk, tb, x, b, y, op, scale, alpha, beta, zero_dir, kn, m, s);
 }
 
@@ -1856,8 +1999,10 @@ __global__ void __launch_bounds__(256) k_restrict(LK f, LK c, Tables tb, const T
   // grid over the padded coarse block; zc (if given) is cleared over the whole block: the
   // coarse correction of the next cycle starts from zero without a separate fill launch
   const int nchunk = (int)((c.S + 255) >> 8);
-  const int m = blockIdx.x / nchunk;
-  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
+  const int blk = d_xcd_block();
+  const int m = blk / nchunk;
+  const int s = (blk - m * nchunk) * 256 + threadIdx.x;
+  if (m >= c.nmacro) return;
   if (zc && s < c.S) zc[(int64_t)m * c.S + s] = (T)0;
   if (s >= c.Sraw) return;
   restrict_point<D, T>(f, c, tb, rf, bc, m, s);
@@ -1888,9 +2033,10 @@ template <int D, typename T>
 __global__ void __launch_bounds__(256) k_prolong(LK f, LK c, Tables tb, const T* __restrict__ ec, T* __restrict__ uf,
                                                   T* __restrict__ w, const T* __restrict__ g, int mode) {
   const int nchunk = (f.Sraw + 255) >> 8;
-  const int m = blockIdx.x / nchunk;
-  const int s = (blockIdx.x - m * nchunk) * 256 + threadIdx.x;
-  if (s >= f.Sraw) return;
+  const int blk = d_xcd_block();
+  const int m = blk / nchunk;
+  const int s = (blk - m * nchunk) * 256 + threadIdx.x;
+  if (m >= f.nmacro || s >= f.Sraw) return;
   prolong_point<D, T>(f, c, tb, ec, uf, w, g, mode, m, s);
 }
 
@@ -2660,6 +2806,8 @@ __global__ void __launch_bounds__(256) k_copy(double* __restrict__ dst, const do
 // ------------------------------------------------------------------------------------------
 // launchers
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+// grid of kernels that map blocks with d_xcd_block: padded to a multiple of 8
+static inline unsigned grid8(int64_t blocks) { return (unsigned)((blocks + 7) / 8 * 8); }
 
 #define HHG_DISPATCH_D(dim, F, ...) \
   do {                              \
@@ -2680,7 +2828,7 @@ void launch_smooth_interior(int dim, bool p1, const LK& lk, const Tables& tb, co
     else k_gs3d_rows<T, false><<<g, 256, 0, st>>>(lk, tb, uout, b, colour, rb, sA, nrows);
     return;
   }
-  const unsigned g = (unsigned)(lk.nmacro * ((lk.NI + 255) / 256));
+  const unsigned g = grid8((int64_t)lk.nmacro * ((lk.NI + 255) / 256));
 #define HHG_SI(D, P, F) k_smooth_interior<D, T, P, F><<<g, 256, 0, st>>>(lk, tb, uin, uout, b, colour, rb, jacobi, omega, sA, kn)
   if (dim == 3) {
     if (p1) { if (fine) HHG_SI(3, true, true); else HHG_SI(3, true, false); }
@@ -2750,7 +2898,7 @@ void launch_iface_tasks(int dim, const LK& lk, const Tables& tb, const int32_t* 
                         const int32_t* tseg, const int32_t* wmax, int w0, int w1, const T* xi, const T* xf, T* uout,
                         T* umirror, const T* b, int jacobi, double omega, double sA, hipStream_t st) {
   if (w1 <= w0) return;
-  const unsigned g = (unsigned)((w1 - w0 + 3) / 4);
+  const unsigned g = grid8((w1 - w0 + 3) / 4);
   if (dim == 3)
     k_iface_tasks<3, T><<<g, 256, 0, st>>>(lk, tb, tp, tq, tco, tseg, wmax, w0, w1, xi, xf, uout, umirror, b, jacobi,
                                            omega, sA);
@@ -2834,7 +2982,7 @@ void launch_apply(int dim, bool p1, const LK& lk, const Tables& tb, const Tin* x
     k_apply3d_rows<Tin, Tout><<<gw, 256, 0, st>>>(lk, tb, x, b, y, op, scale, alpha, beta, zero_dir, nrows);
     return;
   }
-  const unsigned g = (unsigned)(lk.nmacro * ((lk.Sraw + 255) / 256));
+  const unsigned g = grid8((int64_t)lk.nmacro * ((lk.Sraw + 255) / 256));
   if (dim == 3) {
     if (p1) k_apply<3, Tin, Tout, true><<<g, 256, 0, st>>>(lk, tb, x, b, y, op, scale, alpha, beta, zero_dir, kn);
     else k_apply<3, Tin, Tout, false><<<g, 256, 0, st>>>(lk, tb, x, b, y, op, scale, alpha, beta, zero_dir, kn);
@@ -2849,7 +2997,7 @@ void launch_iface_residual_tasks(int dim, const LK& lk, const Tables& tb, const 
                                  const int32_t* tco, const int32_t* tseg, const int32_t* wmax, int w0, int w1,
                                  const Tin* x, const Tin* b, Tout* y, double sA, hipStream_t st) {
   if (w1 <= w0) return;
-  const unsigned g = (unsigned)((w1 - w0 + 3) / 4);
+  const unsigned g = grid8((w1 - w0 + 3) / 4);
   if (dim == 3)
     k_iface_residual_tasks<3, Tin, Tout><<<g, 256, 0, st>>>(lk, tb, tp, tq, tco, tseg, wmax, w0, w1, x, b, y, sA);
   else
@@ -2863,7 +3011,7 @@ template <typename Tin, typename Tout>
 void launch_iface_residual(int dim, bool p1, const LK& lk, const Tables& tb, const Tin* x, const Tin* b, Tout* y,
                            double sA, const double* kn, hipStream_t st) {
   if (lk.nIface <= 0) return;
-  const unsigned g = nblk(lk.nIface);
+  const unsigned g = grid8(nblk(lk.nIface));
   if (dim == 3) {
     if (p1) k_iface_residual<3, Tin, Tout, true><<<g, 256, 0, st>>>(lk, tb, x, b, y, sA, kn);
     else k_iface_residual<3, Tin, Tout, false><<<g, 256, 0, st>>>(lk, tb, x, b, y, sA, kn);
@@ -2881,7 +3029,7 @@ void launch_restrict(int dim, const LK& f, const LK& c, const Tables& tb, const 
     k_restrict2d_rows<T><<<gw, 256, 0, st>>>(f, c, tb, rf, bc, zc, nseg);
     return;
   }
-  const unsigned g = (unsigned)(c.nmacro * ((c.S + 255) / 256));
+  const unsigned g = grid8((int64_t)c.nmacro * ((c.S + 255) / 256));
   if (dim == 3) k_restrict<3, T><<<g, 256, 0, st>>>(f, c, tb, rf, bc, zc);
   else k_restrict<2, T><<<g, 256, 0, st>>>(f, c, tb, rf, bc, zc);
 }
@@ -2895,7 +3043,7 @@ void launch_prolong(int dim, const LK& f, const LK& c, const Tables& tb, const T
     k_prolong2d_rows<T><<<gw, 256, 0, st>>>(f, c, tb, ec, uf, w, g, mode, nseg);
     return;
   }
-  const unsigned gr = (unsigned)(f.nmacro * ((f.Sraw + 255) / 256));
+  const unsigned gr = grid8((int64_t)f.nmacro * ((f.Sraw + 255) / 256));
   if (dim == 3) k_prolong<3, T><<<gr, 256, 0, st>>>(f, c, tb, ec, uf, w, g, mode);
   else k_prolong<2, T><<<gr, 256, 0, st>>>(f, c, tb, ec, uf, w, g, mode);
 }

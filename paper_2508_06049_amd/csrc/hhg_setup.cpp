@@ -594,8 +594,9 @@ hhg_status build_colouring(hhg_ctx c) {
     // values between lanes; a wheel's lanes (one per copy of each DoF, DoFs in class order)
     // never split across wavefronts
     lv.wheels = false;
+    lv.wh_merge = false;
     lv.wh_copy.clear(); lv.wh_info.clear(); lv.wh_loc.clear(); lv.wh_seg.clear(); lv.wh_src.clear();
-    lv.wh_wmax.clear(); lv.wh_cw.clear();
+    lv.wh_wmax.clear(); lv.wh_cw.clear(); lv.wh_e2.clear(); lv.wh_a2i.clear(); lv.wh_a2w.clear();
     if (lv.fused_iface && lv.ncolours - lv.c_vr0 <= 15) {
       bool ok = true;
       const int n = lv.n;
@@ -664,9 +665,13 @@ hhg_status build_colouring(hhg_ctx c) {
         lv.wh_copy.push_back(-1); lv.wh_info.push_back(0); lv.wh_loc.push_back(0); lv.wh_seg.push_back(0);
       }
       // per lane and direction: the lane holding that neighbour if it is a DoF of the same
-      // wheel (0xff otherwise: read from memory); no vertex-class neighbour may lie outside
+      // wheel (0xff otherwise: read from memory); no vertex-class neighbour may lie outside.
+      // A neighbour in an edge class (at most one per lane: a = 2 from the wheel's vertex on
+      // the lane's own edge) is recorded for the one-launch form, which recomputes it
+      bool merge = true;
       for (size_t idx = 0; idx < lv.wh_copy.size() && ok; ++idx) {
         uint32_t sa = 0xffffffffu, sb = 0xffffffffu;
+        int32_t e2 = -1;
         if (lv.wh_copy[idx] >= 0) {
           const int m = lv.wh_info[idx] & 0xffffff, mask = (lv.wh_info[idx] >> 24) & 15;
           const int i = lv.wh_loc[idx] & 2047, j = lv.wh_loc[idx] >> 11;
@@ -678,7 +683,16 @@ hhg_status build_colouring(hhg_ctx c) {
             if (zero_mask(2, n, i2, j2, 0) == 0) continue;
             const int64_t tn = canonical_index(c, lv, m, i2, j2, 0);
             if (tn < 0 || tn >= lv.nIface) { ok = false; break; }
-            if (col[tn] < lv.c_vr0) continue;   // edge class or Dirichlet: from memory
+            if (col[tn] < lv.c_vr0) {   // edge class or Dirichlet: from memory
+              int p2, co2[3];
+              iface_decode(c, lv, tn, p2, co2);
+              if (p2 >= c->nV && p2 < c->nV + c->nE && !c->primdir[p2]) {
+                const int a2 = co2[1];
+                if (e2 >= 0 || (a2 != 2 && a2 != n - 2) || (c->nE >= (1 << 24))) merge = false;
+                else e2 = (p2 - (int)c->nV) | ((a2 == 2 ? 0 : 1) << 24) | (dd << 25);
+              }
+              continue;
+            }
             if (wheel_of[tn] != wheel_of[tself] || lead_of[tn] < 0) { ok = false; break; }
             const uint32_t sl = (uint32_t)lead_of[tn];
             if (dd <= 4) sa = (sa & ~(0xffu << (8 * (dd - 1)))) | (sl << (8 * (dd - 1)));
@@ -687,6 +701,7 @@ hhg_status build_colouring(hhg_ctx c) {
         }
         lv.wh_src.push_back((int32_t)sa);
         lv.wh_src.push_back((int32_t)sb);
+        lv.wh_e2.push_back(e2);
       }
       // per lane: the macro's coefficient (filled in at upload) and its unit stencil weights
       // for the lane's mask, as a struct of arrays
@@ -702,6 +717,45 @@ hhg_status build_colouring(hhg_ctx c) {
       for (int w = 0; w < nw; ++w)
         for (int q = 0; q < 64; ++q) lv.wh_wmax[w] = std::max(lv.wh_wmax[w], lv.wh_seg[w * 64 + q] >> 8);
       lv.wheels = ok;
+      lv.wh_merge = ok && merge && !c->erec.empty();
+      if (lv.wh_merge) {
+        // the rows of each lane's edge-class neighbour, from the edge records (the coefficient
+        // is filled in with the others, fill_kappa_tables)
+        lv.wh_a2i.assign(nl * 16, -1);
+        lv.wh_a2w.assign(nl * 16, 0.0);
+        for (size_t idx = 0; idx < nl && lv.wh_merge; ++idx) {
+          const int32_t e2 = lv.wh_e2[idx];
+          if (e2 < 0) continue;
+          const int e = e2 & 0xffffff, a = ((e2 >> 24) & 1) ? n - 2 : 2;
+          const int32_t* Rr = &c->erec[(size_t)e * kEdgeRecWords];
+          const int ncp = Rr[0] & 3;
+          for (int k = 0; k < ncp && k < 2; ++k) {
+            const int32_t* Cc = Rr + 2 + kEdgeCopyWords * k;
+            const int macro = Cc[0], sl = Cc[1];
+            const int s0 = sl & 3, s1 = (sl >> 8) & 3, mask = (sl >> 16) & 15;
+            int lc[3] = {0, 0, 0};
+            lc[s0] = n - a;
+            lc[s1] = a;
+            const int64_t base = (int64_t)macro * lv.S;
+            const int64_t cpk = base + lin_closure(2, n, lc[1], lc[2], 0);
+            if (cpk < 0 || cpk >= lv.nfull) { lv.wh_merge = false; break; }
+            lv.wh_a2i[(size_t)(8 * k) * nl + idx] = (int32_t)cpk;
+            int fl = 0;
+            for (int dd = 1; dd < kNDir2; ++dd) {
+              if (!((c->validdirs[mask] >> dd) & 1)) continue;
+              const int i2 = lc[1] + kOff2[dd][0], j2 = lc[2] + kOff2[dd][1];
+              const int64_t ix = base + lin_closure(2, n, i2, j2, 0);
+              if (i2 < 0 || j2 < 0 || i2 + j2 > n || ix < base || ix >= base + lv.Sraw) { lv.wh_merge = false; break; }
+              lv.wh_a2i[(size_t)(8 * k + dd) * nl + idx] = (int32_t)ix;
+              if (zero_mask(2, n, i2, j2, 0) != 0) fl |= 1 << (dd - 1);
+            }
+            lv.wh_a2i[(size_t)(8 * k + 7) * nl + idx] = fl;
+            for (int dd = 0; dd < kNDir2; ++dd)
+              lv.wh_a2w[(size_t)(8 * k + 1 + dd) * nl + idx] = c->stiff[((size_t)macro * kMaxMask + mask) * kNDir2 + dd];
+          }
+        }
+      }
+      if (!lv.wh_merge) { lv.wh_e2.clear(); lv.wh_a2i.clear(); lv.wh_a2w.clear(); }
       if (!ok) {
         lv.wh_copy.clear(); lv.wh_info.clear(); lv.wh_loc.clear(); lv.wh_seg.clear(); lv.wh_src.clear();
         lv.wh_wmax.clear(); lv.wh_cw.clear();
@@ -964,9 +1018,21 @@ void fill_kappa_tables(hhg_ctx c) {
       reinterpret_cast<double*>(Cc + 2)[0] = c->kappa_cell[Cc[0]];
     }
   }
-  for (auto& lv : c->lev)
+  for (auto& lv : c->lev) {
     for (size_t idx = 0; idx < lv.wh_copy.size(); ++idx)
       if (lv.wh_copy[idx] >= 0) lv.wh_cw[idx] = c->kappa_cell[lv.wh_info[idx] & 0xffffff];
+    // the coefficients of the recomputed edge-class neighbours (copy k's macro from the edge
+    // record of the lane's edge)
+    const size_t nl = lv.wh_copy.size();
+    if (lv.wh_a2w.size() == nl * 16)
+      for (size_t idx = 0; idx < nl; ++idx) {
+        const int32_t e2 = lv.wh_e2[idx];
+        if (e2 < 0) continue;
+        const int32_t* Rr = &c->erec[(size_t)(e2 & 0xffffff) * kEdgeRecWords];
+        for (int k = 0; k < (Rr[0] & 3) && k < 2; ++k)
+          lv.wh_a2w[(size_t)(8 * k) * nl + idx] = c->kappa_cell[Rr[2 + kEdgeCopyWords * k]];
+      }
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1037,6 +1103,9 @@ void plan_workspace(hhg_ctx c) {
     lv.off_twoff = take((int64_t)lv.task_woff.size() * 4);
     lv.off_dvcopy = take((int64_t)lv.dvcopy.size() * 4);
     lv.off_whcw = take((int64_t)lv.wh_cw.size() * 8);
+    lv.off_whe2 = take((int64_t)lv.wh_e2.size() * 4);
+    lv.off_wha2i = take((int64_t)lv.wh_a2i.size() * 4);
+    lv.off_wha2w = take((int64_t)lv.wh_a2w.size() * 8);
     lv.off_whcopy = take((int64_t)lv.wh_copy.size() * 4);
     lv.off_whinfo = take((int64_t)lv.wh_info.size() * 4);
     lv.off_whloc = take((int64_t)lv.wh_loc.size() * 4);

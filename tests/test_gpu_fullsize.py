@@ -346,16 +346,18 @@ def test_largest_3d_level():
 
 @pytest.mark.parametrize("L,precision", [(4, "fp64"), (6, "fp32_refined"), (9, "fp64"), (9, "fp32_refined")])
 def test_one_launch_interface_equals_classwise(lshape, L, precision):
-    # all interface classes of a 2D sweep in one launch (the edge classes by edge chunks, the
-    # vertex classes in the last workgroup to finish) against one launch per class (or per run
-    # of small classes): three sweeps from a random iterate, then a solve, bitwise identical
+    # all interface classes of a 2D sweep in one launch (edge-chunk workgroups sweep the edge
+    # classes, wheel workgroups the vertex classes, recomputing their edge-class neighbours)
+    # against the edge and vertex classes in two launches and against one launch per class (or
+    # per run of small classes): three sweeps from a random iterate, then a solve, bitwise
+    # identical
     import torch
     from paper_2508_06049_amd import HHG
-    from paper_2508_06049_amd._lib import HHG_FLAG_CLASSWISE_IFACE
+    from paper_2508_06049_amd._lib import HHG_FLAG_CLASSWISE_IFACE, HHG_FLAG_TWO_LAUNCH_IFACE
     w = lshape
     _note("one-launch vs classwise interface", w.name, L, precision)
     out = []
-    for flags in (0, HHG_FLAG_CLASSWISE_IFACE):
+    for flags in (0, HHG_FLAG_CLASSWISE_IFACE, HHG_FLAG_TWO_LAUNCH_IFACE):
         hh = HHG(w.mesh.coords, w.mesh.cells, L, smoother=w.smoother, flags=flags)
         X = hh.dof_coords().cpu().numpy()
         rng = np.random.default_rng(7)
@@ -366,5 +368,6 @@ def test_one_launch_interface_equals_classwise(lshape, L, precision):
         hh.close()
         del hh
         torch.cuda.synchronize()
-    assert np.array_equal(out[0][0], out[1][0])
-    assert np.array_equal(out[0][1], out[1][1])
+    for o in out[1:]:
+        assert np.array_equal(out[0][0], o[0])
+        assert np.array_equal(out[0][1], o[1])
