@@ -145,6 +145,25 @@ hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
   const bool fused = fused_available(c, l, sizeof(T));
   // out-of-place interior sweep (k_gs2d_fused, k_gs3d_planes, k_gs3d_stream)
   const bool twobuf = fused && (c->dim == 2 || !lv.tiles.empty());
+  if (!jac && lv.NI == 0 && lv.task_ok && !c->no_tasks && !lv.fused_iface && sweeps > 1) {
+    // no macro interiors (n = 2) and every interface class in the single-workgroup form that
+    // does not preload: all sweeps in one launch, the same class sequence repeated
+    bool one = true, pre = !c->no_preload;
+    for (int cc = lv.interior_colours; cc < lv.ncolours; ++cc) {
+      const int wv = lv.task_woff[cc + 1] - lv.task_woff[cc];
+      if (wv > kTaskOneGroupWaves) one = false;
+      if (wv > 16) pre = false;
+    }
+    if (pre && lv.ncolours - lv.interior_colours <= iface_pre_classes(c->dim, sizeof(T) == 8)) one = false;
+    if (one) {
+      T* x = Arr<T>::x(lv);
+      launch_iface_tasks_1wg<T>(c->dim, k, c->tab, lv.d_task_copy, lv.d_task_info, lv.d_task_loc, lv.d_task_seg,
+                                lv.d_task_wmax, lv.d_task_woff, lv.interior_colours, lv.ncolours, x, x, x, (T*)nullptr,
+                                b, sA(c, l), false, ST(c), sweeps);
+      LAUNCHCHK();
+      return HHG_OK;
+    }
+  }
   for (int s = 0; s < sweeps; ++s) {
     T* x = Arr<T>::x(lv);
     if (jac) {

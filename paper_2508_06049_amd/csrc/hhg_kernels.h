@@ -41,7 +41,7 @@ template <typename T>
 void launch_iface_tasks_1wg(int dim, const LK& lk, const Tables& tb, const int32_t* tp, const int32_t* tq,
                             const int32_t* tco, const int32_t* tseg, const int32_t* wmax, const int32_t* woff, int c0,
                             int c1, const T* xi, const T* xf, T* uout, T* umirror, const T* b, double sA, bool pre,
-                            hipStream_t st);
+                            hipStream_t st, int sweeps = 1);
 // 2D: both edge classes of a sweep in one launch (edge chunks; erec: one record of
 // kEdgeRecWords words per macro edge), plus the copies of the Dirichlet vertex values
 template <typename T>

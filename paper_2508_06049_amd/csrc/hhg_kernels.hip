@@ -870,14 +870,15 @@ __global__ void __launch_bounds__(1024) k_iface_tasks_1wg(LK lk, Tables tb, cons
                                                            const int32_t* __restrict__ wmax,
                                                            const int32_t* __restrict__ woff, int c0, int c1, const T* xi,
                                                            const T* xf, T* uout, T* umirror, const T* __restrict__ b,
-                                                           double sA) {
+                                                           double sA, int sweeps) {
   const int wave = (int)(threadIdx.x >> 6);
-  for (int c = c0; c < c1; ++c) {
-    const int e = woff[c + 1];
-    for (int w = woff[c] + wave; w < e; w += 16)
-      iface_task_wave<D, T>(lk, tb, tcopy, tinfo, tloc, tseg, wmax[w], w, xi, xf, uout, umirror, b, 0, 0.0, sA);
-    __syncthreads();
-  }
+  for (int sw = 0; sw < sweeps; ++sw)
+    for (int c = c0; c < c1; ++c) {
+      const int e = woff[c + 1];
+      for (int w = woff[c] + wave; w < e; w += 16)
+        iface_task_wave<D, T>(lk, tb, tcopy, tinfo, tloc, tseg, wmax[w], w, xi, xf, uout, umirror, b, 0, 0.0, sA);
+      __syncthreads();
+    }
 }
 
 // The same classes in one workgroup with the sweep-invariant part of every row loaded before
@@ -2911,7 +2912,7 @@ template <typename T>
 void launch_iface_tasks_1wg(int dim, const LK& lk, const Tables& tb, const int32_t* tp, const int32_t* tq,
                             const int32_t* tco, const int32_t* tseg, const int32_t* wmax, const int32_t* woff, int c0,
                             int c1, const T* xi, const T* xf, T* uout, T* umirror, const T* b, double sA, bool pre,
-                            hipStream_t st) {
+                            hipStream_t st, int sweeps) {
   if (c1 <= c0) return;
   // preloading form: the caller has checked that every class has at most 16 wavefronts
   if (pre && c1 - c0 <= iface_pre_classes(dim, sizeof(T) == 8)) {
@@ -2927,10 +2928,10 @@ void launch_iface_tasks_1wg(int dim, const LK& lk, const Tables& tb, const int32
   }
   if (dim == 3)
     k_iface_tasks_1wg<3, T><<<1, 1024, 0, st>>>(lk, tb, tp, tq, tco, tseg, wmax, woff, c0, c1, xi, xf, uout, umirror, b,
-                                                sA);
+                                                sA, sweeps);
   else
     k_iface_tasks_1wg<2, T><<<1, 1024, 0, st>>>(lk, tb, tp, tq, tco, tseg, wmax, woff, c0, c1, xi, xf, uout, umirror, b,
-                                                sA);
+                                                sA, sweeps);
 }
 
 template <typename T>
@@ -3188,11 +3189,11 @@ template void launch_iface_tasks<float>(int, const LK&, const Tables&, const int
 template void launch_iface_tasks_1wg<double>(int, const LK&, const Tables&, const int32_t*, const int32_t*,
                                              const int32_t*, const int32_t*, const int32_t*, const int32_t*, int, int,
                                              const double*, const double*, double*, double*, const double*, double, bool,
-                                             hipStream_t);
+                                             hipStream_t, int);
 template void launch_iface_tasks_1wg<float>(int, const LK&, const Tables&, const int32_t*, const int32_t*,
                                             const int32_t*, const int32_t*, const int32_t*, const int32_t*, int, int,
                                             const float*, const float*, float*, float*, const float*, double, bool,
-                                            hipStream_t);
+                                            hipStream_t, int);
 template void launch_smooth_iface<double>(int, bool, const LK&, const Tables&, const int32_t*, int, const double*,
                                           const double*, double*, double*, const double*, int, double, double,
                                           const double*, hipStream_t);
