@@ -446,10 +446,13 @@ def main():
     kname = KERNEL_NAME.get((w.mesh.dim, w.smoother, w.coefficient), "k_smooth_interior")
     if w.mesh.dim == 3 and 2 ** w.L > 32:
         # 3D levels above n = 32 (the macro does not fit in LDS): red-black with a per-macro
-        # coefficient streams planes (both colours in one launch) from n = 256 on, other
-        # smoothers and smaller levels go class by class
-        if w.smoother == "redblack" and w.coefficient == "macro" and 2 ** w.L >= 256:
+        # coefficient sweeps whole planes at n = 64 and streams tiles from n = 256 on (both
+        # colours in one launch), other smoothers and levels go class by class
+        rbm = w.smoother == "redblack" and w.coefficient == "macro"
+        if rbm and 2 ** w.L >= 256:
             kname = "k_gs3d_stream<float, true>"
+        elif rbm and 2 ** w.L == 64:
+            kname = "k_gs3d_planes<float, 64, true>"
         else:
             kname = "k_gs3d_rows<float, true>" if 2 ** w.L >= 128 else "k_smooth_interior"
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",

@@ -179,6 +179,47 @@ __device__ __forceinline__ T d_prolong_val(int nc, const T* __restrict__ ec, int
   return (T)0.5 * (lo + hi);
 }
 
+// closure index of the neighbour of (i,j,k) in 3D direction q (kOff3), from the plane and row
+// offsets of the point: the 14 neighbours lie on 7 rows (row j + b of plane k + c), and with
+// P(k) the first point of plane k and r = rowin(j, k) = j (n - k + 1) - j (j - 1) / 2,
+// rowin(j + 1, k) = r + (n - k + 1) - j, rowin(j, k + 1) = r - j, P(k + 1) = P(k) + (n - k + 1)
+// (n - k + 2) / 2.  Only neighbours inside the closure are meaningful.
+struct Nbr3 {
+  int c00, cp0, cm0, c0p, c0m, cmp, cpm;   // row starts + i of the rows (b, c) = (0,0) (1,0) (-1,0) (0,1) (0,-1) (-1,1) (1,-1)
+  __device__ __forceinline__ Nbr3(int n, int i, int j, int k) {
+    const int pk = d_tet(n) - d_tet(n - k);
+    const int n1 = n - k + 1;
+    const int r = j * n1 - ((j * (j - 1)) >> 1);
+    const int pp = pk + ((n1 * (n1 + 1)) >> 1), pm = pk - (((n1 + 1) * (n1 + 2)) >> 1);
+    c00 = pk + r + i;
+    cp0 = c00 + n1 - j;
+    cm0 = c00 - n1 + j - 1;
+    c0p = pp + r - j + i;
+    c0m = pm + r + j + i;
+    cmp = pp + r - n1 + i;
+    cpm = pm + r + n1 + 1 + i;
+  }
+  __device__ __forceinline__ int at(int q) const {
+    const int b = kOff3[q][1], c = kOff3[q][2], a = kOff3[q][0];
+    const int rb = c == 0 ? (b == 0 ? c00 : (b > 0 ? cp0 : cm0)) : (c > 0 ? (b == 0 ? c0p : cmp) : (b == 0 ? c0m : cpm));
+    return rb + a;
+  }
+};
+
+// closure index of the neighbour in direction q of a 2D or 3D closure point
+template <int D>
+struct NbrIdx;
+template <>
+struct NbrIdx<3> : Nbr3 {
+  __device__ __forceinline__ NbrIdx(int n, int i, int j, int k) : Nbr3(n, i, j, k) {}
+};
+template <>
+struct NbrIdx<2> {
+  int n, i, j;
+  __device__ __forceinline__ NbrIdx(int n_, int i_, int j_, int) : n(n_), i(i_), j(j_) {}
+  __device__ __forceinline__ int at(int q) const { return d_lin2(n, i + kOff2[q][0], j + kOff2[q][1]); }
+};
+
 // row of the partial operator of macro m at closure point (i,j,k) with zero-set `mask`:
 // off = sum_{neighbours} a_q x_q, diag = a_centre.  Constant-coefficient stencil table.
 template <int D, typename T>
@@ -186,12 +227,21 @@ __device__ __forceinline__ void d_row_const(const LK& lk, const double* __restri
                                             const T* __restrict__ x, int64_t base, int i, int j, int k, T& off, T& diag) {
   constexpr int ND = ndir<D>();
   T acc = (T)0;
+  if constexpr (D == 3) {
+    const Nbr3 nb(lk.n, i, j, k);
 #pragma unroll
-  for (int q = 1; q < ND; ++q) {
-    if (!((valid >> q) & 1)) continue;
-    int a, b, c;
-    d_off<D>(q, a, b, c);
-    acc += (T)(scale * W[q]) * x[base + d_lin<D>(lk.n, i + a, j + b, k + c)];
+    for (int q = 1; q < ND; ++q) {
+      if (!((valid >> q) & 1)) continue;
+      acc += (T)(scale * W[q]) * x[base + nb.at(q)];
+    }
+  } else {
+#pragma unroll
+    for (int q = 1; q < ND; ++q) {
+      if (!((valid >> q) & 1)) continue;
+      int a, b, c;
+      d_off<D>(q, a, b, c);
+      acc += (T)(scale * W[q]) * x[base + d_lin<D>(lk.n, i + a, j + b, k + c)];
+    }
   }
   off = acc;
   diag = (T)(scale * W[0]);
@@ -722,13 +772,14 @@ __device__ __forceinline__ void iface_update(const LK& lk, const Tables& tb, int
       const double* W = tb.stiff + ((size_t)in.macro * kMaxMask + in.mask) * ndir<D>();
       const uint32_t valid = tb.validdirs[in.mask];
       const double scale = sA * tb.kappa[in.macro];
+      const NbrIdx<D> nb(lk.n, i, j, k);
 #pragma unroll
       for (int dd = 1; dd < ndir<D>(); ++dd) {
         if (!((valid >> dd) & 1)) continue;
         int a, b2, c;
         d_off<D>(dd, a, b2, c);
         const int i2 = i + a, j2 = j + b2, k2 = k + c;
-        off += (T)(scale * W[dd]) * (d_mask<D>(lk.n, i2, j2, k2) ? xf : xi)[base + d_lin<D>(lk.n, i2, j2, k2)];
+        off += (T)(scale * W[dd]) * (d_mask<D>(lk.n, i2, j2, k2) ? xf : xi)[base + nb.at(dd)];
       }
       diag += (T)(scale * W[0]);
     }
@@ -809,20 +860,22 @@ __device__ __forceinline__ void iface_task_wave(const LK& lk, const Tables& tb, 
       const double* W = tb.stiff + ((size_t)m * kMaxMask + mask) * ndir<D>();
       const uint32_t valid = tb.validdirs[mask];
       const double scale = sA * tb.kappa[m];
+      const NbrIdx<D> nb(lk.n, i, j, k);
 #pragma unroll
       for (int dd = 1; dd < ndir<D>(); ++dd) {
         if (!((valid >> dd) & 1)) continue;
         int a, b2, c;
         d_off<D>(dd, a, b2, c);
         const int i2 = i + a, j2 = j + b2, k2 = k + c;
-        const uint32_t o = (uint32_t)(base + d_lin<D>(lk.n, i2, j2, k2)) * (uint32_t)sizeof(T);
+        const uint32_t li = (uint32_t)(base + nb.at(dd));
+        const uint32_t o = li * (uint32_t)sizeof(T);
         T v;
         if (same) {
           d_bload(rxf, o, v);
         } else {
           // interface neighbours from xf, interior ones from xi: one load through a per-lane
           // address (a buffer descriptor must be wave-uniform)
-          v = (d_mask<D>(lk.n, i2, j2, k2) ? xf : xi)[(uint32_t)(base + d_lin<D>(lk.n, i2, j2, k2))];
+          v = (d_mask<D>(lk.n, i2, j2, k2) ? xf : xi)[li];
         }
         off += (T)(scale * W[dd]) * v;
       }
@@ -926,13 +979,14 @@ __device__ __forceinline__ void task_pre_load(const LK& lk, const Tables& tb, co
   const double* W = tb.stiff + ((size_t)m * kMaxMask + mask) * ndir<D>();
   q.valid = tb.validdirs[mask];
   const double scale = sA * tb.kappa[m];
+  const NbrIdx<D> nb(lk.n, i, j, k);
 #pragma unroll
   for (int dd = 1; dd < ndir<D>(); ++dd) {
     if (!((q.valid >> dd) & 1)) continue;
     int a, b2, c;
     d_off<D>(dd, a, b2, c);
     const int i2 = i + a, j2 = j + b2, k2 = k + c;
-    q.o[dd - 1] = (uint32_t)(base + d_lin<D>(lk.n, i2, j2, k2)) * (uint32_t)sizeof(T);
+    q.o[dd - 1] = (uint32_t)(base + nb.at(dd)) * (uint32_t)sizeof(T);
     q.coef[dd - 1] = (T)(scale * W[dd]);
     if (d_mask<D>(lk.n, i2, j2, k2)) q.ifm |= 1u << dd;
     else d_bload(rxi, q.o[dd - 1], q.v[dd - 1]);
@@ -1983,13 +2037,12 @@ __device__ __forceinline__ void restrict_point(const LK& f, const LK& c, const T
   if ((tb.dirbits[m] >> mask) & 1) { bc[cb + s] = (T)0; return; }
   const uint32_t valid = tb.validdirs[mask];
   const int fi = 2 * i, fj = 2 * j, fk = 2 * k;
+  const NbrIdx<D> nb(f.n, fi, fj, fk);
   T acc = (T)0;
 #pragma unroll
   for (int q = 1; q < ndir<D>(); ++q) {
     if (!((valid >> q) & 1)) continue;
-    int a, b2, cc;
-    d_off<D>(q, a, b2, cc);
-    acc += rf[fb + d_lin<D>(f.n, fi + a, fj + b2, fk + cc)];
+    acc += rf[fb + nb.at(q)];
   }
   bc[cb + s] = rf[fb + d_lin<D>(f.n, fi, fj, fk)] + (T)0.5 * acc;
 }
