@@ -132,7 +132,10 @@ bool fused_available(hhg_ctx c, int l, size_t tsize) {
   const Level& lv = c->lev[l];
   if (p1(c) || lv.NI <= 0 || c->opt.smoother == HHG_JACOBI || c->no_fused) return false;
   if (c->dim == 2) return !lv.tiles.empty();
-  if (!lv.tiles.empty()) return true;   // the whole-plane or plane-streaming 3D sweep
+  // the whole-plane 3D sweep serves float32 only: in float64 (twice the LDS per plane, one
+  // workgroup per compute unit) the class-by-class sweep measured faster
+  if (lv.planes3d) return tsize == 4;
+  if (!lv.tiles.empty()) return true;   // the plane-streaming 3D sweep
   return !lv.itab.empty() && (size_t)lv.Sraw * tsize <= 64 * 1024;
 }
 
@@ -182,7 +185,11 @@ hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
     if (fused) interior_launch<T>(c, l, k, x, y, b, -1, rb, 0);
     else
       for (int col = 0; col < lv.interior_colours; ++col) interior_launch<T>(c, l, k, x, x, b, col, rb, 0);
-    T* mir = twobuf ? x : (T*)nullptr;
+    // the whole-plane 3D sweep also copies the interface values into y, so the interface
+    // classes then update y in place: one buffer, no mirror writes
+    const bool in_y = twobuf && lv.planes3d;
+    T* xf = in_y ? y : x;
+    T* mir = twobuf && !in_y ? x : (T*)nullptr;
     if (lv.task_ok && !c->no_tasks) {
       // 2D with large edge classes: both edge classes in one launch by edge chunks; then, as
       // for all classes otherwise, a class of more than kTaskOneGroupWaves wavefronts gets a
@@ -212,7 +219,7 @@ hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
         auto waves = [&](int cc) { return lv.task_woff[cc + 1] - lv.task_woff[cc]; };
         if (waves(col) > kTaskOneGroupWaves) {
           launch_iface_tasks<T>(c->dim, k, c->tab, lv.d_task_copy, lv.d_task_info, lv.d_task_loc, lv.d_task_seg,
-                                lv.d_task_wmax, lv.task_woff[col], lv.task_woff[col + 1], y, x, y, mir, b, 0, 0.0,
+                                lv.d_task_wmax, lv.task_woff[col], lv.task_woff[col + 1], y, xf, y, mir, b, 0, 0.0,
                                 sA(c, l), ST(c));
           ++col;
           continue;
@@ -224,16 +231,16 @@ hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
           ++c1;
         }
         launch_iface_tasks_1wg<T>(c->dim, k, c->tab, lv.d_task_copy, lv.d_task_info, lv.d_task_loc, lv.d_task_seg,
-                                  lv.d_task_wmax, lv.d_task_woff, col, c1, y, x, y, mir, b, sA(c, l), pre, ST(c));
+                                  lv.d_task_wmax, lv.d_task_woff, col, c1, y, xf, y, mir, b, sA(c, l), pre, ST(c));
         col = c1;
       }
     } else if (lv.max_iface_class <= kIfaceOneGroup) {
       launch_iface_sweep_1wg<T>(c->dim, p1(c), k, c->tab, lv.d_colour_list, lv.d_colour_off, lv.interior_colours,
-                                lv.ncolours, y, x, y, mir, b, sA(c, l), lv.kn, ST(c));
+                                lv.ncolours, y, xf, y, mir, b, sA(c, l), lv.kn, ST(c));
     } else {
       for (int col = lv.interior_colours; col < lv.ncolours; ++col) {
         const int cnt = lv.colour_off[col + 1] - lv.colour_off[col];
-        launch_smooth_iface<T>(c->dim, p1(c), k, c->tab, lv.d_colour_list + lv.colour_off[col], cnt, y, x, y, mir, b, 0,
+        launch_smooth_iface<T>(c->dim, p1(c), k, c->tab, lv.d_colour_list + lv.colour_off[col], cnt, y, xf, y, mir, b, 0,
                                0.0, sA(c, l), lv.kn, ST(c));
       }
     }

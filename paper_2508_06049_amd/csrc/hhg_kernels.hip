@@ -563,7 +563,8 @@ __global__ void __launch_bounds__(256) k_gs3d_stream(LK lk, Tables tb, const T* 
 }
 
 // Red-black Gauss-Seidel sweep of all macro interiors of a 3D level with n <= NMAX (NMAX <= 65),
-// both colours in one launch, out of place: reads u, writes the interior of uo.  One workgroup
+// both colours in one launch, out of place: reads u, writes the interior of uo and copies the
+// interface points of u into uo (so uo holds the whole iterate after the launch).  One workgroup
 // streams the planes k0 .. k1-1 of one macro.  A plane of the closure (the points of height k,
 // a triangle of side n - k stored contiguously) is copied whole into LDS, so in-plane
 // neighbours need no halo and the copy is one contiguous run.  Per plane p: copy plane p, update
@@ -666,6 +667,12 @@ __global__ void __launch_bounds__(512) k_gs3d_planes(LK lk, Tables tb, const T* 
     return off;
   };
   const int p0 = k0 - 2;
+  // the apex (plane n, one point) is copied by the last chunk
+  if (k1 == n - 2 && tid == 0) {
+    T v;
+    d_bload(ru, (uint32_t)plane(n) * (uint32_t)sizeof(T), v);
+    d_bstore(ro, (uint32_t)plane(n) * (uint32_t)sizeof(T), v);
+  }
   load_u(U[0], p0);
   load_u(U[1], p0 + 1);
   load_b(B[0], p0);
@@ -686,6 +693,25 @@ __global__ void __launch_bounds__(512) k_gs3d_planes(LK lk, Tables tb, const T* 
       if (p + 2 <= k1 + 1) load_u(U[s & 1], p + 2);
       if (p + 1 <= k1) load_b(B[(s + 1) & 3], p + 1);   // the set of plane p - 3, no longer read
       __syncthreads();
+      // the interface points of plane p (the macro boundary: i = 0, j = 0 or i + j = n - p, and
+      // all of plane 0), which the sweep does not change, go from LDS into uo as well, so that
+      // the interface classes can update uo in place.  Each plane is copied by one workgroup:
+      // the planes of its chunk, plane 0 by the first chunk, planes n-2 and n-1 by the last
+      if (p >= 0 && ((p >= k0 && p < k1) || (k0 == 1 && p == 0) || (k1 == n - 2 && p >= n - 2))) {
+        const int mm = n - p, nb = p == 0 ? psize(0) : 3 * mm, pp = plane(p);
+        const T* Sl = sU + slot(p);
+        for (int t = tid; t < nb; t += 512) {
+          int li = t;   // plane 0: every point, in order
+          if (p > 0) {
+            int i, j;
+            if (t <= mm) { i = t; j = 0; }
+            else if (t <= 2 * mm) { i = 0; j = t - mm; }
+            else { j = t - 2 * mm; i = mm - j; }
+            li = rowin(j, p) + i;
+          }
+          d_bstore(ro, (uint32_t)(pp + li) * (uint32_t)sizeof(T), Sl[li]);
+        }
+      }
       const int q = p - 1;   // red points of plane q, in place (b of plane q: set s + 3)
       if (q >= k0 - 1 && q <= k1 && q >= 1) {
 #pragma unroll

@@ -215,10 +215,10 @@ def test_3d_stream_sweep_matches(name, L):
 @pytest.mark.parametrize("name,L", [("kuhn1", 4), ("kuhn2", 5), ("kuhn1", 6)])
 def test_3d_plane_sweep_matches(name, L):
     # the whole-plane red-black 3D sweep (both colours in one out-of-place launch, chunks of
-    # whole closure planes in LDS; used at n = 64, forced here from n = 16 on with
-    # HHG_FLAG_PLANES3D) gives bit for bit the iterates
-    # of the class-by-class row sweep in float64 sweeps and in the float32-refined solve, over
-    # odd and even smoothing counts, and the oracle's smoother on the same input
+    # whole closure planes in LDS; used for the float32 sweeps at n = 64, forced here from n = 16
+    # on with HHG_FLAG_PLANES3D) gives bit for bit the iterates of the class-by-class row sweep
+    # in the float32-refined solve (float32 V-cycles); the float64 sweeps of the same context
+    # (class by class) match the row sweep and the oracle's smoother
     from paper_2508_06049_amd import HHG
     from paper_2508_06049_amd._lib import HHG_FLAG_NO_FUSED, HHG_FLAG_PLANES3D, HHG_FLAG_ROWS3D
     _note("3d plane sweep", name, L)
