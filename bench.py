@@ -426,11 +426,12 @@ def main():
             err = l2_error(hh, u, u_ex)
         ms, st, est = timed_steps(hh, f, g, w, prec, extra, args.steps, args.warmup, rtol)
         res[prec] = dict(extra_cycles=st.ir_steps, l2_error=err, ms=ms, vcycles=st.vcycles,
-                         dofs_per_s=N / (ms * 1e-3), eta_1=est["eta_j"], theta=est["theta"])
+                         dofs_per_s=N / (ms * 1e-3), eta_1=est["eta_j"], theta=est["theta"], dense_level=st.dense_level)
         if rtol:
             res[prec]["rtol"] = rtol
+        dense = f"levels 0..{st.dense_level} as a dense map" if st.dense_level >= 1 else "no dense coarse map"
         log(f"{prec}: FMG + {st.ir_steps} extra cycles, L2 error {err:.6e}, {st.vcycles} V-cycles, {ms:.2f} ms/step, "
-            f"{N / (ms * 1e-3):.3e} DoF/s, eta_1 {est['eta_j']:.4e}")
+            f"{N / (ms * 1e-3):.3e} DoF/s, eta_1 {est['eta_j']:.4e}, {dense}")
 
     sm = {}
     for prec in ("fp64", "fp32_refined"):

@@ -122,7 +122,15 @@ typedef struct {
                                  vertex classes in two launches (the vertex classes reading the
                                  new edge values from memory) instead of one launch in which
                                  they recompute them (identical result; for checking and
-                                 timing the one-launch form)                                   */
+                                 timing the one-launch form).
+                                 HHG_FLAG_NO_DENSE_COARSE: run the cycle on every coarse level
+                                 kernel by kernel instead of applying the dense map of the
+                                 coarse cycle (same result up to rounding; for checking and
+                                 timing the map).
+                                 HHG_FLAG_DENSE_COARSE: build the dense map on the largest
+                                 level that fits, up to L - 1, instead of only when the finest
+                                 level lies at least three levels above it (for checking it on
+                                 small problems)                                                */
 } hhg_options;
 
 enum {
@@ -136,7 +144,9 @@ enum {
   HHG_FLAG_CLASSWISE_IFACE = 128,
   HHG_FLAG_NO_PLANES3D = 256,
   HHG_FLAG_PLANES3D = 512,
-  HHG_FLAG_TWO_LAUNCH_IFACE = 1024
+  HHG_FLAG_TWO_LAUNCH_IFACE = 1024,
+  HHG_FLAG_NO_DENSE_COARSE = 2048,
+  HHG_FLAG_DENSE_COARSE = 4096
 };
 
 typedef struct {
@@ -158,6 +168,13 @@ typedef struct {
   double final_rel_residual;  /* ||r|| / ||r_0|| after the solve (computed only if max_iter > 0
                                  and rtol > 0; else -1)                                       */
   double ms_total;            /* device time of the solve (HIP events), milliseconds          */
+  int dense_level;            /* coarse level k whose cycle from a zero iterate (levels k..0)
+                                 ran as one product with its dense map, built on first use for
+                                 the precision and sweep counts; -1 if none.  The map is the
+                                 same linear map as those launches, so results agree up to
+                                 rounding.  Level k is the largest with at most 2048 inner
+                                 DoFs and at most 4096 closure entries, k <= L - 3 (L - 1 with
+                                 HHG_FLAG_DENSE_COARSE), k >= 1                                */
 } hhg_solve_stats;
 
 /* Validate the macro mesh, build primitives, per-macro stencils and colourings for levels

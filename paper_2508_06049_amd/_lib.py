@@ -36,6 +36,8 @@ HHG_FLAG_CLASSWISE_IFACE = 128
 HHG_FLAG_NO_PLANES3D = 256
 HHG_FLAG_PLANES3D = 512
 HHG_FLAG_TWO_LAUNCH_IFACE = 1024
+HHG_FLAG_NO_DENSE_COARSE = 2048
+HHG_FLAG_DENSE_COARSE = 4096
 
 SMOOTHERS = {"redblack": HHG_GS_REDBLACK, "multicolour": HHG_GS_MULTICOLOR, "jacobi": HHG_JACOBI}
 PRECISIONS = {"fp64": HHG_FP64, "fp32_refined": HHG_FP32_REFINED}
@@ -58,7 +60,7 @@ class hhg_solve_params(C.Structure):
 
 class hhg_solve_stats(C.Structure):
     _fields_ = [("vcycles", C.c_int), ("ir_steps", C.c_int), ("final_rel_residual", C.c_double),
-                ("ms_total", C.c_double)]
+                ("ms_total", C.c_double), ("dense_level", C.c_int)]
 
 
 _ctx = C.c_void_p
@@ -152,6 +154,7 @@ class SolveStats:
     ir_steps: int
     final_rel_residual: float
     ms_total: float
+    dense_level: int = -1
 
 
 def setup_host(coords, cells, L: int, smoother: str = "redblack", coefficient: str = "macro",
@@ -262,7 +265,7 @@ class HHG:
         n = self._nd()
         _check(self.lib.hhg_fmg_solve(self.ctx, _dptr(f, n), _dptr(g, n), _dptr(u, n), C.byref(p), C.byref(st)),
                self.ctx)
-        return u, SolveStats(st.vcycles, st.ir_steps, st.final_rel_residual, st.ms_total)
+        return u, SolveStats(st.vcycles, st.ir_steps, st.final_rel_residual, st.ms_total, st.dense_level)
 
     def cycle_solve(self, f, g, u0, **kw):
         """hhg_cycle_solve: V-cycles from the iterate u0 (copied); returns (u, stats)."""
@@ -272,7 +275,7 @@ class HHG:
         n = self._nd()
         _check(self.lib.hhg_cycle_solve(self.ctx, _dptr(f, n), _dptr(g, n), _dptr(u, n), C.byref(p), C.byref(st)),
                self.ctx)
-        return u, SolveStats(st.vcycles, st.ir_steps, st.final_rel_residual, st.ms_total)
+        return u, SolveStats(st.vcycles, st.ir_steps, st.final_rel_residual, st.ms_total, st.dense_level)
 
     def transfer_from(self, old: "HHG", u_old):
         """hhg_transfer: u_old on old's level L evaluated at this context's level-L DoFs."""

@@ -275,9 +275,24 @@ hhg_status coarse_step(hhg_ctx c, const T* b, bool x_is_zero) {
   return HHG_OK;
 }
 
-// V(pre,post) cycle on level l for A x_l = b; x_is_zero lets the coarsest step skip a residual
+template <typename T> constexpr int prec_of() { return sizeof(T) == 4 ? 1 : 0; }
+template <typename T> T* dense_of(hhg_ctx c);
+template <> double* dense_of<double>(hhg_ctx c) { return c->d_dense64; }
+template <> float* dense_of<float>(hhg_ctx c) { return c->d_dense32; }
+int64_t dense_key(int pre, int post) { return (int64_t)pre | ((int64_t)post << 16); }
+
+// V(pre,post) cycle on level l for A x_l = b; x_is_zero lets the coarsest step skip a residual.
+// On the dense-map level, a cycle from a zero iterate is one product with the map built for
+// these sweep counts (the same linear map as the launches below, up to rounding).
 template <typename T>
 hhg_status vcycle(hhg_ctx c, int l, const T* b, int pre, int post, bool x_is_zero) {
+  if (x_is_zero && l == c->dense_k && !c->dense_building && c->dense_key[prec_of<T>()] == dense_key(pre, post)) {
+    const Level& lv = c->lev[l];
+    launch_dense_map<T>(c->dense_rows, c->dense_cols, c->dense_ld, (int)lv.S, (int)lv.Sraw, dense_of<T>(c), b,
+                        c->d_doff, c->d_dcopy, Arr<T>::x(c->lev[l]), ST(c));
+    LAUNCHCHK();
+    return HHG_OK;
+  }
   if (l == 0) return coarse_step<T>(c, b, x_is_zero);
   Level& lv = c->lev[l];
   Level& lc = c->lev[l - 1];
@@ -292,6 +307,40 @@ hhg_status vcycle(hhg_ctx c, int l, const T* b, int pre, int post, bool x_is_zer
   TRY(smooth<T>(c, l, b, post));
   LAUNCHCHK();
   return HHG_OK;
+}
+
+// Build the dense map of level dense_k for this precision and these sweep counts, unless it
+// is there: one probe per inner DoF r (b_k = 1 at one copy of r, x_k = 0, the cycle of levels
+// k .. 0 by its ordinary launches), whose result is column r of the map (every copy's
+// column).  The map is linear in the sums of the dual copies, which is all the cycle reads of
+// b_k.  Runs eagerly, outside any recording, before a solve touches the level vectors.
+template <typename T>
+hhg_status ensure_dense_t(hhg_ctx c, int pre, int post) {
+  const int k = c->dense_k;
+  const int64_t key = dense_key(pre, post);
+  if (k < 1 || c->dense_key[prec_of<T>()] == key) return HHG_OK;
+  Level& lv = c->lev[k];
+  T* B = dense_of<T>(c);
+  c->dense_key[prec_of<T>()] = -1;
+  launch_fill<T>(B, (int64_t)c->dense_rows * c->dense_ld, (T)0, ST(c));
+  c->dense_building = true;
+  for (int r = 0; r < c->dense_rows; ++r) {
+    T* rc = Arr<T>::rc(lv);
+    launch_unit<T>(rc, lv.nfull, c->dense_copy[c->dense_off[r]], ST(c));
+    launch_fill<T>(Arr<T>::x(lv), lv.nfull, (T)0, ST(c));
+    const hhg_status s = vcycle<T>(c, k, rc, pre, post, true);
+    if (s != HHG_OK) { c->dense_building = false; return s; }
+    launch_dense_harvest<T>(c->dense_rows, c->d_doff, c->d_dcopy, (int)lv.S, (int)lv.Sraw, c->dense_ld, r,
+                            Arr<T>::x(lv), B, ST(c));
+  }
+  c->dense_building = false;
+  LAUNCHCHK();
+  c->dense_key[prec_of<T>()] = key;
+  return HHG_OK;
+}
+
+hhg_status ensure_dense(hhg_ctx c, const hhg_solve_params& p) {
+  return p.precision == HHG_FP64 ? ensure_dense_t<double>(c, p.pre, p.post) : ensure_dense_t<float>(c, p.pre, p.post);
 }
 
 // float64 residual of level l rounded to the float32 right-hand side b32_l of the correction
@@ -486,6 +535,11 @@ hhg_status fmg_core(hhg_ctx c, const hhg_solve_params& p, hhg_solve_stats* stats
   return HHG_OK;
 }
 
+int dense_level_used(hhg_ctx c, const hhg_solve_params& p) {
+  const int prec = p.precision == HHG_FP64 ? 0 : 1;
+  return c->dense_k >= 1 && c->dense_key[prec] == dense_key(p.pre, p.post) ? c->dense_k : -1;
+}
+
 // right-hand sides of the primal problem on every level from nodal f and g on level L
 hhg_status setup_rhs(hhg_ctx c, const double* f_nodal, const double* g_nodal) {
   const int L = c->L;
@@ -646,6 +700,13 @@ hhg_status bind_impl(hhg_ctx c, void* ptr, void* stream, bool no_alloc) {
   c->d_cscr = (double*)(w + c->o_cscr);
   c->d_aux0 = (double*)(w + c->o_aux0);
   c->d_aux1 = (double*)(w + c->o_aux1);
+  c->d_dense32 = (float*)(w + c->o_dense32);
+  c->d_dense64 = (double*)(w + c->o_dense64);
+  c->d_doff = (int32_t*)(w + c->o_doff);
+  c->d_dcopy = (int32_t*)(w + c->o_dcopy);
+  HIPCHK(up(c->o_doff, c->dense_off.data(), c->dense_off.size() * 4));
+  HIPCHK(up(c->o_dcopy, c->dense_copy.data(), c->dense_copy.size() * 4));
+  c->dense_key[0] = c->dense_key[1] = -1;
   for (auto& lv : c->lev) {
     lv.x = (double*)(w + lv.off_x);
     lv.t = (double*)(w + lv.off_t);
@@ -783,6 +844,8 @@ hhg_status hhg_setup(const hhg_mesh* mesh, int L, const hhg_options* opt, hhg_ct
   c->force_planes3d = (opt->flags & HHG_FLAG_PLANES3D) != 0;
   c->two_launch_iface = (opt->flags & HHG_FLAG_TWO_LAUNCH_IFACE) != 0;
   c->generic_est = (opt->flags & HHG_FLAG_GENERIC_EST) != 0;
+  c->no_dense = (opt->flags & HHG_FLAG_NO_DENSE_COARSE) != 0;
+  c->force_dense = (opt->flags & HHG_FLAG_DENSE_COARSE) != 0;
   c->nV = mesh->n_vertices;
   c->nC = mesh->n_cells;
   const int nv = c->dim + 1;
@@ -815,6 +878,7 @@ hhg_status hhg_setup(const hhg_mesh* mesh, int L, const hhg_options* opt, hhg_ct
   s = build_colouring(c);
   if (s == HHG_OK) s = build_coarse(c, nullptr);
   if (s != HHG_OK) { g_err = c->err; delete c; return s; }
+  build_dense_plan(c);
   plan_workspace(c);
   *out = c;
   return HHG_OK;
@@ -897,6 +961,7 @@ hhg_status hhg_set_kappa_cell(hhg_ctx c, const double* kappa) {
   for (int64_t m = 0; m < c->nC; ++m)
     if (!(kappa[m] > 0) || !std::isfinite(kappa[m])) { c->err = "kappa_cell must be positive"; return HHG_EINVAL; }
   c->kappa_cell.assign(kappa, kappa + c->nC);
+  c->dense_key[0] = c->dense_key[1] = -1;
   TRY(build_coarse(c, nullptr));
   fill_kappa_tables(c);
   if (c->bound) {
@@ -930,6 +995,7 @@ hhg_status hhg_set_kappa_nodal(hhg_ctx c, const double* kappa) {
   HIPCHK(hipStreamSynchronize(ST(c)));
   for (double k : kv)
     if (!(k > 0) || !std::isfinite(k)) { c->err = "nodal kappa must be positive"; return HHG_EINVAL; }
+  c->dense_key[0] = c->dense_key[1] = -1;
   TRY(build_coarse(c, kv.data()));
   TRY(upload_coarse(c));
   c->kappa_nodal_set = true;
@@ -943,6 +1009,7 @@ hhg_status hhg_fmg_solve(hhg_ctx c, const double* f, const double* g, double* u_
   TRY(check_ready(c));
   TRY(validate_params(c, p));
   if (!f || !g || !u_out) { c->err = "NULL vector"; return HHG_EINVAL; }
+  TRY(ensure_dense(c, *p));
   HIPCHK(record(c, c->ev0));
   TRY(setup_rhs(c, f, g));
   hhg_solve_stats st{};
@@ -953,6 +1020,7 @@ hhg_status hhg_fmg_solve(hhg_ctx c, const double* f, const double* g, double* u_
   HIPCHK(record(c, c->ev1));
   if (stats) {
     TRY(elapsed(c, &st.ms_total));
+    st.dense_level = dense_level_used(c, *p);
     *stats = st;
   }
   c->solved = (s == HHG_OK);
@@ -968,6 +1036,7 @@ hhg_status hhg_cycle_solve(hhg_ctx c, const double* f, const double* g, double* 
   if (!f || !g || !u) { c->err = "NULL vector"; return HHG_EINVAL; }
   if (p->max_iter < 1) { c->err = "hhg_cycle_solve needs max_iter >= 1"; return HHG_EINVAL; }
   c->solved = c->have_u = false;
+  TRY(ensure_dense(c, *p));
   HIPCHK(record(c, c->ev0));
   TRY(setup_rhs(c, f, g));
   const int L = c->L;
@@ -983,6 +1052,7 @@ hhg_status hhg_cycle_solve(hhg_ctx c, const double* f, const double* g, double* 
   HIPCHK(record(c, c->ev1));
   if (stats) {
     TRY(elapsed(c, &st.ms_total));
+    st.dense_level = dense_level_used(c, *p);
     *stats = st;
   }
   c->have_u = (s == HHG_OK);
@@ -1230,6 +1300,7 @@ hhg_status hhg_adjoint(hhg_ctx c, const double* f, const double* g, const double
   const int L = c->L;
   Level& lL = c->lev[L];
   // 1. recompute u (nothing from the forward pass is stored)
+  TRY(ensure_dense(c, *p));
   TRY(setup_rhs(c, f, g));
   TRY(fmg_core(c, *p, nullptr));
   launch_copy(c->d_aux0, lL.x, lL.nfull, ST(c));   // keep u

@@ -59,6 +59,12 @@ constexpr int kEdgeRecWords = 2 + 2 * kEdgeCopyWords;
 // level 0 is solved by its explicit inverse up to this many inner vertices, above it by the
 // factored form (envelope Cholesky after reverse Cuthill-McKee)
 constexpr int kCoarseDenseMax = 2048;
+// dense map of the cycle on one coarse level k (the V-cycle of levels k .. 0 from a zero
+// iterate, as one matrix from the dual right-hand side to the iterate): at most this many rows
+// (inner DoFs of level k), columns (closure entries of level k, rounded up to 256) and bytes
+// (the float32 and float64 maps together)
+constexpr int kDenseMaxRows = 2048, kDenseMaxCols = 4096;
+constexpr int64_t kDenseMaxBytes = 48ll << 20;
 // blocks of the interior part of a squared norm (one partial each)
 constexpr int kNormBlocks = 8192;
 // interior rows per wavefront of the 2D row estimator
@@ -266,6 +272,21 @@ struct hhg_ctx_s {
   bool force_planes3d = false;      // whole-plane 3D sweep from n = 16 on (testing)
   bool two_launch_iface = false;    // 2D edge and vertex classes in two launches (testing, timing)
   bool generic_est = false;         // 2D L2 estimate by the one-thread-per-node kernel (testing)
+  bool no_dense = false;            // no dense map of the coarse cycle (testing, timing)
+  bool force_dense = false;         // dense map on the largest level that fits, up to L - 1 (testing)
+  // dense map of the cycle on level dense_k: row r is inner DoF r of that level (canonical
+  // order), with its copies dense_copy[dense_off[r] .. dense_off[r+1]) (level-vector indices);
+  // column m Sraw + s is closure entry s of macro m; dense_ld = columns rounded up to 256.
+  // dense_key[p] = pre | post << 16 of the map built for precision p (-1: none)
+  int dense_k = -1;
+  int dense_rows = 0, dense_cols = 0, dense_ld = 0;
+  std::vector<int32_t> dense_off, dense_copy;
+  int64_t o_dense32 = 0, o_dense64 = 0, o_doff = 0, o_dcopy = 0;
+  float* d_dense32 = nullptr;
+  double* d_dense64 = nullptr;
+  int32_t *d_doff = nullptr, *d_dcopy = nullptr;
+  int64_t dense_key[2] = {-1, -1};
+  bool dense_building = false;      // the map's own probe cycles run the ordinary path
   bool classwise_iface = false;     // 2D interface classes one launch each (testing)
   uint32_t xswap = 0;               // bit l (+16 for float32): level l's iterate is in its second buffer
   void* cap_stream = nullptr;       // hipStream_t used only while recording
@@ -287,6 +308,7 @@ hhg_status build_topology(hhg_ctx c);
 hhg_status build_stencils(hhg_ctx c);
 hhg_status build_colouring(hhg_ctx c);
 hhg_status build_coarse(hhg_ctx c, const double* kappa_vertex /* nullable, per vertex */);
+void build_dense_plan(hhg_ctx c);
 void plan_workspace(hhg_ctx c);
 void fill_kappa_tables(hhg_ctx c);
 

@@ -2486,6 +2486,82 @@ __global__ void __launch_bounds__(256) k_coarse_bwd(int n0, const double* __rest
 }
 
 // ------------------------------------------------------------------------------------------
+// dense map of the cycle on one coarse level k: x_k = scatter(B b_k) with B row-major
+// [rows][ld] (row r: inner DoF r of level k; column m Sraw + s: closure entry m S + s of the
+// dual right-hand side, zero for entries that are no inner DoF's copy).  One wavefront per row
+// with all of the row's loads in flight at once (lane l holds columns 256 q + 4 l .. + 3; the
+// chunks q >= ld / 256 lie past the row's buffer range and load zeros); b staged in LDS by
+// each workgroup; the row is summed in float64 in a fixed order, then written to every copy.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int NQ>
+__global__ void __launch_bounds__(256) k_dense_map(int rows, int cols, int ld, int S, int Sraw, const T* __restrict__ B,
+                                                    const T* __restrict__ b, const int32_t* __restrict__ off,
+                                                    const int32_t* __restrict__ copy, T* __restrict__ x) {
+  __shared__ T sb[NQ * 256];
+  const int lane = (int)(threadIdx.x & 63);
+  const int row = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int rr = __builtin_amdgcn_readfirstlane(min(row, rows - 1));   // uniform per wavefront
+  const int o0 = off[rr], nc = off[rr + 1] - o0;
+  constexpr int W = (int)(4 * sizeof(T) / 16);   // 16-byte loads per 4 entries
+  const __amdgpu_buffer_rsrc_t rB = d_rsrc(B + (size_t)rr * ld, (uint32_t)((size_t)ld * sizeof(T)));
+  u32x4 v[NQ][W];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int h = 0; h < W; ++h)
+      v[q][h] = __builtin_amdgcn_raw_buffer_load_b128(rB, (uint32_t)(((256 * q + 4 * lane) * (int)sizeof(T)) + 16 * h), 0, 0);
+  // b: every load of the workgroup's share in flight at once (columns past the end load zeros)
+  const __amdgpu_buffer_rsrc_t rb = d_rsrc(b, (uint32_t)((size_t)(cols / Sraw) * S * sizeof(T)));
+  T g[NQ];
+#pragma unroll
+  for (int t = 0; t < NQ; ++t) {
+    const int cc = (int)threadIdx.x + 256 * t, m = cc / Sraw;
+    d_bload(rb, cc < cols ? (uint32_t)(((int64_t)m * S + (cc - m * Sraw)) * (int64_t)sizeof(T)) : 0xfffffff0u, g[t]);
+  }
+  const int32_t dst = lane < nc ? copy[o0 + lane] : -1;
+#pragma unroll
+  for (int t = 0; t < NQ; ++t) sb[threadIdx.x + 256 * t] = g[t];
+  __syncthreads();
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    T e[4];
+    __builtin_memcpy(e, &v[q][0], sizeof(e));
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc += (double)e[t] * (double)sb[256 * q + 4 * lane + t];
+  }
+  // butterfly: at every step both partners add the same two values, so every lane ends with
+  // bitwise the same sum and all copies get one value
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (row >= rows) return;
+  if (dst >= 0) x[dst] = (T)acc;
+  for (int q = o0 + 64 + lane; q < o0 + nc; q += 64) x[copy[q]] = (T)acc;
+}
+
+// one probe of the dense map: b = unit vector at level-vector index idx (n entries)
+template <typename T>
+__global__ void __launch_bounds__(256) k_unit(T* __restrict__ b, int64_t n, int64_t idx) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) b[i] = i == idx ? (T)1 : (T)0;
+}
+
+// the probe's result as column(s) of the dense map: B[r][columns of the probed DoF's copies] =
+// x at row r's first copy
+template <typename T>
+__global__ void __launch_bounds__(256) k_dense_harvest(int rows, const int32_t* __restrict__ off,
+                                                        const int32_t* __restrict__ copy, int S, int Sraw, int ld,
+                                                        int probe, const T* __restrict__ x, T* __restrict__ B) {
+  const int r = (int)(blockIdx.x * 256 + threadIdx.x);
+  if (r >= rows) return;
+  const T val = x[copy[off[r]]];
+  for (int q = off[probe]; q < off[probe + 1]; ++q) {
+    const int e = copy[q];
+    B[(size_t)r * ld + (size_t)(e / S) * Sraw + (e % S)] = val;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // reductions
 // sum over macro-interior nodes of r^2 (per block partials)
 template <int D>
@@ -3162,6 +3238,38 @@ template void launch_coarse_factored<double>(int, const int32_t*, const int64_t*
                                              double*, const double*, double*, int, hipStream_t);
 template void launch_coarse_factored<float>(int, const int32_t*, const int64_t*, const int32_t*, const double*,
                                             double*, const float*, float*, int, hipStream_t);
+
+template <typename T>
+void launch_dense_map(int rows, int cols, int ld, int S, int Sraw, const T* B, const T* b, const int32_t* off,
+                      const int32_t* copy, T* x, hipStream_t st) {
+  if (rows <= 0) return;
+  const unsigned g = (unsigned)((rows + 3) / 4);
+  const int nq = ld / 256;
+  if (nq <= 4) k_dense_map<T, 4><<<g, 256, 0, st>>>(rows, cols, ld, S, Sraw, B, b, off, copy, x);
+  else if (nq <= 8) k_dense_map<T, 8><<<g, 256, 0, st>>>(rows, cols, ld, S, Sraw, B, b, off, copy, x);
+  else k_dense_map<T, 16><<<g, 256, 0, st>>>(rows, cols, ld, S, Sraw, B, b, off, copy, x);
+}
+template void launch_dense_map<double>(int, int, int, int, int, const double*, const double*, const int32_t*,
+                                       const int32_t*, double*, hipStream_t);
+template void launch_dense_map<float>(int, int, int, int, int, const float*, const float*, const int32_t*,
+                                      const int32_t*, float*, hipStream_t);
+
+template <typename T>
+void launch_unit(T* b, int64_t n, int64_t idx, hipStream_t st) {
+  k_unit<T><<<nblk(n), 256, 0, st>>>(b, n, idx);
+}
+template void launch_unit<double>(double*, int64_t, int64_t, hipStream_t);
+template void launch_unit<float>(float*, int64_t, int64_t, hipStream_t);
+
+template <typename T>
+void launch_dense_harvest(int rows, const int32_t* off, const int32_t* copy, int S, int Sraw, int ld, int probe,
+                          const T* x, T* B, hipStream_t st) {
+  k_dense_harvest<T><<<nblk(rows), 256, 0, st>>>(rows, off, copy, S, Sraw, ld, probe, x, B);
+}
+template void launch_dense_harvest<double>(int, const int32_t*, const int32_t*, int, int, int, int, const double*,
+                                           double*, hipStream_t);
+template void launch_dense_harvest<float>(int, const int32_t*, const int32_t*, int, int, int, int, const float*,
+                                          float*, hipStream_t);
 
 void launch_sqnorm(int dim, const LK& lk, const Tables& tb, const double* r, double* partial, double* out, hipStream_t st) {
   // 2D: one wavefront per row; 3D: one block per 256-entry chunk of a macro block

@@ -1009,6 +1009,48 @@ hhg_status build_coarse(hhg_ctx c, const double* kappa_vertex) {
   return HHG_OK;
 }
 
+// Level of the dense coarse map: the largest k <= L - 3 (L - 1 when forced) whose inner DoFs
+// and closure entries fit the limits.  Its rows are the inner (non-Dirichlet) DoFs of level k
+// in canonical order, each with the level-vector indices of its copies.
+void build_dense_plan(hhg_ctx c) {
+  c->dense_k = -1;
+  c->dense_rows = c->dense_cols = c->dense_ld = 0;
+  c->dense_off.clear();
+  c->dense_copy.clear();
+  if (c->no_dense) return;
+  const int d = c->dim;
+  for (int k = c->force_dense ? c->L - 1 : c->L - 3; k >= 1; --k) {
+    const Level& lv = c->lev[k];
+    const int n = lv.n;
+    const int64_t cols = c->nC * lv.Sraw, ld = (cols + 255) / 256 * 256;
+    if (ld > kDenseMaxCols) continue;
+    std::vector<std::vector<int32_t>> copies(lv.ndof);
+    for (int64_t m = 0; m < c->nC; ++m)
+      for (int kk = 0; kk <= (d == 3 ? n : 0); ++kk)
+        for (int j = 0; j <= n - kk; ++j)
+          for (int i = 0; i <= n - kk - j; ++i) {
+            const int mask = zero_mask(d, n, i, j, kk);
+            if (mask != 0 && ((c->dirbits[m] >> mask) & 1)) continue;
+            const int64_t t = canonical_index(c, lv, (int)m, i, j, kk);
+            copies[t].push_back((int32_t)(m * lv.S + lin_closure(d, n, i, j, kk)));
+          }
+    int64_t rows = 0;
+    for (const auto& v : copies) rows += v.empty() ? 0 : 1;
+    if (rows == 0 || rows > kDenseMaxRows || rows * ld * 12 > kDenseMaxBytes) continue;
+    c->dense_off.push_back(0);
+    for (const auto& v : copies) {
+      if (v.empty()) continue;
+      c->dense_copy.insert(c->dense_copy.end(), v.begin(), v.end());
+      c->dense_off.push_back((int32_t)c->dense_copy.size());
+    }
+    c->dense_k = k;
+    c->dense_rows = (int)rows;
+    c->dense_cols = (int)cols;
+    c->dense_ld = (int)ld;
+    return;
+  }
+}
+
 // the per-macro coefficients inside the edge records and the wheel lane tables
 void fill_kappa_tables(hhg_ctx c) {
   for (int64_t e = 0; e < (int64_t)(c->erec.size() / kEdgeRecWords); ++e) {
@@ -1062,6 +1104,10 @@ void plan_workspace(hhg_ctx c) {
   c->o_ainv = take((int64_t)c->n0 * c->n0 * 8 + 8);
   c->o_cperm = take((int64_t)c->n0 * 4 + 4);
   c->o_cscr = take((int64_t)c->n0 * 2 * 8 + 16);
+  c->o_dense32 = take((int64_t)c->dense_rows * c->dense_ld * 4);
+  c->o_dense64 = take((int64_t)c->dense_rows * c->dense_ld * 8);
+  c->o_doff = take((int64_t)c->dense_off.size() * 4);
+  c->o_dcopy = take((int64_t)c->dense_copy.size() * 4);
   // reduction scratch: per macro per block (4 values) on the finest level, and per block norms
   const Level& lt = c->lev[c->L];
   int64_t bpm = (lt.Sraw + 255) / 256;

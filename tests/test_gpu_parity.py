@@ -646,3 +646,73 @@ def test_recorded_graphs_replay_equal_eager(name, precision):
         # eager work between replays
         hh.apply(L, "stiffness", u)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name,L,smoother,forced", [
+    ("lshape", 5, "multicolour", True), ("lshape", 6, "jacobi", False), ("square", 6, "redblack", False),
+    ("kuhn2", 4, "multicolour", True), ("kuhn1", 5, "redblack", False)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_dense_coarse_map_matches_launches(name, L, smoother, forced, precision):
+    # the cycle of levels k .. 0 from a zero iterate as one product with its dense map (built
+    # from one probe cycle of the same kernels per inner DoF of level k) against the cycle
+    # launched kernel by kernel, iterate by iterate: after the FMG pass and after each of four
+    # extra cycles.  float64: 1e-12 of |u|.  float32-refined: the bounds for two float32 cycles
+    # that differ only in rounding order (test_mixed_precision_iterates_match_oracle_float32_cycle)
+    from paper_2508_06049_amd import HHG
+    from paper_2508_06049_amd._lib import HHG_FLAG_DENSE_COARSE, HHG_FLAG_NO_DENSE_COARSE
+    mk = MESHES[name][0]
+    _note("dense coarse map", name, L, smoother, forced, precision)
+    m = mk()
+    hd = HHG(m.coords, m.cells, L, smoother=smoother, flags=HHG_FLAG_DENSE_COARSE if forced else 0)
+    hp = HHG(m.coords, m.cells, L, smoother=smoother, flags=HHG_FLAG_NO_DENSE_COARSE)
+    X = hd.dof_coords().cpu().numpy()
+    f, g = _rhs(name, X, m.dim)
+    fd, gd = to_dev(f), to_dev(g)
+    prev = None
+    for k in range(5):
+        ud, sd = hd.fmg_solve(fd, gd, nu=1, precision=precision, rtol=1e-300, max_iter=k)
+        up, sp = hp.fmg_solve(fd, gd, nu=1, precision=precision, rtol=1e-300, max_iter=k)
+        assert sp.dense_level == -1
+        assert 1 <= sd.dense_level <= (L - 1 if forced else L - 3)
+        assert sd.vcycles == sp.vcycles
+        a, b = to_host(ud), to_host(up)
+        scale = np.abs(b).max()
+        if precision == "fp64":
+            tol = 1e-12 * scale
+        else:
+            tol = 5e-6 * scale if k == 0 else 1e-4 * np.abs(b - prev).max() + 1e-12 * scale
+        assert np.abs(a - b).max() <= tol, (k, sd.dense_level, np.abs(a - b).max(), tol)
+        prev = b
+
+
+def test_dense_coarse_map_follows_parameters_and_coefficients():
+    # the map depends on the sweep counts, the precision and the coefficients: a context that
+    # solves with V(2,2), V(4,4), V(1,2) (odd: no recorded graphs), V(2,2) again, then after new
+    # per-macro coefficients, reproduces fresh contexts bit for bit (recorded graphs replay the
+    # map's product; the map itself is rebuilt for each parameter set)
+    from paper_2508_06049_amd import HHG
+    from paper_2508_06049_amd._lib import HHG_FLAG_DENSE_COARSE
+    m = meshes.kuhn_cube(2)
+    L = 4
+    _note("dense coarse map parameters", m.n_cells, L)
+    kc = problems.kappa_cells_uniform(5, m.n_cells)
+    kc2 = problems.kappa_cells_uniform(9, m.n_cells)
+    hh = HHG(m.coords, m.cells, L, smoother="multicolour", kappa_cell=kc, flags=HHG_FLAG_DENSE_COARSE)
+    X = hh.dof_coords().cpu().numpy()
+    f, g = _rhs("kuhn2", X, 3)
+    fd, gd = to_dev(f), to_dev(g)
+    runs = [dict(pre=2, post=2, precision="fp64"), dict(pre=4, post=4, precision="fp64"),
+            dict(pre=2, post=2, precision="fp32_refined"), dict(pre=1, post=2, precision="fp64"),
+            dict(pre=2, post=2, precision="fp64")]
+    for kw in runs:
+        u, s = hh.fmg_solve(fd, gd, nu=1, rtol=0.0, max_iter=2, **kw)
+        fresh = HHG(m.coords, m.cells, L, smoother="multicolour", kappa_cell=kc, flags=HHG_FLAG_DENSE_COARSE)
+        ur, sr = fresh.fmg_solve(fd, gd, nu=1, rtol=0.0, max_iter=2, **kw)
+        assert s.dense_level == sr.dense_level >= 1
+        assert np.array_equal(to_host(u), to_host(ur)), kw
+        fresh.close()
+    hh.set_kappa_cell(kc2)
+    u, s = hh.fmg_solve(fd, gd, nu=1, rtol=0.0, max_iter=2)
+    fresh = HHG(m.coords, m.cells, L, smoother="multicolour", kappa_cell=kc2, flags=HHG_FLAG_DENSE_COARSE)
+    ur, _ = fresh.fmg_solve(fd, gd, nu=1, rtol=0.0, max_iter=2)
+    assert np.array_equal(to_host(u), to_host(ur))
