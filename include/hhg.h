@@ -130,7 +130,11 @@ typedef struct {
                                  HHG_FLAG_DENSE_COARSE: build the dense map on the largest
                                  level that fits, up to L - 1, instead of only when the finest
                                  level lies at least three levels above it (for checking it on
-                                 small problems)                                                */
+                                 small problems).
+                                 HHG_FLAG_NO_FUSED_PROLONG: in 2D, run the cycle's
+                                 prolongation as a launch of its own instead of inside the
+                                 first post-smoothing sweep (identical result; for checking
+                                 and timing the fused form)                                     */
 } hhg_options;
 
 enum {
@@ -146,7 +150,8 @@ enum {
   HHG_FLAG_PLANES3D = 512,
   HHG_FLAG_TWO_LAUNCH_IFACE = 1024,
   HHG_FLAG_NO_DENSE_COARSE = 2048,
-  HHG_FLAG_DENSE_COARSE = 4096
+  HHG_FLAG_DENSE_COARSE = 4096,
+  HHG_FLAG_NO_FUSED_PROLONG = 8192
 };
 
 typedef struct {

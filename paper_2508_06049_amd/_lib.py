@@ -38,6 +38,7 @@ HHG_FLAG_PLANES3D = 512
 HHG_FLAG_TWO_LAUNCH_IFACE = 1024
 HHG_FLAG_NO_DENSE_COARSE = 2048
 HHG_FLAG_DENSE_COARSE = 4096
+HHG_FLAG_NO_FUSED_PROLONG = 8192
 
 SMOOTHERS = {"redblack": HHG_GS_REDBLACK, "multicolour": HHG_GS_MULTICOLOR, "jacobi": HHG_JACOBI}
 PRECISIONS = {"fp64": HHG_FP64, "fp32_refined": HHG_FP32_REFINED}

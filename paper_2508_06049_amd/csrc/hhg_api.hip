@@ -105,7 +105,8 @@ template <> struct Arr<float> {
 
 // interior smoother launch(es); while profiling, finest-level launches are bracketed by events
 template <typename T>
-void interior_launch(hhg_ctx c, int l, const LK& k, const T* x, T* y, const T* b, int col, int rb, int jac) {
+void interior_launch(hhg_ctx c, int l, const LK& k, const T* x, T* y, const T* b, int col, int rb, int jac,
+                     const T* pro_ec = nullptr, T* pro_t = nullptr) {
   Level& lv = c->lev[l];
   const bool fine = l == c->L;
   const bool rec = fine && c->prof_on && c->prof_used + 2 <= (int)c->prof_ev.size();
@@ -113,8 +114,7 @@ void interior_launch(hhg_ctx c, int l, const LK& k, const T* x, T* y, const T* b
   int64_t npts;
   if (col < 0) {   // all interior colours fused in one launch
     launch_gs_fused<T>(c->dim, p1(c), k, c->tab, const_cast<T*>(x), y, b, lv.d_tiles, (int)lv.tiles.size(), lv.d_itab,
-                       lv.d_itab_off, rb,
-                       sA(c, l), fine, ST(c));
+                       lv.d_itab_off, rb, sA(c, l), fine, ST(c), pro_ec, pro_ec ? (int)c->lev[l - 1].S : 0, pro_t);
     npts = lv.NI * c->nC;
   } else {
     launch_smooth_interior<T>(c->dim, p1(c), k, c->tab, x, y, b, col, rb, jac, omega(c), sA(c, l), lv.kn, fine, ST(c));
@@ -139,8 +139,17 @@ bool fused_available(hhg_ctx c, int l, size_t tsize) {
   return !lv.itab.empty() && (size_t)lv.Sraw * tsize <= 64 * 1024;
 }
 
+// the cycle's prolongation x_l += P e_{l-1} can run inside the first post-smoothing sweep
+// (2D fused out-of-place sweep)
+bool pro_fusable(hhg_ctx c, int l, size_t tsize) {
+  return c->dim == 2 && l >= 1 && !c->no_pro && fused_available(c, l, tsize);
+}
+
+// sweeps of the level-l smoother; with pro (pro_fusable), the first sweep starts from
+// x_l + P pro: its interior launch adds the prolongation on load and writes the start values
+// of the macro-boundary nodes to t_l, from which the interface classes of that sweep read
 template <typename T>
-hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
+hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps, const T* pro = nullptr) {
   Level& lv = c->lev[l];
   const LK k = lk_of(c, l);
   const bool jac = c->opt.smoother == HHG_JACOBI;
@@ -182,14 +191,17 @@ hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
     // the interface reads interior neighbours from the new buffer y and interface values from x
     // (current), and writes both
     T* y = twobuf ? Arr<T>::x2(lv) : x;
-    if (fused) interior_launch<T>(c, l, k, x, y, b, -1, rb, 0);
+    const T* pe = s == 0 && twobuf && c->dim == 2 ? pro : (const T*)nullptr;
+    if (fused) interior_launch<T>(c, l, k, x, y, b, -1, rb, 0, pe, Arr<T>::t(lv));
     else
       for (int col = 0; col < lv.interior_colours; ++col) interior_launch<T>(c, l, k, x, x, b, col, rb, 0);
     // the whole-plane 3D sweep also copies the interface values into y, so the interface
-    // classes then update y in place: one buffer, no mirror writes
+    // classes then update y in place: one buffer, no mirror writes.  After a fused
+    // prolongation the old interface values are those in t.
     const bool in_y = twobuf && lv.planes3d;
-    T* xf = in_y ? y : x;
-    T* mir = twobuf && !in_y ? x : (T*)nullptr;
+    T* xo = pe ? Arr<T>::t(lv) : x;
+    T* xf = in_y ? y : xo;
+    T* mir = twobuf && !in_y ? xo : (T*)nullptr;
     if (lv.task_ok && !c->no_tasks) {
       // 2D with large edge classes: both edge classes in one launch by edge chunks; then, as
       // for all classes otherwise, a class of more than kTaskOneGroupWaves wavefronts gets a
@@ -202,15 +214,15 @@ hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps) {
         launch_iface2d_sweep<T>(k, c->tab, (const int32_t*)(c->ws + c->o_erec), (int)c->nE, lv.d_dvcopy,
                                 (int)lv.dvcopy.size(), lv.d_whcopy, lv.d_whinfo, lv.d_whloc, lv.d_whseg, lv.d_whsrc,
                                 lv.d_whcw, lv.d_whwmax, (int)lv.wh_wmax.size(), lv.ncolours - lv.c_vr0, lv.d_whe2,
-                                lv.d_wha2i, lv.d_wha2w, y, x, y, b, sA(c, l), ST(c));
+                                lv.d_wha2i, lv.d_wha2w, y, xo, y, b, sA(c, l), ST(c));
         col = lv.ncolours;
       } else if (lv.fused_iface && !c->classwise_iface) {
         launch_iface2d_edges<T>(k, (const int32_t*)(c->ws + c->o_erec), (int)c->nE, lv.d_dvcopy, (int)lv.dvcopy.size(),
-                                y, x, y, mir, b, sA(c, l), ST(c));
+                                y, xo, y, mir, b, sA(c, l), ST(c));
         col = lv.c_vr0;
         if (lv.wheels) {
           launch_iface2d_wheels<T>(k, c->tab, lv.d_whcopy, lv.d_whinfo, lv.d_whloc, lv.d_whseg, lv.d_whsrc, lv.d_whcw,
-                                   lv.d_whwmax, (int)lv.wh_wmax.size(), lv.ncolours - lv.c_vr0, y, x, y, mir, b,
+                                   lv.d_whwmax, (int)lv.wh_wmax.size(), lv.ncolours - lv.c_vr0, y, xo, y, mir, b,
                                    sA(c, l), ST(c));
           col = lv.ncolours;
         }
@@ -302,9 +314,13 @@ hhg_status vcycle(hhg_ctx c, int l, const T* b, int pre, int post, bool x_is_zer
   // restriction; the same launch clears the coarse correction (homogeneous, Dirichlet copies included)
   launch_restrict<T>(c->dim, lk_of(c, l), lk_of(c, l - 1), c->tab, Arr<T>::t(lv), Arr<T>::rc(lc), ST(c), Arr<T>::x(lc));
   TRY(vcycle<T>(c, l - 1, Arr<T>::rc(lc), pre, post, true));
-  launch_prolong<T>(c->dim, lk_of(c, l), lk_of(c, l - 1), c->tab, Arr<T>::x(lc), Arr<T>::x(lv), (T*)nullptr,
-                    (const T*)nullptr, 0, ST(c));
-  TRY(smooth<T>(c, l, b, post));
+  if (post >= 1 && pro_fusable(c, l, sizeof(T))) {
+    TRY(smooth<T>(c, l, b, post, Arr<T>::x(lc)));
+  } else {
+    launch_prolong<T>(c->dim, lk_of(c, l), lk_of(c, l - 1), c->tab, Arr<T>::x(lc), Arr<T>::x(lv), (T*)nullptr,
+                      (const T*)nullptr, 0, ST(c));
+    TRY(smooth<T>(c, l, b, post));
+  }
   LAUNCHCHK();
   return HHG_OK;
 }
@@ -846,6 +862,7 @@ hhg_status hhg_setup(const hhg_mesh* mesh, int L, const hhg_options* opt, hhg_ct
   c->generic_est = (opt->flags & HHG_FLAG_GENERIC_EST) != 0;
   c->no_dense = (opt->flags & HHG_FLAG_NO_DENSE_COARSE) != 0;
   c->force_dense = (opt->flags & HHG_FLAG_DENSE_COARSE) != 0;
+  c->no_pro = (opt->flags & HHG_FLAG_NO_FUSED_PROLONG) != 0;
   c->nV = mesh->n_vertices;
   c->nC = mesh->n_cells;
   const int nv = c->dim + 1;

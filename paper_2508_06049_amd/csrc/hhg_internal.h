@@ -273,6 +273,7 @@ struct hhg_ctx_s {
   bool two_launch_iface = false;    // 2D edge and vertex classes in two launches (testing, timing)
   bool generic_est = false;         // 2D L2 estimate by the one-thread-per-node kernel (testing)
   bool no_dense = false;            // no dense map of the coarse cycle (testing, timing)
+  bool no_pro = false;              // cycle prolongation as its own launch (testing, timing)
   bool force_dense = false;         // dense map on the largest level that fits, up to L - 1 (testing)
   // dense map of the cycle on level dense_k: row r is inner DoF r of that level (canonical
   // order), with its copies dense_copy[dense_off[r] .. dense_off[r+1]) (level-vector indices);

@@ -1601,6 +1601,51 @@ __device__ __forceinline__ double from_prev(double v) {
                           __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
 }
 
+// The cycle's prolongation fused into the first post-smoothing sweep of a 2D level: each loaded
+// node gets u + (P e_c) (Dirichlet nodes keep u), exactly as the separate prolongation would
+// store it, and every loaded node on the macro boundary is written to tout, where the interface
+// classes of that sweep read their old values.  Every boundary node lies in the loaded region
+// of some tile, and tiles that load the same node write the same value.
+template <typename T>
+struct ProLoad {
+  __amdgpu_buffer_rsrc_t ec, tout;   // this macro's coarse correction (side nc) and boundary output
+  int nc;
+  uint32_t dirb;                     // Dirichlet bits of the macro by zero-set mask
+};
+
+// rows jstart + r (r < NR, jstart of parity PAR) of lane column i, in u[]; only the rows
+// R0 <= r < R1 hold loaded values.  Coarse row jc of the region is t = jc - (jstart >> 1); per
+// lane A holds coarse column i >> 1 and Bv column (i + 1) >> 1, which give both nodes of every
+// fine parity pattern
+template <typename T, int NR, int PAR, int R0, int R1>
+__device__ __forceinline__ void pro_rows(int n, const ProLoad<T>& P, int i, int jstart, T* u) {
+  constexpr int NCR = (NR + PAR + 1) / 2 + 1;
+  const int jcb = jstart >> 1, ia = i >> 1, ib = (i + 1) >> 1, nc = P.nc;
+  T A[NCR], Bv[NCR];
+#pragma unroll
+  for (int t = 0; t < NCR; ++t) {
+    const int jc = jcb + t;
+    const bool oka = ia >= 0 && jc >= 0 && ia + jc <= nc, okb = ib >= 0 && jc >= 0 && ib + jc <= nc;
+    d_bload(P.ec, oka ? (uint32_t)d_lin2(nc, ia, jc) * (uint32_t)sizeof(T) : 0xfffffff0u, A[t]);
+    d_bload(P.ec, okb ? (uint32_t)d_lin2(nc, ib, jc) * (uint32_t)sizeof(T) : 0xfffffff0u, Bv[t]);
+  }
+  const bool iodd = (i & 1) != 0;
+#pragma unroll
+  for (int r = R0; r < R1; ++r) {
+    const int t = (r + PAR) >> 1;
+    const int j = jstart + r;
+    T lo, hi;
+    if (((PAR + r) & 1) == 0) { lo = A[t]; hi = Bv[t]; }   // even row: along the row
+    else { lo = iodd ? Bv[t] : A[t]; hi = A[t + 1]; }       // odd row: along j, or the diagonal
+    const int mk = d_mask<2>(n, i, j, 0);
+    const bool dir = mk != 0 && ((P.dirb >> mk) & 1);
+    const T v = dir ? u[r] : u[r] + (T)0.5 * (lo + hi);
+    u[r] = v;
+    if (mk != 0 && i >= 0 && j >= 0 && i + j <= n)
+      d_bstore(P.tout, (uint32_t)(d_lin2(n, 0, j) + i) * (uint32_t)sizeof(T), v);
+  }
+}
+
 // Fused Gauss-Seidel sweep over the macro-interior nodes of a 2D level: every interior colour
 // class in one launch (the interface nodes stay fixed during this part of the sweep).  Each
 // wavefront owns a core tile of (64 - 2C) columns x TS rows and loads it with a halo of C
@@ -1610,10 +1655,10 @@ __device__ __forceinline__ double from_prev(double v) {
 // through DPP shifts; those values equal what C class-by-class passes over the whole macro
 // produce, because each pass only needs correct values one layer further out.  After C passes
 // the core is exact and is written to uo; the halo work is redundant.  No LDS and no barriers.
-template <typename T, int C, int TS, bool FINE>
+template <typename T, int C, int TS, bool FINE, bool PRO>
 __device__ __forceinline__ void gs2d_wave_tile(int n, __amdgpu_buffer_rsrc_t um, __amdgpu_buffer_rsrc_t uom,
                                                __amdgpu_buffer_rsrc_t bm, int i0, int j0, int rb, int s1, int s2,
-                                               T w1, T w2, T w3, T w4, T w5, T w6, T inv) {
+                                               T w1, T w2, T w3, T w4, T w5, T w6, T inv, const ProLoad<T>& P) {
   constexpr int H = C, RH = TS + 2 * H;
   const int q = threadIdx.x & 63;
   const int i = i0 + q;
@@ -1631,6 +1676,10 @@ __device__ __forceinline__ void gs2d_wave_tile(int n, __amdgpu_buffer_rsrc_t um,
     d_bload(um, g, ur[r]);
     d_bload(bm, g, br[r]);
     roff += n + 1 - j;
+  }
+  if constexpr (PRO) {
+    if (j0 & 1) pro_rows<T, RH, 1, 0, RH>(n, P, i, j0, ur);
+    else pro_rows<T, RH, 0, 0, RH>(n, P, i, j0, ur);
   }
   // colour of (i, j0): red-black parity or (i + 2 j) mod 3.  Row r has colour col0 + r s2
   // (mod 2) or col0 + 2 r (mod 3); with r and c compile-time constants the colour test is one
@@ -1686,10 +1735,10 @@ __device__ __forceinline__ void gs2d_wave_tile(int n, __amdgpu_buffer_rsrc_t um,
 // lane offers, by its own column mod 3, the slot that holds the asking lane's row (right,
 // left, up-left, down-right neighbours), and DPP shifts deliver it.  The valid region
 // shrinks by one node per pass exactly as in the row-aligned form.
-template <typename T, int TS, bool FINE>
+template <typename T, int TS, bool FINE, bool PRO>
 __device__ __forceinline__ void gs2d_wave_tile_mc3(int n, __amdgpu_buffer_rsrc_t um, __amdgpu_buffer_rsrc_t uom,
                                                    __amdgpu_buffer_rsrc_t bm, int i0, int j0, T w1, T w2, T w3, T w4,
-                                                   T w5, T w6, T inv) {
+                                                   T w5, T w6, T inv, const ProLoad<T>& P) {
   constexpr int H = 3, RH = TS + 2 * H, K = 3, RS = RH + K + 1;
   const int q = threadIdx.x & 63;
   const int i = i0 + q;
@@ -1709,6 +1758,11 @@ __device__ __forceinline__ void gs2d_wave_tile_mc3(int n, __amdgpu_buffer_rsrc_t
       d_bload(bm, g, bs[t]);
       roff += n + 1 - j;
       ++j;
+    }
+    if constexpr (PRO) {
+      // the aligned rows t = K .. K + RH - 1 are the loaded ones (the others hold placeholders)
+      if ((j0 - K) & 1) pro_rows<T, RS + 2, 1, K, K + RH>(n, P, i, j0 - K, us);
+      else pro_rows<T, RS + 2, 0, K, K + RH>(n, P, i, j0 - K, us);
     }
     const bool p1 = rho == 1, p2 = rho == 2;
 #pragma unroll
@@ -1760,10 +1814,11 @@ __device__ __forceinline__ void gs2d_wave_tile_mc3(int n, __amdgpu_buffer_rsrc_t
 // halos, so an in-place update would let one tile read rows another tile has already
 // written.  Blocks are spread over the XCDs in contiguous runs of tiles (block b runs on
 // XCD b mod 8), so neighbouring tiles share their halo rows in one L2.
-template <typename T, int C, int TJ, int SUB, bool FINE>
+template <typename T, int C, int TJ, int SUB, bool FINE, bool PRO>
 __global__ void __launch_bounds__(256) k_gs2d_fused(LK lk, Tables tb, const T* __restrict__ u, T* __restrict__ uo,
                                                      const T* __restrict__ b,
-                                                     const int32_t* __restrict__ tiles, int ntiles, int rb, double sA) {
+                                                     const int32_t* __restrict__ tiles, int ntiles, int rb, double sA,
+                                                     const T* __restrict__ ec, int cS, T* __restrict__ tout) {
   constexpr int H = C, TI = 64 - 2 * H, TS = TJ / SUB;
   const int per_xcd = (int)(gridDim.x >> 3);   // gridDim.x is a multiple of 8
   const int blk = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
@@ -1781,16 +1836,24 @@ __global__ void __launch_bounds__(256) k_gs2d_fused(LK lk, Tables tb, const T* _
   const T w4 = (T)(ks * W[4]), w5 = (T)(ks * W[5]), w6 = (T)(ks * W[6]);
   const T inv = (T)(1.0 / (ks * W[0]));
   const int s1 = rb ? tb.rbpar[m * 4 + 1] : 0, s2 = rb ? tb.rbpar[m * 4 + 2] : 0;
+  ProLoad<T> P{};
+  if constexpr (PRO) {
+    const int nc = lk.n >> 1;
+    P.ec = d_rsrc(ec + (int64_t)m * cS, (uint32_t)(((nc + 1) * (nc + 2)) / 2) * (uint32_t)sizeof(T));
+    P.tout = d_rsrc(tout + base, bytes);
+    P.nc = nc;
+    P.dirb = tb.dirbits[m];
+  }
 #pragma unroll
   for (int sub = 0; sub < SUB; ++sub) {
     const int j0 = 1 + (tile >> 16) * TJ + sub * TS - H;
     if (j0 + H > lk.n - 2) break;
     if constexpr (C == 3 && TJ % 3 == 0 && TS % 3 == 0)
-      gs2d_wave_tile_mc3<T, TS, FINE>(lk.n, d_rsrc(u + base, bytes), d_rsrc(uo + base, bytes), d_rsrc(b + base, bytes),
-                                      i0, j0, w1, w2, w3, w4, w5, w6, inv);
+      gs2d_wave_tile_mc3<T, TS, FINE, PRO>(lk.n, d_rsrc(u + base, bytes), d_rsrc(uo + base, bytes),
+                                           d_rsrc(b + base, bytes), i0, j0, w1, w2, w3, w4, w5, w6, inv, P);
     else
-      gs2d_wave_tile<T, C, TS, FINE>(lk.n, d_rsrc(u + base, bytes), d_rsrc(uo + base, bytes), d_rsrc(b + base, bytes),
-                                     i0, j0, rb, s1, s2, w1, w2, w3, w4, w5, w6, inv);
+      gs2d_wave_tile<T, C, TS, FINE, PRO>(lk.n, d_rsrc(u + base, bytes), d_rsrc(uo + base, bytes),
+                                          d_rsrc(b + base, bytes), i0, j0, rb, s1, s2, w1, w2, w3, w4, w5, w6, inv, P);
   }
 }
 
@@ -2999,14 +3062,22 @@ void launch_smooth_interior(int dim, bool p1, const LK& lk, const Tables& tb, co
 template <typename T>
 bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* uo, const T* b, const int32_t* tiles,
                      int ntiles, const uint32_t* itab, const int32_t* itab_off, int rb, double sA, bool fine,
-                     hipStream_t st) {
+                     hipStream_t st, const T* pro_ec, int pro_cS, T* pro_t) {
   if (p1 || lk.NI <= 0) return false;
   if (dim == 2) {
     if (ntiles <= 0) return false;
     const unsigned g = (unsigned)(((int64_t)lk.nmacro * ntiles + 31) / 32 * 8);   // 4 tiles per block, 8 XCDs
+    const bool pro = pro_ec != nullptr;
 #define HHG_F2(C, N, F)                                                                                          \
-  k_gs2d_fused<T, C, tile_rows(C, N), (sizeof(T) == 8 && tile_rows(C, N) > 18) ? 2 : 1, F><<<g, 256, 0, st>>>(       \
-      lk, tb, u, uo, b, tiles, ntiles, rb, sA)
+  do {                                                                                                           \
+    constexpr int TR = tile_rows(C, N), SB = (sizeof(T) == 8 && tile_rows(C, N) > 18) ? 2 : 1;                    \
+    if (pro)                                                                                                     \
+      k_gs2d_fused<T, C, TR, SB, F, true><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA, pro_ec, pro_cS, \
+                                                             pro_t);                                             \
+    else                                                                                                         \
+      k_gs2d_fused<T, C, TR, SB, F, false><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA, nullptr, 0,   \
+                                                              nullptr);                                          \
+  } while (0)
 #define HHG_F2N(C, F)                                       \
   do {                                                      \
     if (lk.n <= 8) HHG_F2(C, 8, F);                         \
@@ -3364,9 +3435,11 @@ template void launch_smooth_interior<double>(int, bool, const LK&, const Tables&
 template void launch_smooth_interior<float>(int, bool, const LK&, const Tables&, const float*, float*, const float*, int,
                                             int, int, double, double, const double*, bool, hipStream_t);
 template bool launch_gs_fused<double>(int, bool, const LK&, const Tables&, double*, double*, const double*,
-                                      const int32_t*, int, const uint32_t*, const int32_t*, int, double, bool, hipStream_t);
+                                      const int32_t*, int, const uint32_t*, const int32_t*, int, double, bool, hipStream_t,
+                                      const double*, int, double*);
 template bool launch_gs_fused<float>(int, bool, const LK&, const Tables&, float*, float*, const float*, const int32_t*,
-                                     int, const uint32_t*, const int32_t*, int, double, bool, hipStream_t);
+                                     int, const uint32_t*, const int32_t*, int, double, bool, hipStream_t, const float*,
+                                     int, float*);
 template void launch_iface_tasks<double>(int, const LK&, const Tables&, const int32_t*, const int32_t*, const int32_t*,
                                          const int32_t*, const int32_t*, int, int, const double*, const double*, double*,
                                          double*, const double*, int, double, double, hipStream_t);

@@ -716,3 +716,30 @@ def test_dense_coarse_map_follows_parameters_and_coefficients():
     fresh = HHG(m.coords, m.cells, L, smoother="multicolour", kappa_cell=kc2, flags=HHG_FLAG_DENSE_COARSE)
     ur, _ = fresh.fmg_solve(fd, gd, nu=1, rtol=0.0, max_iter=2)
     assert np.array_equal(to_host(u), to_host(ur))
+
+
+@pytest.mark.parametrize("name,smoother", [("lshape7", "multicolour"), ("square8", "redblack"),
+                                           ("grid4", "multicolour"), ("lshape", "redblack")])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+@pytest.mark.parametrize("iface", ["one_launch", "classwise", "two_launch"])
+def test_fused_prolongation_equals_separate_launch(name, smoother, precision, iface):
+    # the cycle's prolongation inside the first post-smoothing sweep (2D) against its own
+    # launch, bit for bit: FMG with two extra cycles, under each form of the interface sweep
+    # (the forms that mirror their writes read the prolongated boundary values from the
+    # scratch vector the fused sweep fills)
+    from paper_2508_06049_amd import HHG
+    from paper_2508_06049_amd._lib import (HHG_FLAG_CLASSWISE_IFACE, HHG_FLAG_NO_FUSED_PROLONG,
+                                           HHG_FLAG_TWO_LAUNCH_IFACE)
+    mk, L, _ = MESHES[name]
+    _note("fused prolongation", name, L, smoother, precision, iface)
+    m = mk()
+    fl = {"one_launch": 0, "classwise": HHG_FLAG_CLASSWISE_IFACE, "two_launch": HHG_FLAG_TWO_LAUNCH_IFACE}[iface]
+    hf = HHG(m.coords, m.cells, L, smoother=smoother, flags=fl)
+    hs = HHG(m.coords, m.cells, L, smoother=smoother, flags=fl | HHG_FLAG_NO_FUSED_PROLONG)
+    X = hf.dof_coords().cpu().numpy()
+    f, g = _rhs(name, X, m.dim)
+    fd, gd = to_dev(f), to_dev(g)
+    uf, sf = hf.fmg_solve(fd, gd, nu=1, precision=precision, rtol=0.0, max_iter=2)
+    us, ss = hs.fmg_solve(fd, gd, nu=1, precision=precision, rtol=0.0, max_iter=2)
+    assert sf.vcycles == ss.vcycles
+    assert np.array_equal(to_host(uf), to_host(us))
