@@ -133,8 +133,10 @@ typedef struct {
                                  small problems).
                                  HHG_FLAG_NO_FUSED_PROLONG: in 2D, run the cycle's
                                  prolongation as a launch of its own instead of inside the
-                                 first post-smoothing sweep (identical result; for checking
-                                 and timing the fused form)                                     */
+                                 first post-smoothing sweep, and clear a zero correction
+                                 before the first pre-smoothing sweep instead of starting
+                                 that sweep from zero (identical result; for checking and
+                                 timing the fused forms)                                        */
 } hhg_options;
 
 enum {

@@ -106,7 +106,7 @@ template <> struct Arr<float> {
 // interior smoother launch(es); while profiling, finest-level launches are bracketed by events
 template <typename T>
 void interior_launch(hhg_ctx c, int l, const LK& k, const T* x, T* y, const T* b, int col, int rb, int jac,
-                     const T* pro_ec = nullptr, T* pro_t = nullptr) {
+                     const T* pro_ec = nullptr, T* pro_t = nullptr, bool zero_start = false) {
   Level& lv = c->lev[l];
   const bool fine = l == c->L;
   const bool rec = fine && c->prof_on && c->prof_used + 2 <= (int)c->prof_ev.size();
@@ -114,7 +114,8 @@ void interior_launch(hhg_ctx c, int l, const LK& k, const T* x, T* y, const T* b
   int64_t npts;
   if (col < 0) {   // all interior colours fused in one launch
     launch_gs_fused<T>(c->dim, p1(c), k, c->tab, const_cast<T*>(x), y, b, lv.d_tiles, (int)lv.tiles.size(), lv.d_itab,
-                       lv.d_itab_off, rb, sA(c, l), fine, ST(c), pro_ec, pro_ec ? (int)c->lev[l - 1].S : 0, pro_t);
+                       lv.d_itab_off, rb, sA(c, l), fine, ST(c), pro_ec, pro_ec ? (int)c->lev[l - 1].S : 0, pro_t,
+                       zero_start);
     npts = lv.NI * c->nC;
   } else {
     launch_smooth_interior<T>(c->dim, p1(c), k, c->tab, x, y, b, col, rb, jac, omega(c), sA(c, l), lv.kn, fine, ST(c));
@@ -139,17 +140,19 @@ bool fused_available(hhg_ctx c, int l, size_t tsize) {
   return !lv.itab.empty() && (size_t)lv.Sraw * tsize <= 64 * 1024;
 }
 
-// the cycle's prolongation x_l += P e_{l-1} can run inside the first post-smoothing sweep
-// (2D fused out-of-place sweep)
+// the cycle's prolongation x_l += P e_{l-1} can run inside the first post-smoothing sweep, and
+// a sweep on a zero iterate can start without reading (or clearing) it (2D fused out-of-place
+// sweep, float32: in float64 the longer sweep measured slower than the two launches)
 bool pro_fusable(hhg_ctx c, int l, size_t tsize) {
-  return c->dim == 2 && l >= 1 && !c->no_pro && fused_available(c, l, tsize);
+  return c->dim == 2 && tsize == 4 && l >= 1 && !c->no_pro && fused_available(c, l, tsize);
 }
 
-// sweeps of the level-l smoother; with pro (pro_fusable), the first sweep starts from
-// x_l + P pro: its interior launch adds the prolongation on load and writes the start values
-// of the macro-boundary nodes to t_l, from which the interface classes of that sweep read
+// sweeps of the level-l smoother.  With pro (pro_fusable), the first sweep starts from
+// x_l + P pro; with zero_start (pro_fusable), from x_l = 0 whatever x_l holds.  Its interior
+// launch forms that start on load and writes the start values of the macro-boundary nodes to
+// t_l, from which the interface classes of that sweep read.
 template <typename T>
-hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps, const T* pro = nullptr) {
+hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps, const T* pro = nullptr, bool zero_start = false) {
   Level& lv = c->lev[l];
   const LK k = lk_of(c, l);
   const bool jac = c->opt.smoother == HHG_JACOBI;
@@ -191,15 +194,17 @@ hhg_status smooth(hhg_ctx c, int l, const T* b, int sweeps, const T* pro = nullp
     // the interface reads interior neighbours from the new buffer y and interface values from x
     // (current), and writes both
     T* y = twobuf ? Arr<T>::x2(lv) : x;
-    const T* pe = s == 0 && twobuf && c->dim == 2 ? pro : (const T*)nullptr;
-    if (fused) interior_launch<T>(c, l, k, x, y, b, -1, rb, 0, pe, Arr<T>::t(lv));
+    const bool first = s == 0 && twobuf && c->dim == 2;
+    const T* pe = first ? pro : (const T*)nullptr;
+    const bool z = first && !pro && zero_start;
+    if (fused) interior_launch<T>(c, l, k, x, y, b, -1, rb, 0, pe, Arr<T>::t(lv), z);
     else
       for (int col = 0; col < lv.interior_colours; ++col) interior_launch<T>(c, l, k, x, x, b, col, rb, 0);
     // the whole-plane 3D sweep also copies the interface values into y, so the interface
     // classes then update y in place: one buffer, no mirror writes.  After a fused
     // prolongation the old interface values are those in t.
     const bool in_y = twobuf && lv.planes3d;
-    T* xo = pe ? Arr<T>::t(lv) : x;
+    T* xo = pe || z ? Arr<T>::t(lv) : x;
     T* xf = in_y ? y : xo;
     T* mir = twobuf && !in_y ? xo : (T*)nullptr;
     if (lv.task_ok && !c->no_tasks) {
@@ -295,9 +300,10 @@ int64_t dense_key(int pre, int post) { return (int64_t)pre | ((int64_t)post << 1
 
 // V(pre,post) cycle on level l for A x_l = b; x_is_zero lets the coarsest step skip a residual.
 // On the dense-map level, a cycle from a zero iterate is one product with the map built for
-// these sweep counts (the same linear map as the launches below, up to rounding).
+// these sweep counts (the same linear map as the launches below, up to rounding).  zero_first:
+// x_l has not been cleared, the first sweep starts from zero (pro_fusable levels only)
 template <typename T>
-hhg_status vcycle(hhg_ctx c, int l, const T* b, int pre, int post, bool x_is_zero) {
+hhg_status vcycle(hhg_ctx c, int l, const T* b, int pre, int post, bool x_is_zero, bool zero_first = false) {
   if (x_is_zero && l == c->dense_k && !c->dense_building && c->dense_key[prec_of<T>()] == dense_key(pre, post)) {
     const Level& lv = c->lev[l];
     launch_dense_map<T>(c->dense_rows, c->dense_cols, c->dense_ld, (int)lv.S, (int)lv.Sraw, dense_of<T>(c), b,
@@ -308,7 +314,7 @@ hhg_status vcycle(hhg_ctx c, int l, const T* b, int pre, int post, bool x_is_zer
   if (l == 0) return coarse_step<T>(c, b, x_is_zero);
   Level& lv = c->lev[l];
   Level& lc = c->lev[l - 1];
-  TRY(smooth<T>(c, l, b, pre));
+  TRY(smooth<T>(c, l, b, pre, nullptr, zero_first));
   launch_apply<T, T>(c->dim, p1(c), lk_of(c, l), c->tab, Arr<T>::x(lv), b, Arr<T>::t(lv), 0, sA(c, l), 1.0, -1.0, 1,
                      lv.kn, ST(c));
   // restriction; the same launch clears the coarse correction (homogeneous, Dirichlet copies included)
@@ -383,8 +389,11 @@ hhg_status cycle(hhg_ctx c, int l, const double* b, const hhg_solve_params& p, b
   Level& lv = c->lev[l];
   if (p.precision == HHG_FP64) return vcycle<double>(c, l, b, p.pre, p.post, false);
   if (!rhs_ready) residual_f32(c, l, b);
-  launch_fill<float>(lv.x32, lv.nfull, 0.0f, ST(c));
-  TRY(vcycle<float>(c, l, lv.b32, p.pre, p.post, l == 0));
+  // the correction starts from zero; the first sweep can start from zero without the clear
+  // (not on the dense-map level, whose product writes the inner DoFs only)
+  const bool zs = l >= 1 && l != c->dense_k && p.pre >= 1 && pro_fusable(c, l, sizeof(float));
+  if (!zs) launch_fill<float>(lv.x32, lv.nfull, 0.0f, ST(c));
+  TRY(vcycle<float>(c, l, lv.b32, p.pre, p.post, l == 0 || zs, zs));
   launch_add_f32(lv.x, lv.x32, lv.nfull, ST(c));
   LAUNCHCHK();
   return HHG_OK;

@@ -26,11 +26,13 @@ void launch_smooth_interior(int dim, bool p1, const LK& lk, const Tables& tb, co
 // (2D, and 3D with streaming tiles: reads u and writes the interior of uo; the 3D LDS macro
 // sweep updates u in place and ignores uo).  2D with pro_ec: the sweep starts from u + P pro_ec
 // (the prolongation of the coarse correction pro_ec, coarse closure stride pro_cS) and writes
-// that start value of every macro-boundary node to pro_t
+// that start value of every macro-boundary node to pro_t; with zero_start instead, it starts
+// from zero (u is not read) and writes zeros to the macro-boundary nodes of pro_t
 template <typename T>
 bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* uo, const T* b, const int32_t* tiles,
                      int ntiles, const uint32_t* itab, const int32_t* itab_off, int rb, double sA, bool fine,
-                     hipStream_t st, const T* pro_ec = nullptr, int pro_cS = 0, T* pro_t = nullptr);
+                     hipStream_t st, const T* pro_ec = nullptr, int pro_cS = 0, T* pro_t = nullptr,
+                     bool zero_start = false);
 // interface update of one colour class (xi: source of interior neighbours, xf: of interface
 // neighbours; umirror, if not NULL, receives the new values too)
 // lane-parallel interface update of the wavefronts w0..w1-1 (one colour class), or of all

@@ -1610,40 +1610,75 @@ template <typename T>
 struct ProLoad {
   __amdgpu_buffer_rsrc_t ec, tout;   // this macro's coarse correction (side nc) and boundary output
   int nc;
-  uint32_t dirb;                     // Dirichlet bits of the macro by zero-set mask
 };
 
+// boundary nodes of rows j0r .. j1r in the columns i0 .. i0 + 63: the store offset of node (i, j)
+// if it is a macro-boundary node of the closure, else an offset past the buffer (the store is
+// dropped); whether the region holds any boundary node at all is wave-uniform
+__device__ __forceinline__ bool region_has_boundary(int n, int i0, int j0r, int j1r) {
+  return i0 <= 0 || j0r <= 0 || i0 + 63 + j1r >= n;
+}
+template <typename T>
+__device__ __forceinline__ uint32_t boundary_offset(int n, int i, int j) {
+  // j is wave-uniform: row 0 is boundary in every column of the closure, rows 1 .. n only in
+  // columns 0 and n - j
+  const bool bnd = j == 0 ? (uint32_t)i <= (uint32_t)n : ((uint32_t)j <= (uint32_t)n && (i == 0 || i == n - j));
+  return bnd ? (uint32_t)(d_lin2(n, 0, j) + i) * (uint32_t)sizeof(T) : 0xfffffff0u;
+}
+
 // rows jstart + r (r < NR, jstart of parity PAR) of lane column i, in u[]; only the rows
-// R0 <= r < R1 hold loaded values.  Coarse row jc of the region is t = jc - (jstart >> 1); per
-// lane A holds coarse column i >> 1 and Bv column (i + 1) >> 1, which give both nodes of every
-// fine parity pattern
+// R0 <= r < R1 hold loaded values.  Coarse row jc of the region is t = jc - (jstart >> 1).
+// Every fine parity pattern takes its nodes from coarse columns i >> 1 (a) and (i + 1) >> 1
+// (b; the same for even i).  Each lane loads its column a and takes b from the next lane; the
+// last lane loads its b instead and takes its a from the lane before (for odd i), so every
+// coarse value comes from one load per lane and row and DPP shifts.
 template <typename T, int NR, int PAR, int R0, int R1>
 __device__ __forceinline__ void pro_rows(int n, const ProLoad<T>& P, int i, int jstart, T* u) {
-  constexpr int NCR = (NR + PAR + 1) / 2 + 1;
-  const int jcb = jstart >> 1, ia = i >> 1, ib = (i + 1) >> 1, nc = P.nc;
-  T A[NCR], Bv[NCR];
+  constexpr int T0 = (R0 + PAR) >> 1, T1 = ((R1 - 1 + PAR) >> 1) + 2;   // coarse rows used
+  const int q = (int)(threadIdx.x & 63);
+  const int i0w = __builtin_amdgcn_readfirstlane(i - q);   // the wavefront's first column
+  const bool iodd = (i & 1) != 0, last = q == 63;
+  const int jcb = jstart >> 1, ic = last ? (i + 1) >> 1 : i >> 1, nc = P.nc;
+  T A[T1];
 #pragma unroll
-  for (int t = 0; t < NCR; ++t) {
+  for (int t = T0; t < T1; ++t) {
     const int jc = jcb + t;
-    const bool oka = ia >= 0 && jc >= 0 && ia + jc <= nc, okb = ib >= 0 && jc >= 0 && ib + jc <= nc;
-    d_bload(P.ec, oka ? (uint32_t)d_lin2(nc, ia, jc) * (uint32_t)sizeof(T) : 0xfffffff0u, A[t]);
-    d_bload(P.ec, okb ? (uint32_t)d_lin2(nc, ib, jc) * (uint32_t)sizeof(T) : 0xfffffff0u, Bv[t]);
+    const bool ok = ic >= 0 && jc >= 0 && ic + jc <= nc;
+    d_bload(P.ec, ok ? (uint32_t)d_lin2(nc, ic, jc) * (uint32_t)sizeof(T) : 0xfffffff0u, A[t]);
   }
-  const bool iodd = (i & 1) != 0;
+  // the coarse correction is zero on Dirichlet nodes (restriction clears it, no sweep writes
+  // there), so P e adds exactly zero on fine Dirichlet nodes: no Dirichlet test is needed
+  auto col_a = [&](int t) {
+    const T pv = from_prev(A[t]);   // shifts run on every lane (a lane left out supplies nothing)
+    return last && iodd ? pv : A[t];
+  };
+  auto col_b = [&](int t) {
+    const T nx = from_next(A[t]);
+    return iodd ? (last ? A[t] : nx) : A[t];
+  };
 #pragma unroll
   for (int r = R0; r < R1; ++r) {
     const int t = (r + PAR) >> 1;
-    const int j = jstart + r;
     T lo, hi;
-    if (((PAR + r) & 1) == 0) { lo = A[t]; hi = Bv[t]; }   // even row: along the row
-    else { lo = iodd ? Bv[t] : A[t]; hi = A[t + 1]; }       // odd row: along j, or the diagonal
-    const int mk = d_mask<2>(n, i, j, 0);
-    const bool dir = mk != 0 && ((P.dirb >> mk) & 1);
-    const T v = dir ? u[r] : u[r] + (T)0.5 * (lo + hi);
-    u[r] = v;
-    if (mk != 0 && i >= 0 && j >= 0 && i + j <= n)
-      d_bstore(P.tout, (uint32_t)(d_lin2(n, 0, j) + i) * (uint32_t)sizeof(T), v);
+    if (((PAR + r) & 1) == 0) { lo = col_a(t); hi = col_b(t); }   // even row: along the row
+    else { lo = col_b(t); hi = col_a(t + 1); }                       // odd row: along j, or the diagonal
+    u[r] = u[r] + (T)0.5 * (lo + hi);
   }
+  if (region_has_boundary(n, i0w, jstart + R0, jstart + R1 - 1)) {
+#pragma unroll
+    for (int r = R0; r < R1; ++r) d_bstore(P.tout, boundary_offset<T>(n, i, jstart + r), u[r]);
+  }
+}
+
+// zero start (the first sweep of a cycle on a zero correction, without clearing it first): the
+// loaded nodes are zeros, and the boundary nodes of rows R0 <= r < R1 are written as zeros to
+// tout for the interface classes
+template <typename T, int R0, int R1>
+__device__ __forceinline__ void zero_rows(int n, const ProLoad<T>& P, int i, int jstart) {
+  const int i0w = __builtin_amdgcn_readfirstlane(i - (int)(threadIdx.x & 63));
+  if (!region_has_boundary(n, i0w, jstart + R0, jstart + R1 - 1)) return;
+#pragma unroll
+  for (int r = R0; r < R1; ++r) d_bstore(P.tout, boundary_offset<T>(n, i, jstart + r), (T)0);
 }
 
 // Fused Gauss-Seidel sweep over the macro-interior nodes of a 2D level: every interior colour
@@ -1655,7 +1690,7 @@ __device__ __forceinline__ void pro_rows(int n, const ProLoad<T>& P, int i, int 
 // through DPP shifts; those values equal what C class-by-class passes over the whole macro
 // produce, because each pass only needs correct values one layer further out.  After C passes
 // the core is exact and is written to uo; the halo work is redundant.  No LDS and no barriers.
-template <typename T, int C, int TS, bool FINE, bool PRO>
+template <typename T, int C, int TS, bool FINE, int MODE>
 __device__ __forceinline__ void gs2d_wave_tile(int n, __amdgpu_buffer_rsrc_t um, __amdgpu_buffer_rsrc_t uom,
                                                __amdgpu_buffer_rsrc_t bm, int i0, int j0, int rb, int s1, int s2,
                                                T w1, T w2, T w3, T w4, T w5, T w6, T inv, const ProLoad<T>& P) {
@@ -1673,13 +1708,16 @@ __device__ __forceinline__ void gs2d_wave_tile(int n, __amdgpu_buffer_rsrc_t um,
     const bool in = i >= 0 && j >= 0 && i + j <= n;
     // unsigned 32-bit byte offset from the wave-uniform base: scalar-base + vector-offset loads
     const uint32_t g = in ? (uint32_t)(roff + i) * (uint32_t)sizeof(T) : 0u;
-    d_bload(um, g, ur[r]);
+    if constexpr (MODE == 2) ur[r] = (T)0;
+    else d_bload(um, g, ur[r]);
     d_bload(bm, g, br[r]);
     roff += n + 1 - j;
   }
-  if constexpr (PRO) {
+  if constexpr (MODE == 1) {
     if (j0 & 1) pro_rows<T, RH, 1, 0, RH>(n, P, i, j0, ur);
     else pro_rows<T, RH, 0, 0, RH>(n, P, i, j0, ur);
+  } else if constexpr (MODE == 2) {
+    zero_rows<T, 0, RH>(n, P, i, j0);
   }
   // colour of (i, j0): red-black parity or (i + 2 j) mod 3.  Row r has colour col0 + r s2
   // (mod 2) or col0 + 2 r (mod 3); with r and c compile-time constants the colour test is one
@@ -1735,7 +1773,7 @@ __device__ __forceinline__ void gs2d_wave_tile(int n, __amdgpu_buffer_rsrc_t um,
 // lane offers, by its own column mod 3, the slot that holds the asking lane's row (right,
 // left, up-left, down-right neighbours), and DPP shifts deliver it.  The valid region
 // shrinks by one node per pass exactly as in the row-aligned form.
-template <typename T, int TS, bool FINE, bool PRO>
+template <typename T, int TS, bool FINE, int MODE>
 __device__ __forceinline__ void gs2d_wave_tile_mc3(int n, __amdgpu_buffer_rsrc_t um, __amdgpu_buffer_rsrc_t uom,
                                                    __amdgpu_buffer_rsrc_t bm, int i0, int j0, T w1, T w2, T w3, T w4,
                                                    T w5, T w6, T inv, const ProLoad<T>& P) {
@@ -1754,15 +1792,18 @@ __device__ __forceinline__ void gs2d_wave_tile_mc3(int n, __amdgpu_buffer_rsrc_t
       const int r = t - K;   // row of the loaded region, 0 .. RH-1
       const bool in = r >= 0 && r < RH && i >= 0 && j >= 0 && i + j <= n;
       const uint32_t g = in ? (uint32_t)(roff + i) * (uint32_t)sizeof(T) : 0u;
-      d_bload(um, g, us[t]);
+      if constexpr (MODE == 2) us[t] = (T)0;
+      else d_bload(um, g, us[t]);
       d_bload(bm, g, bs[t]);
       roff += n + 1 - j;
       ++j;
     }
-    if constexpr (PRO) {
-      // the aligned rows t = K .. K + RH - 1 are the loaded ones (the others hold placeholders)
+    // the aligned rows t = K .. K + RH - 1 are the loaded ones (the others hold placeholders)
+    if constexpr (MODE == 1) {
       if ((j0 - K) & 1) pro_rows<T, RS + 2, 1, K, K + RH>(n, P, i, j0 - K, us);
       else pro_rows<T, RS + 2, 0, K, K + RH>(n, P, i, j0 - K, us);
+    } else if constexpr (MODE == 2) {
+      zero_rows<T, K, K + RH>(n, P, i, j0 - K);
     }
     const bool p1 = rho == 1, p2 = rho == 2;
 #pragma unroll
@@ -1814,7 +1855,7 @@ __device__ __forceinline__ void gs2d_wave_tile_mc3(int n, __amdgpu_buffer_rsrc_t
 // halos, so an in-place update would let one tile read rows another tile has already
 // written.  Blocks are spread over the XCDs in contiguous runs of tiles (block b runs on
 // XCD b mod 8), so neighbouring tiles share their halo rows in one L2.
-template <typename T, int C, int TJ, int SUB, bool FINE, bool PRO>
+template <typename T, int C, int TJ, int SUB, bool FINE, int MODE>
 __global__ void __launch_bounds__(256) k_gs2d_fused(LK lk, Tables tb, const T* __restrict__ u, T* __restrict__ uo,
                                                      const T* __restrict__ b,
                                                      const int32_t* __restrict__ tiles, int ntiles, int rb, double sA,
@@ -1837,22 +1878,21 @@ __global__ void __launch_bounds__(256) k_gs2d_fused(LK lk, Tables tb, const T* _
   const T inv = (T)(1.0 / (ks * W[0]));
   const int s1 = rb ? tb.rbpar[m * 4 + 1] : 0, s2 = rb ? tb.rbpar[m * 4 + 2] : 0;
   ProLoad<T> P{};
-  if constexpr (PRO) {
+  if constexpr (MODE == 1) {
     const int nc = lk.n >> 1;
     P.ec = d_rsrc(ec + (int64_t)m * cS, (uint32_t)(((nc + 1) * (nc + 2)) / 2) * (uint32_t)sizeof(T));
-    P.tout = d_rsrc(tout + base, bytes);
     P.nc = nc;
-    P.dirb = tb.dirbits[m];
   }
+  if constexpr (MODE != 0) P.tout = d_rsrc(tout + base, bytes);
 #pragma unroll
   for (int sub = 0; sub < SUB; ++sub) {
     const int j0 = 1 + (tile >> 16) * TJ + sub * TS - H;
     if (j0 + H > lk.n - 2) break;
     if constexpr (C == 3 && TJ % 3 == 0 && TS % 3 == 0)
-      gs2d_wave_tile_mc3<T, TS, FINE, PRO>(lk.n, d_rsrc(u + base, bytes), d_rsrc(uo + base, bytes),
+      gs2d_wave_tile_mc3<T, TS, FINE, MODE>(lk.n, d_rsrc(u + base, bytes), d_rsrc(uo + base, bytes),
                                            d_rsrc(b + base, bytes), i0, j0, w1, w2, w3, w4, w5, w6, inv, P);
     else
-      gs2d_wave_tile<T, C, TS, FINE, PRO>(lk.n, d_rsrc(u + base, bytes), d_rsrc(uo + base, bytes),
+      gs2d_wave_tile<T, C, TS, FINE, MODE>(lk.n, d_rsrc(u + base, bytes), d_rsrc(uo + base, bytes),
                                           d_rsrc(b + base, bytes), i0, j0, rb, s1, s2, w1, w2, w3, w4, w5, w6, inv, P);
   }
 }
@@ -3062,21 +3102,28 @@ void launch_smooth_interior(int dim, bool p1, const LK& lk, const Tables& tb, co
 template <typename T>
 bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* uo, const T* b, const int32_t* tiles,
                      int ntiles, const uint32_t* itab, const int32_t* itab_off, int rb, double sA, bool fine,
-                     hipStream_t st, const T* pro_ec, int pro_cS, T* pro_t) {
+                     hipStream_t st, const T* pro_ec, int pro_cS, T* pro_t, bool zero_start) {
   if (p1 || lk.NI <= 0) return false;
   if (dim == 2) {
     if (ntiles <= 0) return false;
     const unsigned g = (unsigned)(((int64_t)lk.nmacro * ntiles + 31) / 32 * 8);   // 4 tiles per block, 8 XCDs
-    const bool pro = pro_ec != nullptr;
+    const int mode = pro_ec ? 1 : (zero_start ? 2 : 0);
+    // with the prolongation, large levels take the sweep in two half-height sub-tiles: fewer
+    // registers, more wavefronts per SIMD (the extra halo rows come from L2)
 #define HHG_F2(C, N, F)                                                                                          \
   do {                                                                                                           \
     constexpr int TR = tile_rows(C, N), SB = (sizeof(T) == 8 && tile_rows(C, N) > 18) ? 2 : 1;                    \
-    if (pro)                                                                                                     \
-      k_gs2d_fused<T, C, TR, SB, F, true><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA, pro_ec, pro_cS, \
-                                                             pro_t);                                             \
+    if (mode == 1 && TR > 18 && lk.n >= 256)                                                                     \
+      k_gs2d_fused<T, C, TR, 2, F, 1><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA, pro_ec, pro_cS,     \
+                                                         pro_t);                                                 \
+    else if (mode == 1)                                                                                          \
+      k_gs2d_fused<T, C, TR, SB, F, 1><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA, pro_ec, pro_cS,    \
+                                                          pro_t);                                                \
+    else if (mode == 2)                                                                                          \
+      k_gs2d_fused<T, C, TR, SB, F, 2><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA, nullptr, 0, pro_t); \
     else                                                                                                         \
-      k_gs2d_fused<T, C, TR, SB, F, false><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA, nullptr, 0,   \
-                                                              nullptr);                                          \
+      k_gs2d_fused<T, C, TR, SB, F, 0><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA, nullptr, 0,       \
+                                                          nullptr);                                              \
   } while (0)
 #define HHG_F2N(C, F)                                       \
   do {                                                      \
@@ -3436,10 +3483,10 @@ template void launch_smooth_interior<float>(int, bool, const LK&, const Tables&,
                                             int, int, double, double, const double*, bool, hipStream_t);
 template bool launch_gs_fused<double>(int, bool, const LK&, const Tables&, double*, double*, const double*,
                                       const int32_t*, int, const uint32_t*, const int32_t*, int, double, bool, hipStream_t,
-                                      const double*, int, double*);
+                                      const double*, int, double*, bool);
 template bool launch_gs_fused<float>(int, bool, const LK&, const Tables&, float*, float*, const float*, const int32_t*,
                                      int, const uint32_t*, const int32_t*, int, double, bool, hipStream_t, const float*,
-                                     int, float*);
+                                     int, float*, bool);
 template void launch_iface_tasks<double>(int, const LK&, const Tables&, const int32_t*, const int32_t*, const int32_t*,
                                          const int32_t*, const int32_t*, int, int, const double*, const double*, double*,
                                          double*, const double*, int, double, double, hipStream_t);
