@@ -1132,7 +1132,29 @@ __device__ __forceinline__ void iface2d_edges_body(int vblk, int nvblk, T* s_e0,
   uint32_t vmask[2] = {0u, 0u};
   if (has) {
     const int32_t* R = erec + (size_t)e * kEdgeRecWords;
+    // every word of the record the lanes use, read before any of it is used (the record always
+    // has room for two copies), so the copies' words do not wait for the header
     const int hdr = R[0];
+    int cmac[2], csl[2];
+    uint32_t cval[2];
+    double ckw[2][kNDir2 + 1];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int32_t* C = R + 2 + kEdgeCopyWords * k;
+      cmac[k] = C[0];
+      csl[k] = C[1];
+      cval[k] = (uint32_t)C[18];
+      const double* KW = reinterpret_cast<const double*>(C + 2);   // kappa, then the 7 weights
+#pragma unroll
+      for (int d = 0; d <= kNDir2; ++d) ckw[k][d] = KW[d];
+    }
+    // keep the loads here: without a use the compiler sinks each into the branch that needs it,
+    // behind the header's round trip
+    asm volatile("" ::"s"(hdr), "s"(cmac[0]), "s"(cmac[1]), "s"(csl[0]), "s"(csl[1]), "s"(cval[0]), "s"(cval[1]));
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int d = 0; d <= kNDir2; ++d) asm volatile("" ::"s"(ckw[k][d]));
     ncp = min(hdr & 3, 2);   // 1 or 2 (checked by the host)
     dir = (hdr >> 2) & 1;
     a = 1 + 64 * chunk + lane;
@@ -1141,8 +1163,7 @@ __device__ __forceinline__ void iface2d_edges_body(int vblk, int nvblk, T* s_e0,
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         if (k >= ncp) break;
-        const int32_t* C = R + 2 + kEdgeCopyWords * k;
-        const int macro = C[0], sl = C[1];
+        const int macro = cmac[k], sl = csl[k];
         const int s0 = sl & 3, s1 = (sl >> 8) & 3, mask = (sl >> 16) & 15;
         int lc[3] = {0, 0, 0};
         lc[s0] = n - a;
@@ -1152,8 +1173,8 @@ __device__ __forceinline__ void iface2d_edges_body(int vblk, int nvblk, T* s_e0,
         cp[k] = base + d_lin2(n, i, j);
         if (!isE) continue;
         rhs[k] = b[cp[k]];
-        const double* KW = reinterpret_cast<const double*>(C + 2);   // kappa, then the 7 weights
-        const uint32_t valid = (uint32_t)C[18];
+        const double* KW = ckw[k];
+        const uint32_t valid = cval[k];
         vmask[k] = valid;
         const double scale = sA * KW[0];
 #pragma unroll
