@@ -1252,7 +1252,8 @@ __device__ __forceinline__ void iface2d_edges_body(int vblk, int nvblk, T* s_e0,
       if (umirror) umirror[cp[k]] = v;
     }
   }
-  for (int q = vblk * 1024 + (int)threadIdx.x; q < n_dv; q += nvblk * 1024) {
+  const int bs = (int)blockDim.x;
+  for (int q = vblk * bs + (int)threadIdx.x; q < n_dv; q += nvblk * bs) {
     const int c = dvcopy[q];
     const T v = xf[c];
     uout[c] = v;
@@ -1484,11 +1485,14 @@ void launch_iface2d_sweep(const LK& lk, const Tables& tb, const int32_t* erec, i
                           const int32_t* wsrc, const double* wcw, const int32_t* wwmax, int nwaves, int ncls,
                           const int32_t* we2, const int32_t* a2i, const double* a2w, const T* xi, const T* xf, T* uout,
                           const T* b, double sA, hipStream_t st) {
-  const int nch = (lk.n - 1 + 63) / 64, epb = 16 / nch;
+  // workgroups of 4 wavefronts while an edge fits them (n <= 257): the wheel workgroups then
+  // carry no idle wavefronts and the edges are spread over more compute units
+  const int nch = (lk.n - 1 + 63) / 64, threads = nch <= 4 ? 256 : 1024, epb = threads / 64 / nch;
   const int ge = std::max(1, (nE + epb - 1) / epb), gw = (nwaves + 3) / 4;
-  k_iface2d_sweep<T><<<(unsigned)(ge + gw), 1024, 0, st>>>(lk, tb, erec, nE, nch, epb, ge, dvcopy, n_dv, wcopy, winfo,
-                                                           wloc, wseg, wsrc, wcw, wwmax, nwaves, ncls, we2, a2i, a2w,
-                                                           xi, xf, uout, b, sA);
+  k_iface2d_sweep<T><<<(unsigned)(ge + gw), (unsigned)threads, 0, st>>>(lk, tb, erec, nE, nch, epb, ge, dvcopy, n_dv,
+                                                                        wcopy, winfo, wloc, wseg, wsrc, wcw, wwmax,
+                                                                        nwaves, ncls, we2, a2i, a2w, xi, xf, uout, b,
+                                                                        sA);
 }
 template void launch_iface2d_sweep<double>(const LK&, const Tables&, const int32_t*, int, const int32_t*, int,
                                            const int32_t*, const int32_t*, const int32_t*, const int32_t*,
