@@ -63,8 +63,8 @@ constexpr int kCoarseDenseMax = 2048;
 // iterate, as one matrix from the dual right-hand side to the iterate): at most this many rows
 // (inner DoFs of level k), columns (closure entries of level k, rounded up to 256) and bytes
 // (the float32 and float64 maps together)
-constexpr int kDenseMaxRows = 2048, kDenseMaxCols = 4096;
-constexpr int64_t kDenseMaxBytes = 48ll << 20;
+constexpr int kDenseMaxRows = 8192, kDenseMaxCols = 8192;
+constexpr int64_t kDenseMaxBytes = 512ll << 20;
 // blocks of the interior part of a squared norm (one partial each)
 constexpr int kNormBlocks = 8192;
 // interior rows per wavefront of the 2D row estimator

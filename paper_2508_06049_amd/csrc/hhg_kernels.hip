@@ -2616,48 +2616,58 @@ __global__ void __launch_bounds__(256) k_coarse_bwd(int n0, const double* __rest
 // ------------------------------------------------------------------------------------------
 // dense map of the cycle on one coarse level k: x_k = scatter(B b_k) with B row-major
 // [rows][ld] (row r: inner DoF r of level k; column m Sraw + s: closure entry m S + s of the
-// dual right-hand side, zero for entries that are no inner DoF's copy).  One wavefront per row
-// with all of the row's loads in flight at once (lane l holds columns 256 q + 4 l .. + 3; the
-// chunks q >= ld / 256 lie past the row's buffer range and load zeros); b staged in LDS by
-// each workgroup; the row is summed in float64 in a fixed order, then written to every copy.
+// dual right-hand side, zero for entries that are no inner DoF's copy).  One wavefront per row,
+// 16 rows per workgroup, b staged in LDS once per workgroup (zero past the columns).  A lane
+// holds columns 256 q + 4 l .. + 3; the row is read in groups of kDenseQC such chunks, each
+// group's loads in flight at once (chunks past ld / 256 lie outside the row's buffer range and
+// load zeros).  The row is summed in float64 in a fixed order, then written to every copy.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <typename T> constexpr int dense_qc() { return sizeof(T) == 4 ? 8 : 4; }
 
-template <typename T, int NQ>
-__global__ void __launch_bounds__(256) k_dense_map(int rows, int cols, int ld, int S, int Sraw, const T* __restrict__ B,
-                                                    const T* __restrict__ b, const int32_t* __restrict__ off,
-                                                    const int32_t* __restrict__ copy, T* __restrict__ x) {
-  __shared__ T sb[NQ * 256];
-  const int lane = (int)(threadIdx.x & 63);
-  const int row = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+template <typename T>
+__global__ void __launch_bounds__(1024) k_dense_map(int rows, int cols, int ld, int S, int Sraw, const T* __restrict__ B,
+                                                     const T* __restrict__ b, const int32_t* __restrict__ off,
+                                                     const int32_t* __restrict__ copy, T* __restrict__ x) {
+  extern __shared__ unsigned char dense_smem[];
+  T* sb = reinterpret_cast<T*>(dense_smem);
+  constexpr int QC = dense_qc<T>(), W = (int)(4 * sizeof(T) / 16);   // 16-byte loads per 4 entries
+  const int nq = ld / 256, nqr = (nq + QC - 1) / QC * QC;             // chunks, rounded to groups
+  const int lane = (int)(threadIdx.x & 63), nw = (int)(blockDim.x >> 6);
+  const int row = (int)blockIdx.x * nw + (int)(threadIdx.x >> 6);
   const int rr = __builtin_amdgcn_readfirstlane(min(row, rows - 1));   // uniform per wavefront
   const int o0 = off[rr], nc = off[rr + 1] - o0;
-  constexpr int W = (int)(4 * sizeof(T) / 16);   // 16-byte loads per 4 entries
   const __amdgpu_buffer_rsrc_t rB = d_rsrc(B + (size_t)rr * ld, (uint32_t)((size_t)ld * sizeof(T)));
-  u32x4 v[NQ][W];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int h = 0; h < W; ++h)
-      v[q][h] = __builtin_amdgcn_raw_buffer_load_b128(rB, (uint32_t)(((256 * q + 4 * lane) * (int)sizeof(T)) + 16 * h), 0, 0);
-  // b: every load of the workgroup's share in flight at once (columns past the end load zeros)
+  // b into LDS, up to 8 loads per thread in flight at once (ld <= 8192, blockDim = 1024)
   const __amdgpu_buffer_rsrc_t rb = d_rsrc(b, (uint32_t)((size_t)(cols / Sraw) * S * sizeof(T)));
-  T g[NQ];
+  T g[8];
 #pragma unroll
-  for (int t = 0; t < NQ; ++t) {
-    const int cc = (int)threadIdx.x + 256 * t, m = cc / Sraw;
+  for (int t = 0; t < 8; ++t) {
+    const int cc = (int)threadIdx.x + (int)blockDim.x * t, m = cc / Sraw;
     d_bload(rb, cc < cols ? (uint32_t)(((int64_t)m * S + (cc - m * Sraw)) * (int64_t)sizeof(T)) : 0xfffffff0u, g[t]);
   }
   const int32_t dst = lane < nc ? copy[o0 + lane] : -1;
 #pragma unroll
-  for (int t = 0; t < NQ; ++t) sb[threadIdx.x + 256 * t] = g[t];
+  for (int t = 0; t < 8; ++t) {
+    const int cc = (int)threadIdx.x + (int)blockDim.x * t;
+    if (cc < nqr * 256) sb[cc] = g[t];
+  }
   __syncthreads();
   double acc = 0.0;
+  for (int q0 = 0; q0 < nq; q0 += QC) {
+    u32x4 v[QC][W];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    T e[4];
-    __builtin_memcpy(e, &v[q][0], sizeof(e));
+    for (int q = 0; q < QC; ++q)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc += (double)e[t] * (double)sb[256 * q + 4 * lane + t];
+      for (int h = 0; h < W; ++h)
+        v[q][h] = __builtin_amdgcn_raw_buffer_load_b128(
+            rB, (uint32_t)(((256 * (q0 + q) + 4 * lane) * (int)sizeof(T)) + 16 * h), 0, 0);
+#pragma unroll
+    for (int q = 0; q < QC; ++q) {
+      T e[4];
+      __builtin_memcpy(e, &v[q][0], sizeof(e));
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc += (double)e[t] * (double)sb[256 * (q0 + q) + 4 * lane + t];
+    }
   }
   // butterfly: at every step both partners add the same two values, so every lane ends with
   // bitwise the same sum and all copies get one value
@@ -3386,11 +3396,10 @@ template <typename T>
 void launch_dense_map(int rows, int cols, int ld, int S, int Sraw, const T* B, const T* b, const int32_t* off,
                       const int32_t* copy, T* x, hipStream_t st) {
   if (rows <= 0) return;
-  const unsigned g = (unsigned)((rows + 3) / 4);
-  const int nq = ld / 256;
-  if (nq <= 4) k_dense_map<T, 4><<<g, 256, 0, st>>>(rows, cols, ld, S, Sraw, B, b, off, copy, x);
-  else if (nq <= 8) k_dense_map<T, 8><<<g, 256, 0, st>>>(rows, cols, ld, S, Sraw, B, b, off, copy, x);
-  else k_dense_map<T, 16><<<g, 256, 0, st>>>(rows, cols, ld, S, Sraw, B, b, off, copy, x);
+  // 16 rows (wavefronts) per workgroup; LDS for the staged b, rounded up to whole load groups
+  const unsigned g = (unsigned)((rows + 15) / 16);
+  const int qc = sizeof(T) == 4 ? 8 : 4, nqr = (ld / 256 + qc - 1) / qc * qc;
+  k_dense_map<T><<<g, 1024, (size_t)nqr * 256 * sizeof(T), st>>>(rows, cols, ld, S, Sraw, B, b, off, copy, x);
 }
 template void launch_dense_map<double>(int, int, int, int, int, const double*, const double*, const int32_t*,
                                        const int32_t*, double*, hipStream_t);
