@@ -2145,6 +2145,7 @@ __global__ void __launch_bounds__(256) k_apply2d_rows(LK lk, Tables tb, const Ti
   const int64_t base = (int64_t)m * lk.S;
   const __amdgpu_buffer_rsrc_t rx = d_rsrc(x + base, (uint32_t)lk.Sraw * (uint32_t)sizeof(Tin));
   const __amdgpu_buffer_rsrc_t ry = d_rsrc(y + base, (uint32_t)lk.Sraw * (uint32_t)sizeof(Tout));
+  const __amdgpu_buffer_rsrc_t rbb = d_rsrc(b ? b + base : x + base, b ? (uint32_t)lk.Sraw * (uint32_t)sizeof(Tin) : 0u);
   const double* Wt = (op == 0 ? tb.stiff : tb.mass) + (size_t)m * kMaxMask * 7;
   const double sc = op == 0 ? scale * tb.kappa[m] : scale;
   Tin w[7];
@@ -2160,6 +2161,15 @@ __global__ void __launch_bounds__(256) k_apply2d_rows(LK lk, Tables tb, const Ti
     d_bload(rx, in ? (uint32_t)(d_lin2(n, 0, j) + i) * (uint32_t)sizeof(Tin) : 0u, v);
     xr[q] = in ? v : (Tin)0;
   }
+  // b of the wavefront's own rows, loaded with x (past the closure, or without b through an
+  // empty descriptor: zeros), so no row waits for a load of its own
+  Tin br[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = jb * R + r;
+    const bool in = j <= n && i >= 0 && i <= n - j;
+    d_bload(rbb, in ? (uint32_t)(d_lin2(n, 0, j) + i) * (uint32_t)sizeof(Tin) : 0xfffffff0u, br[r]);
+  }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j = jb * R + r;
@@ -2168,14 +2178,14 @@ __global__ void __launch_bounds__(256) k_apply2d_rows(LK lk, Tables tb, const Ti
     // (i,j-1) (i+1,j-1); the shifts run on every lane
     const Tin nb[7] = {xc, from_next(xc), xu, from_prev(xu), from_prev(xc), xd, from_next(xd)};
     const bool ok = lane >= 1 && lane <= 62 && j >= 1 && i >= 1 && i + j <= n - 1;
-    if (!ok) continue;
     const int ctr = d_lin2(n, 0, j) + i;
     Tin off = (Tin)0;
 #pragma unroll
     for (int d = 1; d < 7; ++d) off += w[d] * nb[d];
     Tin v = (Tin)beta * (off + w[0] * nb[0]);
-    if (b) v += (Tin)alpha * b[base + ctr];
-    d_bstore(ry, (uint32_t)ctr * (uint32_t)sizeof(Tout), (Tout)v);
+    if (b) v += (Tin)alpha * br[r];
+    // nodes not owned here take an offset past the buffer: the store is dropped
+    d_bstore(ry, ok ? (uint32_t)ctr * (uint32_t)sizeof(Tout) : 0xfffffff0u, (Tout)v);
   }
 }
 
