@@ -2095,20 +2095,21 @@ __global__ void __launch_bounds__(256) k_apply3d_rows(LK lk, Tables tb, const Ti
 }
 
 // 2D y = alpha b + beta (A_m x) with a per-macro coefficient in two wavefront roles of one
-// launch.  Interior role (wavefronts 0 .. nint-1): a 62-node segment of kApplyRows rows of one
+// launch.  Interior role (wavefronts 0 .. nint-1): a 62-node segment of kApplyRowsOp rows of one
 // macro, lanes along i, the macro's full stencil with weights computed once per wavefront;
-// each lane loads its column of the kApplyRows + 2 rows once, all before the arithmetic, and
+// each lane loads its column of the kApplyRowsOp + 2 rows once, all before the arithmetic, and
 // takes the neighbours along i from the adjacent lanes; nodes on the macro boundary are left
 // to the other role.  Boundary role: one lane per boundary node (3n per macro: row j = 0,
 // column i = 0, the edge i + j = n) with its partial stencil.  x and y are accessed through
 // buffer descriptors bounded to the macro block.
-constexpr int kApplyRows = 4;
+constexpr int kApplyRows = 4;    // rows per wavefront of the transfer kernels
+constexpr int kApplyRowsOp = 8;  // rows per wavefront of the operator application
 template <typename Tin, typename Tout>
 __global__ void __launch_bounds__(256) k_apply2d_rows(LK lk, Tables tb, const Tin* __restrict__ x,
                                                       const Tin* __restrict__ b, Tout* __restrict__ y, int op,
                                                       double scale, double alpha, double beta, int zero_dir, int nseg,
                                                       int nint) {
-  constexpr int R = kApplyRows;
+  constexpr int R = kApplyRowsOp;
   const int n = lk.n;
   const int nrb = (n + 1 + R - 1) / R;
   const int wid = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
@@ -3287,7 +3288,7 @@ template <typename Tin, typename Tout>
 void launch_apply(int dim, bool p1, const LK& lk, const Tables& tb, const Tin* x, const Tin* b, Tout* y, int op,
                   double scale, double alpha, double beta, int zero_dir, const double* kn, hipStream_t st) {
   if (dim == 2 && !(p1 && op == 0)) {
-    const int nseg = (lk.n + 1 + 61) / 62, nrb = (lk.n + 1 + kApplyRows - 1) / kApplyRows;
+    const int nseg = (lk.n + 1 + 61) / 62, nrb = (lk.n + 1 + kApplyRowsOp - 1) / kApplyRowsOp;
     const int nint = lk.nmacro * nrb * nseg;
     const int nbnd = (int)(((int64_t)lk.nmacro * 3 * lk.n + 63) / 64);
     const unsigned gw = (unsigned)(((int64_t)nint + nbnd + 3) / 4);
