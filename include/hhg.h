@@ -180,9 +180,9 @@ typedef struct {
                                  the precision and sweep counts; -1 if none.  The map is the
                                  same linear map as those launches, so results agree up to
                                  rounding.  Level k is the largest with at most 8192 inner
-                                 DoFs, at most 8192 closure entries (rounded up to 256) and at
-                                 most 512 MiB for its float32 and float64 maps together,
-                                 k <= L - 3 (L - 1 with HHG_FLAG_DENSE_COARSE), k >= 1          */
+                                 DoFs and at most 512 MiB for its float32 and float64 maps
+                                 together, k <= L - 3 (L - 1 with HHG_FLAG_DENSE_COARSE),
+                                 k >= 1                                                        */
 } hhg_solve_stats;
 
 /* Validate the macro mesh, build primitives, per-macro stencils and colourings for levels

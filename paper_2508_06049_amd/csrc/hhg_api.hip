@@ -306,8 +306,8 @@ template <typename T>
 hhg_status vcycle(hhg_ctx c, int l, const T* b, int pre, int post, bool x_is_zero, bool zero_first = false) {
   if (x_is_zero && l == c->dense_k && !c->dense_building && c->dense_key[prec_of<T>()] == dense_key(pre, post)) {
     const Level& lv = c->lev[l];
-    launch_dense_map<T>(c->dense_rows, c->dense_cols, c->dense_ld, (int)lv.S, (int)lv.Sraw, dense_of<T>(c), b,
-                        c->d_doff, c->d_dcopy, Arr<T>::x(c->lev[l]), ST(c));
+    launch_dense_map<T>(c->dense_rows, c->dense_ld, c->dense_kmax, c->d_dgat, (T*)c->d_dsum, dense_of<T>(c), b,
+                        lv.nfull, c->d_doff, c->d_dcopy, Arr<T>::x(c->lev[l]), ST(c));
     LAUNCHCHK();
     return HHG_OK;
   }
@@ -333,9 +333,9 @@ hhg_status vcycle(hhg_ctx c, int l, const T* b, int pre, int post, bool x_is_zer
 
 // Build the dense map of level dense_k for this precision and these sweep counts, unless it
 // is there: one probe per inner DoF r (b_k = 1 at one copy of r, x_k = 0, the cycle of levels
-// k .. 0 by its ordinary launches), whose result is column r of the map (every copy's
-// column).  The map is linear in the sums of the dual copies, which is all the cycle reads of
-// b_k.  Runs eagerly, outside any recording, before a solve touches the level vectors.
+// k .. 0 by its ordinary launches), whose result is column r of the map.  The cycle reads b_k
+// only through the sums of each DoF's dual copies, so the map acts on those sums.  Runs
+// eagerly, outside any recording, before a solve touches the level vectors.
 template <typename T>
 hhg_status ensure_dense_t(hhg_ctx c, int pre, int post) {
   const int k = c->dense_k;
@@ -352,8 +352,7 @@ hhg_status ensure_dense_t(hhg_ctx c, int pre, int post) {
     launch_fill<T>(Arr<T>::x(lv), lv.nfull, (T)0, ST(c));
     const hhg_status s = vcycle<T>(c, k, rc, pre, post, true);
     if (s != HHG_OK) { c->dense_building = false; return s; }
-    launch_dense_harvest<T>(c->dense_rows, c->d_doff, c->d_dcopy, (int)lv.S, (int)lv.Sraw, c->dense_ld, r,
-                            Arr<T>::x(lv), B, ST(c));
+    launch_dense_harvest<T>(c->dense_rows, c->d_doff, c->d_dcopy, c->dense_ld, r, Arr<T>::x(lv), B, ST(c));
   }
   c->dense_building = false;
   LAUNCHCHK();
@@ -729,8 +728,11 @@ hhg_status bind_impl(hhg_ctx c, void* ptr, void* stream, bool no_alloc) {
   c->d_dense64 = (double*)(w + c->o_dense64);
   c->d_doff = (int32_t*)(w + c->o_doff);
   c->d_dcopy = (int32_t*)(w + c->o_dcopy);
+  c->d_dgat = (int32_t*)(w + c->o_dgat);
+  c->d_dsum = (void*)(w + c->o_dsum);
   HIPCHK(up(c->o_doff, c->dense_off.data(), c->dense_off.size() * 4));
   HIPCHK(up(c->o_dcopy, c->dense_copy.data(), c->dense_copy.size() * 4));
+  HIPCHK(up(c->o_dgat, c->dense_gat.data(), c->dense_gat.size() * 4));
   c->dense_key[0] = c->dense_key[1] = -1;
   for (auto& lv : c->lev) {
     lv.x = (double*)(w + lv.off_x);

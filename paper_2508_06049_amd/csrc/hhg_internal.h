@@ -60,10 +60,9 @@ constexpr int kEdgeRecWords = 2 + 2 * kEdgeCopyWords;
 // factored form (envelope Cholesky after reverse Cuthill-McKee)
 constexpr int kCoarseDenseMax = 2048;
 // dense map of the cycle on one coarse level k (the V-cycle of levels k .. 0 from a zero
-// iterate, as one matrix from the dual right-hand side to the iterate): at most this many rows
-// (inner DoFs of level k), columns (closure entries of level k, rounded up to 256) and bytes
-// (the float32 and float64 maps together)
-constexpr int kDenseMaxRows = 8192, kDenseMaxCols = 8192;
+// iterate, as one matrix from the assembled right-hand side to the iterate): at most this many
+// rows and columns (inner DoFs of level k) and bytes (the float32 and float64 maps together)
+constexpr int kDenseMaxRows = 8192, kDenseMaxCopies = 64;
 constexpr int64_t kDenseMaxBytes = 512ll << 20;
 // blocks of the interior part of a squared norm (one partial each)
 constexpr int kNormBlocks = 8192;
@@ -275,17 +274,20 @@ struct hhg_ctx_s {
   bool no_dense = false;            // no dense map of the coarse cycle (testing, timing)
   bool no_pro = false;              // cycle prolongation as its own launch (testing, timing)
   bool force_dense = false;         // dense map on the largest level that fits, up to L - 1 (testing)
-  // dense map of the cycle on level dense_k: row r is inner DoF r of that level (canonical
-  // order), with its copies dense_copy[dense_off[r] .. dense_off[r+1]) (level-vector indices);
-  // column m Sraw + s is closure entry s of macro m; dense_ld = columns rounded up to 256.
-  // dense_key[p] = pre | post << 16 of the map built for precision p (-1: none)
+  // dense map of the cycle on level dense_k: row and column r are inner DoF r of that level
+  // (canonical order), with its copies dense_copy[dense_off[r] .. dense_off[r+1]) (level-vector
+  // indices); dense_ld = rows rounded up to 256.  dense_key[p] = pre | post << 16 of the map
+  // built for precision p (-1: none)
+  // dense_gat[q * rows + r] = index + 1 of copy q of row r (0: none), q < dense_kmax; d_dsum
+  // holds the gathered right-hand side of one product
   int dense_k = -1;
-  int dense_rows = 0, dense_cols = 0, dense_ld = 0;
-  std::vector<int32_t> dense_off, dense_copy;
-  int64_t o_dense32 = 0, o_dense64 = 0, o_doff = 0, o_dcopy = 0;
+  int dense_rows = 0, dense_ld = 0, dense_kmax = 0;
+  std::vector<int32_t> dense_off, dense_copy, dense_gat;
+  int64_t o_dense32 = 0, o_dense64 = 0, o_doff = 0, o_dcopy = 0, o_dgat = 0, o_dsum = 0;
   float* d_dense32 = nullptr;
   double* d_dense64 = nullptr;
-  int32_t *d_doff = nullptr, *d_dcopy = nullptr;
+  int32_t *d_doff = nullptr, *d_dcopy = nullptr, *d_dgat = nullptr;
+  void* d_dsum = nullptr;
   int64_t dense_key[2] = {-1, -1};
   bool dense_building = false;      // the map's own probe cycles run the ordinary path
   bool classwise_iface = false;     // 2D interface classes one launch each (testing)

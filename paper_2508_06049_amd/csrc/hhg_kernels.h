@@ -105,17 +105,18 @@ void launch_coarse(int n0, const int32_t* coff, const int64_t* copy, const doubl
 template <typename T>
 void launch_coarse_factored(int n0, const int32_t* coff, const int64_t* copy, const int32_t* perm, const double* X,
                             double* scr, const T* rhs, T* x, int accumulate, hipStream_t st);
-// dense map of the coarse cycle: x[copies of row r] = sum_c B[r][c] b[entry of column c]
-// (ld a multiple of 256, at most 4096); its probes: b = unit vector at idx, and the probe's
-// result x written into the probed DoF's columns of B
+// dense map of the coarse cycle: sum[c] = sum of b (nb entries) over the copies of DoF c (gather
+// table gat, kmax copies at most), then x[copies of DoF r] = sum_c B[r][c] sum[c] (ld a multiple
+// of 256, at most 8192); its probes: b = unit vector at idx, and the probe's result x written
+// into column `probe` of B
 template <typename T>
-void launch_dense_map(int rows, int cols, int ld, int S, int Sraw, const T* B, const T* b, const int32_t* off,
-                      const int32_t* copy, T* x, hipStream_t st);
+void launch_dense_map(int rows, int ld, int kmax, const int32_t* gat, T* sum, const T* B, const T* b, int64_t nb,
+                      const int32_t* off, const int32_t* copy, T* x, hipStream_t st);
 template <typename T>
 void launch_unit(T* b, int64_t n, int64_t idx, hipStream_t st);
 template <typename T>
-void launch_dense_harvest(int rows, const int32_t* off, const int32_t* copy, int S, int Sraw, int ld, int probe,
-                          const T* x, T* B, hipStream_t st);
+void launch_dense_harvest(int rows, const int32_t* off, const int32_t* copy, int ld, int probe, const T* x, T* B,
+                          hipStream_t st);
 void launch_sqnorm(int dim, const LK& lk, const Tables& tb, const double* r, double* partial, double* out, hipStream_t st);
 // sum of squares of every closure entry (interface rows assembled in one copy)
 template <typename T>

@@ -2625,19 +2625,45 @@ __global__ void __launch_bounds__(256) k_coarse_bwd(int n0, const double* __rest
 }
 
 // ------------------------------------------------------------------------------------------
-// dense map of the cycle on one coarse level k: x_k = scatter(B b_k) with B row-major
-// [rows][ld] (row r: inner DoF r of level k; column m Sraw + s: closure entry m S + s of the
-// dual right-hand side, zero for entries that are no inner DoF's copy).  One wavefront per row,
-// 16 rows per workgroup, b staged in LDS once per workgroup (zero past the columns).  A lane
-// holds columns 256 q + 4 l .. + 3; the row is read in groups of kDenseQC such chunks, each
-// group's loads in flight at once (chunks past ld / 256 lie outside the row's buffer range and
-// load zeros).  The row is summed in float64 in a fixed order, then written to every copy.
+// dense map of the cycle on one coarse level k: x_k = scatter(B gather(b_k)) with B row-major
+// [rows][ld]; row and column r are inner DoF r of level k, gather sums a DoF's dual copies of
+// b_k in their list order, scatter writes a row's value to every copy.
+//
+// Gather: one thread per DoF, all of its copy indices and then all of their values in flight
+// at once (table entries past kmax, and the empty ones, read index 0 = none, whose value loads
+// past the buffer and reads zero), summed in list order.
+template <typename T, int KB>
+__global__ void __launch_bounds__(256) k_dense_gather(int rows, int kmax, const int32_t* __restrict__ gat,
+                                                       const T* __restrict__ b, int64_t nb, T* __restrict__ s) {
+  const int r = (int)(blockIdx.x * 256 + threadIdx.x);
+  if (r >= rows) return;
+  const __amdgpu_buffer_rsrc_t rg = d_rsrc(gat, (uint32_t)((size_t)kmax * rows * 4));
+  const __amdgpu_buffer_rsrc_t rb = d_rsrc(b, (uint32_t)((size_t)nb * sizeof(T)));
+  int32_t id[KB];
+#pragma unroll
+  for (int q = 0; q < KB; ++q)
+    id[q] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rg, (uint32_t)(((size_t)q * rows + r) * 4), 0, 0);
+  T v[KB];
+#pragma unroll
+  for (int q = 0; q < KB; ++q)
+    d_bload(rb, id[q] > 0 ? (uint32_t)(id[q] - 1) * (uint32_t)sizeof(T) : 0xfffffff0u, v[q]);
+  T acc = (T)0;
+#pragma unroll
+  for (int q = 0; q < KB; ++q) acc += v[q];
+  s[r] = acc;
+}
+
+// Product: one wavefront per row, 16 rows per workgroup, the gathered b staged in LDS once per
+// workgroup (zero past the rows).  A lane holds columns 256 q + 4 l .. + 3; the row is read in
+// groups of dense_qc such chunks, each group's loads in flight at once (chunks past ld / 256 lie
+// outside the row's buffer range and load zeros).  The row is summed in float64 in a fixed
+// order, then written to every copy.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 template <typename T> constexpr int dense_qc() { return sizeof(T) == 4 ? 8 : 4; }
 
 template <typename T>
-__global__ void __launch_bounds__(1024) k_dense_map(int rows, int cols, int ld, int S, int Sraw, const T* __restrict__ B,
-                                                     const T* __restrict__ b, const int32_t* __restrict__ off,
+__global__ void __launch_bounds__(1024) k_dense_map(int rows, int ld, const T* __restrict__ B,
+                                                     const T* __restrict__ sg, const int32_t* __restrict__ off,
                                                      const int32_t* __restrict__ copy, T* __restrict__ x) {
   extern __shared__ unsigned char dense_smem[];
   T* sb = reinterpret_cast<T*>(dense_smem);
@@ -2648,14 +2674,11 @@ __global__ void __launch_bounds__(1024) k_dense_map(int rows, int cols, int ld, 
   const int rr = __builtin_amdgcn_readfirstlane(min(row, rows - 1));   // uniform per wavefront
   const int o0 = off[rr], nc = off[rr + 1] - o0;
   const __amdgpu_buffer_rsrc_t rB = d_rsrc(B + (size_t)rr * ld, (uint32_t)((size_t)ld * sizeof(T)));
-  // b into LDS, up to 8 loads per thread in flight at once (ld <= 8192, blockDim = 1024)
-  const __amdgpu_buffer_rsrc_t rb = d_rsrc(b, (uint32_t)((size_t)(cols / Sraw) * S * sizeof(T)));
+  // the gathered b into LDS: up to 8 loads per thread (rows <= 8192, blockDim = 1024)
+  const __amdgpu_buffer_rsrc_t rs = d_rsrc(sg, (uint32_t)((size_t)rows * sizeof(T)));
   T g[8];
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const int cc = (int)threadIdx.x + (int)blockDim.x * t, m = cc / Sraw;
-    d_bload(rb, cc < cols ? (uint32_t)(((int64_t)m * S + (cc - m * Sraw)) * (int64_t)sizeof(T)) : 0xfffffff0u, g[t]);
-  }
+  for (int t = 0; t < 8; ++t) d_bload(rs, (uint32_t)(((int)threadIdx.x + (int)blockDim.x * t) * (int)sizeof(T)), g[t]);
   const int32_t dst = lane < nc ? copy[o0 + lane] : -1;
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
@@ -2695,19 +2718,14 @@ __global__ void __launch_bounds__(256) k_unit(T* __restrict__ b, int64_t n, int6
   if (i < n) b[i] = i == idx ? (T)1 : (T)0;
 }
 
-// the probe's result as column(s) of the dense map: B[r][columns of the probed DoF's copies] =
-// x at row r's first copy
+// the probe's result as column `probe` of the dense map: B[r][probe] = x at row r's first copy
 template <typename T>
 __global__ void __launch_bounds__(256) k_dense_harvest(int rows, const int32_t* __restrict__ off,
-                                                        const int32_t* __restrict__ copy, int S, int Sraw, int ld,
-                                                        int probe, const T* __restrict__ x, T* __restrict__ B) {
+                                                        const int32_t* __restrict__ copy, int ld, int probe,
+                                                        const T* __restrict__ x, T* __restrict__ B) {
   const int r = (int)(blockIdx.x * 256 + threadIdx.x);
   if (r >= rows) return;
-  const T val = x[copy[off[r]]];
-  for (int q = off[probe]; q < off[probe + 1]; ++q) {
-    const int e = copy[q];
-    B[(size_t)r * ld + (size_t)(e / S) * Sraw + (e % S)] = val;
-  }
+  B[(size_t)r * ld + probe] = x[copy[off[r]]];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -3404,18 +3422,23 @@ template void launch_coarse_factored<float>(int, const int32_t*, const int64_t*,
                                             double*, const float*, float*, int, hipStream_t);
 
 template <typename T>
-void launch_dense_map(int rows, int cols, int ld, int S, int Sraw, const T* B, const T* b, const int32_t* off,
-                      const int32_t* copy, T* x, hipStream_t st) {
+void launch_dense_map(int rows, int ld, int kmax, const int32_t* gat, T* sum, const T* B, const T* b, int64_t nb,
+                      const int32_t* off, const int32_t* copy, T* x, hipStream_t st) {
   if (rows <= 0) return;
-  // 16 rows (wavefronts) per workgroup; LDS for the staged b, rounded up to whole load groups
+  // table loads for the smallest bucket of copies per DoF that holds kmax
+  if (kmax <= 8) k_dense_gather<T, 8><<<nblk(rows), 256, 0, st>>>(rows, kmax, gat, b, nb, sum);
+  else if (kmax <= 16) k_dense_gather<T, 16><<<nblk(rows), 256, 0, st>>>(rows, kmax, gat, b, nb, sum);
+  else if (kmax <= 32) k_dense_gather<T, 32><<<nblk(rows), 256, 0, st>>>(rows, kmax, gat, b, nb, sum);
+  else k_dense_gather<T, kDenseMaxCopies><<<nblk(rows), 256, 0, st>>>(rows, kmax, gat, b, nb, sum);
+  // 16 rows (wavefronts) per workgroup; LDS for the gathered b, rounded up to whole load groups
   const unsigned g = (unsigned)((rows + 15) / 16);
   const int qc = sizeof(T) == 4 ? 8 : 4, nqr = (ld / 256 + qc - 1) / qc * qc;
-  k_dense_map<T><<<g, 1024, (size_t)nqr * 256 * sizeof(T), st>>>(rows, cols, ld, S, Sraw, B, b, off, copy, x);
+  k_dense_map<T><<<g, 1024, (size_t)nqr * 256 * sizeof(T), st>>>(rows, ld, B, sum, off, copy, x);
 }
-template void launch_dense_map<double>(int, int, int, int, int, const double*, const double*, const int32_t*,
-                                       const int32_t*, double*, hipStream_t);
-template void launch_dense_map<float>(int, int, int, int, int, const float*, const float*, const int32_t*,
-                                      const int32_t*, float*, hipStream_t);
+template void launch_dense_map<double>(int, int, int, const int32_t*, double*, const double*, const double*, int64_t,
+                                       const int32_t*, const int32_t*, double*, hipStream_t);
+template void launch_dense_map<float>(int, int, int, const int32_t*, float*, const float*, const float*, int64_t,
+                                      const int32_t*, const int32_t*, float*, hipStream_t);
 
 template <typename T>
 void launch_unit(T* b, int64_t n, int64_t idx, hipStream_t st) {
@@ -3425,14 +3448,14 @@ template void launch_unit<double>(double*, int64_t, int64_t, hipStream_t);
 template void launch_unit<float>(float*, int64_t, int64_t, hipStream_t);
 
 template <typename T>
-void launch_dense_harvest(int rows, const int32_t* off, const int32_t* copy, int S, int Sraw, int ld, int probe,
-                          const T* x, T* B, hipStream_t st) {
-  k_dense_harvest<T><<<nblk(rows), 256, 0, st>>>(rows, off, copy, S, Sraw, ld, probe, x, B);
+void launch_dense_harvest(int rows, const int32_t* off, const int32_t* copy, int ld, int probe, const T* x, T* B,
+                          hipStream_t st) {
+  k_dense_harvest<T><<<nblk(rows), 256, 0, st>>>(rows, off, copy, ld, probe, x, B);
 }
-template void launch_dense_harvest<double>(int, const int32_t*, const int32_t*, int, int, int, int, const double*,
-                                           double*, hipStream_t);
-template void launch_dense_harvest<float>(int, const int32_t*, const int32_t*, int, int, int, int, const float*,
-                                          float*, hipStream_t);
+template void launch_dense_harvest<double>(int, const int32_t*, const int32_t*, int, int, const double*, double*,
+                                           hipStream_t);
+template void launch_dense_harvest<float>(int, const int32_t*, const int32_t*, int, int, const float*, float*,
+                                          hipStream_t);
 
 void launch_sqnorm(int dim, const LK& lk, const Tables& tb, const double* r, double* partial, double* out, hipStream_t st) {
   // 2D: one wavefront per row; 3D: one block per 256-entry chunk of a macro block

@@ -1010,20 +1010,20 @@ hhg_status build_coarse(hhg_ctx c, const double* kappa_vertex) {
 }
 
 // Level of the dense coarse map: the largest k <= L - 3 (L - 1 when forced) whose inner DoFs
-// and closure entries fit the limits.  Its rows are the inner (non-Dirichlet) DoFs of level k
-// in canonical order, each with the level-vector indices of its copies.
+// and map bytes fit the limits.  Its rows, and its columns, are the inner (non-Dirichlet) DoFs
+// of level k in canonical order, each with the level-vector indices of its copies.
 void build_dense_plan(hhg_ctx c) {
   c->dense_k = -1;
-  c->dense_rows = c->dense_cols = c->dense_ld = 0;
+  c->dense_rows = c->dense_ld = c->dense_kmax = 0;
   c->dense_off.clear();
   c->dense_copy.clear();
+  c->dense_gat.clear();
   if (c->no_dense) return;
   const int d = c->dim;
   for (int k = c->force_dense ? c->L - 1 : c->L - 3; k >= 1; --k) {
     const Level& lv = c->lev[k];
     const int n = lv.n;
-    const int64_t cols = c->nC * lv.Sraw, ld = (cols + 255) / 256 * 256;
-    if (ld > kDenseMaxCols) continue;
+    if (lv.ndof > 4 * (int64_t)kDenseMaxRows) continue;   // far too large: not worth counting
     std::vector<std::vector<int32_t>> copies(lv.ndof);
     for (int64_t m = 0; m < c->nC; ++m)
       for (int kk = 0; kk <= (d == 3 ? n : 0); ++kk)
@@ -1035,17 +1035,28 @@ void build_dense_plan(hhg_ctx c) {
             copies[t].push_back((int32_t)(m * lv.S + lin_closure(d, n, i, j, kk)));
           }
     int64_t rows = 0;
-    for (const auto& v : copies) rows += v.empty() ? 0 : 1;
-    if (rows == 0 || rows > kDenseMaxRows || rows * ld * 12 > kDenseMaxBytes) continue;
+    size_t kmax = 0;
+    for (const auto& v : copies) {
+      rows += v.empty() ? 0 : 1;
+      kmax = std::max(kmax, v.size());
+    }
+    const int64_t ld = (rows + 255) / 256 * 256;
+    if (rows == 0 || rows > kDenseMaxRows || kmax > (size_t)kDenseMaxCopies || rows * ld * 12 > kDenseMaxBytes)
+      continue;
     c->dense_off.push_back(0);
     for (const auto& v : copies) {
       if (v.empty()) continue;
       c->dense_copy.insert(c->dense_copy.end(), v.begin(), v.end());
       c->dense_off.push_back((int32_t)c->dense_copy.size());
     }
+    // the gather table: copy q of row r at [q][r] as level-vector index + 1 (0: none)
+    c->dense_kmax = (int)kmax;
+    c->dense_gat.assign(kmax * (size_t)rows, 0);
+    for (int64_t r = 0; r < rows; ++r)
+      for (int32_t q = c->dense_off[r]; q < c->dense_off[r + 1]; ++q)
+        c->dense_gat[(size_t)(q - c->dense_off[r]) * rows + r] = c->dense_copy[q] + 1;
     c->dense_k = k;
     c->dense_rows = (int)rows;
-    c->dense_cols = (int)cols;
     c->dense_ld = (int)ld;
     return;
   }
@@ -1108,6 +1119,8 @@ void plan_workspace(hhg_ctx c) {
   c->o_dense64 = take((int64_t)c->dense_rows * c->dense_ld * 8);
   c->o_doff = take((int64_t)c->dense_off.size() * 4);
   c->o_dcopy = take((int64_t)c->dense_copy.size() * 4);
+  c->o_dgat = take((int64_t)c->dense_gat.size() * 4);
+  c->o_dsum = take((int64_t)c->dense_rows * 8);
   // reduction scratch: per macro per block (4 values) on the finest level, and per block norms
   const Level& lt = c->lev[c->L];
   int64_t bpm = (lt.Sraw + 255) / 256;
