@@ -371,3 +371,38 @@ def test_one_launch_interface_equals_classwise(lshape, L, precision):
     for o in out[1:]:
         assert np.array_equal(out[0][0], o[0])
         assert np.array_equal(out[0][1], o[1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_dense_map_and_fused_prolongation_full_size(lshape, precision):
+    # the bench's step at full size (L = 9, FMG + 5 extra cycles): the dense map of levels
+    # 3 .. 0 against the launches it replaces (rounding only: 1e-12 of |u| in float64; in the
+    # float32-refined form the bound of the iterate test for two float32 cycles that differ in
+    # rounding order, 1e-4 of the last correction), and the prolongation and zero start inside
+    # the first sweeps against their own launches (bitwise)
+    import torch
+    from paper_2508_06049_amd import HHG
+    from paper_2508_06049_amd._lib import HHG_FLAG_NO_DENSE_COARSE, HHG_FLAG_NO_FUSED_PROLONG
+    w = lshape
+    _note("dense map and fused prolongation at full size", w.name, w.L, precision)
+    res = {}
+    for name, flags, iters in (("default", 0, (5,)), ("no_dense", HHG_FLAG_NO_DENSE_COARSE, (4, 5)),
+                               ("no_fused", HHG_FLAG_NO_FUSED_PROLONG, (5,))):
+        hh = HHG(w.mesh.coords, w.mesh.cells, w.L, smoother=w.smoother, flags=flags)
+        X = hh.dof_coords().cpu().numpy()
+        fd, gd = to_dev(w.f(X)), to_dev(w.g(X))
+        for it in iters:
+            u, st = hh.fmg_solve(fd, gd, nu=1, precision=precision, rtol=0.0, max_iter=it)
+            res[(name, it)] = (to_host(u), st.dense_level)
+        hh.close()
+        del hh
+        torch.cuda.synchronize()
+    assert res[("default", 5)][1] == 3 and res[("no_dense", 5)][1] == -1
+    assert np.array_equal(res[("default", 5)][0], res[("no_fused", 5)][0])
+    a, b = res[("default", 5)][0], res[("no_dense", 5)][0]
+    scale = np.abs(b).max()
+    if precision == "fp64":
+        tol = 1e-12 * scale
+    else:
+        tol = 1e-4 * np.abs(b - res[("no_dense", 4)][0]).max() + 1e-12 * scale
+    assert np.abs(a - b).max() <= tol, (np.abs(a - b).max(), tol)
