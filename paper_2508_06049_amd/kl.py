@@ -180,7 +180,7 @@ def kl_refine(coarse: CoarseMesh, L: int, K: int, f: Callable, g: Callable,
     of the experiments in Section 5.  For every j in ``estimate_js`` (1 <= j < L) each FMG step
     also records the global estimate eta_j in ``extra["eta"][j]``."""
     import torch
-    from ._lib import HHG
+    from ._lib import HHG, HHG_FLAG_NO_DENSE_COARSE
 
     if criterion not in ("error", "estimate"):
         raise ValueError("criterion is 'error' or 'estimate'")
@@ -203,7 +203,9 @@ def kl_refine(coarse: CoarseMesh, L: int, K: int, f: Callable, g: Callable,
     for k in range(K + 1):
         m = rg.mesh(f"{coarse.name}_k{k}")          # macro order = conforming-cell order
         t0 = time.perf_counter()
-        hh = HHG(m.coords, m.cells, L, smoother=smoother, device=device)
+        # one context per mesh, solved once (or a few warm rounds): the dense map of the coarse
+        # cycle would cost about one probe cycle per coarse DoF and never pay off here
+        hh = HHG(m.coords, m.cells, L, smoother=smoother, device=device, flags=HHG_FLAG_NO_DENSE_COARSE)
         X = hh.dof_coords()
         fd, gd = _nodal(f, X, hh.device), _nodal(g, X, hh.device)
         ud = None if u_exact is None else _nodal(u_exact, X, hh.device)
