@@ -2,7 +2,7 @@
 """Benchmark of the HHG full-multigrid hot path on one MI355X.
 
 Workload (default): the L-shape domain with its 6 macro triangles k-refined 6 times towards
-the re-entrant corner (144 macros), L = 9 structured levels (19.9 M DoFs), Dirichlet data
+the re-entrant corner (144 macros), L = 9 structured levels (18.9 M DoFs), Dirichlet data
 u = r^(2/3) sin(2 phi / 3), f = 0, multicolour Gauss-Seidel V(2,2), one V-cycle per FMG
 level.  One step = one FMG solve to the fixed discretisation-level L2 error + the error
 estimate of every macro element.
