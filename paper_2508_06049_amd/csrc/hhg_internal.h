@@ -29,10 +29,13 @@ constexpr int kNType3 = 6, kNType2 = 2;
 constexpr int kTileJ = 32;
 // multicolour (C = 3) tiles are 30 rows high, so every tile starts on a row = 1 (mod 3)
 constexpr int kTileJ3 = 30;
-// tile height by level: small levels (n <= 16) use short tiles, which shortens the per-tile
-// chain of the fused sweep; multicolour heights stay multiples of 3 (and of 3 per half tile)
+// tile height by level: small levels (n <= kShortTileMaxN) use short tiles, which shortens the
+// per-tile chain of the fused sweep; multicolour heights stay multiples of 3 (and of 3 per half
+// tile)
+constexpr int kShortTileMaxN = 128;
 constexpr int tile_rows(int C, int n) {
-  return C == 3 ? (n <= 8 ? 6 : (n <= 16 ? 18 : kTileJ3)) : (n <= 8 ? 8 : (n <= 16 ? 16 : kTileJ));
+  return C == 3 ? (n <= 8 ? 6 : (n <= kShortTileMaxN ? 18 : kTileJ3))
+                : (n <= 8 ? 8 : (n <= kShortTileMaxN ? 16 : kTileJ));
 }
 constexpr int kMacroLdsN = 32;
 // plane-streaming 3D red-black sweep: a tile holds kS3I x kS3J interior points of a plane and

@@ -3189,11 +3189,13 @@ bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* 
       k_gs2d_fused<T, C, TR, SB, F, 0><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA, nullptr, 0,       \
                                                           nullptr);                                              \
   } while (0)
-#define HHG_F2N(C, F)                                       \
-  do {                                                      \
-    if (lk.n <= 8) HHG_F2(C, 8, F);                         \
-    else if (lk.n <= 16) HHG_F2(C, 16, F);                  \
-    else HHG_F2(C, 32, F);                                  \
+    // the kernel's tile height is the one the host built the tile table with
+#define HHG_F2N(C, F)                                                          \
+  do {                                                                         \
+    const int tr = tile_rows(C, lk.n);                                         \
+    if (tr == tile_rows(C, 8)) HHG_F2(C, 8, F);                                \
+    else if (tr == tile_rows(C, kShortTileMaxN)) HHG_F2(C, kShortTileMaxN, F); \
+    else HHG_F2(C, 1 << 20, F);                                                \
   } while (0)
     if (rb) { if (fine) HHG_F2N(2, true); else HHG_F2N(2, false); }
     else { if (fine) HHG_F2N(3, true); else HHG_F2N(3, false); }
