@@ -32,7 +32,7 @@ constexpr int kTileJ3 = 30;
 // tile height by level: small levels (n <= kShortTileMaxN) use short tiles, which shortens the
 // per-tile chain of the fused sweep; multicolour heights stay multiples of 3 (and of 3 per half
 // tile)
-constexpr int kShortTileMaxN = 128;
+constexpr int kShortTileMaxN = 256;
 constexpr int tile_rows(int C, int n) {
   return C == 3 ? (n <= 8 ? 6 : (n <= kShortTileMaxN ? 18 : kTileJ3))
                 : (n <= 8 ? 8 : (n <= kShortTileMaxN ? 16 : kTileJ));
