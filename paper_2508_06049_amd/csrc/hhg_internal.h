@@ -32,10 +32,10 @@ constexpr int kTileJ3 = 30;
 // tile height by level: small levels (n <= kShortTileMaxN) use short tiles, which shortens the
 // per-tile chain of the fused sweep; multicolour heights stay multiples of 3 (and of 3 per half
 // tile)
-constexpr int kShortTileMaxN = 256;
+constexpr int kTinyTileMaxN = 32, kShortTileMaxN = 256;
 constexpr int tile_rows(int C, int n) {
-  return C == 3 ? (n <= 8 ? 6 : (n <= kShortTileMaxN ? 18 : kTileJ3))
-                : (n <= 8 ? 8 : (n <= kShortTileMaxN ? 16 : kTileJ));
+  return C == 3 ? (n <= kTinyTileMaxN ? 6 : (n <= kShortTileMaxN ? 18 : kTileJ3))
+                : (n <= kTinyTileMaxN ? 8 : (n <= kShortTileMaxN ? 16 : kTileJ));
 }
 constexpr int kMacroLdsN = 32;
 // plane-streaming 3D red-black sweep: a tile holds kS3I x kS3J interior points of a plane and

@@ -3193,7 +3193,7 @@ bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* 
 #define HHG_F2N(C, F)                                                          \
   do {                                                                         \
     const int tr = tile_rows(C, lk.n);                                         \
-    if (tr == tile_rows(C, 8)) HHG_F2(C, 8, F);                                \
+    if (tr == tile_rows(C, kTinyTileMaxN)) HHG_F2(C, kTinyTileMaxN, F);        \
     else if (tr == tile_rows(C, kShortTileMaxN)) HHG_F2(C, kShortTileMaxN, F); \
     else HHG_F2(C, 1 << 20, F);                                                \
   } while (0)
