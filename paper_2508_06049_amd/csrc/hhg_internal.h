@@ -32,7 +32,7 @@ constexpr int kTileJ3 = 30;
 // tile height by level: small levels (n <= kShortTileMaxN) use short tiles, which shortens the
 // per-tile chain of the fused sweep; multicolour heights stay multiples of 3 (and of 3 per half
 // tile)
-constexpr int kTinyTileMaxN = 64, kShortTileMaxN = 256;
+constexpr int kTinyTileMaxN = 128, kShortTileMaxN = 256;
 constexpr int tile_rows(int C, int n) {
   return C == 3 ? (n <= kTinyTileMaxN ? 6 : (n <= kShortTileMaxN ? 18 : kTileJ3))
                 : (n <= kTinyTileMaxN ? 8 : (n <= kShortTileMaxN ? 16 : kTileJ));
