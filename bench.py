@@ -39,11 +39,11 @@ COPY_BYTES = 1 << 30          # plain copy used to scale the HBM byte counters
 # FETCH_SIZE and WRITE_SIZE counter runs of `bench.py --kernel-only`, each scaled by the same
 # counter's reading for a 1 GiB device copy (fetch x2.000, write x1.000); valid for the kernel
 # as committed with profiles/k_gs2d_fused_lshape_L9_traffic.md, else reported as null
-TRAFFIC_BYTES = {("lshape_corner", 9, "k_gs2d_fused<float, 3, 30, 1, true, 0>"): 228.2e6}
+TRAFFIC_BYTES = {("lshape_corner", 9, "k_gs2d_fused<float, 3, 18, 1, true, 0>"): 228.5e6}
 # the finest-level interior smoother kernel per workload type (float32 sweeps)
 KERNEL_NAME = {
-    (2, "multicolour", "macro"): "k_gs2d_fused<float, 3, 30, 1, true, 0>",
-    (2, "redblack", "macro"): "k_gs2d_fused<float, 2, 32, 1, true, 0>",
+    (2, "multicolour", "macro"): "k_gs2d_fused<float, 3, 18, 1, true, 0>",
+    (2, "redblack", "macro"): "k_gs2d_fused<float, 2, 16, 1, true, 0>",
     (3, "multicolour", "macro"): "k_gs3d_macro<float, 4, true>",
     (3, "redblack", "macro"): "k_gs3d_macro<float, 2, true>",
 }

@@ -24,19 +24,16 @@ namespace hhg {
 constexpr int kMaxMask = 16;   // zero-set masks of the barycentric coordinates (bit q: c_q == 0)
 constexpr int kNDir3 = 15, kNDir2 = 7;
 constexpr int kNType3 = 6, kNType2 = 2;
-// fused interior sweeps: 2D core tile of (64 - 2 C) columns (one wavefront) x kTileJ rows
-// (C = interior colours), and the largest 3D macro level kept whole in LDS
-constexpr int kTileJ = 32;
-// multicolour (C = 3) tiles are 30 rows high, so every tile starts on a row = 1 (mod 3)
-constexpr int kTileJ3 = 30;
-// tile height by level: small levels (n <= kShortTileMaxN) use short tiles, which shortens the
-// per-tile chain of the fused sweep; multicolour heights stay multiples of 3 (and of 3 per half
-// tile)
-constexpr int kTinyTileMaxN = 128, kShortTileMaxN = 256;
+// fused interior sweeps: a 2D tile is (64 - 2 C) columns (one wavefront) x tile_rows(C, n) rows
+// (C = interior colours).  A wavefront sweeps its tile's rows one after another, so the height
+// sets both the length of its chain and the number of workgroups of a launch: short tiles up to
+// n = kShortTileMaxN (latency-bound levels), taller ones above.  Multicolour heights are
+// multiples of 3, so every tile starts on a row = 1 (mod 3).
+constexpr int kShortTileMaxN = 128;
 constexpr int tile_rows(int C, int n) {
-  return C == 3 ? (n <= kTinyTileMaxN ? 6 : (n <= kShortTileMaxN ? 18 : kTileJ3))
-                : (n <= kTinyTileMaxN ? 8 : (n <= kShortTileMaxN ? 16 : kTileJ));
+  return C == 3 ? (n <= kShortTileMaxN ? 6 : 18) : (n <= kShortTileMaxN ? 8 : 16);
 }
+// the largest 3D macro level kept whole in LDS
 constexpr int kMacroLdsN = 32;
 // plane-streaming 3D red-black sweep: a tile holds kS3I x kS3J interior points of a plane and
 // streams kS3K planes; LDS planes are 64 x (kS3J + 4) points (two-point halo in i and j)

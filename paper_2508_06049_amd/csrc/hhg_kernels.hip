@@ -3172,30 +3172,23 @@ bool launch_gs_fused(int dim, bool p1, const LK& lk, const Tables& tb, T* u, T* 
     if (ntiles <= 0) return false;
     const unsigned g = (unsigned)(((int64_t)lk.nmacro * ntiles + 31) / 32 * 8);   // 4 tiles per block, 8 XCDs
     const int mode = pro_ec ? 1 : (zero_start ? 2 : 0);
-    // with the prolongation, large levels take the sweep in two half-height sub-tiles: fewer
-    // registers, more wavefronts per SIMD (the extra halo rows come from L2)
 #define HHG_F2(C, N, F)                                                                                          \
   do {                                                                                                           \
-    constexpr int TR = tile_rows(C, N), SB = (sizeof(T) == 8 && tile_rows(C, N) > 18) ? 2 : 1;                    \
-    if (mode == 1 && TR > 18 && lk.n >= 256)                                                                     \
-      k_gs2d_fused<T, C, TR, 2, F, 1><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA, pro_ec, pro_cS,     \
+    constexpr int TR = tile_rows(C, N);                                                                          \
+    if (mode == 1)                                                                                               \
+      k_gs2d_fused<T, C, TR, 1, F, 1><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA, pro_ec, pro_cS,     \
                                                          pro_t);                                                 \
-    else if (mode == 1)                                                                                          \
-      k_gs2d_fused<T, C, TR, SB, F, 1><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA, pro_ec, pro_cS,    \
-                                                          pro_t);                                                \
     else if (mode == 2)                                                                                          \
-      k_gs2d_fused<T, C, TR, SB, F, 2><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA, nullptr, 0, pro_t); \
+      k_gs2d_fused<T, C, TR, 1, F, 2><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA, nullptr, 0, pro_t);  \
     else                                                                                                         \
-      k_gs2d_fused<T, C, TR, SB, F, 0><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA, nullptr, 0,       \
-                                                          nullptr);                                              \
+      k_gs2d_fused<T, C, TR, 1, F, 0><<<g, 256, 0, st>>>(lk, tb, u, uo, b, tiles, ntiles, rb, sA, nullptr, 0,        \
+                                                         nullptr);                                               \
   } while (0)
     // the kernel's tile height is the one the host built the tile table with
-#define HHG_F2N(C, F)                                                          \
-  do {                                                                         \
-    const int tr = tile_rows(C, lk.n);                                         \
-    if (tr == tile_rows(C, kTinyTileMaxN)) HHG_F2(C, kTinyTileMaxN, F);        \
-    else if (tr == tile_rows(C, kShortTileMaxN)) HHG_F2(C, kShortTileMaxN, F); \
-    else HHG_F2(C, 1 << 20, F);                                                \
+#define HHG_F2N(C, F)                                                               \
+  do {                                                                              \
+    if (tile_rows(C, lk.n) == tile_rows(C, kShortTileMaxN)) HHG_F2(C, kShortTileMaxN, F); \
+    else HHG_F2(C, 2 * kShortTileMaxN, F);                                          \
   } while (0)
     if (rb) { if (fine) HHG_F2N(2, true); else HHG_F2N(2, false); }
     else { if (fine) HHG_F2N(3, true); else HHG_F2N(3, false); }
