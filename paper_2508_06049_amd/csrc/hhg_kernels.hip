@@ -2330,11 +2330,17 @@ __global__ void __launch_bounds__(256) k_prolong2d_rows(LK f, LK c, Tables tb, c
 }
 
 // 2D restriction r_c = P^T r_f by rows of coarse nodes (as k_restrict, optional clearing of
-// zc over the coarse block done by the same launch)
+// zc over the coarse block done by the same launch).  A wavefront takes kRestrictCols coarse
+// columns of R coarse rows: lane l holds fine column 2 i0 - 1 + l of the 2R + 1 fine rows around
+// them (whole-row loads), and each odd lane, the centre 2i of one coarse node, takes the values
+// of the fine columns 2i - 1 and 2i + 1 from the lanes beside it by DPP shifts.  Fine nodes
+// outside the closure count as zero.  The seven terms are summed in the order of the lattice
+// directions, as k_restrict does.
+constexpr int kRestrictCols = 31;
 template <typename T>
 __global__ void __launch_bounds__(256) k_restrict2d_rows(LK f, LK c, Tables tb, const T* __restrict__ rf,
                                                          T* __restrict__ bc, T* __restrict__ zc, int nseg) {
-  constexpr int R = kApplyRows;
+  constexpr int R = kApplyRows, NF = 2 * R + 1;
   const int n = c.n, nf = f.n;
   const int nrb = (n + 1 + R - 1) / R;
   const int wid = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
@@ -2343,48 +2349,54 @@ __global__ void __launch_bounds__(256) k_restrict2d_rows(LK f, LK c, Tables tb, 
   const int rem = wid - m * nrb * nseg;
   const int jb = rem / nseg, seg = rem - jb * nseg;
   const int lane = (int)(threadIdx.x & 63);
-  const int i = seg * 64 + lane;
   const int64_t fb = (int64_t)m * f.S, cb = (int64_t)m * c.S;
   // the padding of the coarse block (beyond the closure) is cleared by the wavefronts of the
   // first row block
   if (zc && jb == 0)
     for (int64_t s = c.Sraw + seg * 64 + lane; s < c.S; s += (int64_t)nseg * 64) zc[cb + s] = (T)0;
-  if (seg * 64 > n - jb * R) return;
+  const int j0 = jb * R, i0 = seg * kRestrictCols;
+  if (i0 > n - j0) return;   // no coarse node of this wavefront lies in the closure
   const __amdgpu_buffer_rsrc_t rr = d_rsrc(rf + fb, (uint32_t)f.Sraw * (uint32_t)sizeof(T));
   const __amdgpu_buffer_rsrc_t rc = d_rsrc(bc + cb, (uint32_t)c.Sraw * (uint32_t)sizeof(T));
   const uint32_t dirb = tb.dirbits[m];
-  T xv[R][7];
-  int sidx[R], mk[R];
-  bool ok[R];
+  // fine rows 2 j0 - 1 .. 2 (j0 + R - 1) + 1 at fine column a, every lane (the shifts need all)
+  const int a = 2 * i0 - 1 + lane;
+  T v[NF], vn[NF], vp[NF];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int j = jb * R + r;
-    ok[r] = j <= n && i < n + 1 - j;
-    mk[r] = ok[r] ? d_mask<2>(n, i, j, 0) : 0;
-    sidx[r] = ok[r] ? d_lin2(n, i, j) : 0;
-    const int fi = 2 * i, fj = 2 * j;
-#pragma unroll
-    for (int d = 0; d < 7; ++d) {
-      // fine neighbour inside the fine closure (the valid directions of this zero-set)
-      const int a = fi + kOff2[d][0], bb = fj + kOff2[d][1];
-      const bool use = ok[r] && a >= 0 && bb >= 0 && a + bb <= nf;
-      d_bload(rr, use ? (uint32_t)d_lin2(nf, a, bb) * (uint32_t)sizeof(T) : 0u, xv[r][d]);
-      xv[r][d] = use ? xv[r][d] : (T)0;
-    }
+  for (int t = 0; t < NF; ++t) {
+    const int b = 2 * j0 - 1 + t;
+    const bool use = a >= 0 && b >= 0 && a + b <= nf;
+    d_bload(rr, use ? (uint32_t)d_lin2(nf, a, b) * (uint32_t)sizeof(T) : 0u, v[t]);
+    v[t] = use ? v[t] : (T)0;
   }
 #pragma unroll
+  for (int t = 0; t < NF; ++t) {
+    vn[t] = from_next(v[t]);
+    vp[t] = from_prev(v[t]);
+  }
+  const bool centre = (lane & 1) != 0 && lane < 2 * kRestrictCols;
+  const int i = i0 + ((lane - 1) >> 1);
+#pragma unroll
   for (int r = 0; r < R; ++r) {
-    if (!ok[r]) continue;
-    const uint32_t co = (uint32_t)sidx[r] * (uint32_t)sizeof(T);
-    if (zc) zc[cb + sidx[r]] = (T)0;
-    if ((dirb >> mk[r]) & 1) {
+    const int j = j0 + r;
+    if (!(centre && j <= n && i < n + 1 - j)) continue;
+    const int s = d_lin2(n, i, j);
+    const uint32_t co = (uint32_t)s * (uint32_t)sizeof(T);
+    if (zc) zc[cb + s] = (T)0;
+    if ((dirb >> d_mask<2>(n, i, j, 0)) & 1) {
       d_bstore(rc, co, (T)0);
       continue;
     }
+    // rows 2j - 1, 2j, 2j + 1 are v[2r], v[2r + 1], v[2r + 2]; directions (1,0), (0,1),
+    // (-1,1), (-1,0), (0,-1), (1,-1)
     T acc = (T)0;
-#pragma unroll
-    for (int d = 1; d < 7; ++d) acc += xv[r][d];
-    d_bstore(rc, co, xv[r][0] + (T)0.5 * acc);
+    acc += vn[2 * r + 1];
+    acc += v[2 * r + 2];
+    acc += vp[2 * r + 2];
+    acc += vp[2 * r + 1];
+    acc += v[2 * r];
+    acc += vn[2 * r];
+    d_bstore(rc, co, v[2 * r + 1] + (T)0.5 * acc);
   }
 }
 
@@ -3357,7 +3369,7 @@ void launch_iface_residual(int dim, bool p1, const LK& lk, const Tables& tb, con
 template <typename T>
 void launch_restrict(int dim, const LK& f, const LK& c, const Tables& tb, const T* rf, T* bc, hipStream_t st, T* zc) {
   if (dim == 2) {
-    const int nseg = (c.n + 1 + 63) / 64, nrb = (c.n + 1 + kApplyRows - 1) / kApplyRows;
+    const int nseg = (c.n + 1 + kRestrictCols - 1) / kRestrictCols, nrb = (c.n + 1 + kApplyRows - 1) / kApplyRows;
     const unsigned gw = (unsigned)(((int64_t)c.nmacro * nrb * nseg + 3) / 4);
     k_restrict2d_rows<T><<<gw, 256, 0, st>>>(f, c, tb, rf, bc, zc, nseg);
     return;
