@@ -2331,16 +2331,16 @@ __global__ void __launch_bounds__(256) k_prolong2d_rows(LK f, LK c, Tables tb, c
 
 // 2D restriction r_c = P^T r_f by rows of coarse nodes (as k_restrict, optional clearing of
 // zc over the coarse block done by the same launch).  A wavefront takes kRestrictCols coarse
-// columns of R coarse rows: lane l holds fine column 2 i0 - 1 + l of the 2R + 1 fine rows around
-// them (whole-row loads), and each odd lane, the centre 2i of one coarse node, takes the values
-// of the fine columns 2i - 1 and 2i + 1 from the lanes beside it by DPP shifts.  Fine nodes
-// outside the closure count as zero.  The seven terms are summed in the order of the lattice
-// directions, as k_restrict does.
-constexpr int kRestrictCols = 31;
+// columns of R = kRestrictRows coarse rows: lane l holds fine column 2 i0 - 1 + l of the 2R + 1
+// fine rows around them (whole-row loads), and each odd lane, the centre 2i of one coarse node,
+// takes the values of the fine columns 2i - 1 and 2i + 1 from the lanes beside it by DPP
+// shifts.  Fine nodes outside the closure count as zero.  The seven terms are summed in the
+// order of the lattice directions, as k_restrict does.
+constexpr int kRestrictCols = 31, kRestrictRows = 8;
 template <typename T>
 __global__ void __launch_bounds__(256) k_restrict2d_rows(LK f, LK c, Tables tb, const T* __restrict__ rf,
                                                          T* __restrict__ bc, T* __restrict__ zc, int nseg) {
-  constexpr int R = kApplyRows, NF = 2 * R + 1;
+  constexpr int R = kRestrictRows, NF = 2 * R + 1;
   const int n = c.n, nf = f.n;
   const int nrb = (n + 1 + R - 1) / R;
   const int wid = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
@@ -3369,7 +3369,7 @@ void launch_iface_residual(int dim, bool p1, const LK& lk, const Tables& tb, con
 template <typename T>
 void launch_restrict(int dim, const LK& f, const LK& c, const Tables& tb, const T* rf, T* bc, hipStream_t st, T* zc) {
   if (dim == 2) {
-    const int nseg = (c.n + 1 + kRestrictCols - 1) / kRestrictCols, nrb = (c.n + 1 + kApplyRows - 1) / kApplyRows;
+    const int nseg = (c.n + 1 + kRestrictCols - 1) / kRestrictCols, nrb = (c.n + 1 + kRestrictRows - 1) / kRestrictRows;
     const unsigned gw = (unsigned)(((int64_t)c.nmacro * nrb * nseg + 3) / 4);
     k_restrict2d_rows<T><<<gw, 256, 0, st>>>(f, c, tb, rf, bc, zc, nseg);
     return;
