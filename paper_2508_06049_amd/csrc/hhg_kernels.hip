@@ -1486,8 +1486,9 @@ void launch_iface2d_sweep(const LK& lk, const Tables& tb, const int32_t* erec, i
                           const int32_t* we2, const int32_t* a2i, const double* a2w, const T* xi, const T* xf, T* uout,
                           const T* b, double sA, hipStream_t st) {
   // workgroups of 4 wavefronts while an edge fits them (n <= 257): the wheel workgroups then
-  // carry no idle wavefronts and the edges are spread over more compute units
-  const int nch = (lk.n - 1 + 63) / 64, threads = nch <= 4 ? 256 : 1024, epb = threads / 64 / nch;
+  // carry no idle wavefronts and the edges are spread over more compute units; above that, one
+  // edge per workgroup (the wheel part needs at least 4 wavefronts per workgroup)
+  const int nch = (lk.n - 1 + 63) / 64, threads = nch <= 4 ? 256 : 64 * nch, epb = threads / 64 / nch;
   const int ge = std::max(1, (nE + epb - 1) / epb), gw = (nwaves + 3) / 4;
   k_iface2d_sweep<T><<<(unsigned)(ge + gw), (unsigned)threads, 0, st>>>(lk, tb, erec, nE, nch, epb, ge, dvcopy, n_dv,
                                                                         wcopy, winfo, wloc, wseg, wsrc, wcw, wwmax,
